@@ -1,0 +1,324 @@
+"""Python face of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Wraps ``liboracle.so`` (plain C, built from ``fmm_oracle.c``) and adds the
+hierarchical Hamiltonian splitting (HHS) integrator of the paper (Sec. 2.2,
+Algorithms 1-3) in plain numpy on top of the oracle's force solve.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this module.  It imports nothing from the GPU package, and the GPU
+package imports nothing from here.
+
+Conventions (shared with the GPU path only through their documented meaning):
+positions are SoA float64 arrays of shape (3, n); accelerations are per unit
+mass, a_i = -grad_i Phi; potentials Phi_i = sum_{j != i} m_j psi(r_ij) with
+G = 1 and psi < 0.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fmm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+WENDLAND = 0
+PLUMMER = 1
+
+
+def build_oracle() -> str:
+    """Compile the C oracle (gcc, FP64, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           _SRC, "-o", _LIB, "-lm"]
+    subprocess.check_call(cmd)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build_oracle()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        L.orc_fmm.restype = ctypes.c_int
+        L.orc_tree_build.restype = ctypes.c_void_p
+        L.orc_tree_build.argtypes = [dp, i64, ctypes.c_void_p, i64, ctypes.c_void_p]
+        L.orc_tree_free.argtypes = [ctypes.c_void_p]
+        L.orc_tree_info.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_tree_export.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 11
+        L.orc_tree_eval_ex.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp,
+                                       ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_direct.argtypes = [dp, dp, i64, ctypes.c_void_p, i64, ctypes.c_int,
+                                 ctypes.c_double, dp, dp]
+        L.orc_derivs_export.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp,
+                                        ctypes.POINTER(ctypes.c_int)]
+        for name in ("orc_wendland_phi", "orc_wendland_g", "orc_plummer_phi", "orc_plummer_g"):
+            f = getattr(L, name)
+            f.restype = ctypes.c_double
+            f.argtypes = [ctypes.c_double, ctypes.c_double]
+        _lib = L
+    return _lib
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("theta", ctypes.c_double), ("eps", ctypes.c_double),
+                ("leaf_size", ctypes.c_int), ("kernel", ctypes.c_int)]
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _vp(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _pos(pos):
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    assert pos.ndim == 2 and pos.shape[0] == 3
+    return pos
+
+
+def _active(active):
+    if active is None:
+        return None
+    return np.ascontiguousarray(active, dtype=np.int32)
+
+
+def kernel_phi(kernel, r, eps):
+    f = lib().orc_plummer_phi if kernel == PLUMMER else lib().orc_wendland_phi
+    return f(float(r), float(eps))
+
+
+def kernel_g(kernel, r, eps):
+    f = lib().orc_plummer_g if kernel == PLUMMER else lib().orc_wendland_g
+    return f(float(r), float(eps))
+
+
+def coeff_count(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def derivs(p, R, e2=0.0):
+    """D^k psi(R) for |k| <= p by power-series composition; returns (D, k)."""
+    K = coeff_count(p)
+    D = np.zeros(K)
+    k = np.zeros(3 * K, dtype=np.int32)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    rc = lib().orc_derivs_export(p, _dp(R), float(e2), _dp(D),
+                                 k.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    assert rc == 0
+    return D, k.reshape(K, 3)
+
+
+def direct(pos, mass, kernel, eps, sinks=None):
+    """O(N^2) direct summation: (acc (3, n_sinks), pot (n_sinks))."""
+    pos = _pos(pos)
+    n = pos.shape[1]
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    s = None if sinks is None else np.ascontiguousarray(sinks, dtype=np.int64)
+    ns = n if s is None else len(s)
+    acc = np.zeros((3, ns))
+    pot = np.zeros(ns)
+    rc = lib().orc_direct(_dp(pos), _dp(mass), n, _vp(s), ns, int(kernel), float(eps),
+                          _dp(acc), _dp(pot))
+    assert rc == 0
+    return acc, pot
+
+
+class Tree:
+    """Oracle tree + interaction lists over the active set, canonical export."""
+
+    def __init__(self, pos, active=None, *, p, theta, eps, leaf_size, kernel):
+        self.pos = _pos(pos)
+        self.n_total = self.pos.shape[1]
+        self.active = _active(active)
+        self.n = self.n_total if self.active is None else len(self.active)
+        self.prm = _Params(int(p), float(theta), float(eps), int(leaf_size), int(kernel))
+        self.p = int(p)
+        self._h = lib().orc_tree_build(_dp(self.pos), self.n_total, _vp(self.active), self.n,
+                                       ctypes.byref(self.prm))
+        if not self._h:
+            raise ValueError("oracle tree build rejected its arguments")
+        info = np.zeros(6, dtype=np.int64)
+        lib().orc_tree_info(self._h, _vp(info))
+        self.n_nodes, self.n_m2l, self.n_p2p, self.depth, self.n_leaves = (
+            int(info[1]), int(info[2]), int(info[3]), int(info[4]), int(info[5]))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_tree_free(h)
+            self._h = None
+
+    def export(self):
+        nn = self.n_nodes
+        out = dict(
+            perm=np.zeros(self.n, dtype=np.int64),
+            level=np.zeros(nn, dtype=np.int32),
+            prefix=np.zeros(nn, dtype=np.uint64),
+            begin=np.zeros(nn, dtype=np.int64),
+            end=np.zeros(nn, dtype=np.int64),
+            is_leaf=np.zeros(nn, dtype=np.int32),
+            centre=np.zeros((nn, 3)),
+            half=np.zeros(nn),
+            m2l=np.zeros((self.n_m2l, 2), dtype=np.int64),
+            p2p=np.zeros((self.n_p2p, 2), dtype=np.int64),
+            box=np.zeros(5),
+        )
+        lib().orc_tree_export(self._h, *[_vp(out[k]) for k in (
+            "perm", "level", "prefix", "begin", "end", "is_leaf", "centre", "half", "m2l",
+            "p2p", "box")])
+        return out
+
+    def evaluate(self, mass, want_expansions=False):
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        acc = np.zeros((3, self.n))
+        pot = np.zeros(self.n)
+        M = L = None
+        if want_expansions:
+            K = coeff_count(self.p)
+            M = np.zeros((self.n_nodes, K))
+            L = np.zeros((self.n_nodes, K))
+        rc = lib().orc_tree_eval_ex(self._h, _dp(mass), self.n_total, _vp(self.active),
+                                    _dp(acc), _dp(pot), _vp(M), _vp(L))
+        assert rc == 0
+        if want_expansions:
+            return acc, pot, M, L
+        return acc, pot
+
+
+def fmm(pos, mass, active=None, *, p, theta, eps, leaf_size, kernel):
+    """One oracle FMM force evaluation on the active set: (acc (3,n), pot (n))."""
+    t = Tree(pos, active, p=p, theta=theta, eps=eps, leaf_size=leaf_size, kernel=kernel)
+    return t.evaluate(mass)
+
+
+# --------------------------------------------------------------------------
+# HHS integrator, Sec. 2.2, Algorithms 1-3, in plain numpy
+# --------------------------------------------------------------------------
+class HHSState:
+    """Particle state of the HHS integrator (float64, SoA)."""
+
+    def __init__(self, pos, vel, mass):
+        self.pos = np.array(pos, dtype=np.float64, copy=True)
+        self.vel = np.array(vel, dtype=np.float64, copy=True)
+        self.mass = np.array(mass, dtype=np.float64, copy=True)
+        n = self.mass.shape[0]
+        self.a_old = np.zeros(n)   # |a| from the latest second kickS2F
+        self.a_cur = np.zeros(n)   # |a| from the latest second kickFS2S
+        self.rung = np.zeros(n, dtype=np.int32)
+        self.t = 0.0
+        self.force_calls = 0
+        self.force_particles = 0
+
+
+class HHSOracle:
+    """EVOLVE_HOLD / KDK / KICK of Algorithms 1-3 with the oracle FMM.
+
+    Readings where the paper is silent: a particle's timestep is
+    sqrt(eta*eps/|a|) (Sec. 2.2) with |a| = |a_old| + |a_cur|; its rung is the
+    smallest r >= 0 with dt_top*2^-r <= dt_i (clamped to max_levels-1), decided
+    as (dt_r*dt_r)*|a| <= eta*eps so no square root enters the decision;
+    at rung k the slow set is {rung <= k}, the fast set {rung > k}; rungs of the
+    system are recomputed on entry when calc_timestep is set; a_old is refreshed
+    at second kickS2F kicks and a_cur at second kickFS2S kicks (Algorithm 3).
+    """
+
+    def __init__(self, *, p, theta, eps, leaf_size, kernel, eta, max_levels, freeze_rungs=False):
+        self.kw = dict(p=p, theta=theta, eps=eps, leaf_size=leaf_size, kernel=kernel)
+        self.eps = float(eps)
+        self.eta = float(eta)
+        self.max_levels = int(max_levels)
+        self.freeze_rungs = bool(freeze_rungs)
+
+    def forces(self, st, active, mass):
+        st.force_calls += 1
+        st.force_particles += len(active)
+        return fmm(st.pos, mass, active.astype(np.int32), **self.kw)
+
+    def init_forces(self, st):
+        idx = np.arange(st.mass.shape[0], dtype=np.int32)
+        acc, pot = self.forces(st, idx, st.mass)
+        st.a_cur = np.sqrt((acc * acc).sum(axis=0))
+        st.a_old = np.zeros_like(st.a_cur)
+        return acc, pot
+
+    def rungs(self, st, idx, dt_top):
+        a = st.a_old[idx] + st.a_cur[idx]
+        rhs = self.eta * self.eps
+        r = np.full(len(idx), self.max_levels - 1, dtype=np.int32)
+        for k in range(self.max_levels - 1, -1, -1):
+            dtk = np.ldexp(dt_top, -k)
+            ok = (dtk * dtk) * a <= rhs
+            r = np.where(ok, k, r)
+        return r
+
+    def kick(self, st, sys1, joint, dt, kick_s2f, second):
+        mass = st.mass.copy()
+        if kick_s2f:
+            mass[sys1] = 0.0
+        acc, _ = self.forces(st, joint, mass)
+        pos_in_joint = np.searchsorted(joint, sys1)
+        a1 = acc[:, pos_in_joint]
+        st.vel[:, sys1] += a1 * dt
+        if second:
+            mag = np.sqrt((a1 * a1).sum(axis=0))
+            if kick_s2f:
+                st.a_old[sys1] = mag
+            else:
+                st.a_cur[sys1] = mag
+
+    def kdk(self, st, slow, fast, sysall, dt):
+        # Algorithm 2.  A kick whose sink set is empty, or a kickS2F whose source
+        # set S is empty (every force would be zero), is skipped; this is what
+        # makes a two-rung system cost 2 + 2 + 2^(k+1) solver calls (Sec. 2.2).
+        s2f = len(fast) > 0 and len(slow) > 0
+        if s2f:
+            self.kick(st, fast, sysall, dt / 2, True, False)
+        if len(slow):
+            self.kick(st, slow, sysall, dt / 2, False, False)
+        st.pos[:, slow] += st.vel[:, slow] * dt
+        if len(slow):
+            self.kick(st, slow, sysall, dt / 2, False, True)
+        if s2f:
+            self.kick(st, fast, sysall, dt / 2, True, True)
+
+    def evolve(self, st, k, sysall, dt, calc, dt_top):
+        if calc and not self.freeze_rungs:
+            st.rung[sysall] = self.rungs(st, sysall, dt_top)
+        r = st.rung[sysall]
+        slow = sysall[r <= k]
+        fast = sysall[r > k]
+        if len(fast):
+            self.evolve(st, k + 1, fast, dt / 2, False, dt_top)
+        self.kdk(st, slow, fast, sysall, dt)
+        if len(fast):
+            self.evolve(st, k + 1, fast, dt / 2, True, dt_top)
+
+    def step(self, st, dt_top):
+        """Advance every particle by dt_top (one top-level EVOLVE_HOLD)."""
+        sysall = np.arange(st.mass.shape[0], dtype=np.int32)
+        self.evolve(st, 0, sysall, dt_top, True, dt_top)
+        st.t += dt_top
+
+
+def invariants(pos, vel, mass, acc=None, pot=None):
+    """Total momentum, angular momentum, kinetic energy, (potential energy, sum m a)."""
+    P = (mass * vel).sum(axis=1)
+    Lm = (mass * np.cross(pos.T, vel.T).T).sum(axis=1)
+    T = 0.5 * (mass * (vel * vel).sum(axis=0)).sum()
+    out = dict(P=P, L=Lm, T=T)
+    if pot is not None:
+        out["W"] = 0.5 * (mass * pot).sum()
+    if acc is not None:
+        out["F"] = (mass * acc).sum(axis=1)
+    return out

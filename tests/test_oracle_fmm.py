@@ -1,0 +1,135 @@
+"""Pins of the oracle FMM force solve against direct summation, closed forms
+and the conservation law the paper is about (no GPU).
+
+* special cases that reduce the FMM to direct summation: one leaf, or a tiny
+  opening angle (no cell-cell interaction at all);
+* convergence to direct summation as the expansion order grows and as the
+  opening angle shrinks (the error falls like theta^p, Sec. 3.2.2);
+* the Plummer sphere's closed-form potential and radial acceleration;
+* total momentum: sum_i m_i a_i = 0 to round-off because every cell-cell and
+  leaf-leaf interaction is applied to both sides (Sec. 2.1, Eq. 2), also across
+  the two differently masked calls of a kick pair (Sec. 2.3, Fig. 2);
+* M2M exactness against moments taken directly from the particles.
+"""
+import numpy as np
+import pytest
+
+from paper_1712_10116_amd import workloads as W
+
+
+def _err(a, ref):
+    mag = np.sqrt((ref * ref).sum(axis=0))
+    floor = 1e-6 * np.sqrt((mag * mag).mean())
+    e = np.sqrt(((a - ref) ** 2).sum(axis=0)) / np.maximum(mag, floor)
+    return np.sqrt((e * e).mean()), np.percentile(e, 99)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_reduces_to_direct(oracle, kernel):
+    pos, _, m = W.config(0, n=1500)
+    ad, pd = oracle.direct(pos, m, kernel, 0.02)
+    for theta, leaf in ((1e-6, 8), (0.5, 4096)):
+        a, pt = oracle.fmm(pos, m, p=4, theta=theta, eps=0.02, leaf_size=leaf, kernel=kernel)
+        np.testing.assert_allclose(a, ad, rtol=0, atol=1e-13 * np.abs(ad).max())
+        np.testing.assert_allclose(pt, pd, rtol=0, atol=1e-13 * np.abs(pd).max())
+
+
+def test_converges_with_order(oracle):
+    pos, _, m = W.config(1, n=2000)
+    ad, pd = oracle.direct(pos, m, 0, 0.005)
+    errs = []
+    for p in (1, 2, 3, 4, 6, 8, 10):
+        a, pt = oracle.fmm(pos, m, p=p, theta=0.35, eps=0.005, leaf_size=16, kernel=0)
+        errs.append(_err(a, ad)[0])
+    assert all(e2 < e1 for e1, e2 in zip(errs[:-1], errs[1:])), errs
+    assert errs[-1] < 5e-6, errs
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_converges_with_theta(oracle, kernel):
+    pos, _, m = W.config(0, n=3000)
+    ad, _ = oracle.direct(pos, m, kernel, 0.01)
+    errs = [_err(oracle.fmm(pos, m, p=4, theta=th, eps=0.01, leaf_size=16, kernel=kernel)[0], ad)[0]
+            for th in (0.55, 0.45, 0.35, 0.25)]
+    assert all(e2 < e1 for e1, e2 in zip(errs[:-1], errs[1:])), errs
+
+
+def test_plummer_closed_form(oracle):
+    # Phi(r) = -M/sqrt(r^2 + a^2) and a_r = -M r/(r^2 + a^2)^(3/2), G = M = a = 1,
+    # compared on radial bins within shot noise (the kernel softening is small)
+    n = 8192
+    pos, _, m = W.plummer(n, seed=77)
+    a, pt = oracle.fmm(pos, m, p=5, theta=0.4, eps=0.002, leaf_size=16, kernel=1)
+    r = np.sqrt((pos * pos).sum(axis=0))
+    ar = (a * pos).sum(axis=0) / r
+    edges = np.array([0.1, 0.3, 0.6, 1.0, 1.6, 2.5, 4.0])
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = (r >= lo) & (r < hi)
+        k = sel.sum()
+        assert k > 100
+        phi_cf = -1.0 / np.sqrt(r[sel] ** 2 + 1.0)
+        ar_cf = -r[sel] / (r[sel] ** 2 + 1.0) ** 1.5
+        tol = 4.0 / np.sqrt(k)
+        assert abs(pt[sel].mean() / phi_cf.mean() - 1) < tol
+        assert abs(ar[sel].mean() / ar_cf.mean() - 1) < 3 * tol
+
+
+@pytest.mark.parametrize("cfg,kernel,eps", [(0, 1, 0.01), (1, 0, 0.005)])
+def test_momentum_round_off(oracle, cfg, kernel, eps):
+    pos, _, m = W.config(cfg, n=6000)
+    a, _ = oracle.fmm(pos, m, p=4, theta=0.5, eps=eps, leaf_size=16, kernel=kernel)
+    rel = np.abs((m * a).sum(axis=1)).max() / (m * np.sqrt((a * a).sum(axis=0))).sum()
+    assert rel < 1e-13
+
+
+def test_cross_call_cancellation(oracle):
+    # kickS2F (masses of F zeroed, sinks F) and kickFS2S (all masses, sinks S)
+    # over the same joint set and tree: sum_F m a^S2F + sum_S m a^FS2S = 0
+    pos, _, m = W.config(1, n=5000)
+    rng = np.random.default_rng(3)
+    fast = rng.uniform(size=m.size) < 0.3
+    t = oracle.Tree(pos, p=4, theta=0.5, eps=0.005, leaf_size=16, kernel=0)
+    mm = m.copy(); mm[fast] = 0.0
+    a_s2f, _ = t.evaluate(mm)
+    a_fs2s, _ = t.evaluate(m)
+    tot = (m[fast] * a_s2f[:, fast]).sum(axis=1) + (m[~fast] * a_fs2s[:, ~fast]).sum(axis=1)
+    scale = (m * np.sqrt((a_fs2s ** 2).sum(axis=0))).sum()
+    assert np.abs(tot).max() / scale < 1e-13
+    # and it is not zero by accident: the F-on-F part alone does not vanish
+    assert np.abs((m[fast] * a_fs2s[:, fast]).sum(axis=1)).max() / scale > 1e-6
+
+
+def test_m2m_exact(oracle):
+    pos, _, m = W.config(0, n=800)
+    t = oracle.Tree(pos, p=4, theta=0.5, eps=0.01, leaf_size=8, kernel=1)
+    ex = t.export()
+    _, _, M, _ = t.evaluate(m, want_expansions=True)
+    _, k = oracle.derivs(4, np.array([1.0, 0.0, 0.0]))
+    from math import factorial
+    fk = np.array([factorial(a) * factorial(b) * factorial(c) for a, b, c in k], dtype=float)
+    perm = ex["perm"]
+    for i in range(t.n_nodes):
+        sl = perm[ex["begin"][i]:ex["end"][i]]
+        u = pos[:, sl] - ex["centre"][i][:, None]
+        mono = np.prod(u[None, :, :] ** k[:, :, None], axis=1) / fk[:, None]
+        direct = (mono * m[sl][None, :]).sum(axis=1)
+        np.testing.assert_allclose(M[i], direct, rtol=1e-10, atol=1e-14 * np.abs(direct).max())
+
+
+def test_empty_and_single(oracle):
+    pos = np.zeros((3, 1))
+    a, pt = oracle.fmm(pos, np.ones(1), p=4, theta=0.5, eps=0.01, leaf_size=16, kernel=0)
+    assert (a == 0).all() and (pt == 0).all()
+    pos = np.random.default_rng(0).uniform(size=(3, 10))
+    a, pt = oracle.fmm(pos, np.ones(10), np.zeros(0, dtype=np.int32), p=4, theta=0.5, eps=0.01,
+                       leaf_size=16, kernel=0)
+    assert a.shape == (3, 0)
+
+
+def test_active_subset_order(oracle):
+    # forces on an active subset equal the forces of the gathered sub-system
+    pos, _, m = W.config(1, n=3000)
+    act = np.random.default_rng(5).permutation(3000)[:1234].astype(np.int32)
+    a1, p1 = oracle.fmm(pos, m, act, p=4, theta=0.5, eps=0.005, leaf_size=16, kernel=0)
+    a2, p2 = oracle.fmm(pos[:, act], m[act], p=4, theta=0.5, eps=0.005, leaf_size=16, kernel=0)
+    np.testing.assert_allclose(a1, a2, rtol=1e-12, atol=1e-12 * np.abs(a2).max())

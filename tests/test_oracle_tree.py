@@ -1,0 +1,201 @@
+"""Pins of the oracle's Morton tree and symmetric interaction lists (no GPU).
+
+The tree is checked against invariants any correct top-down octree split must
+satisfy (Sec. 2.3: recursive split while a cell holds more than n_crit
+particles), and against Morton keys recomputed here by plain numpy bit
+interleaving.  The lists are checked for exactly-once coverage of every
+ordered particle pair by brute force, for the well-separation rule on every
+M2L pair, and against the printed walk of Algorithm 4 run literally on
+ordered pairs from (root, root)."""
+import numpy as np
+import pytest
+
+from paper_1712_10116_amd import workloads as W
+
+
+def _tree(oracle, pos, **kw):
+    prm = dict(p=3, theta=0.5, eps=0.01, leaf_size=8, kernel=oracle.WENDLAND)
+    prm.update(kw)
+    t = oracle.Tree(pos, **prm)
+    return t, t.export(), prm
+
+
+def _keys_numpy(pos):
+    lo, hi = pos.min(axis=1), pos.max(axis=1)
+    c = 0.5 * (lo + hi)
+    L = (hi - lo).max()
+    L = 1.0 if L == 0 else L
+    o = c - 0.5 * L
+    s = 2097152.0 / L
+    q = np.clip(np.floor((pos - o[:, None]) * s), 0, 2 ** 21 - 1).astype(np.uint64)
+    key = np.zeros(pos.shape[1], dtype=np.uint64)
+    for b in range(21):
+        for ax, off in ((0, 2), (1, 1), (2, 0)):
+            key |= ((q[ax] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + off)
+    return key, o, L
+
+
+@pytest.mark.parametrize("cfg,n,leaf", [(0, 700, 8), (1, 1000, 16), (0, 64, 1), (1, 3, 8)])
+def test_tree_invariants(oracle, cfg, n, leaf):
+    pos, _, _ = W.config(cfg, n=n)
+    t, ex, prm = _tree(oracle, pos, leaf_size=leaf)
+    key, o, L = _keys_numpy(pos)
+    perm = ex["perm"]
+    # permutation is a stable sort of the independently computed keys
+    assert sorted(perm.tolist()) == list(range(n))
+    np.testing.assert_array_equal(perm, np.lexsort((np.arange(n), key)))
+    np.testing.assert_allclose(ex["box"][:3], o, rtol=0, atol=0)
+    assert ex["box"][3] == L
+    skey = key[perm]
+    lvl, beg, end, leafm = ex["level"], ex["begin"], ex["end"], ex["is_leaf"].astype(bool)
+    # pre-order == sorted by (begin, level)
+    order = np.lexsort((lvl, beg))
+    np.testing.assert_array_equal(order, np.arange(t.n_nodes))
+    # leaves partition [0, n)
+    lv = np.where(leafm)[0]
+    lv = lv[np.argsort(beg[lv])]
+    assert beg[lv[0]] == 0 and end[lv[-1]] == n
+    assert (beg[lv[1:]] == end[lv[:-1]]).all()
+    for i in range(t.n_nodes):
+        cnt = end[i] - beg[i]
+        assert cnt >= 1
+        sh = np.uint64(3 * (21 - lvl[i]))
+        pref = skey[beg[i]:end[i]] >> sh
+        assert (pref == ex["prefix"][i]).all()           # one key prefix per node
+        if leafm[i]:
+            assert cnt <= leaf or lvl[i] == 21
+        else:
+            assert cnt > leaf
+        # every particle lies inside its node's cube (geometric centre, half side)
+        pts = pos[:, perm[beg[i]:end[i]]]
+        d = np.abs(pts - ex["centre"][i][:, None])
+        assert (d <= ex["half"][i] * (1 + 1e-12) + 1e-300).all()
+        assert ex["half"][i] == L * 2.0 ** -(lvl[i] + 1)
+    # children: contiguous ranges partitioning the parent, one level deeper
+    for i in np.where(~leafm)[0]:
+        kids = [j for j in range(i + 1, t.n_nodes) if lvl[j] == lvl[i] + 1 and beg[i] <= beg[j] < end[i]]
+        assert beg[kids[0]] == beg[i] and end[kids[-1]] == end[i]
+        for a, b in zip(kids[:-1], kids[1:]):
+            assert end[a] == beg[b]
+            assert ex["prefix"][a] < ex["prefix"][b]
+
+
+def test_tree_degenerate_coincident(oracle):
+    # all particles at one point: keys identical, split stops at depth 21
+    pos = np.zeros((3, 40)) + 0.25
+    t, ex, _ = _tree(oracle, pos, leaf_size=4)
+    assert t.depth == 21
+    assert ex["is_leaf"][-1] == 1 and ex["end"][-1] - ex["begin"][-1] == 40
+    assert t.n_m2l == 0
+
+
+def _ancestors(ex):
+    nn = len(ex["level"])
+    parent = np.full(nn, -1)
+    stack = []
+    for i in range(nn):
+        while stack and ex["level"][stack[-1]] >= ex["level"][i]:
+            stack.pop()
+        parent[i] = stack[-1] if stack else -1
+        stack.append(i)
+    return parent
+
+
+def _leaf_of(ex, n):
+    leaf = np.zeros(n, dtype=np.int64)
+    for i in np.where(ex["is_leaf"] == 1)[0]:
+        leaf[ex["begin"][i]:ex["end"][i]] = i
+    return leaf
+
+
+@pytest.mark.parametrize("cfg,n,leaf,theta", [(0, 300, 4, 0.5), (1, 400, 8, 0.4), (0, 200, 1, 0.55)])
+def test_exactly_once_coverage(oracle, cfg, n, leaf, theta):
+    pos, _, _ = W.config(cfg, n=n)
+    t, ex, prm = _tree(oracle, pos, leaf_size=leaf, theta=theta, eps=0.002)
+    parent = _ancestors(ex)
+    leafof = _leaf_of(ex, n)
+    # ancestor-or-self chains per sorted particle
+    chain = []
+    for i in range(n):
+        c, a = set(), leafof[i]
+        while a >= 0:
+            c.add(int(a)); a = parent[a]
+        chain.append(c)
+    cover = np.zeros((n, n), dtype=np.int64)
+    node_members = {}
+    for i in range(n):
+        for a in chain[i]:
+            node_members.setdefault(a, []).append(i)
+    for a, b in ex["m2l"]:
+        ia, ib = node_members[int(a)], node_members[int(b)]
+        cover[np.ix_(ia, ib)] += 1
+        cover[np.ix_(ib, ia)] += 1
+    for a, b in ex["p2p"]:
+        assert ex["is_leaf"][a] and ex["is_leaf"][b]
+        ia, ib = node_members[int(a)], node_members[int(b)]
+        if a == b:
+            cover[np.ix_(ia, ia)] += 1
+        else:
+            cover[np.ix_(ia, ib)] += 1
+            cover[np.ix_(ib, ia)] += 1
+    # a leaf's self pair also marks i == j once; no interaction may touch i == j otherwise
+    assert (cover.diagonal() == 1).all()
+    off = ~np.eye(n, dtype=bool)
+    assert (cover[off] == 1).all()
+    # the well-separation rule holds on every M2L pair, fails on every P2P leaf pair
+    th2 = prm["theta"] * prm["theta"]
+    for lst, want in ((ex["m2l"], True), (ex["p2p"], False)):
+        for a, b in lst:
+            if a == b:
+                continue
+            d = ex["centre"][a] - ex["centre"][b]
+            d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+            S = ex["half"][a] + ex["half"][b]
+            e = prm["eps"] + np.sqrt(3.0) * S
+            assert ((d2 * th2 > S * S) and (d2 > e * e)) == want
+
+
+def _alg4(ex, prm):
+    """Algorithm 4 run literally on ordered pairs from (root, root)."""
+    nn = len(ex["level"])
+    parent = _ancestors(ex)
+    kids = [[] for _ in range(nn)]
+    for i in range(1, nn):
+        kids[parent[i]].append(i)
+    th2 = prm["theta"] * prm["theta"]
+
+    def well_sep(a, b):
+        d = ex["centre"][a] - ex["centre"][b]
+        d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+        S = ex["half"][a] + ex["half"][b]
+        e = prm["eps"] + np.sqrt(3.0) * S
+        return d2 * th2 > S * S and d2 > e * e
+
+    m2l, p2p = set(), set()
+    stack = [(0, 0)]
+    while stack:
+        ci, cj = stack.pop()
+        if well_sep(ci, cj):
+            m2l.add((ci, cj))
+        elif not kids[ci] and not kids[cj]:
+            p2p.add((ci, cj))
+        elif not kids[ci]:
+            stack.extend((ci, c) for c in kids[cj])
+        elif not kids[cj]:
+            stack.extend((c, cj) for c in kids[ci])
+        else:
+            stack.extend((a, b) for a in kids[ci] for b in kids[cj])
+    return m2l, p2p
+
+
+@pytest.mark.parametrize("cfg,n,leaf,theta", [(0, 1500, 8, 0.5), (1, 2000, 16, 0.3)])
+def test_symmetric_closure_equals_algorithm4(oracle, cfg, n, leaf, theta):
+    pos, _, _ = W.config(cfg, n=n)
+    t, ex, prm = _tree(oracle, pos, leaf_size=leaf, theta=theta)
+    m2l, p2p = _alg4(ex, prm)
+    sym = lambda lst: {(int(a), int(b)) for a, b in lst} | {(int(b), int(a)) for a, b in lst}
+    assert sym(ex["m2l"]) == m2l
+    assert sym(ex["p2p"]) == p2p
+    # unordered lists hold no duplicates
+    assert len({tuple(x) for x in ex["m2l"].tolist()}) == t.n_m2l
+    assert len({tuple(x) for x in ex["p2p"].tolist()}) == t.n_p2p
