@@ -1,0 +1,177 @@
+/*
+ * fmm355.h -- C ABI of the MI355X (gfx950) symmetric FMM gravity solver and
+ * hierarchical-Hamiltonian-splitting (HHS) integrator.
+ *
+ * The method is that of Q. Zhu, "A momentum conserving N-body scheme with
+ * individual timesteps" (arXiv:1712.10116):
+ *   - a fast multipole (FMM) gravity solve on an oct-tree whose dual tree walk
+ *     opens BOTH cells of a pair that fails the well-separation test, so that
+ *     the cell-cell (M2L) and leaf-leaf (P2P) interaction lists are symmetric
+ *     and every interaction acts on both sides (Sec. 2.1, Eq. (1)-(2);
+ *     Sec. 2.3, Algorithm 4);
+ *   - the HOLD/HHS integrator that splits particles into slow and fast systems
+ *     on power-of-two timestep rungs, with kickS2F forces computed by masking
+ *     the masses of the fast system (Sec. 2.2, Algorithms 1-3; Sec. 2.3).
+ *
+ * Conventions for every call
+ *   - Units: G = 1.  Outputs are accelerations per unit mass,
+ *     a_i = -grad_i Phi_i, and potentials Phi_i = sum_{j != i} m_j psi(r_ij),
+ *     psi < 0 (Wendland C2 softening of Eq. (8), or Plummer softening).
+ *   - Particle arrays are structure-of-arrays in DEVICE memory: a position
+ *     array of n_total particles is x[0..n_total) followed by y and z (3 x
+ *     n_total doubles); masses are n_total doubles.  The caller owns every
+ *     particle, index and output buffer; the library owns its workspace.
+ *   - "active" lists n_active distinct indices into [0, n_total) (int32, device
+ *     memory); NULL means all n_total particles in order.  Outputs are written
+ *     in active-list order (output slot s belongs to particle active[s]).
+ *   - Every call is ordered on the stream given to fmm_create.  Argument
+ *     errors are returned synchronously without touching the GPU.  fmm_build
+ *     waits for its own work (it reads back list sizes); fmm_evaluate and
+ *     fmm_forces return once their kernels are queued.
+ *   - No call aborts the process.  On any status other than FMM_OK,
+ *     fmm_last_error() describes the failure.
+ *   - A context is not thread safe; use one context per host thread.
+ */
+#ifndef FMM355_H
+#define FMM355_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_EINVAL = 1,      /* bad argument (sizes, parameters, NULL pointers)      */
+    FMM_ENOMEM = 2,      /* device allocation failed                              */
+    FMM_EDEVICE = 3,     /* a HIP runtime call failed                             */
+    FMM_ENONFINITE = 4,  /* an input position was NaN or infinite                 */
+    FMM_ESTALE = 5,      /* fmm_evaluate without a tree built for these particles */
+    FMM_EOVERFLOW = 6    /* a list or tree exceeded its workspace after regrowth  */
+} fmm_status;
+
+typedef enum {
+    FMM_KERNEL_WENDLAND_C2 = 0, /* Eq. (8): Wendland C2 inside eps, -1/r outside   */
+    FMM_KERNEL_PLUMMER = 1      /* psi = -(r^2 + eps^2)^(-1/2)                     */
+} fmm_kernel;
+
+typedef enum {
+    FMM_PREC_FP64 = 0,  /* every step in IEEE double                                */
+    FMM_PREC_MIXED = 1  /* P2P, M2L and the expansions in FP32 on cell-local, size-
+                           scaled quantities; positions, centres, accumulation of
+                           the near field and the outputs in FP64                  */
+} fmm_precision;
+
+/* Solver parameters fixed for the life of a context. */
+typedef struct {
+    int p_max;          /* largest expansion order a call may ask for (1..8)       */
+    int leaf_size;      /* n_crit: a cell splits while it holds more particles (>=1) */
+    int kernel;         /* fmm_kernel                                              */
+    int precision;      /* fmm_precision                                           */
+} fmm_params;
+
+typedef struct fmm_ctx fmm_ctx;
+
+/* Create a solver context on the current HIP device for up to max_n active
+ * particles per call.  stream: a hipStream_t (NULL = the null stream).
+ * Allocates the whole workspace; later calls allocate only if an interaction
+ * list outgrows its estimate (the list buffer is then regrown once). */
+fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *stream, fmm_ctx **out);
+fmm_status fmm_destroy(fmm_ctx *ctx);
+const char *fmm_last_error(const fmm_ctx *ctx);
+
+/* Geometry-only part of the solve (independent of masses): root box, 63-bit
+ * Morton keys (21 bits per axis), stable key sort, top-down oct-tree split
+ * while a cell holds more than leaf_size particles (to depth 21), geometric
+ * cell centres, and the symmetric dual walk producing the M2L and P2P lists.
+ * Well-separation (Eq. (1) with R = cell half side, plus the softening rule of
+ * Sec. 2.3): |zA-zB|^2 theta^2 > (hA+hB)^2 and
+ * |zA-zB|^2 > (eps + sqrt(3)(hA+hB))^2.
+ * pos: device, 3 x n_total doubles.  active: device int32[n_active] or NULL.
+ * Requires 0 <= n_active <= max_n, 0 < theta, eps >= 0.  Blocks until the tree
+ * and lists are complete.  The tree stays valid for fmm_evaluate until the
+ * next fmm_build/fmm_forces on this context. */
+fmm_status fmm_build(fmm_ctx *ctx, const double *pos, int64_t n_total, const int32_t *active,
+                     int64_t n_active, double eps, double theta);
+
+/* Mass-dependent part on the tree of the last fmm_build: P2M, M2M (upward),
+ * M2L over the symmetric cell-pair list, P2P over the symmetric leaf-pair list,
+ * L2L (downward), L2P.  pos/active/n_active must be those of the build (else
+ * FMM_ESTALE).  mass: device, n_total doubles (zeros allowed: masked sources).
+ * acc: device, 3 x n_active doubles (SoA); pot: device, n_active doubles.
+ * 1 <= p <= p_max.  Asynchronous on the context's stream. */
+fmm_status fmm_evaluate(fmm_ctx *ctx, const double *pos, const double *mass, int64_t n_total,
+                        const int32_t *active, int64_t n_active, int p, double *acc,
+                        double *pot);
+
+/* fmm_build followed by fmm_evaluate: acceleration and potential of every
+ * active particle due to all active masses (the Poisson solve called by each
+ * kick of Algorithm 3). */
+fmm_status fmm_forces(fmm_ctx *ctx, const double *pos, const double *mass, int64_t n_total,
+                      const int32_t *active, int64_t n_active, double eps, double theta,
+                      int p, double *acc, double *pot);
+
+/* Sizes of the current tree: info[0] n_active, [1] nodes, [2] unordered M2L
+ * pairs, [3] unordered P2P leaf pairs (self pairs included), [4] depth,
+ * [5] leaves, [6] ordered M2L entries, [7] ordered P2P entries, [8] ordered
+ * particle-particle interactions evaluated by P2P. */
+fmm_status fmm_tree_info(fmm_ctx *ctx, int64_t info[9]);
+
+/* Canonical host copy of the current tree, for comparison with other
+ * implementations: nodes in pre-order (sorted by (begin, level)); perm[i] =
+ * active slot of the i-th particle in Morton order; pairs as (a <= b) over
+ * pre-order ids, sorted.  All outputs are HOST buffers sized from
+ * fmm_tree_info; any pointer may be NULL.  Synchronises the stream. */
+fmm_status fmm_export_tree(fmm_ctx *ctx, int64_t *perm, int32_t *level, uint64_t *prefix,
+                           int64_t *begin, int64_t *end, int32_t *is_leaf, double *centre,
+                           double *half, int64_t *m2l_pairs, int64_t *p2p_pairs, double *box);
+
+/* Stream-ordered FP64 reductions over n particles (device SoA inputs, any may
+ * be NULL): out[0..2] sum m a, out[3..5] sum m v, out[6..8] sum m x cross v,
+ * out[9] kinetic energy, out[10] potential energy 0.5 sum m Phi,
+ * out[11] sum m |a|.  out is a HOST array of 12 doubles; synchronises. */
+fmm_status fmm_invariants(fmm_ctx *ctx, const double *pos, const double *vel, const double *mass,
+                          const double *acc, const double *pot, int64_t n, double out[12]);
+
+/* ---------------------------------------------------------------------------
+ * HHS integrator (Sec. 2.2, Algorithms 1-3)
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double *pos;      /* device, 3 x n SoA, FP64 (updated in place)             */
+    double *vel;      /* device, 3 x n SoA, FP64 (updated in place)             */
+    const double *mass; /* device, n                                            */
+    double *a_old;    /* device, n: |a| of the latest second kickS2F            */
+    double *a_cur;    /* device, n: |a| of the latest second kickFS2S           */
+    int32_t *rung;    /* device, n: timestep rung (0 = dt_top)                  */
+    int64_t n;
+    double t;         /* host-side time, advanced by hhs_step                    */
+} hhs_state;
+
+typedef struct {
+    double eps, theta; /* as for fmm_build                                      */
+    int p;             /* expansion order                                       */
+    double eta;        /* timestep dt_i = sqrt(eta * eps / (|a_old| + |a_cur|))  */
+    int max_levels;    /* rungs 0 .. max_levels-1 (>= 1)                         */
+    int freeze_rungs;  /* nonzero: keep the rungs in state->rung                 */
+} hhs_params;
+
+/* Full force solve on all n particles, then a_cur = |a|, a_old = 0. */
+fmm_status hhs_init(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp);
+
+/* One top-level step of length dt_top (EVOLVE_HOLD at rung 0).  Rung of a
+ * particle: the smallest r >= 0 with dt_top 2^-r <= dt_i (clamped to
+ * max_levels-1), recomputed for a subsystem on entry when Algorithm 1 asks
+ * for it.  At rung k the slow set is {rung <= k}, the fast set {rung > k}.
+ * Each KDK (Algorithm 2) evaluates kickS2F (fast sinks, masses of the fast set
+ * zeroed) and kickFS2S (slow sinks, all masses) on one tree built over the
+ * joint set; a kick with no sinks, or a kickS2F with an empty slow set, is
+ * skipped.  Kicks and drifts are FP64.  stats (host, may be NULL):
+ * [0] force calls, [1] sum of active particles over the calls, [2] tree builds. */
+fmm_status hhs_step(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp, double dt_top,
+                    int64_t stats[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM355_H */

@@ -1,0 +1,604 @@
+// Host side of the C ABI declared in include/fmm355.h.
+//
+// A context owns one device workspace sized from max_n at creation.  Every
+// call is queued on the context's stream; fmm_build waits once, at its end,
+// to read the list sizes (and to regrow a list buffer that turned out too
+// small, which is then rebuilt once).
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "../../include/fmm355.h"
+#include "common.h"
+#include "hhs_kernels.h"
+
+struct fmm_ctx {
+  fmm_params prm;
+  int64_t max_n;
+  hipStream_t stream;
+  int device;
+  DevTree t;
+  std::vector<void *> allocs;
+  // host copy of the last build
+  Header hh;
+  bool tree_valid;
+  const double *b_pos;
+  int64_t b_n_total;
+  const int32_t *b_active;
+  int64_t b_n;
+  double b_eps, b_theta;
+  int n_nodes, depth;
+  // HHS scratch
+  int hhs_levels;
+  int32_t **lv_slow, **lv_slow_pos, **lv_fast, **lv_fast_pos;
+  int32_t *all_idx;
+  uint32_t *flag;
+  int32_t *count;
+  double *mmask, *acc, *pot;
+  double *inv_part;
+  int64_t stat_calls, stat_parts, stat_builds;
+  char err[512];
+};
+
+static fmm_status fail(fmm_ctx *c, fmm_status st, const char *fmt, ...) {
+  if (c) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+  }
+  return st;
+}
+
+#define HIPCHK(c, call)                                                                       \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail((c), FMM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));          \
+  } while (0)
+
+static int coeffs(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+
+template <typename T>
+static bool dalloc(fmm_ctx *c, T **p, int64_t count) {
+  void *q = nullptr;
+  size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  if (hipMalloc(&q, bytes) != hipSuccess) return false;
+  c->allocs.push_back(q);
+  *p = (T *)q;
+  return true;
+}
+
+static void dfree(fmm_ctx *c, void *p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+// node-sized arrays
+static bool alloc_nodes(fmm_ctx *c, int64_t cap) {
+  DevTree &t = c->t;
+  t.cap_nodes = cap;
+  size_t real = c->prm.precision == FMM_PREC_MIXED ? sizeof(float) : sizeof(double);
+  bool ok = dalloc(c, &t.nbeg, cap) && dalloc(c, &t.nend, cap) && dalloc(c, &t.nlev, cap) &&
+            dalloc(c, &t.nparent, cap) && dalloc(c, &t.nchild0, cap) &&
+            dalloc(c, &t.nnchild, cap) && dalloc(c, &t.ngeo, cap) &&
+            dalloc(c, &t.bounds, cap * 8) && dalloc(c, &t.m2l_off, cap) &&
+            dalloc(c, &t.m2l_cnt, cap) && dalloc(c, &t.p2p_off, cap) &&
+            dalloc(c, &t.p2p_cnt, cap) && dalloc(c, &t.open_off, cap) &&
+            dalloc(c, &t.open_cnt, cap);
+  if (!ok) return false;
+  char *m = nullptr, *l = nullptr;
+  ok = dalloc(c, &m, (int64_t)(cap * t.kmax * real)) && dalloc(c, &l, (int64_t)(cap * t.kmax * real));
+  t.M = m;
+  t.L = l;
+  return ok;
+}
+
+static void free_nodes(fmm_ctx *c) {
+  DevTree &t = c->t;
+  void *ptrs[] = {t.nbeg, t.nend, t.nlev, t.nparent, t.nchild0, t.nnchild, t.ngeo, t.bounds,
+                  t.m2l_off, t.m2l_cnt, t.p2p_off, t.p2p_cnt, t.open_off, t.open_cnt, t.M, t.L};
+  for (void *p : ptrs) dfree(c, p);
+}
+
+extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *stream,
+                                 fmm_ctx **out) {
+  if (!prm || !out) return FMM_EINVAL;
+  *out = nullptr;
+  if (max_n < 1 || max_n > (int64_t)1 << 30) return FMM_EINVAL;
+  if (prm->p_max < 1 || prm->p_max > 8 || prm->leaf_size < 1 || prm->leaf_size > 4096 ||
+      (prm->kernel != FMM_KERNEL_WENDLAND_C2 && prm->kernel != FMM_KERNEL_PLUMMER) ||
+      (prm->precision != FMM_PREC_FP64 && prm->precision != FMM_PREC_MIXED))
+    return FMM_EINVAL;
+  fmm_ctx *c = new (std::nothrow) fmm_ctx();
+  if (!c) return FMM_ENOMEM;
+  c->prm = *prm;
+  c->max_n = max_n;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return FMM_EDEVICE;
+  }
+  DevTree &t = c->t;
+  memset(&t, 0, sizeof(t));
+  t.kmax = coeffs(prm->p_max);
+  t.cap_n = max_n;
+  int64_t n = max_n;
+  int64_t cap_nodes = 8 * n / prm->leaf_size + 1024;
+  bool ok = dalloc(c, &t.key, n) && dalloc(c, &t.key2, n) && dalloc(c, &t.slot, n) &&
+            dalloc(c, &t.slot2, n) && dalloc(c, &t.sx, n) && dalloc(c, &t.sy, n) &&
+            dalloc(c, &t.sz, n) && dalloc(c, &t.lx, n) && dalloc(c, &t.ly, n) &&
+            dalloc(c, &t.lz, n) && dalloc(c, &t.sm, n) && dalloc(c, &t.sm32, n) &&
+            dalloc(c, &t.leaf_of, n) && dalloc(c, &t.near, 4 * n) &&
+            dalloc(c, &t.scan_part, FMM_SCAN_BLOCKS) && dalloc(c, &t.bbox_part, FMM_SCAN_BLOCKS * 6) &&
+            dalloc(c, &t.sort_hist, 256 * ((n + 4095) / 4096) + 256) && dalloc(c, &t.hdr, 1) &&
+            dalloc(c, &t.box, 1) && alloc_nodes(c, cap_nodes);
+  if (ok) {
+    t.cap_m2l = 96 * cap_nodes;
+    t.cap_p2p = 32 * cap_nodes;
+    t.cap_open = 16 * cap_nodes;
+    ok = dalloc(c, &t.m2l_src, t.cap_m2l) && dalloc(c, &t.p2p_src, t.cap_p2p) &&
+         dalloc(c, &t.open_buf0, t.cap_open) && dalloc(c, &t.open_buf1, t.cap_open);
+  }
+  // HHS scratch (levels allocated lazily)
+  ok = ok && dalloc(c, &c->all_idx, n) && dalloc(c, &c->flag, n) && dalloc(c, &c->count, 4) &&
+       dalloc(c, &c->mmask, n) && dalloc(c, &c->acc, 3 * n) && dalloc(c, &c->pot, n) &&
+       dalloc(c, &c->inv_part, 512 * 12);
+  if (!ok) {
+    fmm_destroy(c);
+    return FMM_ENOMEM;
+  }
+  if (hipMemsetAsync(t.hdr, 0, sizeof(Header), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    fmm_destroy(c);
+    return FMM_EDEVICE;
+  }
+  *out = c;
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
+  if (!c) return FMM_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->allocs) (void)hipFree(p);
+  if (c->lv_slow) {
+    free(c->lv_slow);
+    free(c->lv_slow_pos);
+    free(c->lv_fast);
+    free(c->lv_fast_pos);
+  }
+  delete c;
+  return FMM_OK;
+}
+
+extern "C" const char *fmm_last_error(const fmm_ctx *c) { return c ? c->err : "null context"; }
+
+static fmm_status check_particles(fmm_ctx *c, const double *pos, int64_t n_total,
+                                  const int32_t *active, int64_t n_active) {
+  if (!c) return FMM_EINVAL;
+  if (n_active < 0 || n_active > c->max_n)
+    return fail(c, FMM_EINVAL, "n_active=%lld outside [0, max_n=%lld]", (long long)n_active,
+                (long long)c->max_n);
+  if (n_total < 0 || (!active && n_total != n_active) || (active && n_total < 1 && n_active > 0))
+    return fail(c, FMM_EINVAL, "n_total=%lld inconsistent with n_active=%lld",
+                (long long)n_total, (long long)n_active);
+  if (n_total > (int64_t)INT32_MAX) return fail(c, FMM_EINVAL, "n_total too large");
+  if (n_active > 0 && !pos) return fail(c, FMM_EINVAL, "pos is NULL");
+  return FMM_OK;
+}
+
+static fmm_status regrow_lists(fmm_ctx *c, int which, int64_t need) {
+  DevTree &t = c->t;
+  int64_t cap = need + need / 4 + 1024;
+  if (which == OVF_M2L) {
+    dfree(c, t.m2l_src);
+    t.m2l_src = nullptr;
+    if (!dalloc(c, &t.m2l_src, cap)) return fail(c, FMM_ENOMEM, "M2L list regrow failed");
+    t.cap_m2l = cap;
+  } else if (which == OVF_P2P) {
+    dfree(c, t.p2p_src);
+    t.p2p_src = nullptr;
+    if (!dalloc(c, &t.p2p_src, cap)) return fail(c, FMM_ENOMEM, "P2P list regrow failed");
+    t.cap_p2p = cap;
+  } else {
+    dfree(c, t.open_buf0);
+    dfree(c, t.open_buf1);
+    t.open_buf0 = t.open_buf1 = nullptr;
+    if (!dalloc(c, &t.open_buf0, cap) || !dalloc(c, &t.open_buf1, cap))
+      return fail(c, FMM_ENOMEM, "open list regrow failed");
+    t.cap_open = cap;
+  }
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
+                                const int32_t *active, int64_t n_active, double eps,
+                                double theta) {
+  fmm_status st = check_particles(c, pos, n_total, active, n_active);
+  if (st != FMM_OK) return st;
+  if (!(theta > 0.0) || !(eps >= 0.0) || !std::isfinite(theta) || !std::isfinite(eps))
+    return fail(c, FMM_EINVAL, "need theta > 0 and eps >= 0");
+  c->tree_valid = false;
+  BuildArgs a;
+  a.pos = pos;
+  a.n_total = n_total;
+  a.active = active;
+  a.n = (int)n_active;
+  a.leaf_size = c->prm.leaf_size;
+  a.eps = eps;
+  a.theta = theta;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    HIPCHK(c, hipMemsetAsync(&c->t.hdr->nonfinite, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, launch_build_tree(c->t, a, c->stream));
+    HIPCHK(c, launch_traverse(c->t, a, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Header &h = c->hh;
+    if (h.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
+    if (h.overflow & OVF_STACK) return fail(c, FMM_EOVERFLOW, "traversal descent stack overflow");
+    if (h.overflow & OVF_NODES) {
+      int64_t need = std::max<int64_t>((int64_t)h.lvl_start[FMM_NLEVELS], 2 * c->t.cap_nodes);
+      free_nodes(c);
+      if (!alloc_nodes(c, need + need / 4))
+        return fail(c, FMM_ENOMEM, "node workspace regrow to %lld failed", (long long)need);
+      continue;
+    }
+    if (h.overflow & (OVF_M2L | OVF_P2P | OVF_OPEN)) {
+      if (h.overflow & OVF_M2L) {
+        st = regrow_lists(c, OVF_M2L, h.m2l_cursor);
+        if (st != FMM_OK) return st;
+      }
+      if (h.overflow & OVF_P2P) {
+        st = regrow_lists(c, OVF_P2P, h.p2p_cursor);
+        if (st != FMM_OK) return st;
+      }
+      if (h.overflow & OVF_OPEN) {
+        uint32_t mx = 0;
+        for (int l = 0; l < FMM_NLEVELS; ++l) mx = std::max(mx, h.open_cursor[l]);
+        st = regrow_lists(c, OVF_OPEN, mx);
+        if (st != FMM_OK) return st;
+      }
+      continue;
+    }
+    c->n_nodes = h.lvl_start[FMM_NLEVELS];
+    int depth = 0;
+    for (int l = 0; l < FMM_NLEVELS; ++l)
+      if (h.lvl_start[l + 1] > h.lvl_start[l]) depth = l;
+    c->depth = depth;
+    c->tree_valid = true;
+    c->b_pos = pos;
+    c->b_n_total = n_total;
+    c->b_active = active;
+    c->b_n = n_active;
+    c->b_eps = eps;
+    c->b_theta = theta;
+    c->stat_builds++;
+    return FMM_OK;
+  }
+  return fail(c, FMM_EOVERFLOW, "workspace still too small after regrowth");
+}
+
+extern "C" fmm_status fmm_evaluate(fmm_ctx *c, const double *pos, const double *mass,
+                                   int64_t n_total, const int32_t *active, int64_t n_active, int p,
+                                   double *acc, double *pot) {
+  fmm_status st = check_particles(c, pos, n_total, active, n_active);
+  if (st != FMM_OK) return st;
+  if (!c->tree_valid || pos != c->b_pos || active != c->b_active || n_active != c->b_n ||
+      n_total != c->b_n_total)
+    return fail(c, FMM_ESTALE, "no tree built for these particles");
+  if (p < 1 || p > c->prm.p_max || !eval_order_supported(p))
+    return fail(c, FMM_EINVAL, "order p=%d unsupported (1..%d)", p, std::min(c->prm.p_max, 6));
+  if (n_active > 0 && (!mass || !acc || !pot)) return fail(c, FMM_EINVAL, "NULL mass/acc/pot");
+  EvalArgs e;
+  e.mass = mass;
+  e.active = active;
+  e.n = (int)n_active;
+  e.n_nodes = c->n_nodes;
+  e.p = p;
+  e.kernel = c->prm.kernel;
+  e.mixed = c->prm.precision == FMM_PREC_MIXED;
+  e.eps = c->b_eps;
+  e.acc = acc;
+  e.pot = pot;
+  e.lvl_start_host = c->hh.lvl_start;
+  e.depth = c->depth;
+  HIPCHK(c, launch_evaluate(c->t, e, c->stream));
+  c->stat_calls++;
+  c->stat_parts += n_active;
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_forces(fmm_ctx *c, const double *pos, const double *mass,
+                                 int64_t n_total, const int32_t *active, int64_t n_active,
+                                 double eps, double theta, int p, double *acc, double *pot) {
+  if (c && (p < 1 || p > c->prm.p_max || !eval_order_supported(p)))
+    return fail(c, FMM_EINVAL, "order p=%d unsupported", p);
+  fmm_status st = fmm_build(c, pos, n_total, active, n_active, eps, theta);
+  if (st != FMM_OK) return st;
+  return fmm_evaluate(c, pos, mass, n_total, active, n_active, p, acc, pot);
+}
+
+extern "C" fmm_status fmm_tree_info(fmm_ctx *c, int64_t info[9]) {
+  if (!c || !info) return FMM_EINVAL;
+  if (!c->tree_valid) return fail(c, FMM_ESTALE, "no tree");
+  const Header &h = c->hh;
+  int64_t leaves = h.n_leaves;
+  info[0] = c->b_n;
+  info[1] = c->n_nodes;
+  info[2] = h.m2l_cursor / 2;
+  info[3] = ((int64_t)h.p2p_cursor - leaves) / 2 + leaves;
+  info[4] = c->depth;
+  info[5] = leaves;
+  info[6] = h.m2l_cursor;
+  info[7] = h.p2p_cursor;
+  info[8] = (int64_t)h.p2p_pairs;
+  return FMM_OK;
+}
+
+template <typename T>
+static hipError_t d2h(std::vector<T> &v, const T *d, int64_t n, hipStream_t s) {
+  v.resize((size_t)std::max<int64_t>(n, 0));
+  if (n <= 0) return hipSuccess;
+  return hipMemcpyAsync(v.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, s);
+}
+
+extern "C" fmm_status fmm_export_tree(fmm_ctx *c, int64_t *perm, int32_t *level, uint64_t *prefix,
+                                      int64_t *begin, int64_t *end, int32_t *is_leaf,
+                                      double *centre, double *half, int64_t *m2l_pairs,
+                                      int64_t *p2p_pairs, double *box) {
+  if (!c) return FMM_EINVAL;
+  if (!c->tree_valid) return fail(c, FMM_ESTALE, "no tree");
+  const int64_t n = c->b_n, nn = c->n_nodes;
+  const DevTree &t = c->t;
+  std::vector<int32_t> nbeg, nend, nlev, nnch, slot, moff, mcnt, msrc, poff, pcnt, psrc;
+  std::vector<uint64_t> key;
+  std::vector<double4> geo;
+  Box hb;
+  hipStream_t s = c->stream;
+  HIPCHK(c, d2h(nbeg, t.nbeg, nn, s));
+  HIPCHK(c, d2h(nend, t.nend, nn, s));
+  HIPCHK(c, d2h(nlev, t.nlev, nn, s));
+  HIPCHK(c, d2h(nnch, t.nnchild, nn, s));
+  HIPCHK(c, d2h(geo, t.ngeo, nn, s));
+  HIPCHK(c, d2h(slot, t.slot, n, s));
+  HIPCHK(c, d2h(key, t.key, n, s));
+  HIPCHK(c, d2h(moff, t.m2l_off, nn, s));
+  HIPCHK(c, d2h(mcnt, t.m2l_cnt, nn, s));
+  HIPCHK(c, d2h(poff, t.p2p_off, nn, s));
+  HIPCHK(c, d2h(pcnt, t.p2p_cnt, nn, s));
+  HIPCHK(c, d2h(msrc, t.m2l_src, (int64_t)c->hh.m2l_cursor, s));
+  HIPCHK(c, d2h(psrc, t.p2p_src, (int64_t)c->hh.p2p_cursor, s));
+  HIPCHK(c, hipMemcpyAsync(&hb, t.box, sizeof(Box), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  // canonical pre-order id: nodes sorted by (begin, level)
+  std::vector<int64_t> order(nn), canon(nn);
+  for (int64_t i = 0; i < nn; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    if (nbeg[a] != nbeg[b]) return nbeg[a] < nbeg[b];
+    return nlev[a] < nlev[b];
+  });
+  for (int64_t r = 0; r < nn; ++r) canon[order[r]] = r;
+  if (perm)
+    for (int64_t i = 0; i < n; ++i) perm[i] = slot[i];
+  for (int64_t r = 0; r < nn; ++r) {
+    int64_t i = order[r];
+    if (level) level[r] = nlev[i];
+    if (prefix) prefix[r] = key[nbeg[i]] >> (3 * (FMM_MAXLEVEL - nlev[i]));
+    if (begin) begin[r] = nbeg[i];
+    if (end) end[r] = nend[i];
+    if (is_leaf) is_leaf[r] = nnch[i] == 0;
+    if (centre) {
+      centre[3 * r] = geo[i].x;
+      centre[3 * r + 1] = geo[i].y;
+      centre[3 * r + 2] = geo[i].z;
+    }
+    if (half) half[r] = geo[i].w;
+  }
+  auto pairs = [&](const std::vector<int32_t> &off, const std::vector<int32_t> &cnt,
+                   const std::vector<int32_t> &src, int64_t *out) {
+    std::vector<std::pair<int64_t, int64_t>> v;
+    for (int64_t a = 0; a < nn; ++a)
+      for (int q = 0; q < cnt[a]; ++q) {
+        int64_t b = src[off[a] + q];
+        int64_t ca = canon[a], cb = canon[b];
+        if (ca <= cb) v.emplace_back(ca, cb);
+      }
+    std::sort(v.begin(), v.end());
+    for (size_t k = 0; k < v.size(); ++k) {
+      out[2 * k] = v[k].first;
+      out[2 * k + 1] = v[k].second;
+    }
+  };
+  if (m2l_pairs) pairs(moff, mcnt, msrc, m2l_pairs);
+  if (p2p_pairs) pairs(poff, pcnt, psrc, p2p_pairs);
+  if (box) {
+    box[0] = hb.o[0];
+    box[1] = hb.o[1];
+    box[2] = hb.o[2];
+    box[3] = hb.L;
+    box[4] = hb.s;
+  }
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_invariants(fmm_ctx *c, const double *pos, const double *vel,
+                                     const double *mass, const double *acc, const double *pot,
+                                     int64_t n, double out[12]) {
+  if (!c || !out || n < 0) return FMM_EINVAL;
+  const int nblk = 512;
+  launch_invariants(pos, vel, mass, acc, pot, n, c->inv_part, nblk, c->stream);
+  std::vector<double> part(nblk * 12);
+  HIPCHK(c, hipMemcpyAsync(part.data(), c->inv_part, sizeof(double) * nblk * 12,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 12; ++k) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[b * 12 + k];
+    out[k] = s;
+  }
+  return FMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// HHS integrator: Algorithms 1-3
+// ---------------------------------------------------------------------------
+static fmm_status hhs_alloc(fmm_ctx *c, int levels) {
+  if (c->hhs_levels >= levels) return FMM_OK;
+  int64_t n = c->max_n;
+  int32_t **a = (int32_t **)calloc(levels, sizeof(int32_t *));
+  int32_t **b = (int32_t **)calloc(levels, sizeof(int32_t *));
+  int32_t **d = (int32_t **)calloc(levels, sizeof(int32_t *));
+  int32_t **e = (int32_t **)calloc(levels, sizeof(int32_t *));
+  for (int l = 0; l < c->hhs_levels; ++l) {
+    a[l] = c->lv_slow[l];
+    b[l] = c->lv_slow_pos[l];
+    d[l] = c->lv_fast[l];
+    e[l] = c->lv_fast_pos[l];
+  }
+  for (int l = c->hhs_levels; l < levels; ++l)
+    if (!dalloc(c, &a[l], n) || !dalloc(c, &b[l], n) || !dalloc(c, &d[l], n) ||
+        !dalloc(c, &e[l], n))
+      return fail(c, FMM_ENOMEM, "HHS level buffers");
+  free(c->lv_slow);
+  free(c->lv_slow_pos);
+  free(c->lv_fast);
+  free(c->lv_fast_pos);
+  c->lv_slow = a;
+  c->lv_slow_pos = b;
+  c->lv_fast = d;
+  c->lv_fast_pos = e;
+  c->hhs_levels = levels;
+  return FMM_OK;
+}
+
+struct HHSRun {
+  fmm_ctx *c;
+  hhs_state *st;
+  const hhs_params *hp;
+  double dt_top;
+};
+
+// one kick of Algorithm 3 on `set` (positions setpos inside the joint list)
+static fmm_status hhs_force(HHSRun &r, const int32_t *joint, int n_joint, const double *mass) {
+  fmm_ctx *c = r.c;
+  return fmm_evaluate(c, r.st->pos, mass, r.st->n, joint, n_joint, r.hp->p, c->acc, c->pot);
+}
+
+static fmm_status hhs_kdk(HHSRun &r, int k, const int32_t *sys, int n_sys, const int32_t *slow,
+                          const int32_t *slow_pos, int n_slow, const int32_t *fast,
+                          const int32_t *fast_pos, int n_fast, double dt) {
+  fmm_ctx *c = r.c;
+  hhs_state *st = r.st;
+  const hhs_params *hp = r.hp;
+  const bool s2f = n_fast > 0 && n_slow > 0;
+  fmm_status e;
+  for (int half = 0; half < 2; ++half) {
+    const bool second = half == 1;
+    if (half == 1) hhs_launch_drift(slow, n_slow, st->vel, st->pos, st->n, dt, c->stream);
+    if (!(s2f || n_slow > 0)) continue;
+    e = fmm_build(c, st->pos, st->n, sys, n_sys, hp->eps, hp->theta);
+    if (e != FMM_OK) return e;
+    // kickS2F before kickFS2S on the first half, after it on the second
+    for (int kk = 0; kk < 2; ++kk) {
+      const bool do_s2f = (kk == 0) != second;
+      if (do_s2f) {
+        if (!s2f) continue;
+        hhs_launch_masked_mass(st->mass, st->n, fast, n_fast, c->mmask, c->stream);
+        e = hhs_force(r, sys, n_sys, c->mmask);
+        if (e != FMM_OK) return e;
+        hhs_launch_kick(fast, fast_pos, n_fast, c->acc, n_sys, st->vel, st->n, 0.5 * dt,
+                        second ? st->a_old : nullptr, c->stream);
+      } else {
+        if (n_slow == 0) continue;
+        e = hhs_force(r, sys, n_sys, st->mass);
+        if (e != FMM_OK) return e;
+        hhs_launch_kick(slow, slow_pos, n_slow, c->acc, n_sys, st->vel, st->n, 0.5 * dt,
+                        second ? st->a_cur : nullptr, c->stream);
+      }
+    }
+  }
+  (void)k;
+  return FMM_OK;
+}
+
+static fmm_status hhs_evolve(HHSRun &r, int k, const int32_t *sys, int n_sys, double dt,
+                             bool calc) {
+  fmm_ctx *c = r.c;
+  hhs_state *st = r.st;
+  const hhs_params *hp = r.hp;
+  if (k >= c->hhs_levels) return fail(c, FMM_EINVAL, "rung recursion deeper than max_levels");
+  if (calc && !hp->freeze_rungs)
+    hhs_launch_rungs(sys, n_sys, st->a_old, st->a_cur, st->rung, r.dt_top, hp->eta * hp->eps,
+                     hp->max_levels, c->stream);
+  int32_t *slow = c->lv_slow[k], *slow_pos = c->lv_slow_pos[k];
+  int32_t *fast = c->lv_fast[k], *fast_pos = c->lv_fast_pos[k];
+  hhs_launch_split(sys, n_sys, st->rung, k, c->flag, slow, slow_pos, fast, fast_pos, c->count,
+                   c->stream);
+  int32_t n_fast = 0;
+  HIPCHK(c, hipMemcpyAsync(&n_fast, c->count, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int n_slow = n_sys - n_fast;
+  fmm_status e;
+  if (n_fast > 0) {
+    e = hhs_evolve(r, k + 1, fast, n_fast, 0.5 * dt, false);
+    if (e != FMM_OK) return e;
+  }
+  e = hhs_kdk(r, k, sys, n_sys, slow, slow_pos, n_slow, fast, fast_pos, n_fast, dt);
+  if (e != FMM_OK) return e;
+  if (n_fast > 0) {
+    e = hhs_evolve(r, k + 1, fast, n_fast, 0.5 * dt, true);
+    if (e != FMM_OK) return e;
+  }
+  return FMM_OK;
+}
+
+static fmm_status hhs_check(fmm_ctx *c, hhs_state *st, const hhs_params *hp) {
+  if (!c || !st || !hp) return FMM_EINVAL;
+  if (st->n < 1 || st->n > c->max_n) return fail(c, FMM_EINVAL, "state size outside [1, max_n]");
+  if (!st->pos || !st->vel || !st->mass || !st->a_old || !st->a_cur || !st->rung)
+    return fail(c, FMM_EINVAL, "NULL state array");
+  if (hp->max_levels < 1 || hp->max_levels > 30 || !(hp->eta > 0) || hp->p < 1 ||
+      hp->p > c->prm.p_max)
+    return fail(c, FMM_EINVAL, "bad HHS parameters");
+  return hhs_alloc(c, hp->max_levels + 1);
+}
+
+extern "C" fmm_status hhs_init(fmm_ctx *c, hhs_state *st, const hhs_params *hp) {
+  fmm_status e = hhs_check(c, st, hp);
+  if (e != FMM_OK) return e;
+  e = fmm_forces(c, st->pos, st->mass, st->n, nullptr, st->n, hp->eps, hp->theta, hp->p, c->acc,
+                 c->pot);
+  if (e != FMM_OK) return e;
+  hhs_launch_amag(c->acc, st->n, st->a_cur, st->a_old, c->stream);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FMM_OK;
+}
+
+extern "C" fmm_status hhs_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp, double dt_top,
+                               int64_t stats[3]) {
+  fmm_status e = hhs_check(c, st, hp);
+  if (e != FMM_OK) return e;
+  if (!std::isfinite(dt_top) || dt_top == 0.0) return fail(c, FMM_EINVAL, "dt_top");
+  int64_t c0 = c->stat_calls, p0 = c->stat_parts, b0 = c->stat_builds;
+  hhs_launch_iota(c->all_idx, (int)st->n, c->stream);
+  HHSRun r{c, st, hp, dt_top};
+  e = hhs_evolve(r, 0, c->all_idx, (int)st->n, dt_top, true);
+  if (e != FMM_OK) return e;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  st->t += dt_top;
+  if (stats) {
+    stats[0] = c->stat_calls - c0;
+    stats[1] = c->stat_parts - p0;
+    stats[2] = c->stat_builds - b0;
+  }
+  c->tree_valid = false;
+  return FMM_OK;
+}

@@ -1,0 +1,149 @@
+// Internal declarations shared by the HIP translation units of libfmm355.
+//
+// Data layout in HBM (one context, capacities fixed at creation):
+//   particles (Morton-sorted order, SoA):  keys u64, slot i32 (active slot of
+//     the particle), positions f64 x3, cell-local offsets f32 x3, masses f64 and
+//     f32, leaf id i32, near-field (P2P) results f64 x4;
+//   nodes (level-major: all level-0 nodes, then level 1, ...; inside a level in
+//     Morton order): begin/end/level/parent/first-child/child-count i32,
+//     geometry double4 (centre xyz, half side), multipole and local
+//     coefficient rows of K = C(p+3,3) reals (node-major);
+//   interaction lists: per target node (offset, count) into flat i32 arrays of
+//     source node ids (directed entries; the unordered pair {A,B} appears once
+//     in A's list and once in B's list).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FMM_MAXLEVEL 21
+#define FMM_NLEVELS (FMM_MAXLEVEL + 1)
+#define FMM_BLOCK 256
+#define FMM_SCAN_BLOCKS 256
+
+// error bits latched in Header::overflow
+#define OVF_NODES 1
+#define OVF_M2L 2
+#define OVF_P2P 4
+#define OVF_OPEN 8
+#define OVF_STACK 16
+
+struct Header {
+  int32_t lvl_start[FMM_NLEVELS + 2];  // nodes of level l: [lvl_start[l], lvl_start[l+1])
+  uint32_t m2l_cursor;                 // ordered M2L entries written (or needed)
+  uint32_t p2p_cursor;                 // ordered P2P entries written (or needed)
+  uint32_t open_cursor[FMM_NLEVELS];   // open-list entries per level
+  int32_t overflow;                    // OVF_* bits
+  int32_t nonfinite;                   // an input position was not finite
+  unsigned long long p2p_pairs;        // ordered particle interactions in P2P
+  int32_t n_leaves;
+  int32_t pad;
+};
+
+// Box: o[3] (origin), L (side), s = 2^21/L, lo[3], hi[3]
+struct Box {
+  double o[3];
+  double L;
+  double s;
+  double lo[3];
+  double hi[3];
+};
+
+struct DevTree {
+  // particles, sorted order
+  uint64_t *key, *key2;
+  int32_t *slot, *slot2;
+  double *sx, *sy, *sz;
+  float *lx, *ly, *lz;
+  double *sm;
+  float *sm32;
+  int32_t *leaf_of;
+  double *near;  // [4][cap_n]: ax, ay, az, pot
+  // nodes
+  int32_t *nbeg, *nend, *nlev, *nparent, *nchild0, *nnchild;
+  double4 *ngeo;
+  int32_t *bounds;  // [cap_nodes][8]
+  void *M, *L;      // [cap_nodes][Kmax] of float or double
+  // lists
+  int32_t *m2l_off, *m2l_cnt, *m2l_src;
+  int32_t *p2p_off, *p2p_cnt, *p2p_src;
+  int32_t *open_off, *open_cnt;
+  int32_t *open_buf0, *open_buf1;
+  // scratch
+  int32_t *scan_part;          // [FMM_SCAN_BLOCKS]
+  double *bbox_part;           // [FMM_SCAN_BLOCKS][6]
+  uint32_t *sort_hist;         // [256][sort blocks]
+  Header *hdr;
+  Box *box;
+  int64_t cap_n, cap_nodes, cap_m2l, cap_p2p, cap_open;
+  int kmax;
+};
+
+// ---------------------------------------------------------------------------
+// wavefront helpers (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ unsigned long long lanes_below_mask() {
+  int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ int wave_excl_scan_int(int v, int *total) {
+  // inclusive Hillis-Steele over 64 lanes
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off, 64);
+    if (__lane_id() >= off) x += y;
+  }
+  *total = __shfl(x, 63, 64);
+  return x - v;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers (one translation unit each)
+// ---------------------------------------------------------------------------
+struct BuildArgs {
+  const double *pos;
+  int64_t n_total;
+  const int32_t *active;
+  int n;
+  int leaf_size;
+  double eps;
+  double theta;
+};
+
+// tree.hip
+hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s);
+// traverse.hip
+hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s);
+hipError_t launch_reset_lists(const DevTree &t, hipStream_t s);
+// eval.hip
+struct EvalArgs {
+  const double *mass;
+  const int32_t *active;
+  int n;
+  int n_nodes;
+  int p;
+  int kernel;     // 0 Wendland, 1 Plummer
+  int mixed;      // 0 FP64, 1 mixed
+  double eps;
+  double *acc;
+  double *pot;
+  const int32_t *lvl_start_host;  // host copy, FMM_NLEVELS+1 entries
+  int depth;
+};
+hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s);
+bool eval_order_supported(int p);
+// hhs.hip
+hipError_t launch_gather_mask_mass(const double *mass, const int32_t *sys, int n_sys,
+                                   const int32_t *flag_fast, int mask_fast, double *out,
+                                   hipStream_t s);

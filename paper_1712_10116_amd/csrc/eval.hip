@@ -1,0 +1,362 @@
+// Mass-dependent passes of the FMM on gfx950: P2M, M2M (upward), M2L over
+// each cell's symmetric interaction list, L2L (downward), P2P over each
+// leaf's symmetric near list, L2P.  Templated on the working precision T of
+// the expansions (double, or float for the mixed form) and the order P.
+//
+// Both sides of an unordered cell pair (A, B) evaluate it from their own
+// list: D^k psi is odd/even under R -> -R exactly in IEEE arithmetic, and the
+// particle pair kernel uses x_j - x_i = -(x_i - x_j) exactly, so the force of
+// every pair on A is the negative of its force on B (Eq. (2) of the paper)
+// while no two wavefronts ever write the same cell or particle.
+//
+// Mixed form: cell-local FP32 offsets (x - z_leaf) and the FP64 difference of
+// the two leaf centres rounded once to FP32 give every particle separation;
+// each source leaf's FP32 partial sums are added into FP64 accumulators;
+// expansions are FP32 on size-scaled coefficients.
+#include "common.h"
+#include "expansion.h"
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FMM_BLOCK) void k_gather_mass(DevTree t, const double *__restrict__ mass,
+                                                           const int32_t *__restrict__ active,
+                                                           int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int s = t.slot[j];
+  int64_t g = active ? active[s] : s;
+  double m = mass[g];
+  t.sm[j] = m;
+  t.sm32[j] = (float)m;
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void load_row(const T *__restrict__ base, int kmax, int node,
+                                         T (&v)[MI<P>::K]) {
+  const T *row = base + (size_t)node * kmax;
+#pragma unroll
+  for (int t = 0; t < MI<P>::K; ++t) v[t] = row[t];
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void store_row(T *__restrict__ base, int kmax, int node,
+                                          const T (&v)[MI<P>::K]) {
+  T *row = base + (size_t)node * kmax;
+#pragma unroll
+  for (int t = 0; t < MI<P>::K; ++t) row[t] = v[t];
+}
+
+// P2M at leaves: Mt[k] = sum_j m_j (u_j/h)^k/k!  (compensated in FP32)
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes) {
+  constexpr int K = MI<P>::K;
+  T *M = (T *)t.M;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes; i += gridDim.x * blockDim.x) {
+    if (t.nnchild[i] != 0) continue;
+    const double4 g = t.ngeo[i];
+    const double ih = 1.0 / g.w;
+    T acc[K], cmp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = cmp[k] = T(0);
+    for (int j = t.nbeg[i]; j < t.nend[i]; ++j) {
+      T mono[K];
+      monomials<T, P>((T)((t.sx[j] - g.x) * ih), (T)((t.sy[j] - g.y) * ih),
+                      (T)((t.sz[j] - g.z) * ih), mono);
+      const T m = (T)t.sm[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (sizeof(T) == 4) {  // Kahan-Babuska summation of the FP32 moments
+          T y = m * mono[k] - cmp[k];
+          T s = acc[k] + y;
+          cmp[k] = (s - acc[k]) - y;
+          acc[k] = s;
+        } else {
+          acc[k] = fma(m, mono[k], acc[k]);
+        }
+      }
+    }
+    store_row<T, P>(M, t.kmax, i, acc);
+  }
+}
+
+// M2M for the cells of one level that have children
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e) {
+  constexpr int K = MI<P>::K;
+  T *M = (T *)t.M;
+  for (int i = s + blockIdx.x * blockDim.x + threadIdx.x; i < e; i += gridDim.x * blockDim.x) {
+    int nc = t.nnchild[i];
+    if (nc == 0) continue;
+    const double4 gp = t.ngeo[i];
+    const double ih = 1.0 / gp.w;
+    T acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = T(0);
+    int c0 = t.nchild0[i];
+    for (int c = c0; c < c0 + nc; ++c) {
+      const double4 gc = t.ngeo[c];
+      T q[K], Mc[K];
+      monomials<T, P>((T)((gc.x - gp.x) * ih), (T)((gc.y - gp.y) * ih), (T)((gc.z - gp.z) * ih),
+                      q);
+      load_row<T, P>(M, t.kmax, c, Mc);
+      m2m_shift<T, P>(Mc, (T)(gc.w * ih), q, acc);
+    }
+    store_row<T, P>(M, t.kmax, i, acc);
+  }
+}
+
+// M2L: one wavefront per target cell A, lanes over A's list of sources B.
+// With rho = h_A:  Lt_A[n] = (1/h_A) sum_m (-1)^|m| beta^|m| Mt_B[m]
+//                             D^{n+m} psi_{eps/h_A}((zA - zB)/h_A),  beta = h_B/h_A.
+template <typename T, int P, int KERNEL>
+__global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, double eps) {
+  constexpr int K = MI<P>::K;
+  constexpr MI<P> mi{};
+  const T *M = (const T *)t.M;
+  T *L = (T *)t.L;
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (int A = wave; A < n_nodes; A += nwaves) {
+    const double4 gA = t.ngeo[A];
+    const double ih = 1.0 / gA.w;
+    const T e2 = KERNEL == 1 ? (T)((eps * ih) * (eps * ih)) : T(0);
+    const int off = t.m2l_off[A], cnt = t.m2l_cnt[A];
+    T acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = T(0);
+    for (int q = lane; q < cnt; q += 64) {
+      const int B = t.m2l_src[off + q];
+      const double4 gB = t.ngeo[B];
+      T D[K], Ms[K];
+      derivatives<T, P>((T)((gA.x - gB.x) * ih), (T)((gA.y - gB.y) * ih), (T)((gA.z - gB.z) * ih),
+                        e2, D);
+      load_row<T, P>(M, t.kmax, B, Ms);
+      const T beta = (T)(gB.w * ih);
+      T bp = T(1);
+#pragma unroll
+      for (int d = 0; d <= P; ++d) {
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+          if (mi.deg[m] == d) Ms[m] *= (d & 1) ? -bp : bp;
+        bp *= beta;
+      }
+      m2l_contract<T, P>(Ms, D, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]) * (T)ih;
+    if (lane == 0) store_row<T, P>(L, t.kmax, A, acc);
+  }
+}
+
+// L2L for the cells of one level: Lt_c += shift of the parent's Lt
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_l2l(DevTree t, int s, int e) {
+  constexpr int K = MI<P>::K;
+  T *L = (T *)t.L;
+  for (int c = s + blockIdx.x * blockDim.x + threadIdx.x; c < e; c += gridDim.x * blockDim.x) {
+    const int p = t.nparent[c];
+    const double4 gp = t.ngeo[p], gc = t.ngeo[c];
+    const double ih = 1.0 / gp.w;
+    T q[K], Lp[K], Lc[K];
+    monomials<T, P>((T)((gc.x - gp.x) * ih), (T)((gc.y - gp.y) * ih), (T)((gc.z - gp.z) * ih), q);
+    load_row<T, P>(L, t.kmax, p, Lp);
+    load_row<T, P>(L, t.kmax, c, Lc);
+    l2l_shift<T, P>(Lp, (T)(gc.w * ih), q, Lc);
+    store_row<T, P>(L, t.kmax, c, Lc);
+  }
+}
+
+// L2P + near field + un-permute: one thread per Morton-sorted particle
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, double *__restrict__ acc,
+                                                   double *__restrict__ pot) {
+  constexpr int K = MI<P>::K;
+  const T *L = (const T *)t.L;
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int leaf = t.leaf_of[j];
+  const double4 g = t.ngeo[leaf];
+  const double ih = 1.0 / g.w;
+  T mono[K], Lt[K];
+  monomials<T, P>((T)((t.sx[j] - g.x) * ih), (T)((t.sy[j] - g.y) * ih), (T)((t.sz[j] - g.z) * ih),
+                  mono);
+  load_row<T, P>(L, t.kmax, leaf, Lt);
+  T phi, gx, gy, gz;
+  l2p_eval<T, P>(Lt, mono, phi, gx, gy, gz);
+  const int s = t.slot[j];
+  const int64_t cap = t.cap_n;
+  acc[s] = t.near[j] - (double)gx * ih;
+  acc[(int64_t)n + s] = t.near[cap + j] - (double)gy * ih;
+  acc[2 * (int64_t)n + s] = t.near[2 * cap + j] - (double)gz * ih;
+  pot[s] = t.near[3 * cap + j] + (double)phi;
+}
+
+// ---------------------------------------------------------------------------
+// P2P: one wavefront per target leaf.  Lanes = (target particle, phase); a
+// lane takes every nph-th particle of each source leaf.
+// ---------------------------------------------------------------------------
+template <typename R, int KERNEL>
+struct PairKernel {
+  // acceleration factor g = psi'(r)/r and potential psi for squared distance r2
+  __device__ __forceinline__ static void eval(R r2, R eps2, R inv_eps, R inv_eps3, R &g, R &phi) {
+    if (KERNEL == 1) {
+      R rinv = fast_rsqrt<R>(r2 + eps2);
+      g = rinv * rinv * rinv;
+      phi = -rinv;
+    } else {
+      R rinv = fast_rsqrt<R>(r2);
+      g = rinv * rinv * rinv;
+      phi = -rinv;
+      if (r2 < eps2) {
+        R r = r2 > R(0) ? r2 * rinv : R(0);
+        R u = r * inv_eps;
+        R u2 = u * u;
+        g = fma(fma(fma(fma(R(21), u, R(-90)), u, R(140)), u, R(-84)), u2, R(14)) * inv_eps3;
+        phi = fma(u2, fma(fma(fma(fma(R(3), u, R(-15)), u, R(28)), u, R(-21)), u2, R(7)), R(-3)) *
+              inv_eps;
+      }
+    }
+  }
+};
+
+template <bool MIXED, int KERNEL>
+__global__ __launch_bounds__(FMM_BLOCK) void k_p2p(DevTree t, int n_nodes, double eps) {
+  typedef typename std::conditional<MIXED, float, double>::type R;
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const R eps2 = (R)(eps * eps);
+  const R inv_eps = eps > 0 ? (R)(1.0 / eps) : R(0);
+  const R inv_eps3 = eps > 0 ? (R)(1.0 / (eps * eps * eps)) : R(0);
+  const int64_t cap = t.cap_n;
+  for (int A = wave; A < n_nodes; A += nwaves) {
+    if (t.nnchild[A] != 0) continue;
+    const int bA = t.nbeg[A], nA = t.nend[A] - bA;
+    const int LP = nA <= 16 ? 16 : (nA <= 32 ? 32 : 64);
+    const int nph = 64 / LP;
+    const int ph = lane / LP, ti = lane % LP;
+    const double4 gA = t.ngeo[A];
+    const int off = t.p2p_off[A], cnt = t.p2p_cnt[A];
+    for (int tb = 0; tb < nA; tb += LP) {
+      const int i = tb + ti;
+      const bool vi = i < nA;
+      const int gi = bA + (vi ? i : 0);
+      R xi, yi, zi;
+      if (MIXED) {
+        xi = t.lx[gi]; yi = t.ly[gi]; zi = t.lz[gi];
+      } else {
+        xi = t.sx[gi]; yi = t.sy[gi]; zi = t.sz[gi];
+      }
+      double ax = 0, ay = 0, az = 0, pp = 0;
+      for (int q = 0; q < cnt; ++q) {
+        const int B = t.p2p_src[off + q];
+        const int bB = t.nbeg[B], nB = t.nend[B] - bB;
+        R ox = 0, oy = 0, oz = 0;
+        if (MIXED) {
+          const double4 gB = t.ngeo[B];
+          ox = (R)(gB.x - gA.x);
+          oy = (R)(gB.y - gA.y);
+          oz = (R)(gB.z - gA.z);
+        }
+        R sx = 0, sy = 0, sz = 0, sp = 0;
+        for (int jj = ph; jj < nB; jj += nph) {
+          const int gj = bB + jj;
+          R dx, dy, dz, mj;
+          if (MIXED) {
+            dx = (t.lx[gj] - xi) + ox;
+            dy = (t.ly[gj] - yi) + oy;
+            dz = (t.lz[gj] - zi) + oz;
+            mj = t.sm32[gj];
+          } else {
+            dx = t.sx[gj] - xi;
+            dy = t.sy[gj] - yi;
+            dz = t.sz[gj] - zi;
+            mj = t.sm[gj];
+          }
+          const bool self = gj == gi;
+          R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          r2 = self ? R(1) : r2;
+          mj = self ? R(0) : mj;
+          R g, phi;
+          PairKernel<R, KERNEL>::eval(r2, eps2, inv_eps, inv_eps3, g, phi);
+          const R mg = mj * g;
+          sx = fma(mg, dx, sx);
+          sy = fma(mg, dy, sy);
+          sz = fma(mg, dz, sz);
+          sp = fma(mj, phi, sp);
+        }
+        ax += (double)sx;
+        ay += (double)sy;
+        az += (double)sz;
+        pp += (double)sp;
+      }
+      for (int o = LP; o < 64; o <<= 1) {
+        ax += __shfl_xor(ax, o, 64);
+        ay += __shfl_xor(ay, o, 64);
+        az += __shfl_xor(az, o, 64);
+        pp += __shfl_xor(pp, o, 64);
+      }
+      if (vi && ph == 0) {
+        t.near[gi] = ax;
+        t.near[cap + gi] = ay;
+        t.near[2 * cap + gi] = az;
+        t.near[3 * cap + gi] = pp;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int P, int KERNEL>
+static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
+  const int nn = e.n_nodes;
+  const int nb_nodes = (nn + FMM_BLOCK - 1) / FMM_BLOCK;
+  hipLaunchKernelGGL((k_p2m<T, P>), dim3(nb_nodes), dim3(FMM_BLOCK), 0, s, t, nn);
+  for (int l = e.depth - 1; l >= 0; --l) {
+    int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
+    if (le > ls)
+      hipLaunchKernelGGL((k_m2m<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
+                         dim3(FMM_BLOCK), 0, s, t, ls, le);
+  }
+  const int wave_blocks = (nn + 3) / 4;
+  hipLaunchKernelGGL((k_m2l<T, P, KERNEL>), dim3(wave_blocks), dim3(FMM_BLOCK), 0, s, t, nn,
+                     e.eps);
+  for (int l = 1; l <= e.depth; ++l) {
+    int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
+    if (le > ls)
+      hipLaunchKernelGGL((k_l2l<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
+                         dim3(FMM_BLOCK), 0, s, t, ls, le);
+  }
+  hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL>), dim3(wave_blocks), dim3(FMM_BLOCK), 0, s,
+                     t, nn, e.eps);
+  hipLaunchKernelGGL((k_l2p<T, P>), dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
+                     s, t, e.n, e.acc, e.pot);
+}
+
+template <typename T, int KERNEL>
+static bool dispatch_order(const DevTree &t, const EvalArgs &e, hipStream_t s) {
+  switch (e.p) {
+    case 1: run_passes<T, 1, KERNEL>(t, e, s); return true;
+    case 2: run_passes<T, 2, KERNEL>(t, e, s); return true;
+    case 3: run_passes<T, 3, KERNEL>(t, e, s); return true;
+    case 4: run_passes<T, 4, KERNEL>(t, e, s); return true;
+    case 5: run_passes<T, 5, KERNEL>(t, e, s); return true;
+    case 6: run_passes<T, 6, KERNEL>(t, e, s); return true;
+    default: return false;
+  }
+}
+
+bool eval_order_supported(int p) { return p >= 1 && p <= 6; }
+
+hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s) {
+  if (e.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_mass, dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0, s,
+                     t, e.mass, e.active, e.n);
+  bool ok;
+  if (e.mixed)
+    ok = e.kernel == 1 ? dispatch_order<float, 1>(t, e, s) : dispatch_order<float, 0>(t, e, s);
+  else
+    ok = e.kernel == 1 ? dispatch_order<double, 1>(t, e, s) : dispatch_order<double, 0>(t, e, s);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}

@@ -1,0 +1,214 @@
+// Device kernels of the HHS integrator (Sec. 2.2, Algorithms 1-3) and the
+// FP64 conservation reductions.  The host walks the EVOLVE_HOLD recursion;
+// every per-particle step (rung assignment, slow/fast split, mass masking of
+// the fast system for kickS2F, kicks, drifts) runs here in FP64.
+#include "common.h"
+#include "hhs_kernels.h"
+
+// rung = smallest k with dt_top 2^-k <= sqrt(eta eps / a), a = |a_old| + |a_cur|,
+// decided as (dt_k dt_k) a <= eta eps (no square root), clamped to L-1
+__global__ __launch_bounds__(FMM_BLOCK) void k_rungs(const int32_t *__restrict__ sys, int n_sys,
+                                                     const double *__restrict__ a_old,
+                                                     const double *__restrict__ a_cur,
+                                                     int32_t *__restrict__ rung, double dt_top,
+                                                     double eta_eps, int max_levels) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_sys) return;
+  int p = sys[i];
+  double a = a_old[p] + a_cur[p];
+  int r = max_levels - 1;
+  for (int k = max_levels - 1; k >= 0; --k) {
+    double dtk = ldexp(dt_top, -k);
+    if ((dtk * dtk) * a <= eta_eps) r = k;
+  }
+  rung[p] = r;
+}
+
+// flag[i] = 1 if sys[i] is fast at rung k (rung > k)
+__global__ __launch_bounds__(FMM_BLOCK) void k_fast_flags(const int32_t *__restrict__ sys, int n_sys,
+                                                          const int32_t *__restrict__ rung, int k,
+                                                          uint32_t *__restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_sys) return;
+  flag[i] = rung[sys[i]] > k ? 1u : 0u;
+}
+
+// stable partition of sys into slow and fast lists (+ positions within sys);
+// pre = exclusive scan of the fast flags; count[0] = number of fast
+__global__ __launch_bounds__(FMM_BLOCK) void k_split_scatter(
+    const int32_t *__restrict__ sys, int n_sys, const int32_t *__restrict__ rung, int k,
+    const uint32_t *__restrict__ pre, int32_t *__restrict__ slow, int32_t *__restrict__ slow_pos,
+    int32_t *__restrict__ fast, int32_t *__restrict__ fast_pos, int32_t *__restrict__ count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_sys) return;
+  int p = sys[i];
+  int f = (int)pre[i];
+  if (rung[p] > k) {
+    fast[f] = p;
+    fast_pos[f] = i;
+  } else {
+    slow[i - f] = p;
+    slow_pos[i - f] = i;
+  }
+  if (i == n_sys - 1) count[0] = f + (rung[p] > k ? 1 : 0);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_copy_f64(const double *__restrict__ a,
+                                                        double *__restrict__ b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_zero_at(const int32_t *__restrict__ idx, int n,
+                                                       double *__restrict__ v) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[idx[i]] = 0.0;
+}
+
+// v[p] += a[q] dt for p = set[i], q = setpos[i]; on a second kick also |a|
+__global__ __launch_bounds__(FMM_BLOCK) void k_kick(const int32_t *__restrict__ set,
+                                                    const int32_t *__restrict__ setpos, int n_set,
+                                                    const double *__restrict__ acc, int64_t n_joint,
+                                                    double *__restrict__ vel, int64_t n,
+                                                    double dt, double *__restrict__ amag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_set) return;
+  int p = set[i], q = setpos[i];
+  double ax = acc[q], ay = acc[n_joint + q], az = acc[2 * n_joint + q];
+  vel[p] += ax * dt;
+  vel[n + p] += ay * dt;
+  vel[2 * n + p] += az * dt;
+  if (amag) amag[p] = sqrt(ax * ax + ay * ay + az * az);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_drift(const int32_t *__restrict__ set, int n_set,
+                                                     const double *__restrict__ vel,
+                                                     double *__restrict__ pos, int64_t n,
+                                                     double dt) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_set) return;
+  int p = set[i];
+  pos[p] += vel[p] * dt;
+  pos[n + p] += vel[n + p] * dt;
+  pos[2 * n + p] += vel[2 * n + p] * dt;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_iota(int32_t *__restrict__ v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_amag(const double *__restrict__ acc, int64_t n,
+                                                    double *__restrict__ a_cur,
+                                                    double *__restrict__ a_old) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double ax = acc[i], ay = acc[n + i], az = acc[2 * n + i];
+  a_cur[i] = sqrt(ax * ax + ay * ay + az * az);
+  a_old[i] = 0.0;
+}
+
+// per-block FP64 partial sums of the 12 invariants; the host adds the blocks
+// in a fixed order
+__global__ __launch_bounds__(FMM_BLOCK) void k_invariants(const double *__restrict__ pos,
+                                                          const double *__restrict__ vel,
+                                                          const double *__restrict__ mass,
+                                                          const double *__restrict__ acc,
+                                                          const double *__restrict__ pot,
+                                                          int64_t n, double *__restrict__ part) {
+  double s[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) s[k] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double m = mass ? mass[i] : 1.0;
+    if (acc) {
+      double ax = acc[i], ay = acc[n + i], az = acc[2 * n + i];
+      s[0] += m * ax;
+      s[1] += m * ay;
+      s[2] += m * az;
+      s[11] += m * sqrt(ax * ax + ay * ay + az * az);
+    }
+    if (vel) {
+      double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+      s[3] += m * vx;
+      s[4] += m * vy;
+      s[5] += m * vz;
+      s[9] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+      if (pos) {
+        double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+        s[6] += m * (y * vz - z * vy);
+        s[7] += m * (z * vx - x * vz);
+        s[8] += m * (x * vy - y * vx);
+      }
+    }
+    if (pot) s[10] += 0.5 * m * pot[i];
+  }
+  __shared__ double red[FMM_BLOCK];
+  for (int k = 0; k < 12; ++k) {
+    red[threadIdx.x] = s[k];
+    __syncthreads();
+    for (int o = FMM_BLOCK / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x * 12 + k] = red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+#define NB(n) dim3((unsigned)(((n) + FMM_BLOCK - 1) / FMM_BLOCK))
+
+void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const double *a_cur,
+                      int32_t *rung, double dt_top, double eta_eps, int max_levels, hipStream_t s) {
+  if (n_sys > 0)
+    hipLaunchKernelGGL(k_rungs, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, a_old, a_cur, rung,
+                       dt_top, eta_eps, max_levels);
+}
+
+void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
+                      int32_t *slow, int32_t *slow_pos, int32_t *fast, int32_t *fast_pos,
+                      int32_t *count, hipStream_t s) {
+  if (n_sys <= 0) return;
+  hipLaunchKernelGGL(k_fast_flags, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, rung, k, flag);
+  hhs_launch_scan_u32(flag, n_sys, s);
+  hipLaunchKernelGGL(k_split_scatter, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, rung, k, flag,
+                     slow, slow_pos, fast, fast_pos, count);
+}
+
+void hhs_launch_masked_mass(const double *mass, int64_t n, const int32_t *fast, int n_fast,
+                            double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_f64, NB(n), dim3(FMM_BLOCK), 0, s, mass, out, n);
+  if (n_fast > 0)
+    hipLaunchKernelGGL(k_zero_at, NB(n_fast), dim3(FMM_BLOCK), 0, s, fast, n_fast, out);
+}
+
+void hhs_launch_kick(const int32_t *set, const int32_t *setpos, int n_set, const double *acc,
+                     int64_t n_joint, double *vel, int64_t n, double dt, double *amag,
+                     hipStream_t s) {
+  if (n_set > 0)
+    hipLaunchKernelGGL(k_kick, NB(n_set), dim3(FMM_BLOCK), 0, s, set, setpos, n_set, acc, n_joint,
+                       vel, n, dt, amag);
+}
+
+void hhs_launch_drift(const int32_t *set, int n_set, const double *vel, double *pos, int64_t n,
+                      double dt, hipStream_t s) {
+  if (n_set > 0)
+    hipLaunchKernelGGL(k_drift, NB(n_set), dim3(FMM_BLOCK), 0, s, set, n_set, vel, pos, n, dt);
+}
+
+void hhs_launch_iota(int32_t *v, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_iota, NB(n), dim3(FMM_BLOCK), 0, s, v, n);
+}
+
+void hhs_launch_amag(const double *acc, int64_t n, double *a_cur, double *a_old, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_amag, NB(n), dim3(FMM_BLOCK), 0, s, acc, n, a_cur, a_old);
+}
+
+void launch_invariants(const double *pos, const double *vel, const double *mass,
+                       const double *acc, const double *pot, int64_t n, double *part, int nblk,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_invariants, dim3(nblk), dim3(FMM_BLOCK), 0, s, pos, vel, mass, acc, pot, n,
+                     part);
+}

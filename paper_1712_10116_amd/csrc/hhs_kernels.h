@@ -1,0 +1,24 @@
+// Launchers of the HHS and reduction kernels (hhs.hip) and the shared
+// single-workgroup scan (tree.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+void hhs_launch_scan_u32(uint32_t *v, int m, hipStream_t s);
+void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const double *a_cur,
+                      int32_t *rung, double dt_top, double eta_eps, int max_levels, hipStream_t s);
+void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
+                      int32_t *slow, int32_t *slow_pos, int32_t *fast, int32_t *fast_pos,
+                      int32_t *count, hipStream_t s);
+void hhs_launch_masked_mass(const double *mass, int64_t n, const int32_t *fast, int n_fast,
+                            double *out, hipStream_t s);
+void hhs_launch_kick(const int32_t *set, const int32_t *setpos, int n_set, const double *acc,
+                     int64_t n_joint, double *vel, int64_t n, double dt, double *amag,
+                     hipStream_t s);
+void hhs_launch_drift(const int32_t *set, int n_set, const double *vel, double *pos, int64_t n,
+                      double dt, hipStream_t s);
+void hhs_launch_iota(int32_t *v, int n, hipStream_t s);
+void hhs_launch_amag(const double *acc, int64_t n, double *a_cur, double *a_old, hipStream_t s);
+void launch_invariants(const double *pos, const double *vel, const double *mass,
+                       const double *acc, const double *pot, int64_t n, double *part, int nblk,
+                       hipStream_t s);

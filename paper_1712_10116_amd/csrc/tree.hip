@@ -1,0 +1,468 @@
+// Morton-ordered oct-tree build on gfx950.
+//
+// Steps (all device-side; the host only queues launches):
+//   1. root box: per-axis min/max of the active positions; centre
+//      c = (lo+hi)/2, side L = max extent (1 if zero), origin o = c - L/2,
+//      scale s = 2^21/L;
+//   2. 63-bit Morton keys from q_d = clamp(floor((x_d - o_d) s), 0, 2^21-1),
+//      x bits at 3b+2, y at 3b+1, z at 3b;
+//   3. stable LSD radix sort of (key, active slot), 8 passes of 8 bits; ranks
+//      inside a wavefront come from 8 ballots per 64 keys;
+//   4. top-down split (the paper's recursive build, Sec. 2.3, done level by
+//      level): a cell of level l < 21 holding more than leaf_size particles
+//      gets one child per non-empty octant of its key range; children of a
+//      level are emitted in Morton order after a count / scan / emit sweep;
+//   5. geometric centre z = o + (i + 1/2) L 2^-l and half side h = L 2^-(l+1)
+//      of every cell; cell-local FP32 offsets of every particle.
+// All decisions are the same IEEE double expressions as in the definition
+// above, built with -ffp-contract=off, so keys, octant membership and centres
+// are reproducible bit for bit.
+#include "common.h"
+#include "hhs_kernels.h"
+
+#define SORT_WAVES 4
+#define SORT_ITEMS 16
+#define SORT_TILE (SORT_WAVES * 64 * SORT_ITEMS)
+
+// ---------------------------------------------------------------------------
+// root box
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FMM_BLOCK) void k_bbox_partial(const double *__restrict__ pos,
+                                                            int64_t n_total,
+                                                            const int32_t *__restrict__ active,
+                                                            int n, double *part, Header *hdr) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int64_t g = active ? active[i] : i;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      double x = pos[d * n_total + g];
+      bad |= !isfinite(x);
+      lo[d] = fmin(lo[d], x);
+      hi[d] = fmax(hi[d], x);
+    }
+  }
+  __shared__ double red[6][FMM_BLOCK];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    red[d][threadIdx.x] = lo[d];
+    red[3 + d][threadIdx.x] = hi[d];
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&hdr->nonfinite, 1);
+  for (int s = FMM_BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + s]);
+        red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + s]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_bbox_final(const double *part, int nblk, int n, Box *box) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = 0; b < nblk; ++b)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], part[b * 6 + d]);
+      hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+    }
+  if (n == 0)
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = 0.0;
+  double c[3], L = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    c[d] = 0.5 * (lo[d] + hi[d]);
+    double e = hi[d] - lo[d];
+    if (e > L) L = e;
+  }
+  if (L == 0.0) L = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    box->o[d] = c[d] - 0.5 * L;
+    box->lo[d] = lo[d];
+    box->hi[d] = hi[d];
+  }
+  box->L = L;
+  box->s = 2097152.0 / L;
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t spread3(uint64_t x) {
+  x &= 0x1fffffull;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+__device__ __forceinline__ uint32_t compact3(uint64_t x) {
+  x &= 0x1249249249249249ull;
+  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+  x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+  x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+  x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+  x = (x ^ (x >> 32)) & 0x1fffffull;
+  return (uint32_t)x;
+}
+
+__device__ __forceinline__ uint64_t quantise(double x, double o, double s) {
+  double q = floor((x - o) * s);
+  const double qmax = 2097151.0;
+  if (!(q >= 0.0)) q = 0.0;
+  if (q > qmax) q = qmax;
+  return (uint64_t)q;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_keys(const double *__restrict__ pos, int64_t n_total,
+                                                    const int32_t *__restrict__ active, int n,
+                                                    const Box *__restrict__ box,
+                                                    uint64_t *__restrict__ key,
+                                                    int32_t *__restrict__ slot) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t g = active ? active[i] : i;
+  const double s = box->s;
+  uint64_t qx = quantise(pos[g], box->o[0], s);
+  uint64_t qy = quantise(pos[n_total + g], box->o[1], s);
+  uint64_t qz = quantise(pos[2 * n_total + g], box->o[2], s);
+  key[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+  slot[i] = i;
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FMM_BLOCK) void k_sort_hist(const uint64_t *__restrict__ key, int n,
+                                                         int shift, uint32_t *__restrict__ hist,
+                                                         int nblk) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int base = blockIdx.x * SORT_TILE;
+  for (int e = threadIdx.x; e < SORT_TILE; e += FMM_BLOCK) {
+    int i = base + e;
+    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of m uint32 values in place, one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_scan_u32_1blk(uint32_t *v, int m) {
+  __shared__ uint32_t part[1024];
+  int per = (m + 1023) / 1024;
+  int b = threadIdx.x * per, e = min(m, b + per);
+  uint32_t s = 0;
+  for (int i = b; i < e; ++i) s += v[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t y = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += y;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (int i = b; i < e; ++i) {
+    uint32_t x = v[i];
+    v[i] = run;
+    run += x;
+  }
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
+    const uint64_t *__restrict__ kin, const int32_t *__restrict__ sin, uint64_t *__restrict__ kout,
+    int32_t *__restrict__ sout, int n, int shift, const uint32_t *__restrict__ hist, int nblk) {
+  __shared__ uint32_t cnt[SORT_WAVES][256];
+  __shared__ uint32_t goff[256];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int d = threadIdx.x; d < SORT_WAVES * 256; d += FMM_BLOCK) (&cnt[0][0])[d] = 0;
+  goff[threadIdx.x] = hist[threadIdx.x * nblk + blockIdx.x];
+  __syncthreads();
+  const int base = blockIdx.x * SORT_TILE + w * 64 * SORT_ITEMS;
+  uint64_t k[SORT_ITEMS];
+  int32_t sv[SORT_ITEMS];
+  uint32_t rank[SORT_ITEMS];
+  const unsigned long long below = lanes_below_mask();
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    int i = base + it * 64 + lane;
+    bool valid = i < n;
+    k[it] = valid ? kin[i] : 0;
+    sv[it] = valid ? sin[i] : 0;
+    uint32_t d = (uint32_t)(k[it] >> shift) & 255u;
+    unsigned long long m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      unsigned long long bal = __ballot((d >> b) & 1u);
+      m &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    uint32_t prior = cnt[w][d];
+    rank[it] = prior + (uint32_t)__popcll(m & below);
+    __builtin_amdgcn_wave_barrier();
+    if (valid && (m & below) == 0) cnt[w][d] = prior + (uint32_t)__popcll(m);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // per-digit offsets of the earlier waves of this block
+  uint32_t woff[SORT_WAVES];
+  {
+    uint32_t run = 0;
+#pragma unroll
+    for (int ww = 0; ww < SORT_WAVES; ++ww) {
+      woff[ww] = run;
+      run += cnt[ww][threadIdx.x];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int ww = 0; ww < SORT_WAVES; ++ww) cnt[ww][threadIdx.x] = woff[ww] + goff[threadIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    int i = base + it * 64 + lane;
+    if (i < n) {
+      uint32_t d = (uint32_t)(k[it] >> shift) & 255u;
+      uint32_t dst = cnt[w][d] + rank[it];
+      kout[dst] = k[it];
+      sout[dst] = sv[it];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// sorted particle data
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FMM_BLOCK) void k_gather_sorted(DevTree t, const double *__restrict__ pos,
+                                                             int64_t n_total,
+                                                             const int32_t *__restrict__ active,
+                                                             int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int s = t.slot[j];
+  int64_t g = active ? active[s] : s;
+  t.sx[j] = pos[g];
+  t.sy[j] = pos[n_total + g];
+  t.sz[j] = pos[2 * n_total + g];
+}
+
+// ---------------------------------------------------------------------------
+// level-by-level split
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double4 cell_geometry(const Box &b, uint64_t prefix, int lev) {
+  uint32_t ix = compact3(prefix >> 2), iy = compact3(prefix >> 1), iz = compact3(prefix);
+  double w = ldexp(b.L, -lev);
+  double4 g;
+  g.x = b.o[0] + ((double)ix + 0.5) * w;
+  g.y = b.o[1] + ((double)iy + 0.5) * w;
+  g.z = b.o[2] + ((double)iz + 0.5) * w;
+  g.w = ldexp(b.L, -(lev + 1));
+  return g;
+}
+
+__global__ void k_tree_init(DevTree t, int n) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Header *h = t.hdr;
+  int root = n > 0 ? 1 : 0;
+  h->lvl_start[0] = 0;
+  for (int l = 1; l < FMM_NLEVELS + 2; ++l) h->lvl_start[l] = root;
+  h->overflow = 0;
+  h->n_leaves = 0;
+  if (n > 0) {
+    t.nbeg[0] = 0;
+    t.nend[0] = n;
+    t.nlev[0] = 0;
+    t.nparent[0] = -1;
+    t.nchild0[0] = -1;
+    t.nnchild[0] = 0;
+    t.ngeo[0] = cell_geometry(*t.box, 0ull, 0);
+  }
+}
+
+__device__ __forceinline__ int lower_bound_digit(const uint64_t *__restrict__ key, int b, int e,
+                                                 int shift, uint32_t oct) {
+  while (b < e) {
+    int mid = (b + e) >> 1;
+    if (((uint32_t)(key[mid] >> shift) & 7u) < oct)
+      b = mid + 1;
+    else
+      e = mid;
+  }
+  return b;
+}
+
+__device__ __forceinline__ void level_chunk(const Header *h, int l, int &s, int &e) {
+  int ls = h->lvl_start[l], le = h->lvl_start[l + 1];
+  int cnt = le - ls;
+  int per = (cnt + gridDim.x - 1) / gridDim.x;
+  s = ls + blockIdx.x * per;
+  e = min(le, s + per);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_tree_count(DevTree t, int l, int leaf_size) {
+  int s, e;
+  level_chunk(t.hdr, l, s, e);
+  int sum = 0;
+  const int shift = 3 * (FMM_MAXLEVEL - (l + 1));
+  for (int i = s + threadIdx.x; i < e && i < t.cap_nodes; i += blockDim.x) {
+    int b = t.nbeg[i], en = t.nend[i];
+    int nc = 0;
+    if (en - b > leaf_size && l < FMM_MAXLEVEL) {
+      int bd[9];
+      bd[0] = b;
+      bd[8] = en;
+      for (uint32_t o = 1; o < 8; ++o) bd[o] = lower_bound_digit(t.key, bd[o - 1], en, shift, o);
+      for (int o = 0; o < 8; ++o) {
+        t.bounds[(int64_t)i * 8 + o] = bd[o];
+        nc += bd[o + 1] > bd[o];
+      }
+    }
+    t.nnchild[i] = nc;
+    sum += nc;
+  }
+  __shared__ int red[FMM_BLOCK];
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = FMM_BLOCK / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) t.scan_part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(FMM_SCAN_BLOCKS) void k_tree_scan(DevTree t, int l) {
+  __shared__ int v[FMM_SCAN_BLOCKS];
+  int x = t.scan_part[threadIdx.x];
+  v[threadIdx.x] = x;
+  __syncthreads();
+  for (int off = 1; off < FMM_SCAN_BLOCKS; off <<= 1) {
+    int y = threadIdx.x >= off ? v[threadIdx.x - off] : 0;
+    __syncthreads();
+    v[threadIdx.x] += y;
+    __syncthreads();
+  }
+  t.scan_part[threadIdx.x] = v[threadIdx.x] - x;
+  if (threadIdx.x == FMM_SCAN_BLOCKS - 1) {
+    Header *h = t.hdr;
+    int next = h->lvl_start[l + 1] + v[threadIdx.x];
+    for (int k = l + 2; k < FMM_NLEVELS + 2; ++k) h->lvl_start[k] = next;
+    if (next > t.cap_nodes) h->overflow |= OVF_NODES;
+  }
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l) {
+  int s, e;
+  level_chunk(t.hdr, l, s, e);
+  __shared__ int sc[FMM_BLOCK];
+  const Box box = *t.box;
+  int run = t.hdr->lvl_start[l + 1] + t.scan_part[blockIdx.x];
+  for (int base = s; base < e; base += FMM_BLOCK) {
+    int i = base + threadIdx.x;
+    int nc = (i < e && i < t.cap_nodes) ? t.nnchild[i] : 0;
+    sc[threadIdx.x] = nc;
+    __syncthreads();
+    for (int off = 1; off < FMM_BLOCK; off <<= 1) {
+      int y = threadIdx.x >= off ? sc[threadIdx.x - off] : 0;
+      __syncthreads();
+      sc[threadIdx.x] += y;
+      __syncthreads();
+    }
+    int first = run + sc[threadIdx.x] - nc;
+    int total = sc[FMM_BLOCK - 1];
+    __syncthreads();
+    if (nc > 0) {
+      t.nchild0[i] = first;
+      int c = first;
+      for (int o = 0; o < 8; ++o) {
+        int b = t.bounds[(int64_t)i * 8 + o];
+        int en = o < 7 ? t.bounds[(int64_t)i * 8 + o + 1] : t.nend[i];
+        if (en > b) {
+          if (c < t.cap_nodes) {
+            t.nbeg[c] = b;
+            t.nend[c] = en;
+            t.nlev[c] = l + 1;
+            t.nparent[c] = i;
+            t.nchild0[c] = -1;
+            t.nnchild[c] = 0;
+            uint64_t prefix = t.key[b] >> (3 * (FMM_MAXLEVEL - (l + 1)));
+            t.ngeo[c] = cell_geometry(box, prefix, l + 1);
+          }
+          ++c;
+        }
+      }
+    } else if (i < e && i < t.cap_nodes) {
+      t.nchild0[i] = -1;
+    }
+    run += total;
+  }
+}
+
+// leaf id and FP32 cell-local offsets of every particle
+__global__ __launch_bounds__(FMM_BLOCK) void k_mark_leaves(DevTree t) {
+  const Header *h = t.hdr;
+  int nn = min((int)t.cap_nodes, h->lvl_start[FMM_NLEVELS]);
+  int leaves = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += gridDim.x * blockDim.x) {
+    if (t.nnchild[i] != 0) continue;
+    ++leaves;
+    double4 g = t.ngeo[i];
+    for (int j = t.nbeg[i]; j < t.nend[i]; ++j) {
+      t.leaf_of[j] = i;
+      t.lx[j] = (float)(t.sx[j] - g.x);
+      t.ly[j] = (float)(t.sy[j] - g.y);
+      t.lz[j] = (float)(t.sz[j] - g.z);
+    }
+  }
+  leaves = wave_sum(leaves);
+  if ((threadIdx.x & 63) == 0 && leaves) atomicAdd((int *)&t.hdr->n_leaves, leaves);
+}
+
+hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s) {
+  const int n = a.n;
+  int nb = (n + FMM_BLOCK - 1) / FMM_BLOCK;
+  int nbb = nb < FMM_SCAN_BLOCKS ? (nb > 0 ? nb : 1) : FMM_SCAN_BLOCKS;
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(FMM_BLOCK), 0, s, a.pos, a.n_total, a.active,
+                     n, t.bbox_part, t.hdr);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, t.bbox_part, nbb, n, t.box);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(FMM_BLOCK), 0, s, a.pos, a.n_total, a.active, n,
+                       t.box, t.key, t.slot);
+    const int nblk = (n + SORT_TILE - 1) / SORT_TILE;
+    uint64_t *kin = t.key, *kout = t.key2;
+    int32_t *sin = t.slot, *sout = t.slot2;
+    for (int pass = 0; pass < 8; ++pass) {
+      int shift = pass * 8;
+      hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, n, shift,
+                         t.sort_hist, nblk);
+      hipLaunchKernelGGL(k_scan_u32_1blk, dim3(1), dim3(1024), 0, s, t.sort_hist, 256 * nblk);
+      hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, sin, kout, sout,
+                         n, shift, t.sort_hist, nblk);
+      uint64_t *tk = kin; kin = kout; kout = tk;
+      int32_t *ts = sin; sin = sout; sout = ts;
+    }
+    hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(FMM_BLOCK), 0, s, t, a.pos, a.n_total,
+                       a.active, n);
+  }
+  hipLaunchKernelGGL(k_tree_init, dim3(1), dim3(64), 0, s, t, n);
+  if (n > 0) {
+    for (int l = 0; l < FMM_MAXLEVEL; ++l) {
+      hipLaunchKernelGGL(k_tree_count, dim3(FMM_SCAN_BLOCKS), dim3(FMM_BLOCK), 0, s, t, l,
+                         a.leaf_size);
+      hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(FMM_SCAN_BLOCKS), 0, s, t, l);
+      hipLaunchKernelGGL(k_tree_emit, dim3(FMM_SCAN_BLOCKS), dim3(FMM_BLOCK), 0, s, t, l);
+    }
+    hipLaunchKernelGGL(k_mark_leaves, dim3(1024), dim3(FMM_BLOCK), 0, s, t);
+  }
+  return hipGetLastError();
+}
+
+void hhs_launch_scan_u32(uint32_t *v, int m, hipStream_t s) {
+  if (m > 0) hipLaunchKernelGGL(k_scan_u32_1blk, dim3(1), dim3(1024), 0, s, v, m);
+}

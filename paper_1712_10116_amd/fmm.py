@@ -1,0 +1,231 @@
+"""Python binding of libfmm355 (the C ABI in include/fmm355.h).
+
+Argument marshalling only: torch tensors supply device memory and the HIP
+stream; every step of the solve runs in the library's kernels.  Loading fails
+loudly if the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm355.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_ENONFINITE, FMM_ESTALE, FMM_EOVERFLOW = range(7)
+WENDLAND, PLUMMER = 0, 1
+FP64, MIXED = 0, 1
+
+EXPORTED = (
+    "fmm_create", "fmm_destroy", "fmm_last_error", "fmm_build", "fmm_evaluate", "fmm_forces",
+    "fmm_tree_info", "fmm_export_tree", "fmm_invariants", "hhs_init", "hhs_step",
+)
+
+
+class FMMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fmm status {status}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("p_max", ctypes.c_int), ("leaf_size", ctypes.c_int), ("kernel", ctypes.c_int),
+                ("precision", ctypes.c_int)]
+
+
+class HHSState(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("vel", ctypes.c_void_p), ("mass", ctypes.c_void_p),
+                ("a_old", ctypes.c_void_p), ("a_cur", ctypes.c_void_p), ("rung", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("t", ctypes.c_double)]
+
+
+class HHSParams(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("theta", ctypes.c_double), ("p", ctypes.c_int),
+                ("eta", ctypes.c_double), ("max_levels", ctypes.c_int),
+                ("freeze_rungs", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfmm355.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, dbl, ci = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+        L.fmm_create.argtypes = [ctypes.POINTER(_Params), i64, vp, ctypes.POINTER(vp)]
+        L.fmm_destroy.argtypes = [vp]
+        L.fmm_last_error.argtypes = [vp]
+        L.fmm_last_error.restype = ctypes.c_char_p
+        L.fmm_build.argtypes = [vp, vp, i64, vp, i64, dbl, dbl]
+        L.fmm_evaluate.argtypes = [vp, vp, vp, i64, vp, i64, ci, vp, vp]
+        L.fmm_forces.argtypes = [vp, vp, vp, i64, vp, i64, dbl, dbl, ci, vp, vp]
+        L.fmm_tree_info.argtypes = [vp, vp]
+        L.fmm_export_tree.argtypes = [vp] + [vp] * 11
+        L.fmm_invariants.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
+        L.hhs_init.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams)]
+        L.hhs_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
+        for name in EXPORTED:
+            if name != "fmm_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _check_dev(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Solver:
+    """One solver context (workspace for up to max_n active particles)."""
+
+    def __init__(self, max_n, *, p_max=6, leaf_size=16, kernel=WENDLAND, precision=FP64,
+                 stream=None):
+        self._h = None
+        self.max_n = int(max_n)
+        self.precision = precision
+        self.kernel = kernel
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        prm = _Params(int(p_max), int(leaf_size), int(kernel), int(precision))
+        h = ctypes.c_void_p()
+        st = lib().fmm_create(ctypes.byref(prm), self.max_n, ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.byref(h))
+        if st != FMM_OK:
+            raise FMMError(st, "fmm_create failed")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().fmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st):
+        if st != FMM_OK:
+            raise FMMError(st, lib().fmm_last_error(self._h).decode())
+
+    def build(self, pos, active=None, *, eps, theta):
+        n_total = pos.shape[1]
+        _check_dev(pos, torch.float64, (3, n_total), "pos")
+        n = n_total if active is None else active.shape[0]
+        if active is not None:
+            _check_dev(active, torch.int32, None, "active")
+        self._raise(lib().fmm_build(self._h, _ptr(pos), n_total, _ptr(active), n, float(eps),
+                                    float(theta)))
+
+    def evaluate(self, pos, mass, active=None, *, p, acc=None, pot=None):
+        n_total = pos.shape[1]
+        n = n_total if active is None else active.shape[0]
+        _check_dev(mass, torch.float64, (n_total,), "mass")
+        if acc is None:
+            acc = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        if pot is None:
+            pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        _check_dev(acc, torch.float64, (3, n), "acc")
+        _check_dev(pot, torch.float64, (n,), "pot")
+        self._raise(lib().fmm_evaluate(self._h, _ptr(pos), _ptr(mass), n_total, _ptr(active), n,
+                                       int(p), _ptr(acc), _ptr(pot)))
+        return acc, pot
+
+    def forces(self, pos, mass, active=None, *, eps, theta, p, acc=None, pot=None):
+        self.build(pos, active, eps=eps, theta=theta)
+        return self.evaluate(pos, mass, active, p=p, acc=acc, pot=pot)
+
+    def tree_info(self):
+        import numpy as np
+        info = np.zeros(9, dtype=np.int64)
+        self._raise(lib().fmm_tree_info(self._h, _hptr(info)))
+        keys = ("n", "nodes", "m2l", "p2p", "depth", "leaves", "m2l_directed", "p2p_directed",
+                "p2p_interactions")
+        return dict(zip(keys, (int(x) for x in info)))
+
+    def export_tree(self):
+        import numpy as np
+        info = self.tree_info()
+        nn, n = info["nodes"], info["n"]
+        out = dict(
+            perm=np.zeros(n, dtype=np.int64), level=np.zeros(nn, dtype=np.int32),
+            prefix=np.zeros(nn, dtype=np.uint64), begin=np.zeros(nn, dtype=np.int64),
+            end=np.zeros(nn, dtype=np.int64), is_leaf=np.zeros(nn, dtype=np.int32),
+            centre=np.zeros((nn, 3)), half=np.zeros(nn),
+            m2l=np.zeros((info["m2l"], 2), dtype=np.int64),
+            p2p=np.zeros((info["p2p"], 2), dtype=np.int64), box=np.zeros(5))
+        self._raise(lib().fmm_export_tree(self._h, *[_hptr(out[k]) for k in (
+            "perm", "level", "prefix", "begin", "end", "is_leaf", "centre", "half", "m2l", "p2p",
+            "box")]))
+        return out
+
+    def invariants(self, pos=None, vel=None, mass=None, acc=None, pot=None, n=None):
+        import numpy as np
+        if n is None:
+            for t in (pos, vel, acc, pot, mass):
+                if t is not None:
+                    n = t.shape[-1]
+                    break
+        out = np.zeros(12)
+        self._raise(lib().fmm_invariants(self._h, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(acc),
+                                         _ptr(pot), int(n), _hptr(out)))
+        keys = ("F", "P", "L")
+        res = {k: out[3 * i:3 * i + 3].copy() for i, k in enumerate(keys)}
+        res.update(T=out[9], W=out[10], Fabs=out[11])
+        return res
+
+
+class HHS:
+    """Device-resident HHS integrator state driven by hhs_init / hhs_step."""
+
+    def __init__(self, solver, pos, vel, mass, *, eps, theta, p, eta, max_levels,
+                 freeze_rungs=False):
+        self.solver = solver
+        n = pos.shape[1]
+        for t, nm, shp in ((pos, "pos", (3, n)), (vel, "vel", (3, n)), (mass, "mass", (n,))):
+            _check_dev(t, torch.float64, shp, nm)
+        self.pos, self.vel, self.mass = pos, vel, mass
+        dev = pos.device
+        self.a_old = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.a_cur = torch.zeros(n, dtype=torch.float64, device=dev)
+        self.rung = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.state = HHSState(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), self.a_old.data_ptr(),
+                              self.a_cur.data_ptr(), self.rung.data_ptr(), n, 0.0)
+        self.params = HHSParams(float(eps), float(theta), int(p), float(eta), int(max_levels),
+                                int(bool(freeze_rungs)))
+
+    @property
+    def t(self):
+        return self.state.t
+
+    def init(self):
+        self.solver._raise(lib().hhs_init(self.solver._h, ctypes.byref(self.state),
+                                          ctypes.byref(self.params)))
+
+    def step(self, dt_top):
+        import numpy as np
+        stats = np.zeros(3, dtype=np.int64)
+        self.solver._raise(lib().hhs_step(self.solver._h, ctypes.byref(self.state),
+                                          ctypes.byref(self.params), float(dt_top), _hptr(stats)))
+        return dict(force_calls=int(stats[0]), force_particles=int(stats[1]), builds=int(stats[2]))
