@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""FMM force-solve benchmark on one MI355X.
+
+Workload: cold collapse -- 1,048,576 equal-mass particles uniform in the unit
+sphere (G = M = R = 1), Wendland C2 softening eps = 0.005, expansion order
+p = 4, leaf size 16.  One step = one complete force solve of all particles
+(root box, Morton keys and sort, tree, symmetric dual walk, P2M/M2M, M2L,
+P2P, L2L/L2P) through the C ABI, inputs resident in HBM.
+
+Prints one JSON line: particles/s of the mixed-precision path (the headline),
+the plain FP64 path beside it, force errors of both against FP64 direct
+summation on a seeded sample of sinks (CPU oracle), momentum balance, per-phase
+HIP-event times, the roofline of the dominant kernel, the CPU oracle timed on
+a bounded sample, and one HHS top-level step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector (published)
+PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (published)
+METRIC = "FMM force particles/s at 1e-3 force err (mixed vs FP64); ensemble p99 latency"
+
+
+def coeffs(p):
+    return (p + 1) * (p + 2) * (p + 3) // 6
+
+
+def m2l_flops_per_pair(p):
+    # per unordered cell pair: both contractions (2 x 2 flops per term,
+    # C(p+6,6) terms) plus one derivative tensor, about 2 C(p+3,3) (p+1) flops
+    from math import comb
+    return 4 * comb(p + 6, 6) + 2 * coeffs(p) * (p + 1)
+
+
+P2P_FLOPS_PER_PAIR = 30.0  # per unordered particle pair (rsqrt counted as 1)
+
+
+def force_error(acc, ref):
+    mag = np.sqrt((ref * ref).sum(axis=0))
+    floor = 1e-6 * np.sqrt((mag * mag).mean())
+    e = np.sqrt(((acc - ref) ** 2).sum(axis=0)) / np.maximum(mag, floor)
+    return float(np.sqrt((e * e).mean())), float(np.percentile(e, 99))
+
+
+def time_solver(F, torch, s, tp, tm, acc, pot, prm, steps, warmup, profile):
+    for _ in range(warmup):
+        s.forces(tp, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], acc=acc, pot=pot)
+    torch.cuda.synchronize()
+    if profile:
+        s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.forces(tp, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], acc=acc, pot=pot)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = s.profile_read() if profile else None
+    if profile:
+        s.profile(False)
+    return (t1 - t0) / steps, phases
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--sample", type=int, default=2048, help="sinks checked against direct sum")
+    ap.add_argument("--cpu-sample", type=int, default=262144, help="particles in the CPU oracle run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-hhs", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the FMM solve here is a single-device path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1712_10116_amd.fmm as F
+    from paper_1712_10116_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    prm = dict(p=args.p, theta=args.theta, eps=0.005, leaf_size=args.leaf, kernel=F.WENDLAND)
+    pos, vel, mass = W.uniform_sphere(n, seed=1001)
+    tp = torch.from_numpy(pos).to(dev)
+    tm = torch.from_numpy(mass).to(dev)
+    out = {}
+    res = {}
+    for name, prec in (("mixed", F.MIXED), ("fp64", F.FP64)):
+        s = F.Solver(n, p_max=args.p, leaf_size=args.leaf, kernel=F.WENDLAND, precision=prec)
+        acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+        pot = torch.empty((n,), dtype=torch.float64, device=dev)
+        sec, phases = time_solver(F, torch, s, tp, tm, acc, pot, prm, args.steps, args.warmup,
+                                  profile=True)
+        info = s.tree_info()
+        inv = s.invariants(mass=tm, acc=acc)
+        res[name] = dict(sec=sec, phases=phases, info=info, acc=acc.cpu().numpy(),
+                         momentum=float(np.abs(inv["F"]).max() / inv["Fabs"]))
+        s.close()
+        del acc, pot
+        torch.cuda.synchronize()
+
+    # accuracy against FP64 direct summation (CPU oracle) on a seeded sample
+    from oracle import oracle as O
+    rng = np.random.default_rng(2024)
+    sinks = np.sort(rng.choice(n, size=min(args.sample, n), replace=False))
+    ref, _ = O.direct(pos, mass, O.WENDLAND, prm["eps"], sinks=sinks)
+    err = {k: force_error(res[k]["acc"][:, sinks], ref) for k in res}
+    e_mf = force_error(res["mixed"]["acc"], res["fp64"]["acc"])
+
+    mixed, fp64 = res["mixed"], res["fp64"]
+    ph = mixed["phases"]
+    info = mixed["info"]
+    steps = args.steps
+    # dominant evaluation kernel and its algorithmic work per launch
+    kern = {}
+    p2p_ms = ph["p2p"][0] / max(ph["p2p"][1], 1)
+    m2l_ms = ph["m2l"][0] / max(ph["m2l"][1], 1)
+    p2p_flops = P2P_FLOPS_PER_PAIR * info["p2p_interactions"] / 2.0
+    m2l_flops = m2l_flops_per_pair(args.p) * info["m2l"]
+    kern["p2p"] = dict(ms=p2p_ms, flops=p2p_flops, tflops=p2p_flops / (p2p_ms * 1e-3) / 1e12)
+    kern["m2l"] = dict(ms=m2l_ms, flops=m2l_flops, tflops=m2l_flops / (m2l_ms * 1e-3) / 1e12)
+    dom = max(kern, key=lambda k: kern[k]["ms"])
+    roof = dict(kernel=dom, bound="alu", achieved=round(kern[dom]["tflops"], 3),
+                peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                frac=round(kern[dom]["tflops"] / PEAK_FP32_TFLOPS, 4), traffic=None)
+
+    line = {
+        "metric": METRIC,
+        "value": round(n / mixed["sec"], 1),
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["sec"] * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"cold collapse, uniform unit sphere, N={n}, Wendland C2 eps=0.005, "
+                               f"p={args.p}, theta={args.theta}, leaf {args.leaf}, mixed FP32/FP64",
+                   "n": n, "p": args.p, "theta": args.theta, "eps": 0.005, "leaf_size": args.leaf,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "force_err": {"mixed_vs_direct": {"rms": err["mixed"][0], "p99": err["mixed"][1]},
+                      "fp64_vs_direct": {"rms": err["fp64"][0], "p99": err["fp64"][1]},
+                      "mixed_vs_fp64_gpu": {"rms": e_mf[0], "p99": e_mf[1]},
+                      "sinks": int(len(sinks))},
+        "fp64": {"value": round(n / fp64["sec"], 1), "ms_per_step": round(fp64["sec"] * 1e3, 4),
+                 "phases_ms": {k: round(v[0] / steps, 4) for k, v in fp64["phases"].items()}},
+        "momentum_rel": {"mixed": mixed["momentum"], "fp64": fp64["momentum"]},
+        "phases_ms": {k: round(v[0] / steps, 4) for k, v in ph.items()},
+        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in d.items()}
+                    for k, d in kern.items()},
+        "tree": info,
+        "interactions_per_s": {"p2p_ordered": round(info["p2p_interactions"] / mixed["sec"], 1),
+                               "m2l_ordered": round(info["m2l_directed"] / mixed["sec"], 1)},
+    }
+
+    if not args.no_hhs:
+        # one HHS top-level step of the same particles (mixed precision)
+        s = F.Solver(n, p_max=args.p, leaf_size=args.leaf, kernel=F.WENDLAND, precision=F.MIXED)
+        tpp = tp.clone()
+        tv = torch.from_numpy(vel).to(dev)
+        h = F.HHS(s, tpp, tv, tm, eps=prm["eps"], theta=prm["theta"], p=args.p, eta=0.0025,
+                  max_levels=10)
+        h.init()
+        a = torch.sqrt(h.a_cur.max() / 1.0)
+        dtmax = float(np.sqrt(0.0025 * prm["eps"] / max(float(h.a_cur[h.a_cur > 0].min()), 1e-30)))
+        dt_top = min(2.0 ** np.floor(np.log2(dtmax)), 2.0 ** -4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = h.step(dt_top)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rungs = torch.bincount(h.rung.long()).cpu().numpy().tolist()
+        line["hhs"] = {"dt_top": dt_top, "seconds": round(t1 - t0, 4), **st,
+                       "particles_per_s": round(st["force_particles"] / (t1 - t0), 1),
+                       "rung_histogram": rungs}
+        s.close()
+        del a
+
+    if not args.no_cpu_baseline:
+        ns = min(args.cpu_sample, n)
+        spos, _, smass = W.uniform_sphere(ns, seed=1001)
+        kw = dict(p=args.p, theta=args.theta, eps=0.005, leaf_size=args.leaf, kernel=O.WENDLAND)
+        t0 = time.perf_counter()
+        O.fmm(spos, smass, **kw)
+        t1 = time.perf_counter()
+        line["cpu_baseline"] = {"value": round(ns / (t1 - t0), 1), "unit": "particles/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"one oracle FMM force solve (FP64, single thread) on a "
+                                          f"{ns}-particle uniform sphere of the same recipe, "
+                                          f"{t1 - t0:.1f} s"}
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

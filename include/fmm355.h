@@ -22,7 +22,8 @@
  *     n_total doubles); masses are n_total doubles.  The caller owns every
  *     particle, index and output buffer; the library owns its workspace.
  *   - "active" lists n_active distinct indices into [0, n_total) (int32, device
- *     memory); NULL means all n_total particles in order.  Outputs are written
+ *     memory); NULL means all n_total particles in order (n_active = n_total).
+ *     n_active = 0 is always valid and does nothing.  Outputs are written
  *     in active-list order (output slot s belongs to particle active[s]).
  *   - Every call is ordered on the stream given to fmm_create.  Argument
  *     errors are returned synchronously without touching the GPU.  fmm_build
@@ -133,6 +134,17 @@ fmm_status fmm_export_tree(fmm_ctx *ctx, int64_t *perm, int32_t *level, uint64_t
  * out[11] sum m |a|.  out is a HOST array of 12 doubles; synchronises. */
 fmm_status fmm_invariants(fmm_ctx *ctx, const double *pos, const double *vel, const double *mass,
                           const double *acc, const double *pot, int64_t n, double out[12]);
+
+/* Per-phase timing with HIP events recorded on the context's stream between
+ * launch groups (nothing else changes).  enable != 0 starts recording and
+ * clears the totals; 0 stops. */
+fmm_status fmm_profile_enable(fmm_ctx *ctx, int enable);
+
+/* Totals since enabling: ms[k] milliseconds and calls[k] timed launch groups
+ * of phase k: 0 root box + keys + radix sort, 1 tree split, 2 dual walk,
+ * 3 P2M + M2M, 4 M2L, 5 P2P, 6 L2L + L2P (two groups per evaluation).
+ * Waits for the recorded work. */
+fmm_status fmm_profile_read(fmm_ctx *ctx, double ms[7], int64_t calls[7]);
 
 /* ---------------------------------------------------------------------------
  * HHS integrator (Sec. 2.2, Algorithms 1-3)

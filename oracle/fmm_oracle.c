@@ -750,6 +750,193 @@ int orc_tree_eval(const orc_tree *t, const double *mass_total, int64_t n_total,
     return orc_tree_eval_ex(t, mass_total, n_total, active, acc, pot, NULL, NULL);
 }
 
+/* The FMM result for selected sinks only, computed one sink at a time: the
+ * upward pass (P2M, M2M) for every cell, then for each sink the M2L terms of
+ * every cell on the path from the root to the sink's leaf (from the symmetric
+ * list, each pair taken from the side of the path cell), L2L down that path,
+ * L2P, and P2P over its leaf's partners.  By linearity this is the same
+ * arithmetic as orc_tree_eval for those sinks, up to summation order.
+ * sinks: active slots; outputs acc (SoA 3 x n_sinks), pot (n_sinks). */
+int orc_tree_eval_sinks(const orc_tree *t, const double *mass_total, const int32_t *active,
+                        const int64_t *sinks, int64_t n_sinks, double *acc, double *pot)
+{
+    const int64_t n = t->n, NN = t->n_nodes;
+    if (n == 0 || n_sinks == 0) return ORC_OK;
+    const int p = t->prm.p;
+    orc_mi *mi = (orc_mi *)malloc(sizeof(orc_mi));
+    if (!mi) return ORC_ENOMEM;
+    mi_init(mi, p);
+    const int K = mi->K;
+    double *M = (double *)calloc((size_t)(NN * K), sizeof(double));
+    double *m = (double *)malloc(sizeof(double) * n);
+    int64_t *inv = (int64_t *)malloc(sizeof(int64_t) * n);
+    int64_t *parent = (int64_t *)malloc(sizeof(int64_t) * NN);
+    int64_t *deg = (int64_t *)calloc((size_t)NN + 1, sizeof(int64_t));
+    int64_t *adj = (int64_t *)malloc(sizeof(int64_t) * (2 * t->n_m2l + 1));
+    int64_t *pdeg = (int64_t *)calloc((size_t)NN + 1, sizeof(int64_t));
+    int64_t *padj = (int64_t *)malloc(sizeof(int64_t) * (2 * t->n_p2p + 1));
+    double *D = (double *)malloc(sizeof(double) * K);
+    double *Lpath = (double *)malloc(sizeof(double) * K * (ORC_MAXLEVEL + 2));
+    if (!M || !m || !inv || !parent || !deg || !adj || !pdeg || !padj || !D || !Lpath) {
+        free(mi); free(M); free(m); free(inv); free(parent); free(deg); free(adj);
+        free(pdeg); free(padj); free(D); free(Lpath);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t slot = t->perm[i];
+        m[i] = mass_total[active ? active[slot] : slot];
+        inv[slot] = i;
+    }
+    parent[0] = -1;
+    for (int64_t c = 0; c < NN; ++c)
+        for (int q = 0; q < t->nodes[c].nchild; ++q) parent[t->nodes[c].child[q]] = c;
+    /* upward pass, exactly as in orc_tree_eval_ex */
+    for (int64_t c = 0; c < NN; ++c) {
+        const orc_node *nd = &t->nodes[c];
+        if (nd->nchild) continue;
+        for (int64_t i = nd->begin; i < nd->end; ++i) {
+            int64_t slot = t->perm[i];
+            double u[3] = {t->x[0][slot] - nd->z[0], t->x[1][slot] - nd->z[1],
+                           t->x[2][slot] - nd->z[2]};
+            for (int k = 0; k < K; ++k) M[c * K + k] += m[i] * mono_over_fact(mi, u, k);
+        }
+    }
+    for (int64_t c = NN - 1; c >= 0; --c) {
+        const orc_node *P = &t->nodes[c];
+        for (int q = 0; q < P->nchild; ++q) {
+            const orc_node *C = &t->nodes[P->child[q]];
+            double d[3] = {C->z[0] - P->z[0], C->z[1] - P->z[1], C->z[2] - P->z[2]};
+            for (int mm = 0; mm < K; ++mm) {
+                const int *km = mi->k[mm];
+                double acc_m = 0.0;
+                for (int kk = 0; kk < K; ++kk) {
+                    const int *kk3 = mi->k[kk];
+                    if (kk3[0] > km[0] || kk3[1] > km[1] || kk3[2] > km[2]) continue;
+                    int diff = mi->idx[km[0] - kk3[0]][km[1] - kk3[1]][km[2] - kk3[2]];
+                    acc_m += M[P->child[q] * K + kk] * mono_over_fact(mi, d, diff);
+                }
+                M[c * K + mm] += acc_m;
+            }
+        }
+    }
+    /* partner lists of every cell from the unordered pair lists */
+    for (int64_t q = 0; q < t->n_m2l; ++q) { deg[t->m2l[q].a + 1]++; deg[t->m2l[q].b + 1]++; }
+    for (int64_t c = 0; c < NN; ++c) deg[c + 1] += deg[c];
+    {
+        int64_t *fill = (int64_t *)calloc((size_t)NN, sizeof(int64_t));
+        for (int64_t q = 0; q < t->n_m2l; ++q) {
+            int64_t a = t->m2l[q].a, b = t->m2l[q].b;
+            adj[deg[a] + fill[a]++] = b;
+            adj[deg[b] + fill[b]++] = a;
+        }
+        for (int64_t q = 0; q < t->n_p2p; ++q) { pdeg[t->p2p[q].a + 1]++; if (t->p2p[q].a != t->p2p[q].b) pdeg[t->p2p[q].b + 1]++; }
+        for (int64_t c = 0; c < NN; ++c) pdeg[c + 1] += pdeg[c];
+        memset(fill, 0, sizeof(int64_t) * NN);
+        for (int64_t q = 0; q < t->n_p2p; ++q) {
+            int64_t a = t->p2p[q].a, b = t->p2p[q].b;
+            padj[pdeg[a] + fill[a]++] = b;
+            if (a != b) padj[pdeg[b] + fill[b]++] = a;
+        }
+        free(fill);
+    }
+    const double e2 = t->prm.kernel == ORC_PLUMMER ? t->prm.eps * t->prm.eps : 0.0;
+    for (int64_t s = 0; s < n_sinks; ++s) {
+        int64_t i = inv[sinks[s]];
+        /* path from the root to the leaf holding sorted position i */
+        int64_t path[ORC_MAXLEVEL + 2];
+        int np = 0;
+        int64_t c = 0;
+        path[np++] = 0;
+        while (t->nodes[c].nchild) {
+            const orc_node *nd = &t->nodes[c];
+            int64_t next = -1;
+            for (int q = 0; q < nd->nchild; ++q) {
+                const orc_node *ch = &t->nodes[nd->child[q]];
+                if (i >= ch->begin && i < ch->end) next = nd->child[q];
+            }
+            c = next;
+            path[np++] = c;
+        }
+        for (int lv = 0; lv < np; ++lv) {
+            int64_t A = path[lv];
+            const orc_node *NA = &t->nodes[A];
+            double *L = Lpath + lv * K;
+            for (int k = 0; k < K; ++k) L[k] = 0.0;
+            for (int64_t q = deg[A]; q < deg[A + 1]; ++q) {
+                int64_t B = adj[q];
+                const orc_node *NB = &t->nodes[B];
+                double R[3] = {NA->z[0] - NB->z[0], NA->z[1] - NB->z[1], NA->z[2] - NB->z[2]};
+                orc_derivs(mi, R, e2, D);
+                for (int nn = 0; nn < K; ++nn) {
+                    double la = 0.0;
+                    for (int mm = 0; mm < K; ++mm) {
+                        int sidx = mi_sum_idx(mi, nn, mm);
+                        if (sidx < 0) continue;
+                        double sgn_m = (mi_deg(mi, mm) & 1) ? -1.0 : 1.0;
+                        la += sgn_m * M[B * K + mm] * D[sidx];
+                    }
+                    L[nn] += la;
+                }
+            }
+            if (lv > 0) {
+                const orc_node *P = &t->nodes[path[lv - 1]];
+                const double *Lp = Lpath + (lv - 1) * K;
+                double d[3] = {NA->z[0] - P->z[0], NA->z[1] - P->z[1], NA->z[2] - P->z[2]};
+                for (int nn = 0; nn < K; ++nn) {
+                    const int *kn = mi->k[nn];
+                    double acc_n = 0.0;
+                    for (int kk = 0; kk < K; ++kk) {
+                        const int *k3 = mi->k[kk];
+                        if (k3[0] < kn[0] || k3[1] < kn[1] || k3[2] < kn[2]) continue;
+                        int diff = mi->idx[k3[0] - kn[0]][k3[1] - kn[1]][k3[2] - kn[2]];
+                        acc_n += Lp[kk] * mono_over_fact(mi, d, diff);
+                    }
+                    L[nn] += acc_n;
+                }
+            }
+        }
+        const orc_node *leaf = &t->nodes[c];
+        const double *L = Lpath + (np - 1) * K;
+        int64_t slot = t->perm[i];
+        double xi[3] = {t->x[0][slot], t->x[1][slot], t->x[2][slot]};
+        double u[3] = {xi[0] - leaf->z[0], xi[1] - leaf->z[1], xi[2] - leaf->z[2]};
+        double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < K; ++k) {
+            double mono = mono_over_fact(mi, u, k);
+            f += mono * L[k];
+            const int *kk = mi->k[k];
+            if (kk[0] + kk[1] + kk[2] < p) {
+                g[0] += mono * L[mi->idx[kk[0] + 1][kk[1]][kk[2]]];
+                g[1] += mono * L[mi->idx[kk[0]][kk[1] + 1][kk[2]]];
+                g[2] += mono * L[mi->idx[kk[0]][kk[1]][kk[2] + 1]];
+            }
+        }
+        double ax = -g[0], ay = -g[1], az = -g[2], ph = f;
+        for (int64_t q = pdeg[c]; q < pdeg[c + 1]; ++q) {
+            const orc_node *B = &t->nodes[padj[q]];
+            for (int64_t j = B->begin; j < B->end; ++j) {
+                if (j == i) continue;
+                int64_t sj = t->perm[j];
+                double dx = t->x[0][sj] - xi[0], dy = t->x[1][sj] - xi[1], dz = t->x[2][sj] - xi[2];
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                double phi, gg;
+                pair_kernel(t->prm.kernel, t->prm.eps, r, &phi, &gg);
+                ax += m[j] * gg * dx;
+                ay += m[j] * gg * dy;
+                az += m[j] * gg * dz;
+                ph += m[j] * phi;
+            }
+        }
+        acc[s] = ax;
+        acc[n_sinks + s] = ay;
+        acc[2 * n_sinks + s] = az;
+        pot[s] = ph;
+    }
+    free(mi); free(M); free(m); free(inv); free(parent); free(deg); free(adj);
+    free(pdeg); free(padj); free(D); free(Lpath);
+    return ORC_OK;
+}
+
 /* One complete FMM force evaluation: acceleration (SoA 3 x n_active) and
  * potential (n_active) of every active particle due to all active masses. */
 int orc_fmm(const double *pos, const double *mass, int64_t n_total, const int32_t *active,

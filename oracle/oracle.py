@@ -56,6 +56,8 @@ def lib():
         L.orc_tree_export.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 11
         L.orc_tree_eval_ex.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp,
                                        ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_tree_eval_sinks.argtypes = [ctypes.c_void_p, dp, ctypes.c_void_p, ctypes.c_void_p,
+                                          i64, dp, dp]
         L.orc_direct.argtypes = [dp, dp, i64, ctypes.c_void_p, i64, ctypes.c_int,
                                  ctypes.c_double, dp, dp]
         L.orc_derivs_export.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp,
@@ -193,6 +195,18 @@ class Tree:
         assert rc == 0
         if want_expansions:
             return acc, pot, M, L
+        return acc, pot
+
+
+    def evaluate_sinks(self, mass, sinks):
+        """FMM acceleration/potential of the given active slots only."""
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        sinks = np.ascontiguousarray(sinks, dtype=np.int64)
+        acc = np.zeros((3, len(sinks)))
+        pot = np.zeros(len(sinks))
+        rc = lib().orc_tree_eval_sinks(self._h, _dp(mass), _vp(self.active), _vp(sinks),
+                                       len(sinks), _dp(acc), _dp(pot))
+        assert rc == 0
         return acc, pot
 
 

@@ -43,8 +43,11 @@ struct fmm_ctx {
   double *mmask, *acc, *pot;
   double *inv_part;
   int64_t stat_calls, stat_parts, stat_builds;
+  PhaseTimer timer;
   char err[512];
 };
+
+static PhaseTimer *timer_of(fmm_ctx *c) { return c->timer.on ? &c->timer : nullptr; }
 
 static fmm_status fail(fmm_ctx *c, fmm_status st, const char *fmt, ...) {
   if (c) {
@@ -168,6 +171,11 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
 extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
   if (!c) return FMM_EINVAL;
   (void)hipStreamSynchronize(c->stream);
+  if (c->timer.ready)
+    for (int i = 0; i < PhaseTimer::CAP; ++i) {
+      (void)hipEventDestroy(c->timer.a[i]);
+      (void)hipEventDestroy(c->timer.b[i]);
+    }
   for (void *p : c->allocs) (void)hipFree(p);
   if (c->lv_slow) {
     free(c->lv_slow);
@@ -187,7 +195,8 @@ static fmm_status check_particles(fmm_ctx *c, const double *pos, int64_t n_total
   if (n_active < 0 || n_active > c->max_n)
     return fail(c, FMM_EINVAL, "n_active=%lld outside [0, max_n=%lld]", (long long)n_active,
                 (long long)c->max_n);
-  if (n_total < 0 || (!active && n_total != n_active) || (active && n_total < 1 && n_active > 0))
+  if (n_total < 0 || (n_active > 0 && !active && n_total != n_active) ||
+      (active && n_total < 1 && n_active > 0))
     return fail(c, FMM_EINVAL, "n_total=%lld inconsistent with n_active=%lld",
                 (long long)n_total, (long long)n_active);
   if (n_total > (int64_t)INT32_MAX) return fail(c, FMM_EINVAL, "n_total too large");
@@ -235,6 +244,7 @@ extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
   a.leaf_size = c->prm.leaf_size;
   a.eps = eps;
   a.theta = theta;
+  a.tm = timer_of(c);
   for (int attempt = 0; attempt < 6; ++attempt) {
     HIPCHK(c, hipMemsetAsync(&c->t.hdr->nonfinite, 0, sizeof(int32_t), c->stream));
     HIPCHK(c, launch_build_tree(c->t, a, c->stream));
@@ -310,6 +320,7 @@ extern "C" fmm_status fmm_evaluate(fmm_ctx *c, const double *pos, const double *
   e.pot = pot;
   e.lvl_start_host = c->hh.lvl_start;
   e.depth = c->depth;
+  e.tm = timer_of(c);
   HIPCHK(c, launch_evaluate(c->t, e, c->stream));
   c->stat_calls++;
   c->stat_parts += n_active;
@@ -600,5 +611,35 @@ extern "C" fmm_status hhs_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp, 
     stats[2] = c->stat_builds - b0;
   }
   c->tree_valid = false;
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_profile_enable(fmm_ctx *c, int enable) {
+  if (!c) return FMM_EINVAL;
+  PhaseTimer &tm = c->timer;
+  if (enable && !tm.ready) {
+    for (int i = 0; i < PhaseTimer::CAP; ++i) {
+      HIPCHK(c, hipEventCreate(&tm.a[i]));
+      HIPCHK(c, hipEventCreate(&tm.b[i]));
+    }
+    tm.ready = true;
+  }
+  if (tm.on) tm.flush();
+  tm.on = enable != 0;
+  tm.n = 0;
+  for (int k = 0; k < PH_N; ++k) {
+    tm.ms[k] = 0.0;
+    tm.cnt[k] = 0;
+  }
+  return FMM_OK;
+}
+
+extern "C" fmm_status fmm_profile_read(fmm_ctx *c, double ms[7], int64_t calls[7]) {
+  if (!c || !ms || !calls) return FMM_EINVAL;
+  c->timer.flush();
+  for (int k = 0; k < PH_N; ++k) {
+    ms[k] = c->timer.ms[k];
+    calls[k] = c->timer.cnt[k];
+  }
   return FMM_OK;
 }

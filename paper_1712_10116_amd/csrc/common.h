@@ -109,6 +109,53 @@ __device__ __forceinline__ int wave_excl_scan_int(int v, int *total) {
 }
 
 // ---------------------------------------------------------------------------
+// per-phase HIP-event timing on the context's stream (off unless enabled)
+// ---------------------------------------------------------------------------
+enum {
+  PH_SORT = 0,   // root box, keys, radix sort, sorted gather
+  PH_TREE = 1,   // level-by-level split, leaf marking
+  PH_WALK = 2,   // symmetric dual walk
+  PH_UP = 3,     // mass gather, P2M, M2M
+  PH_M2L = 4,
+  PH_P2P = 5,
+  PH_DOWN = 6,   // L2L, L2P
+  PH_N = 7
+};
+
+struct PhaseTimer {
+  static const int CAP = 512;
+  bool on = false;
+  bool ready = false;
+  hipEvent_t a[CAP], b[CAP];
+  int ph[CAP];
+  int n = 0;
+  double ms[PH_N] = {0};
+  long long cnt[PH_N] = {0};
+  void start(int p, hipStream_t s) {
+    if (!on) return;
+    if (n == CAP) flush();
+    hipEventRecord(a[n], s);
+    ph[n] = p;
+  }
+  void stop(hipStream_t s) {
+    if (!on) return;
+    hipEventRecord(b[n], s);
+    ++n;
+  }
+  void flush() {
+    if (n == 0) return;
+    hipEventSynchronize(b[n - 1]);
+    for (int i = 0; i < n; ++i) {
+      float t = 0.f;
+      hipEventElapsedTime(&t, a[i], b[i]);
+      ms[ph[i]] += t;
+      cnt[ph[i]] += 1;
+    }
+    n = 0;
+  }
+};
+
+// ---------------------------------------------------------------------------
 // host-side launchers (one translation unit each)
 // ---------------------------------------------------------------------------
 struct BuildArgs {
@@ -119,6 +166,7 @@ struct BuildArgs {
   int leaf_size;
   double eps;
   double theta;
+  PhaseTimer *tm;
 };
 
 // tree.hip
@@ -140,6 +188,7 @@ struct EvalArgs {
   double *pot;
   const int32_t *lvl_start_host;  // host copy, FMM_NLEVELS+1 entries
   int depth;
+  PhaseTimer *tm;
 };
 hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s);
 bool eval_order_supported(int p);

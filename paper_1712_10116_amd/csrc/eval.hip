@@ -311,6 +311,7 @@ template <typename T, int P, int KERNEL>
 static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   const int nn = e.n_nodes;
   const int nb_nodes = (nn + FMM_BLOCK - 1) / FMM_BLOCK;
+  PhaseTimer *tm = e.tm;
   hipLaunchKernelGGL((k_p2m<T, P>), dim3(nb_nodes), dim3(FMM_BLOCK), 0, s, t, nn);
   for (int l = e.depth - 1; l >= 0; --l) {
     int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
@@ -319,18 +320,35 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
                          dim3(FMM_BLOCK), 0, s, t, ls, le);
   }
   const int wave_blocks = (nn + 3) / 4;
+  if (tm) {
+    tm->stop(s);
+    tm->start(PH_M2L, s);
+  }
   hipLaunchKernelGGL((k_m2l<T, P, KERNEL>), dim3(wave_blocks), dim3(FMM_BLOCK), 0, s, t, nn,
                      e.eps);
+  if (tm) {
+    tm->stop(s);
+    tm->start(PH_DOWN, s);
+  }
   for (int l = 1; l <= e.depth; ++l) {
     int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
     if (le > ls)
       hipLaunchKernelGGL((k_l2l<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
                          dim3(FMM_BLOCK), 0, s, t, ls, le);
   }
+  if (tm) {
+    tm->stop(s);
+    tm->start(PH_P2P, s);
+  }
   hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL>), dim3(wave_blocks), dim3(FMM_BLOCK), 0, s,
                      t, nn, e.eps);
+  if (tm) {
+    tm->stop(s);
+    tm->start(PH_DOWN, s);
+  }
   hipLaunchKernelGGL((k_l2p<T, P>), dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
                      s, t, e.n, e.acc, e.pot);
+  if (tm) tm->stop(s);
 }
 
 template <typename T, int KERNEL>
@@ -350,6 +368,7 @@ bool eval_order_supported(int p) { return p >= 1 && p <= 6; }
 
 hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   if (e.n <= 0) return hipSuccess;
+  if (e.tm) e.tm->start(PH_UP, s);
   hipLaunchKernelGGL(k_gather_mass, dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0, s,
                      t, e.mass, e.active, e.n);
   bool ok;

@@ -232,8 +232,10 @@ hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s) 
   launch_reset_lists(t, s);
   if (a.n <= 0) return hipGetLastError();
   const double th2 = a.theta * a.theta;
+  if (a.tm) a.tm->start(PH_WALK, s);
   for (int l = 0; l <= FMM_MAXLEVEL; ++l)
     hipLaunchKernelGGL(k_traverse_level, dim3(2048), dim3(TRAV_WAVES * 64), 0, s, t, l, th2,
                        a.eps);
+  if (a.tm) a.tm->stop(s);
   return hipGetLastError();
 }

@@ -428,6 +428,7 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s
   const int n = a.n;
   int nb = (n + FMM_BLOCK - 1) / FMM_BLOCK;
   int nbb = nb < FMM_SCAN_BLOCKS ? (nb > 0 ? nb : 1) : FMM_SCAN_BLOCKS;
+  if (a.tm) a.tm->start(PH_SORT, s);
   hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(FMM_BLOCK), 0, s, a.pos, a.n_total, a.active,
                      n, t.bbox_part, t.hdr);
   hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, t.bbox_part, nbb, n, t.box);
@@ -450,6 +451,10 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s
     hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(FMM_BLOCK), 0, s, t, a.pos, a.n_total,
                        a.active, n);
   }
+  if (a.tm) {
+    a.tm->stop(s);
+    a.tm->start(PH_TREE, s);
+  }
   hipLaunchKernelGGL(k_tree_init, dim3(1), dim3(64), 0, s, t, n);
   if (n > 0) {
     for (int l = 0; l < FMM_MAXLEVEL; ++l) {
@@ -460,6 +465,7 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s
     }
     hipLaunchKernelGGL(k_mark_leaves, dim3(1024), dim3(FMM_BLOCK), 0, s, t);
   }
+  if (a.tm) a.tm->stop(s);
   return hipGetLastError();
 }
 

@@ -21,7 +21,9 @@ FP64, MIXED = 0, 1
 EXPORTED = (
     "fmm_create", "fmm_destroy", "fmm_last_error", "fmm_build", "fmm_evaluate", "fmm_forces",
     "fmm_tree_info", "fmm_export_tree", "fmm_invariants", "hhs_init", "hhs_step",
+    "fmm_profile_enable", "fmm_profile_read",
 )
+PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
 
 class FMMError(RuntimeError):
@@ -70,6 +72,8 @@ def lib():
         L.fmm_invariants.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
         L.hhs_init.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams)]
         L.hhs_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
+        L.fmm_profile_enable.argtypes = [vp, ci]
+        L.fmm_profile_read.argtypes = [vp, vp, vp]
         for name in EXPORTED:
             if name != "fmm_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -179,6 +183,18 @@ class Solver:
             "perm", "level", "prefix", "begin", "end", "is_leaf", "centre", "half", "m2l", "p2p",
             "box")]))
         return out
+
+    def profile(self, enable=True):
+        """Start (clearing totals) or stop per-phase HIP-event timing."""
+        self._raise(lib().fmm_profile_enable(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{phase: (milliseconds, timed launch groups)} since profile(True)."""
+        import numpy as np
+        ms = np.zeros(7)
+        calls = np.zeros(7, dtype=np.int64)
+        self._raise(lib().fmm_profile_read(self._h, _hptr(ms), _hptr(calls)))
+        return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(PHASES)}
 
     def invariants(self, pos=None, vel=None, mass=None, acc=None, pot=None, n=None):
         import numpy as np

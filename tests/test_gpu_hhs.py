@@ -1,0 +1,79 @@
+"""HHS integrator on the GPU (Sec. 2.2, Algorithms 1-3) against the oracle's
+numpy HHS driving the oracle FMM: same rungs, positions and velocities after
+several top-level steps (FP64), solver-call accounting, and total momentum
+conserved to round-off on the GPU in both precisions."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from paper_1712_10116_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _gpu_hhs(pos, vel, m, prm, steps, dt_top, precision=0, freeze=None):
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    n = m.size
+    s = F.Solver(n, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
+                 precision=precision)
+    tp = torch.from_numpy(pos.copy()).cuda()
+    tv = torch.from_numpy(vel.copy()).cuda()
+    tm = torch.from_numpy(m).cuda()
+    h = F.HHS(s, tp, tv, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
+              max_levels=prm["max_levels"], freeze_rungs=freeze is not None)
+    h.init()
+    if freeze is not None:
+        h.rung.copy_(torch.from_numpy(freeze.astype(np.int32)).cuda())
+    stats = [h.step(dt_top) for _ in range(steps)]
+    inv = s.invariants(pos=tp, vel=tv, mass=tm)
+    out = (tp.cpu().numpy(), tv.cpu().numpy(), h.rung.cpu().numpy(), h.a_old.cpu().numpy(),
+           h.a_cur.cpu().numpy(), stats, inv)
+    s.close()
+    return out
+
+
+PRM0 = dict(W.PARAMS[0])
+
+
+def _oracle_hhs(oracle, pos, vel, m, prm, steps, dt_top):
+    H = oracle.HHSOracle(p=prm["p"], theta=prm["theta"], eps=prm["eps"],
+                         leaf_size=prm["leaf_size"], kernel=prm["kernel"], eta=prm["eta"],
+                         max_levels=prm["max_levels"])
+    st = oracle.HHSState(pos, vel, m)
+    H.init_forces(st)
+    calls = []
+    for _ in range(steps):
+        c0 = st.force_calls
+        H.step(st, dt_top)
+        calls.append(st.force_calls - c0)
+    return st, calls
+
+
+@pytest.mark.parametrize("n,steps", [(1024, 2), (4096, 1)])
+def test_hhs_matches_oracle(oracle, n, steps):
+    pos, vel, m = W.plummer(n, seed=1000)
+    prm = dict(PRM0)
+    dt_top = 1.0 / 16
+    st, calls = _oracle_hhs(oracle, pos, vel, m, prm, steps, dt_top)
+    gp, gv, grung, gao, gac, stats, inv = _gpu_hhs(pos, vel, m, prm, steps, dt_top)
+    np.testing.assert_array_equal(grung, st.rung)
+    assert [s["force_calls"] for s in stats] == calls
+    scale_x = np.abs(pos).max()
+    scale_v = np.abs(vel).max()
+    assert np.abs(gp - st.pos).max() / scale_x < 1e-10
+    assert np.abs(gv - st.vel).max() / scale_v < 1e-10
+    np.testing.assert_allclose(gac, st.a_cur, rtol=1e-10)
+    np.testing.assert_allclose(gao, st.a_old, rtol=1e-10, atol=1e-300)
+    assert len(np.unique(grung)) >= 3
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 1e-6)])
+def test_hhs_momentum_conserved(precision, tol):
+    pos, vel, m = W.plummer(8192, seed=1000)
+    prm = dict(PRM0)
+    P0 = (m * vel).sum(axis=1)
+    gp, gv, grung, _, _, stats, inv = _gpu_hhs(pos, vel, m, prm, 2, 1.0 / 16, precision)
+    scale = (m * np.sqrt((vel * vel).sum(axis=0))).sum()
+    assert np.abs(inv["P"] - P0).max() / scale < tol
+    assert sum(s["force_calls"] for s in stats) > 8

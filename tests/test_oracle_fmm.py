@@ -133,3 +133,15 @@ def test_active_subset_order(oracle):
     a1, p1 = oracle.fmm(pos, m, act, p=4, theta=0.5, eps=0.005, leaf_size=16, kernel=0)
     a2, p2 = oracle.fmm(pos[:, act], m[act], p=4, theta=0.5, eps=0.005, leaf_size=16, kernel=0)
     np.testing.assert_allclose(a1, a2, rtol=1e-12, atol=1e-12 * np.abs(a2).max())
+
+
+def test_sink_evaluation_matches_full_evaluation(oracle):
+    # the per-sink path (root-to-leaf M2L + L2L + L2P + leaf P2P) must give the
+    # same numbers as the whole-tree evaluation
+    pos, _, m = W.config(0, n=4000)
+    t = oracle.Tree(pos, p=5, theta=0.5, eps=0.01, leaf_size=16, kernel=1)
+    a, pt = t.evaluate(m)
+    sk = np.random.default_rng(1).choice(4000, 200, replace=False)
+    a2, p2 = t.evaluate_sinks(m, sk)
+    np.testing.assert_allclose(a2, a[:, sk], rtol=0, atol=1e-13 * np.abs(a).max())
+    np.testing.assert_allclose(p2, pt[sk], rtol=0, atol=1e-13 * np.abs(pt).max())
