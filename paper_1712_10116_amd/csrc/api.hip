@@ -88,6 +88,7 @@ static void dfree(fmm_ctx *c, void *p) {
 // node-sized arrays
 static bool alloc_nodes(fmm_ctx *c, int64_t cap) {
   DevTree &t = c->t;
+  if (cap >= ((int64_t)1 << 28)) return false;  // node ids carry a 3-bit tag in the walk
   t.cap_nodes = cap;
   size_t real = c->prm.precision == FMM_PREC_MIXED ? sizeof(float) : sizeof(double);
   bool ok = dalloc(c, &t.nbeg, cap) && dalloc(c, &t.nend, cap) && dalloc(c, &t.nlev, cap) &&
@@ -142,7 +143,9 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
             dalloc(c, &t.lz, n) && dalloc(c, &t.sm, n) && dalloc(c, &t.sm32, n) &&
             dalloc(c, &t.leaf_of, n) && dalloc(c, &t.near, 4 * n) &&
             dalloc(c, &t.scan_part, FMM_SCAN_BLOCKS) && dalloc(c, &t.bbox_part, FMM_SCAN_BLOCKS * 6) &&
-            dalloc(c, &t.sort_hist, 256 * ((n + 4095) / 4096) + 256) && dalloc(c, &t.hdr, 1) &&
+            dalloc(c, &t.sort_hist, 256 * ((n + 4095) / 4096) + 256) &&
+            dalloc(c, &t.sort_dtot, 256) && dalloc(c, &t.scan_blk, n / 1024 + 64) &&
+            dalloc(c, &t.hdr, 1) &&
             dalloc(c, &t.box, 1) && alloc_nodes(c, cap_nodes);
   if (ok) {
     t.cap_m2l = 96 * cap_nodes;
@@ -245,22 +248,39 @@ extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
   a.eps = eps;
   a.theta = theta;
   a.tm = timer_of(c);
-  for (int attempt = 0; attempt < 6; ++attempt) {
+  // 1. tree; one readback of the level sizes (exact launches for the walk)
+  for (int attempt = 0;; ++attempt) {
+    if (attempt == 4) return fail(c, FMM_EOVERFLOW, "node workspace still too small");
     HIPCHK(c, hipMemsetAsync(&c->t.hdr->nonfinite, 0, sizeof(int32_t), c->stream));
-    HIPCHK(c, launch_build_tree(c->t, a, c->stream));
+    HIPCHK(c, launch_sort(c->t, a, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
+    // no cell below level max_prefix + 1 can hold two particles
+    const int max_level = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
+    HIPCHK(c, launch_build_tree(c->t, a, max_level, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!(c->hh.overflow & OVF_NODES)) break;
+    int64_t need = std::max<int64_t>((int64_t)c->hh.lvl_start[FMM_NLEVELS], 2 * c->t.cap_nodes);
+    free_nodes(c);
+    if (!alloc_nodes(c, need + need / 4))
+      return fail(c, FMM_ENOMEM, "node workspace regrow to %lld failed", (long long)need);
+  }
+  int depth = 0;
+  for (int l = 0; l < FMM_NLEVELS; ++l)
+    if (c->hh.lvl_start[l + 1] > c->hh.lvl_start[l]) depth = l;
+  int32_t lvl[FMM_NLEVELS + 2];
+  memcpy(lvl, c->hh.lvl_start, sizeof(lvl));
+  a.lvl_host = lvl;
+  a.depth = depth;
+  // 2. symmetric walk; regrow a list buffer that turned out too small
+  for (int attempt = 0; attempt < 4; ++attempt) {
     HIPCHK(c, launch_traverse(c->t, a, c->stream));
     HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const Header &h = c->hh;
-    if (h.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
-    if (h.overflow & OVF_STACK) return fail(c, FMM_EOVERFLOW, "traversal descent stack overflow");
-    if (h.overflow & OVF_NODES) {
-      int64_t need = std::max<int64_t>((int64_t)h.lvl_start[FMM_NLEVELS], 2 * c->t.cap_nodes);
-      free_nodes(c);
-      if (!alloc_nodes(c, need + need / 4))
-        return fail(c, FMM_ENOMEM, "node workspace regrow to %lld failed", (long long)need);
-      continue;
-    }
+    if (h.overflow & OVF_STACK) return fail(c, FMM_EOVERFLOW, "walk descent stack overflow");
     if (h.overflow & (OVF_M2L | OVF_P2P | OVF_OPEN)) {
       if (h.overflow & OVF_M2L) {
         st = regrow_lists(c, OVF_M2L, h.m2l_cursor);
@@ -279,9 +299,6 @@ extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
       continue;
     }
     c->n_nodes = h.lvl_start[FMM_NLEVELS];
-    int depth = 0;
-    for (int l = 0; l < FMM_NLEVELS; ++l)
-      if (h.lvl_start[l + 1] > h.lvl_start[l]) depth = l;
     c->depth = depth;
     c->tree_valid = true;
     c->b_pos = pos;
@@ -293,7 +310,7 @@ extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
     c->stat_builds++;
     return FMM_OK;
   }
-  return fail(c, FMM_EOVERFLOW, "workspace still too small after regrowth");
+  return fail(c, FMM_EOVERFLOW, "list workspace still too small after regrowth");
 }
 
 extern "C" fmm_status fmm_evaluate(fmm_ctx *c, const double *pos, const double *mass,
@@ -551,8 +568,8 @@ static fmm_status hhs_evolve(HHSRun &r, int k, const int32_t *sys, int n_sys, do
                      hp->max_levels, c->stream);
   int32_t *slow = c->lv_slow[k], *slow_pos = c->lv_slow_pos[k];
   int32_t *fast = c->lv_fast[k], *fast_pos = c->lv_fast_pos[k];
-  hhs_launch_split(sys, n_sys, st->rung, k, c->flag, slow, slow_pos, fast, fast_pos, c->count,
-                   c->stream);
+  hhs_launch_split(sys, n_sys, st->rung, k, c->flag, c->t.scan_blk, slow, slow_pos, fast,
+                   fast_pos, c->count, c->stream);
   int32_t n_fast = 0;
   HIPCHK(c, hipMemcpyAsync(&n_fast, c->count, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -37,7 +37,7 @@ struct Header {
   int32_t nonfinite;                   // an input position was not finite
   unsigned long long p2p_pairs;        // ordered particle interactions in P2P
   int32_t n_leaves;
-  int32_t pad;
+  int32_t max_prefix;  // longest common key prefix (levels) of sorted neighbours
 };
 
 // Box: o[3] (origin), L (side), s = 2^21/L, lo[3], hi[3]
@@ -73,6 +73,8 @@ struct DevTree {
   int32_t *scan_part;          // [FMM_SCAN_BLOCKS]
   double *bbox_part;           // [FMM_SCAN_BLOCKS][6]
   uint32_t *sort_hist;         // [256][sort blocks]
+  uint32_t *sort_dtot;         // [256] digit totals
+  uint32_t *scan_blk;          // block sums of the generic scan
   Header *hdr;
   Box *box;
   int64_t cap_n, cap_nodes, cap_m2l, cap_p2p, cap_open;
@@ -167,10 +169,13 @@ struct BuildArgs {
   double eps;
   double theta;
   PhaseTimer *tm;
+  const int32_t *lvl_host;  // level starts of the built tree (host copy), for the walk
+  int depth;
 };
 
 // tree.hip
-hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s);
+hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s);
+hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, int max_level, hipStream_t s);
 // traverse.hip
 hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s);
 hipError_t launch_reset_lists(const DevTree &t, hipStream_t s);

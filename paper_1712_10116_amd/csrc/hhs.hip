@@ -168,11 +168,11 @@ void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const 
 }
 
 void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
-                      int32_t *slow, int32_t *slow_pos, int32_t *fast, int32_t *fast_pos,
-                      int32_t *count, hipStream_t s) {
+                      uint32_t *scan_part, int32_t *slow, int32_t *slow_pos, int32_t *fast,
+                      int32_t *fast_pos, int32_t *count, hipStream_t s) {
   if (n_sys <= 0) return;
   hipLaunchKernelGGL(k_fast_flags, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, rung, k, flag);
-  hhs_launch_scan_u32(flag, n_sys, s);
+  hhs_launch_scan_u32(flag, n_sys, scan_part, s);
   hipLaunchKernelGGL(k_split_scatter, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, rung, k, flag,
                      slow, slow_pos, fast, fast_pos, count);
 }

@@ -4,12 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-void hhs_launch_scan_u32(uint32_t *v, int m, hipStream_t s);
+void hhs_launch_scan_u32(uint32_t *v, int m, uint32_t *part, hipStream_t s);
 void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const double *a_cur,
                       int32_t *rung, double dt_top, double eta_eps, int max_levels, hipStream_t s);
 void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
-                      int32_t *slow, int32_t *slow_pos, int32_t *fast, int32_t *fast_pos,
-                      int32_t *count, hipStream_t s);
+                      uint32_t *scan_part, int32_t *slow, int32_t *slow_pos, int32_t *fast,
+                      int32_t *fast_pos, int32_t *count, hipStream_t s);
 void hhs_launch_masked_mass(const double *mass, int64_t n, const int32_t *fast, int n_fast,
                             double *out, hipStream_t s);
 void hhs_launch_kick(const int32_t *set, const int32_t *setpos, int n_set, const double *acc,

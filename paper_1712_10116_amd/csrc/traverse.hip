@@ -11,10 +11,12 @@
 // not accepted is recorded in A's "open" list; the children of A then inherit
 // the candidates {children of C} (or C itself if C is a leaf).  A leaf target
 // that meets a non-leaf candidate descends into that candidate's children on
-// a per-wavefront LDS stack.  One wavefront handles one target cell; level l
-// of the tree is one launch.  Outputs are written in two passes (count, then
-// write after an atomic allocation), so each cell's lists are contiguous and
-// their content and order are deterministic.
+// a per-wavefront LDS stack.  One wavefront handles all children of one cell
+// (siblings share their candidates, which are expanded once into LDS and
+// tested against every sibling); level l of the tree is one launch.  Outputs
+// are written in two passes (count, then write after an atomic allocation),
+// so each cell's lists are contiguous and their content and order are
+// deterministic.
 //
 // Well-separation is Eq. (1) with R = half side, plus the softening rule of
 // Sec. 2.3, written in IEEE double without contraction:
@@ -23,7 +25,9 @@
 #include "common.h"
 
 #define TRAV_WAVES 4
-#define TRAV_STACK 2048
+#define TRAV_CAND 512   // expanded candidates of one block of 64 open-list entries
+#define TRAV_STACK 2048 // descent stack (target tag in the top 3 bits)
+#define TRAV_TAG 28
 
 enum { CAT_NONE = 0, CAT_M2L = 1, CAT_P2P = 2, CAT_OPEN = 3, CAT_DEEPEN = 4 };
 
@@ -40,174 +44,231 @@ __device__ __forceinline__ bool well_separated(const double4 a, const double4 b,
   return mac && sep;
 }
 
-struct TravOut {
-  int *m2l, *p2p, *open;
-  int om2l, op2p, oopen;
-  int wm, wp, wo;
-  unsigned long long pairs;
-};
-
-// Classify candidate C of target A and (pass 1) emit it; returns the number
-// of children to push for a descending leaf target.
-template <bool WRITE>
-__device__ __forceinline__ void classify_emit(const DevTree &t, int A, double4 gA, bool leafA,
-                                              int nA, bool valid, int C, double th2, double eps,
-                                              int &cm2l, int &cp2p, int &copen, TravOut &o,
-                                              int *stk, int &sp) {
-  int cat = CAT_NONE;
-  int nC = 0;
-  if (valid) {
-    nC = t.nnchild[C];
-    if (C == A)
-      cat = leafA ? CAT_P2P : CAT_OPEN;
-    else if (well_separated(gA, t.ngeo[C], th2, eps))
-      cat = CAT_M2L;
-    else if (leafA)
-      cat = nC == 0 ? CAT_P2P : CAT_DEEPEN;
-    else
-      cat = CAT_OPEN;
-  }
-  const unsigned long long below = lanes_below_mask();
-  unsigned long long bm = __ballot(cat == CAT_M2L);
-  unsigned long long bp = __ballot(cat == CAT_P2P);
-  unsigned long long bo = __ballot(cat == CAT_OPEN);
-  if (WRITE) {
-    if (cat == CAT_M2L) o.m2l[o.om2l + o.wm + __popcll(bm & below)] = C;
-    if (cat == CAT_P2P) {
-      o.p2p[o.op2p + o.wp + __popcll(bp & below)] = C;
-      int nCp = t.nend[C] - t.nbeg[C];
-      o.pairs += (unsigned long long)nA * (unsigned long long)nCp - (C == A ? (unsigned)nA : 0u);
-    }
-    if (cat == CAT_OPEN) o.open[o.oopen + o.wo + __popcll(bo & below)] = C;
-    o.wm += __popcll(bm);
-    o.wp += __popcll(bp);
-    o.wo += __popcll(bo);
-  }
-  cm2l += __popcll(bm);
-  cp2p += __popcll(bp);
-  copen += __popcll(bo);
-  // push the children of descending candidates
-  int push = cat == CAT_DEEPEN ? nC : 0;
-  int total;
-  int pos = wave_excl_scan_int(push, &total);
-  if (total) {
-    if (sp + total > TRAV_STACK) {
-      // drop the descent (the build reports the overflow as an error); sp only
-      // ever covers entries that were written
-      if (__lane_id() == 0) atomicOr(&t.hdr->overflow, OVF_STACK);
-    } else {
-      if (push) {
-        int c0 = t.nchild0[C];
-        for (int k = 0; k < push; ++k) stk[sp + pos + k] = c0 + k;
-      }
-      sp += total;
-    }
-  }
+__device__ __forceinline__ int classify(int A, const double4 &gA, bool leafA, int C,
+                                        const double4 &gC, bool leafC, double th2, double eps) {
+  if (C == A) return leafA ? CAT_P2P : CAT_OPEN;
+  if (well_separated(gA, gC, th2, eps)) return CAT_M2L;
+  if (leafA) return leafC ? CAT_P2P : CAT_DEEPEN;
+  return CAT_OPEN;
 }
 
+// Per-wavefront state of the sibling targets (children of one parent cell).
+struct Sibs {
+  int n;          // number of targets, 1..8
+  int id[8];
+  bool leaf[8];
+  int np[8];      // particles per target
+  int cnt[8][3];  // M2L / P2P / OPEN entries counted (pass 0) or written (pass 1)
+  int off[8][3];  // list offsets (pass 1)
+};
+
+struct WaveLds {
+  int cand[TRAV_CAND];
+  int stack[TRAV_STACK];
+  double4 geo[8];
+};
+
 template <bool WRITE>
-__device__ void walk_target(const DevTree &t, int l, int A, const int *open_in, TravOut &o,
-                            int *stk, double th2, double eps, int &cm2l, int &cp2p, int &copen) {
+__device__ __forceinline__ void emit(const DevTree &t, Sibs &S, int tg, int cat, bool mine, int C,
+                                     int npC, int *open_out, unsigned long long &pairs) {
+  const unsigned long long below = lanes_below_mask();
+  const unsigned long long bm = __ballot(mine && cat == CAT_M2L);
+  const unsigned long long bp = __ballot(mine && cat == CAT_P2P);
+  const unsigned long long bo = __ballot(mine && cat == CAT_OPEN);
+  if (WRITE) {
+    if (mine && cat == CAT_M2L) t.m2l_src[S.off[tg][0] + S.cnt[tg][0] + __popcll(bm & below)] = C;
+    if (mine && cat == CAT_P2P) {
+      t.p2p_src[S.off[tg][1] + S.cnt[tg][1] + __popcll(bp & below)] = C;
+      pairs += (unsigned long long)S.np[tg] * (unsigned long long)npC -
+               (C == S.id[tg] ? (unsigned long long)S.np[tg] : 0ull);
+    }
+    if (mine && cat == CAT_OPEN) open_out[S.off[tg][2] + S.cnt[tg][2] + __popcll(bo & below)] = C;
+  }
+  S.cnt[tg][0] += __popcll(bm);
+  S.cnt[tg][1] += __popcll(bp);
+  S.cnt[tg][2] += __popcll(bo);
+}
+
+// push the children of C (tagged with target tg) for lanes that descend
+__device__ __forceinline__ void push_children(const DevTree &t, WaveLds &L, int &sp, bool push,
+                                              int tg, int C, int nC) {
+  int k = push ? nC : 0;
+  int total;
+  int pos = wave_excl_scan_int(k, &total);
+  if (total == 0) return;
+  if (sp + total > TRAV_STACK) {
+    if (__lane_id() == 0) atomicOr(&t.hdr->overflow, OVF_STACK);
+    return;  // descent dropped; the build reports the overflow
+  }
+  if (k) {
+    int c0 = t.nchild0[C];
+    for (int q = 0; q < k; ++q) L.stack[sp + pos + q] = (tg << TRAV_TAG) | (c0 + q);
+  }
+  sp += total;
+}
+
+// One pass over the candidates of a sibling group (pass 0 counts, pass 1 writes).
+template <bool WRITE>
+__device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
+                           const int *open_in, int *open_out, double th2, double eps,
+                           unsigned long long &pairs) {
   const int lane = __lane_id();
-  const double4 gA = t.ngeo[A];
-  const bool leafA = t.nnchild[A] == 0;
-  const int nA = t.nend[A] - t.nbeg[A];
+#pragma unroll
+  for (int tg = 0; tg < 8; ++tg) S.cnt[tg][0] = S.cnt[tg][1] = S.cnt[tg][2] = 0;
+  int sp = 0;
   int in_off = 0, in_cnt = 1;
   if (l > 0) {
-    int P = t.nparent[A];
     in_off = t.open_off[P];
     in_cnt = t.open_cnt[P];
   }
-  int sp = 0;
-  cm2l = cp2p = copen = 0;
-  for (int base = 0; base < in_cnt; base += 64) {
-    int ei = base + lane;
-    bool valid = ei < in_cnt;
+  for (int eb = 0; eb < in_cnt; eb += 64) {
+    // expand 64 open-list entries into candidate cells (children, or the leaf itself)
+    const int e = eb + lane;
     int ec = 0, c0 = 0;
-    if (valid) {
+    if (e < in_cnt) {
       if (l == 0) {
-        ec = 1;
-        c0 = 0;  // the pair (root, root)
+        ec = 1;  // the pair (root, root)
       } else {
-        int B = open_in[in_off + ei];
-        int nB = t.nnchild[B];
+        const int B = open_in[in_off + e];
+        const int nB = t.nnchild[B];
         ec = nB > 0 ? nB : 1;
         c0 = nB > 0 ? t.nchild0[B] : B;
       }
     }
-    for (int k = 0; k < 8; ++k) {
-      bool has = k < ec;
-      if (__ballot(has) == 0ull) break;
-      classify_emit<WRITE>(t, A, gA, leafA, nA, has, c0 + k, th2, eps, cm2l, cp2p, copen, o, stk,
-                           sp);
+    int total;
+    const int pos = wave_excl_scan_int(ec, &total);
+    for (int q = 0; q < ec; ++q) L.cand[pos + q] = c0 + q;
+    __builtin_amdgcn_wave_barrier();
+    for (int cb = 0; cb < total; cb += 64) {
+      const bool valid = cb + lane < total;
+      const int C = valid ? L.cand[cb + lane] : 0;
+      double4 gC = make_double4(0, 0, 0, 0);
+      int nC = 0, npC = 0;
+      if (valid) {
+        gC = t.ngeo[C];
+        nC = t.nnchild[C];
+        npC = t.nend[C] - t.nbeg[C];
+      }
+#pragma unroll
+      for (int tg = 0; tg < 8; ++tg) {
+        if (tg < S.n) {
+          const int cat = valid ? classify(S.id[tg], L.geo[tg], S.leaf[tg], C, gC, nC == 0, th2,
+                                           eps)
+                                : CAT_NONE;
+          emit<WRITE>(t, S, tg, cat, valid, C, npC, open_out, pairs);
+          if (S.leaf[tg]) push_children(t, L, sp, cat == CAT_DEEPEN, tg, C, nC);
+        }
+      }
     }
+    __builtin_amdgcn_wave_barrier();
   }
-  // descend candidates of a leaf target (LIFO, up to 64 at a time)
+  // descents of leaf targets into non-leaf candidates (LIFO, 64 at a time)
   while (sp > 0) {
-    int take = min(sp, 64);
-    bool valid = lane < take;
-    int C = valid ? stk[sp - take + lane] : 0;
+    const int take = min(sp, 64);
+    const bool valid = lane < take;
+    const int item = valid ? L.stack[sp - take + lane] : 0;
     __builtin_amdgcn_wave_barrier();
     sp -= take;
-    classify_emit<WRITE>(t, A, gA, leafA, nA, valid, C, th2, eps, cm2l, cp2p, copen, o, stk, sp);
+    const int tgl = item >> TRAV_TAG;
+    const int C = item & ((1 << TRAV_TAG) - 1);
+    double4 gC = make_double4(0, 0, 0, 0);
+    int nC = 0, npC = 0;
+    if (valid) {
+      gC = t.ngeo[C];
+      nC = t.nnchild[C];
+      npC = t.nend[C] - t.nbeg[C];
+    }
+#pragma unroll
+    for (int tg = 0; tg < 8; ++tg) {
+      if (tg < S.n) {
+        const bool mine = valid && tgl == tg;
+        const int cat = mine ? classify(S.id[tg], L.geo[tg], S.leaf[tg], C, gC, nC == 0, th2, eps)
+                             : CAT_NONE;
+        emit<WRITE>(t, S, tg, cat, mine, C, npC, open_out, pairs);
+        push_children(t, L, sp, cat == CAT_DEEPEN, tg, C, nC);
+      }
+    }
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-__global__ __launch_bounds__(TRAV_WAVES * 64) void k_traverse_level(DevTree t, int l, double th2,
-                                                                     double eps) {
-  __shared__ int stack[TRAV_WAVES][TRAV_STACK];
+// Level l >= 1: one wavefront per cell P of level l-1 with children; the
+// children are the targets.  Level 0: one wavefront for the root.
+__global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l, int ps, int pe,
+                                                                double th2, double eps) {
+  __shared__ WaveLds lds[TRAV_WAVES];
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   Header *h = t.hdr;
-  if (h->overflow & OVF_NODES) return;  // child ids may lie beyond the node arrays
-  const int s = h->lvl_start[l], e = min(h->lvl_start[l + 1], (int)t.cap_nodes);
+  const int P = ps + blockIdx.x * TRAV_WAVES + w;
+  if (P >= pe) return;
+  WaveLds &L = lds[w];
+  Sibs S;
+  if (l == 0) {
+    S.n = 1;
+    S.id[0] = 0;
+  } else {
+    const int nc = t.nnchild[P];
+    if (nc == 0) return;
+    S.n = nc;
+    const int c0 = t.nchild0[P];
+#pragma unroll
+    for (int tg = 0; tg < 8; ++tg) S.id[tg] = c0 + (tg < nc ? tg : 0);
+  }
+#pragma unroll
+  for (int tg = 0; tg < 8; ++tg) {
+    const int A = S.id[tg];
+    S.leaf[tg] = t.nnchild[A] == 0;
+    S.np[tg] = t.nend[A] - t.nbeg[A];
+  }
+  if (lane < 8) {
+    int A = S.id[0];
+#pragma unroll
+    for (int tg = 1; tg < 8; ++tg)
+      if (lane == tg) A = S.id[tg];
+    L.geo[lane] = t.ngeo[A];
+  }
+  __builtin_amdgcn_wave_barrier();
   const int *open_in = (l & 1) ? t.open_buf0 : t.open_buf1;
   int *open_out = (l & 1) ? t.open_buf1 : t.open_buf0;
   unsigned long long pairs = 0;
-  for (int A = s + blockIdx.x * TRAV_WAVES + w; A < e; A += gridDim.x * TRAV_WAVES) {
-    TravOut o;
-    o.m2l = t.m2l_src;
-    o.p2p = t.p2p_src;
-    o.open = open_out;
-    o.wm = o.wp = o.wo = 0;
-    o.pairs = 0;
-    int cm, cp, co;
-    walk_target<false>(t, l, A, open_in, o, stack[w], th2, eps, cm, cp, co);
-    int om = 0, op = 0, oo = 0;
-    if (lane == 0) {
-      om = (int)atomicAdd(&h->m2l_cursor, (unsigned)cm);
-      op = (int)atomicAdd(&h->p2p_cursor, (unsigned)cp);
-      oo = (int)atomicAdd(&h->open_cursor[l], (unsigned)co);
-    }
-    om = __shfl(om, 0, 64);
-    op = __shfl(op, 0, 64);
-    oo = __shfl(oo, 0, 64);
-    bool ovf = (int64_t)om + cm > t.cap_m2l || (int64_t)op + cp > t.cap_p2p ||
-               (int64_t)oo + co > t.cap_open;
-    if (lane == 0) {
-      t.m2l_off[A] = om;
-      t.m2l_cnt[A] = ovf ? 0 : cm;
-      t.p2p_off[A] = op;
-      t.p2p_cnt[A] = ovf ? 0 : cp;
-      t.open_off[A] = oo;
-      t.open_cnt[A] = ovf ? 0 : co;
-      if (ovf) {
-        int bits = 0;
-        if ((int64_t)om + cm > t.cap_m2l) bits |= OVF_M2L;
-        if ((int64_t)op + cp > t.cap_p2p) bits |= OVF_P2P;
-        if ((int64_t)oo + co > t.cap_open) bits |= OVF_OPEN;
-        atomicOr(&h->overflow, bits);
-      }
-    }
-    if (!ovf) {
-      o.om2l = om;
-      o.op2p = op;
-      o.oopen = oo;
-      walk_target<true>(t, l, A, open_in, o, stack[w], th2, eps, cm, cp, co);
-      pairs += o.pairs;
-    }
+  walk_group<false>(t, l, P, S, L, open_in, open_out, th2, eps, pairs);
+  // allocate every target's lists (lane tg handles target tg)
+  int mine[3] = {0, 0, 0};
+#pragma unroll
+  for (int tg = 0; tg < 8; ++tg)
+    if (lane == tg)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) mine[k] = S.cnt[tg][k];
+  int o[3] = {0, 0, 0};
+  bool ovf = false;
+  if (lane < S.n) {
+    o[0] = (int)atomicAdd(&h->m2l_cursor, (unsigned)mine[0]);
+    o[1] = (int)atomicAdd(&h->p2p_cursor, (unsigned)mine[1]);
+    o[2] = (int)atomicAdd(&h->open_cursor[l], (unsigned)mine[2]);
+    int bits = 0;
+    if ((int64_t)o[0] + mine[0] > t.cap_m2l) bits |= OVF_M2L;
+    if ((int64_t)o[1] + mine[1] > t.cap_p2p) bits |= OVF_P2P;
+    if ((int64_t)o[2] + mine[2] > t.cap_open) bits |= OVF_OPEN;
+    ovf = bits != 0;
+    int A = S.id[0];
+#pragma unroll
+    for (int tg = 1; tg < 8; ++tg)
+      if (lane == tg) A = S.id[tg];
+    t.m2l_off[A] = o[0];
+    t.m2l_cnt[A] = ovf ? 0 : mine[0];
+    t.p2p_off[A] = o[1];
+    t.p2p_cnt[A] = ovf ? 0 : mine[1];
+    t.open_off[A] = o[2];
+    t.open_cnt[A] = ovf ? 0 : mine[2];
+    if (ovf) atomicOr(&h->overflow, bits);
   }
+  if (__ballot(ovf) != 0ull) return;  // lists incomplete; the host regrows and rebuilds
+#pragma unroll
+  for (int tg = 0; tg < 8; ++tg)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) S.off[tg][k] = __shfl(o[k], tg, 64);
+  walk_group<true>(t, l, P, S, L, open_in, open_out, th2, eps, pairs);
   pairs = wave_sum(pairs);
   if (lane == 0 && pairs) atomicAdd(&h->p2p_pairs, pairs);
 }
@@ -233,9 +294,14 @@ hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s) 
   if (a.n <= 0) return hipGetLastError();
   const double th2 = a.theta * a.theta;
   if (a.tm) a.tm->start(PH_WALK, s);
-  for (int l = 0; l <= FMM_MAXLEVEL; ++l)
-    hipLaunchKernelGGL(k_traverse_level, dim3(2048), dim3(TRAV_WAVES * 64), 0, s, t, l, th2,
-                       a.eps);
+  for (int l = 0; l <= a.depth; ++l) {
+    int ps = l == 0 ? 0 : a.lvl_host[l - 1];
+    int pe = l == 0 ? 1 : a.lvl_host[l];
+    int nw = pe - ps;
+    if (nw <= 0) continue;
+    hipLaunchKernelGGL(k_walk_level, dim3((nw + TRAV_WAVES - 1) / TRAV_WAVES),
+                       dim3(TRAV_WAVES * 64), 0, s, t, l, ps, pe, th2, a.eps);
+  }
   if (a.tm) a.tm->stop(s);
   return hipGetLastError();
 }

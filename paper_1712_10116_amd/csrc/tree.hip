@@ -63,14 +63,21 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_bbox_partial(const double *__rest
   if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const double *part, int nblk, int n, Box *box) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(64) void k_bbox_final(const double *part, int nblk, int n, Box *box) {
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nblk; ++b)
+  for (int b = threadIdx.x; b < nblk; b += 64)
     for (int d = 0; d < 3; ++d) {
       lo[d] = fmin(lo[d], part[b * 6 + d]);
       hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
     }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, 64));
+      hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, 64));
+    }
+  if (threadIdx.x != 0) return;
   if (n == 0)
     for (int d = 0; d < 3; ++d) lo[d] = hi[d] = 0.0;
   double c[3], L = 0.0;
@@ -154,37 +161,116 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_sort_hist(const uint64_t *__restr
   hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of m uint32 values in place, one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan_u32_1blk(uint32_t *v, int m) {
-  __shared__ uint32_t part[1024];
-  int per = (m + 1023) / 1024;
-  int b = threadIdx.x * per, e = min(m, b + per);
-  uint32_t s = 0;
-  for (int i = b; i < e; ++i) s += v[i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t y = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+// Per-digit exclusive scan over the blocks: hist[d][0..nblk) in place, digit
+// total to dtot[d].  One workgroup per digit, coalesced tiles of 256.
+__global__ __launch_bounds__(FMM_BLOCK) void k_sort_digit_scan(uint32_t *hist, int nblk,
+                                                               uint32_t *dtot) {
+  __shared__ uint32_t v[FMM_BLOCK];
+  uint32_t *h = hist + (size_t)blockIdx.x * nblk;
+  uint32_t run = 0;
+  for (int base = 0; base < nblk; base += FMM_BLOCK) {
+    int i = base + threadIdx.x;
+    uint32_t x = i < nblk ? h[i] : 0u;
+    v[threadIdx.x] = x;
     __syncthreads();
-    part[threadIdx.x] += y;
+    for (int off = 1; off < FMM_BLOCK; off <<= 1) {
+      uint32_t y = threadIdx.x >= off ? v[threadIdx.x - off] : 0u;
+      __syncthreads();
+      v[threadIdx.x] += y;
+      __syncthreads();
+    }
+    if (i < nblk) h[i] = run + v[threadIdx.x] - x;
+    run += v[FMM_BLOCK - 1];
     __syncthreads();
   }
-  uint32_t run = part[threadIdx.x] - s;
-  for (int i = b; i < e; ++i) {
-    uint32_t x = v[i];
-    v[i] = run;
-    run += x;
+  if (threadIdx.x == 0) dtot[blockIdx.x] = run;
+}
+
+// Generic exclusive scan of m uint32 values (three launches, any m):
+// block sums, scan of the block sums, block-local scans plus offsets.
+#define SCAN_TILE 1024
+__global__ __launch_bounds__(FMM_BLOCK) void k_scan_reduce(const uint32_t *v, int m, uint32_t *part) {
+  __shared__ uint32_t r[FMM_BLOCK];
+  int base = blockIdx.x * SCAN_TILE;
+  uint32_t s = 0;
+  for (int i = base + threadIdx.x; i < min(m, base + SCAN_TILE); i += FMM_BLOCK) s += v[i];
+  r[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = FMM_BLOCK / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) r[threadIdx.x] += r[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = r[0];
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_scan_partials(uint32_t *part, int nb) {
+  __shared__ uint32_t v[FMM_BLOCK];
+  uint32_t run = 0;
+  for (int base = 0; base < nb; base += FMM_BLOCK) {
+    int i = base + threadIdx.x;
+    uint32_t x = i < nb ? part[i] : 0u;
+    v[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < FMM_BLOCK; off <<= 1) {
+      uint32_t y = threadIdx.x >= off ? v[threadIdx.x - off] : 0u;
+      __syncthreads();
+      v[threadIdx.x] += y;
+      __syncthreads();
+    }
+    if (i < nb) part[i] = run + v[threadIdx.x] - x;
+    run += v[FMM_BLOCK - 1];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_scan_down(uint32_t *v, int m, const uint32_t *part) {
+  __shared__ uint32_t w[FMM_BLOCK];
+  const int base = blockIdx.x * SCAN_TILE + threadIdx.x * 4;
+  uint32_t x[4], s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    x[k] = base + k < m ? v[base + k] : 0u;
+    s += x[k];
+  }
+  w[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < FMM_BLOCK; off <<= 1) {
+    uint32_t y = threadIdx.x >= off ? w[threadIdx.x - off] : 0u;
+    __syncthreads();
+    w[threadIdx.x] += y;
+    __syncthreads();
+  }
+  uint32_t run = part[blockIdx.x] + w[threadIdx.x] - s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < m) v[base + k] = run;
+    run += x[k];
   }
 }
 
 __global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const int32_t *__restrict__ sin, uint64_t *__restrict__ kout,
-    int32_t *__restrict__ sout, int n, int shift, const uint32_t *__restrict__ hist, int nblk) {
+    int32_t *__restrict__ sout, int n, int shift, const uint32_t *__restrict__ hist, int nblk,
+    const uint32_t *__restrict__ dtot) {
   __shared__ uint32_t cnt[SORT_WAVES][256];
   __shared__ uint32_t goff[256];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int d = threadIdx.x; d < SORT_WAVES * 256; d += FMM_BLOCK) (&cnt[0][0])[d] = 0;
-  goff[threadIdx.x] = hist[threadIdx.x * nblk + blockIdx.x];
+  // digit base = exclusive scan of the digit totals
+  {
+    uint32_t x = dtot[threadIdx.x];
+    goff[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      uint32_t y = threadIdx.x >= off ? goff[threadIdx.x - off] : 0u;
+      __syncthreads();
+      goff[threadIdx.x] += y;
+      __syncthreads();
+    }
+    uint32_t base = goff[threadIdx.x] - x;
+    __syncthreads();
+    goff[threadIdx.x] = base + hist[threadIdx.x * nblk + blockIdx.x];
+  }
   __syncthreads();
   const int base = blockIdx.x * SORT_TILE + w * 64 * SORT_ITEMS;
   uint64_t k[SORT_ITEMS];
@@ -237,6 +323,21 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
   }
 }
 
+// deepest level at which two neighbouring sorted keys still share a cell:
+// no cell deeper than that + 1 can hold two particles, so the split stops there
+__global__ __launch_bounds__(FMM_BLOCK) void k_max_common_prefix(const uint64_t *__restrict__ key,
+                                                                 int n, Header *hdr) {
+  int best = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += gridDim.x * blockDim.x) {
+    uint64_t x = key[i] ^ key[i + 1];
+    int digits = x == 0 ? FMM_MAXLEVEL : (__clzll(x) - 1) / 3;
+    best = max(best, digits);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off, 64));
+  if ((threadIdx.x & 63) == 0 && best > 0) atomicMax(&hdr->max_prefix, best);
+}
+
 // ---------------------------------------------------------------------------
 // sorted particle data
 // ---------------------------------------------------------------------------
@@ -275,6 +376,7 @@ __global__ void k_tree_init(DevTree t, int n) {
   for (int l = 1; l < FMM_NLEVELS + 2; ++l) h->lvl_start[l] = root;
   h->overflow = 0;
   h->n_leaves = 0;
+  h->max_prefix = 0;
   if (n > 0) {
     t.nbeg[0] = 0;
     t.nend[0] = n;
@@ -424,7 +526,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_mark_leaves(DevTree t) {
   if ((threadIdx.x & 63) == 0 && leaves) atomicAdd((int *)&t.hdr->n_leaves, leaves);
 }
 
-hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s) {
+hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
   const int n = a.n;
   int nb = (n + FMM_BLOCK - 1) / FMM_BLOCK;
   int nbb = nb < FMM_SCAN_BLOCKS ? (nb > 0 ? nb : 1) : FMM_SCAN_BLOCKS;
@@ -432,6 +534,7 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s
   hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(FMM_BLOCK), 0, s, a.pos, a.n_total, a.active,
                      n, t.bbox_part, t.hdr);
   hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, t.bbox_part, nbb, n, t.box);
+  hipLaunchKernelGGL(k_tree_init, dim3(1), dim3(64), 0, s, t, n);
   if (n > 0) {
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(FMM_BLOCK), 0, s, a.pos, a.n_total, a.active, n,
                        t.box, t.key, t.slot);
@@ -442,22 +545,27 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s
       int shift = pass * 8;
       hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, n, shift,
                          t.sort_hist, nblk);
-      hipLaunchKernelGGL(k_scan_u32_1blk, dim3(1), dim3(1024), 0, s, t.sort_hist, 256 * nblk);
+      hipLaunchKernelGGL(k_sort_digit_scan, dim3(256), dim3(FMM_BLOCK), 0, s, t.sort_hist, nblk,
+                         t.sort_dtot);
       hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, sin, kout, sout,
-                         n, shift, t.sort_hist, nblk);
+                         n, shift, t.sort_hist, nblk, t.sort_dtot);
       uint64_t *tk = kin; kin = kout; kout = tk;
       int32_t *ts = sin; sin = sout; sout = ts;
     }
     hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(FMM_BLOCK), 0, s, t, a.pos, a.n_total,
                        a.active, n);
+    hipLaunchKernelGGL(k_max_common_prefix, dim3(nbb), dim3(FMM_BLOCK), 0, s, t.key, n, t.hdr);
   }
-  if (a.tm) {
-    a.tm->stop(s);
-    a.tm->start(PH_TREE, s);
-  }
-  hipLaunchKernelGGL(k_tree_init, dim3(1), dim3(64), 0, s, t, n);
+  if (a.tm) a.tm->stop(s);
+  return hipGetLastError();
+}
+
+// levels 0 .. max_level-1 are split (cells of level max_level are leaves)
+hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, int max_level, hipStream_t s) {
+  const int n = a.n;
+  if (a.tm) a.tm->start(PH_TREE, s);
   if (n > 0) {
-    for (int l = 0; l < FMM_MAXLEVEL; ++l) {
+    for (int l = 0; l < max_level && l < FMM_MAXLEVEL; ++l) {
       hipLaunchKernelGGL(k_tree_count, dim3(FMM_SCAN_BLOCKS), dim3(FMM_BLOCK), 0, s, t, l,
                          a.leaf_size);
       hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(FMM_SCAN_BLOCKS), 0, s, t, l);
@@ -469,6 +577,10 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, hipStream_t s
   return hipGetLastError();
 }
 
-void hhs_launch_scan_u32(uint32_t *v, int m, hipStream_t s) {
-  if (m > 0) hipLaunchKernelGGL(k_scan_u32_1blk, dim3(1), dim3(1024), 0, s, v, m);
+void hhs_launch_scan_u32(uint32_t *v, int m, uint32_t *part, hipStream_t s) {
+  if (m <= 0) return;
+  const int nb = (m + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(FMM_BLOCK), 0, s, v, m, part);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(FMM_BLOCK), 0, s, part, nb);
+  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(FMM_BLOCK), 0, s, v, m, part);
 }
