@@ -205,8 +205,11 @@ __global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l
   WaveLds &L = lds[w];
   Sibs S;
   if (l == 0) {
+    // the root is the only target; every sibling slot must hold a valid id
+    // because the slots are read below before the S.n guard applies
     S.n = 1;
-    S.id[0] = 0;
+#pragma unroll
+    for (int tg = 0; tg < 8; ++tg) S.id[tg] = 0;
   } else {
     const int nc = t.nnchild[P];
     if (nc == 0) return;
