@@ -219,12 +219,42 @@ struct PairKernel {
   }
 };
 
+// One wavefront per target leaf A.  The particles of every leaf in A's P2P
+// list (A itself included) are staged into LDS as one flattened stream --
+// FP32 offsets from A's centre in the mixed form, absolute FP64 positions in
+// the FP64 form -- in windows of SRC particles.  Lanes = (target particle,
+// phase): LP = smallest power of two >= n_A lanes per phase, 64/LP phases each
+// taking every (64/LP)-th source of the window.  FP32 partial sums are added
+// into FP64 accumulators every 8 sources.  The self term is excluded by its
+// position in the stream (coincident distinct particles still interact).
+#define P2P_WAVES 4
+
+template <bool MIXED>
+struct P2PTypes;
+template <>
+struct P2PTypes<true> {
+  typedef float R;
+  typedef float4 R4;
+  static constexpr int SRC = 512;
+};
+template <>
+struct P2PTypes<false> {
+  typedef double R;
+  typedef double4 R4;
+  static constexpr int SRC = 256;
+};
+
 template <bool MIXED, int KERNEL>
-__global__ __launch_bounds__(FMM_BLOCK) void k_p2p(DevTree t, int n_nodes, double eps) {
-  typedef typename std::conditional<MIXED, float, double>::type R;
+__global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, double eps) {
+  typedef typename P2PTypes<MIXED>::R R;
+  typedef typename P2PTypes<MIXED>::R4 R4;
+  constexpr int SRC = P2PTypes<MIXED>::SRC;
+  __shared__ R4 src_all[P2P_WAVES][SRC];
   const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const int w = threadIdx.x >> 6;
+  R4 *src = src_all[w];
+  const int wave = blockIdx.x * P2P_WAVES + w;
+  const int nwaves = gridDim.x * P2P_WAVES;
   const R eps2 = (R)(eps * eps);
   const R inv_eps = eps > 0 ? (R)(1.0 / eps) : R(0);
   const R inv_eps3 = eps > 0 ? (R)(1.0 / (eps * eps * eps)) : R(0);
@@ -232,9 +262,12 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p(DevTree t, int n_nodes, doubl
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (t.nnchild[A] != 0) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
-    const int LP = nA <= 16 ? 16 : (nA <= 32 ? 32 : 64);
-    const int nph = 64 / LP;
-    const int ph = lane / LP, ti = lane % LP;
+    const int nt = nA < 64 ? nA : 64;
+    int lg = 0;
+    while ((1 << lg) < nt) ++lg;
+    const int LP = 1 << lg;           // lanes per phase
+    const int nph = 64 >> lg;         // phases
+    const int ph = lane >> lg, ti = lane & (LP - 1);
     const double4 gA = t.ngeo[A];
     const int off = t.p2p_off[A], cnt = t.p2p_cnt[A];
     for (int tb = 0; tb < nA; tb += LP) {
@@ -243,52 +276,77 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p(DevTree t, int n_nodes, doubl
       const int gi = bA + (vi ? i : 0);
       R xi, yi, zi;
       if (MIXED) {
-        xi = t.lx[gi]; yi = t.ly[gi]; zi = t.lz[gi];
+        xi = (R)(t.sx[gi] - gA.x);
+        yi = (R)(t.sy[gi] - gA.y);
+        zi = (R)(t.sz[gi] - gA.z);
       } else {
-        xi = t.sx[gi]; yi = t.sy[gi]; zi = t.sz[gi];
+        xi = t.sx[gi];
+        yi = t.sy[gi];
+        zi = t.sz[gi];
       }
       double ax = 0, ay = 0, az = 0, pp = 0;
-      for (int q = 0; q < cnt; ++q) {
-        const int B = t.p2p_src[off + q];
-        const int bB = t.nbeg[B], nB = t.nend[B] - bB;
-        R ox = 0, oy = 0, oz = 0;
-        if (MIXED) {
-          const double4 gB = t.ngeo[B];
-          ox = (R)(gB.x - gA.x);
-          oy = (R)(gB.y - gA.y);
-          oz = (R)(gB.z - gA.z);
-        }
-        R sx = 0, sy = 0, sz = 0, sp = 0;
-        for (int jj = ph; jj < nB; jj += nph) {
-          const int gj = bB + jj;
-          R dx, dy, dz, mj;
-          if (MIXED) {
-            dx = (t.lx[gj] - xi) + ox;
-            dy = (t.ly[gj] - yi) + oy;
-            dz = (t.lz[gj] - zi) + oz;
-            mj = t.sm32[gj];
-          } else {
-            dx = t.sx[gj] - xi;
-            dy = t.sy[gj] - yi;
-            dz = t.sz[gj] - zi;
-            mj = t.sm[gj];
+      for (int qb = 0; qb < cnt; qb += 64) {
+        const int q = qb + lane;
+        const bool vq = q < cnt;
+        const int B = vq ? t.p2p_src[off + q] : A;
+        const int bB = t.nbeg[B];
+        const int nb = vq ? t.nend[B] - bB : 0;
+        int total;
+        const int pos = wave_excl_scan_int(nb, &total);
+        const unsigned long long selfm = __ballot(vq && B == A);
+        const int self_lane = selfm ? (int)__ffsll((long long)selfm) - 1 : 0;
+        const int self_start = selfm ? __shfl(pos, self_lane, 64) : -(1 << 30);
+        for (int w0 = 0; w0 < total; w0 += SRC) {
+          const int W = min(SRC, total - w0);
+          const int k0 = max(0, w0 - pos), k1 = min(nb, w0 + W - pos);
+          for (int k = k0; k < k1; ++k) {
+            const int j = bB + k;
+            R4 v;
+            if (MIXED) {
+              v.x = (R)(t.sx[j] - gA.x);
+              v.y = (R)(t.sy[j] - gA.y);
+              v.z = (R)(t.sz[j] - gA.z);
+              v.w = t.sm32[j];
+            } else {
+              v.x = t.sx[j];
+              v.y = t.sy[j];
+              v.z = t.sz[j];
+              v.w = t.sm[j];
+            }
+            src[pos + k - w0] = v;
           }
-          const bool self = gj == gi;
-          R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-          r2 = self ? R(1) : r2;
-          mj = self ? R(0) : mj;
-          R g, phi;
-          PairKernel<R, KERNEL>::eval(r2, eps2, inv_eps, inv_eps3, g, phi);
-          const R mg = mj * g;
-          sx = fma(mg, dx, sx);
-          sy = fma(mg, dy, sy);
-          sz = fma(mg, dz, sz);
-          sp = fma(mj, phi, sp);
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          const int self_idx = self_start + i - w0;
+          for (int f0 = ph; f0 < W; f0 += 8 * nph) {
+            R sx = 0, sy = 0, sz = 0, sp = 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const int f = f0 + u * nph;
+              if (f < W) {
+                const R4 sv = src[f];
+                const R dx = sv.x - xi, dy = sv.y - yi, dz = sv.z - zi;
+                const bool self = f == self_idx;
+                R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                r2 = self ? R(1) : r2;
+                const R mj = self ? R(0) : sv.w;
+                R g, phi;
+                PairKernel<R, KERNEL>::eval(r2, eps2, inv_eps, inv_eps3, g, phi);
+                const R mg = mj * g;
+                sx = fma(mg, dx, sx);
+                sy = fma(mg, dy, sy);
+                sz = fma(mg, dz, sz);
+                sp = fma(mj, phi, sp);
+              }
+            }
+            ax += (double)sx;
+            ay += (double)sy;
+            az += (double)sz;
+            pp += (double)sp;
+          }
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
-        ax += (double)sx;
-        ay += (double)sy;
-        az += (double)sz;
-        pp += (double)sp;
       }
       for (int o = LP; o < 64; o <<= 1) {
         ax += __shfl_xor(ax, o, 64);
@@ -340,8 +398,8 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
     tm->stop(s);
     tm->start(PH_P2P, s);
   }
-  hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL>), dim3(wave_blocks), dim3(FMM_BLOCK), 0, s,
-                     t, nn, e.eps);
+  hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL>), dim3((nn + P2P_WAVES - 1) / P2P_WAVES),
+                     dim3(P2P_WAVES * 64), 0, s, t, nn, e.eps);
   if (tm) {
     tm->stop(s);
     tm->start(PH_DOWN, s);

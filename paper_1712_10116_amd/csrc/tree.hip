@@ -506,24 +506,28 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l) {
   }
 }
 
-// leaf id and FP32 cell-local offsets of every particle
+// leaf id and FP32 cell-local offsets of every particle: one wavefront per
+// leaf, lanes over its particles
 __global__ __launch_bounds__(FMM_BLOCK) void k_mark_leaves(DevTree t) {
   const Header *h = t.hdr;
-  int nn = min((int)t.cap_nodes, h->lvl_start[FMM_NLEVELS]);
+  const int nn = min((int)t.cap_nodes, h->lvl_start[FMM_NLEVELS]);
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
   int leaves = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += gridDim.x * blockDim.x) {
+  for (int i = wave; i < nn; i += nwaves) {
     if (t.nnchild[i] != 0) continue;
     ++leaves;
-    double4 g = t.ngeo[i];
-    for (int j = t.nbeg[i]; j < t.nend[i]; ++j) {
+    const double4 g = t.ngeo[i];
+    const int e = t.nend[i];
+    for (int j = t.nbeg[i] + lane; j < e; j += 64) {
       t.leaf_of[j] = i;
       t.lx[j] = (float)(t.sx[j] - g.x);
       t.ly[j] = (float)(t.sy[j] - g.y);
       t.lz[j] = (float)(t.sz[j] - g.z);
     }
   }
-  leaves = wave_sum(leaves);
-  if ((threadIdx.x & 63) == 0 && leaves) atomicAdd((int *)&t.hdr->n_leaves, leaves);
+  if (lane == 0 && leaves) atomicAdd((int *)&t.hdr->n_leaves, leaves);
 }
 
 hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
