@@ -107,6 +107,43 @@ __device__ __forceinline__ void push_children(const DevTree &t, WaveLds &L, int 
   sp += total;
 }
 
+// Descents of leaf targets into non-leaf candidates, LIFO.  Each popped cell
+// pushes at most 8 children, so popping take <= (TRAV_STACK - sp) / 7 items
+// can never overflow the stack; take is 64 whenever there is room.
+template <bool WRITE>
+__device__ void drain(const DevTree &t, Sibs &S, WaveLds &L, int &sp, int *open_out, double th2,
+                      double eps, unsigned long long &pairs) {
+  const int lane = __lane_id();
+  while (sp > 0) {
+    const int room = (TRAV_STACK - sp) / 7;
+    const int take = min(sp, max(1, min(64, room)));
+    const bool valid = lane < take;
+    const int item = valid ? L.stack[sp - take + lane] : 0;
+    __builtin_amdgcn_wave_barrier();
+    sp -= take;
+    const int tgl = item >> TRAV_TAG;
+    const int C = item & ((1 << TRAV_TAG) - 1);
+    double4 gC = make_double4(0, 0, 0, 0);
+    int nC = 0, npC = 0;
+    if (valid) {
+      gC = t.ngeo[C];
+      nC = t.nnchild[C];
+      npC = t.nend[C] - t.nbeg[C];
+    }
+#pragma unroll
+    for (int tg = 0; tg < 8; ++tg) {
+      if (tg < S.n) {
+        const bool mine = valid && tgl == tg;
+        const int cat = mine ? classify(S.id[tg], L.geo[tg], S.leaf[tg], C, gC, nC == 0, th2, eps)
+                             : CAT_NONE;
+        emit<WRITE>(t, S, tg, cat, mine, C, npC, open_out, pairs);
+        push_children(t, L, sp, cat == CAT_DEEPEN, tg, C, nC);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // One pass over the candidates of a sibling group (pass 0 counts, pass 1 writes).
 template <bool WRITE>
 __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
@@ -156,40 +193,17 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
                                            eps)
                                 : CAT_NONE;
           emit<WRITE>(t, S, tg, cat, valid, C, npC, open_out, pairs);
-          if (S.leaf[tg]) push_children(t, L, sp, cat == CAT_DEEPEN, tg, C, nC);
+          if (S.leaf[tg]) {
+            // one chunk pushes at most 8 x 64 children for this target
+            if (sp > TRAV_STACK - 512) drain<WRITE>(t, S, L, sp, open_out, th2, eps, pairs);
+            push_children(t, L, sp, cat == CAT_DEEPEN, tg, C, nC);
+          }
         }
       }
     }
     __builtin_amdgcn_wave_barrier();
   }
-  // descents of leaf targets into non-leaf candidates (LIFO, 64 at a time)
-  while (sp > 0) {
-    const int take = min(sp, 64);
-    const bool valid = lane < take;
-    const int item = valid ? L.stack[sp - take + lane] : 0;
-    __builtin_amdgcn_wave_barrier();
-    sp -= take;
-    const int tgl = item >> TRAV_TAG;
-    const int C = item & ((1 << TRAV_TAG) - 1);
-    double4 gC = make_double4(0, 0, 0, 0);
-    int nC = 0, npC = 0;
-    if (valid) {
-      gC = t.ngeo[C];
-      nC = t.nnchild[C];
-      npC = t.nend[C] - t.nbeg[C];
-    }
-#pragma unroll
-    for (int tg = 0; tg < 8; ++tg) {
-      if (tg < S.n) {
-        const bool mine = valid && tgl == tg;
-        const int cat = mine ? classify(S.id[tg], L.geo[tg], S.leaf[tg], C, gC, nC == 0, th2, eps)
-                             : CAT_NONE;
-        emit<WRITE>(t, S, tg, cat, mine, C, npC, open_out, pairs);
-        push_children(t, L, sp, cat == CAT_DEEPEN, tg, C, nC);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
+  drain<WRITE>(t, S, L, sp, open_out, th2, eps, pairs);
 }
 
 // Level l >= 1: one wavefront per cell P of level l-1 with children; the
