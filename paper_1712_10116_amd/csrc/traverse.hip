@@ -26,7 +26,7 @@
 
 #define TRAV_WAVES 4
 #define TRAV_CAND 512   // expanded candidates of one block of 64 open-list entries
-#define TRAV_STACK 2048 // descent stack (target tag in the top 3 bits)
+#define TRAV_STACK 2048 // descent items (target tag in the top 3 bits)
 #define TRAV_TAG 28
 
 enum { CAT_NONE = 0, CAT_M2L = 1, CAT_P2P = 2, CAT_OPEN = 3, CAT_DEEPEN = 4 };
@@ -63,8 +63,9 @@ struct Sibs {
 };
 
 struct WaveLds {
-  int cand[TRAV_CAND];
-  int stack[TRAV_STACK];
+  int cand[TRAV_CAND];   // candidates expanded from a block of open-list entries
+  int dcand[TRAV_CAND];  // children of popped descent items
+  int stack[TRAV_STACK]; // descent items: (target tag << TRAV_TAG) | cell
   double4 geo[8];
 };
 
@@ -89,27 +90,22 @@ __device__ __forceinline__ void emit(const DevTree &t, Sibs &S, int tg, int cat,
   S.cnt[tg][2] += __popcll(bo);
 }
 
-// push the children of C (tagged with target tg) for lanes that descend
-__device__ __forceinline__ void push_children(const DevTree &t, WaveLds &L, int &sp, bool push,
-                                              int tg, int C, int nC) {
-  int k = push ? nC : 0;
-  int total;
-  int pos = wave_excl_scan_int(k, &total);
-  if (total == 0) return;
-  if (sp + total > TRAV_STACK) {
+// push (tg, C) for every lane whose leaf target descends into C
+__device__ __forceinline__ void push_item(const DevTree &t, WaveLds &L, int &sp, bool push, int tg,
+                                          int C) {
+  const unsigned long long m = __ballot(push);
+  const int k = __popcll(m);
+  if (sp + k > TRAV_STACK) {  // cannot happen (see drain); kept as a guard
     if (__lane_id() == 0) atomicOr(&t.hdr->overflow, OVF_STACK);
-    return;  // descent dropped; the build reports the overflow
+    return;
   }
-  if (k) {
-    int c0 = t.nchild0[C];
-    for (int q = 0; q < k; ++q) L.stack[sp + pos + q] = (tg << TRAV_TAG) | (c0 + q);
-  }
-  sp += total;
+  if (push) L.stack[sp + __popcll(m & lanes_below_mask())] = (tg << TRAV_TAG) | C;
+  sp += k;
 }
 
-// Descents of leaf targets into non-leaf candidates, LIFO.  Each popped cell
-// pushes at most 8 children, so popping take <= (TRAV_STACK - sp) / 7 items
-// can never overflow the stack; take is 64 whenever there is room.
+// Descents of leaf targets into non-leaf cells, LIFO.  A popped item (tg, C)
+// makes the children of C candidates of target tg; each may push one item,
+// so popping take <= (TRAV_STACK - sp) / 7 items can never overflow.
 template <bool WRITE>
 __device__ void drain(const DevTree &t, Sibs &S, WaveLds &L, int &sp, int *open_out, double th2,
                       double eps, unsigned long long &pairs) {
@@ -117,27 +113,40 @@ __device__ void drain(const DevTree &t, Sibs &S, WaveLds &L, int &sp, int *open_
   while (sp > 0) {
     const int room = (TRAV_STACK - sp) / 7;
     const int take = min(sp, max(1, min(64, room)));
-    const bool valid = lane < take;
-    const int item = valid ? L.stack[sp - take + lane] : 0;
+    const bool vp = lane < take;
+    const int item = vp ? L.stack[sp - take + lane] : 0;
     __builtin_amdgcn_wave_barrier();
     sp -= take;
-    const int tgl = item >> TRAV_TAG;
-    const int C = item & ((1 << TRAV_TAG) - 1);
-    double4 gC = make_double4(0, 0, 0, 0);
-    int nC = 0, npC = 0;
-    if (valid) {
-      gC = t.ngeo[C];
-      nC = t.nnchild[C];
-      npC = t.nend[C] - t.nbeg[C];
-    }
+    const int tgi = item >> TRAV_TAG;
+    const int Ci = item & ((1 << TRAV_TAG) - 1);
+    const int nCi = vp ? t.nnchild[Ci] : 0;
+    const int c0 = vp ? t.nchild0[Ci] : 0;
+    int total;
+    const int pos = wave_excl_scan_int(nCi, &total);
+    for (int q = 0; q < nCi; ++q) L.dcand[pos + q] = (tgi << TRAV_TAG) | (c0 + q);
+    __builtin_amdgcn_wave_barrier();
+    for (int cb = 0; cb < total; cb += 64) {
+      const bool valid = cb + lane < total;
+      const int it = valid ? L.dcand[cb + lane] : 0;
+      const int tgl = it >> TRAV_TAG;
+      const int C = it & ((1 << TRAV_TAG) - 1);
+      double4 gC = make_double4(0, 0, 0, 0);
+      int nC = 0, npC = 0;
+      if (valid) {
+        gC = t.ngeo[C];
+        nC = t.nnchild[C];
+        npC = t.nend[C] - t.nbeg[C];
+      }
 #pragma unroll
-    for (int tg = 0; tg < 8; ++tg) {
-      if (tg < S.n) {
-        const bool mine = valid && tgl == tg;
-        const int cat = mine ? classify(S.id[tg], L.geo[tg], S.leaf[tg], C, gC, nC == 0, th2, eps)
-                             : CAT_NONE;
-        emit<WRITE>(t, S, tg, cat, mine, C, npC, open_out, pairs);
-        push_children(t, L, sp, cat == CAT_DEEPEN, tg, C, nC);
+      for (int tg = 0; tg < 8; ++tg) {
+        if (tg < S.n) {
+          const bool mine = valid && tgl == tg;
+          const int cat = mine ? classify(S.id[tg], L.geo[tg], S.leaf[tg], C, gC, nC == 0, th2,
+                                          eps)
+                               : CAT_NONE;
+          emit<WRITE>(t, S, tg, cat, mine, C, npC, open_out, pairs);
+          push_item(t, L, sp, cat == CAT_DEEPEN, tg, C);
+        }
       }
     }
     __builtin_amdgcn_wave_barrier();
@@ -177,6 +186,8 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
     for (int q = 0; q < ec; ++q) L.cand[pos + q] = c0 + q;
     __builtin_amdgcn_wave_barrier();
     for (int cb = 0; cb < total; cb += 64) {
+      // a chunk pushes at most 64 items per target, 512 in all
+      if (sp > TRAV_STACK - 512) drain<WRITE>(t, S, L, sp, open_out, th2, eps, pairs);
       const bool valid = cb + lane < total;
       const int C = valid ? L.cand[cb + lane] : 0;
       double4 gC = make_double4(0, 0, 0, 0);
@@ -193,11 +204,7 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
                                            eps)
                                 : CAT_NONE;
           emit<WRITE>(t, S, tg, cat, valid, C, npC, open_out, pairs);
-          if (S.leaf[tg]) {
-            // one chunk pushes at most 8 x 64 children for this target
-            if (sp > TRAV_STACK - 512) drain<WRITE>(t, S, L, sp, open_out, th2, eps, pairs);
-            push_children(t, L, sp, cat == CAT_DEEPEN, tg, C, nC);
-          }
+          if (S.leaf[tg]) push_item(t, L, sp, cat == CAT_DEEPEN, tg, C);
         }
       }
     }
