@@ -70,20 +70,63 @@ def time_solver(F, torch, s, tp, tm, acc, pot, prm, steps, warmup, profile):
     return (t1 - t0) / steps, phases
 
 
+def cpu_leg(args, n, pos, mass, res, line):
+    """CPU side: the oracle timed on a bounded sample of the same workload, and
+    FP64 direct summation (oracle) on seeded sinks as the force-error reference
+    for the GPU results."""
+    from oracle import oracle as O
+    from paper_1712_10116_amd import workloads as W
+    rng = np.random.default_rng(2024)
+    sinks = np.sort(rng.choice(n, size=min(args.sample, n), replace=False))
+    ref, _ = O.direct(pos, mass, O.WENDLAND, 0.005, sinks=sinks)
+    for name, r in res.items():
+        e = force_error(r["acc"][:, sinks], ref)
+        line["force_err"][f"{name}_vs_direct"] = {"rms": e[0], "p99": e[1], "p": r["p"]}
+    line["force_err"]["sinks"] = int(len(sinks))
+    ns = min(args.cpu_sample, n)
+    spos, _, smass = W.uniform_sphere(ns, seed=1001)
+    kw = dict(p=args.p, theta=args.theta, eps=0.005, leaf_size=args.leaf, kernel=O.WENDLAND)
+    t0 = time.perf_counter()
+    O.fmm(spos, smass, **kw)
+    t1 = time.perf_counter()
+    line["cpu_baseline"] = {"value": round(ns / (t1 - t0), 1), "unit": "particles/s", "cores": 1,
+                            "kind": "oracle",
+                            "sample": f"one oracle FMM force solve (FP64, single thread, p={args.p}, "
+                                      f"theta={args.theta}, leaf {args.leaf}) on a {ns}-particle "
+                                      f"uniform sphere of the same recipe, {t1 - t0:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 20)
+    # the workload names theta = 0.5, p = 4; at N = 2^20 that gives ~2e-3 rms force
+    # error, so the headline uses the cheapest setting measured to reach the
+    # metric's 1e-3 (theta = 0.5, p = 5, leaf 32); the named p = 4 is reported beside it
     ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--p", type=int, default=4)
-    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--p", type=int, default=5)
+    ap.add_argument("--leaf", type=int, default=32)
+    ap.add_argument("--config-p", type=int, default=4, help="order named by the workload")
     ap.add_argument("--sample", type=int, default=2048, help="sinks checked against direct sum")
     ap.add_argument("--cpu-sample", type=int, default=262144, help="particles in the CPU oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hhs", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times) and exit; used to "
+                         "scale the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the FMM solve here is a single-device path)", file=sys.stderr)
@@ -101,29 +144,27 @@ def main():
     tm = torch.from_numpy(mass).to(dev)
     out = {}
     res = {}
-    for name, prec in (("mixed", F.MIXED), ("fp64", F.FP64)):
-        s = F.Solver(n, p_max=args.p, leaf_size=args.leaf, kernel=F.WENDLAND, precision=prec)
+    runs = [("mixed", F.MIXED, args.p), ("fp64", F.FP64, args.p)]
+    if args.config_p != args.p:
+        runs.append(("mixed_config_p", F.MIXED, args.config_p))
+    for name, prec, pp in runs:
+        prm = dict(prm, p=pp)
+        s = F.Solver(n, p_max=pp, leaf_size=args.leaf, kernel=F.WENDLAND, precision=prec)
         acc = torch.empty((3, n), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev)
         sec, phases = time_solver(F, torch, s, tp, tm, acc, pot, prm, args.steps, args.warmup,
                                   profile=True)
         info = s.tree_info()
         inv = s.invariants(mass=tm, acc=acc)
-        res[name] = dict(sec=sec, phases=phases, info=info, acc=acc.cpu().numpy(),
+        res[name] = dict(sec=sec, phases=phases, info=info, acc=acc.cpu().numpy(), p=pp,
                          momentum=float(np.abs(inv["F"]).max() / inv["Fabs"]))
         s.close()
         del acc, pot
         torch.cuda.synchronize()
 
-    # accuracy against FP64 direct summation (CPU oracle) on a seeded sample
-    from oracle import oracle as O
-    rng = np.random.default_rng(2024)
-    sinks = np.sort(rng.choice(n, size=min(args.sample, n), replace=False))
-    ref, _ = O.direct(pos, mass, O.WENDLAND, prm["eps"], sinks=sinks)
-    err = {k: force_error(res[k]["acc"][:, sinks], ref) for k in res}
-    e_mf = force_error(res["mixed"]["acc"], res["fp64"]["acc"])
-
+    prm = dict(prm, p=args.p)
     mixed, fp64 = res["mixed"], res["fp64"]
+    e_mf = force_error(mixed["acc"], fp64["acc"])
     ph = mixed["phases"]
     info = mixed["info"]
     steps = args.steps
@@ -158,10 +199,7 @@ def main():
                    "n": n, "p": args.p, "theta": args.theta, "eps": 0.005, "leaf_size": args.leaf,
                    "parallelism": "single GPU"},
         "roofline": roof,
-        "force_err": {"mixed_vs_direct": {"rms": err["mixed"][0], "p99": err["mixed"][1]},
-                      "fp64_vs_direct": {"rms": err["fp64"][0], "p99": err["fp64"][1]},
-                      "mixed_vs_fp64_gpu": {"rms": e_mf[0], "p99": e_mf[1]},
-                      "sinks": int(len(sinks))},
+        "force_err": {"mixed_vs_fp64_gpu": {"rms": e_mf[0], "p99": e_mf[1]}},
         "fp64": {"value": round(n / fp64["sec"], 1), "ms_per_step": round(fp64["sec"] * 1e3, 4),
                  "phases_ms": {k: round(v[0] / steps, 4) for k, v in fp64["phases"].items()}},
         "momentum_rel": {"mixed": mixed["momentum"], "fp64": fp64["momentum"]},
@@ -196,18 +234,13 @@ def main():
         s.close()
         del a
 
+    if "mixed_config_p" in res:
+        r = res["mixed_config_p"]
+        line["config_order"] = {"p": r["p"], "value": round(n / r["sec"], 1),
+                                "ms_per_step": round(r["sec"] * 1e3, 4)}
+
     if not args.no_cpu_baseline:
-        ns = min(args.cpu_sample, n)
-        spos, _, smass = W.uniform_sphere(ns, seed=1001)
-        kw = dict(p=args.p, theta=args.theta, eps=0.005, leaf_size=args.leaf, kernel=O.WENDLAND)
-        t0 = time.perf_counter()
-        O.fmm(spos, smass, **kw)
-        t1 = time.perf_counter()
-        line["cpu_baseline"] = {"value": round(ns / (t1 - t0), 1), "unit": "particles/s", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"one oracle FMM force solve (FP64, single thread) on a "
-                                          f"{ns}-particle uniform sphere of the same recipe, "
-                                          f"{t1 - t0:.1f} s"}
+        cpu_leg(args, n, pos, mass, res, line)
     print(json.dumps(line))
 
 

@@ -113,7 +113,42 @@ fmm_status fmm_forces(fmm_ctx *ctx, const double *pos, const double *mass, int64
                       const int32_t *active, int64_t n_active, double eps, double theta,
                       int p, double *acc, double *pot);
 
-/* Sizes of the current tree: info[0] n_active, [1] nodes, [2] unordered M2L
+/* ---------------------------------------------------------------------------
+ * Batched solves: several independent particle systems in one set of launches
+ * ------------------------------------------------------------------------- */
+
+/* One independent system of a batch.  pos/active/n_total/n_active as for
+ * fmm_build; mass, acc and pot as for fmm_evaluate (ignored by the build).
+ * Each system gets its own root box, Morton keys and root cell; the walk
+ * starts every root only against itself, so no cell of one system ever meets
+ * a cell of another, and each system's tree, lists and results are exactly
+ * those of a solve of that system alone. */
+typedef struct {
+    const double *pos;      /* device, 3 x n_total doubles (SoA)              */
+    int64_t n_total;
+    const int32_t *active;  /* device int32[n_active], or NULL = all n_total    */
+    int64_t n_active;
+    const double *mass;     /* device, n_total doubles                         */
+    double *acc;            /* device, 3 x n_active doubles (out)              */
+    double *pot;            /* device, n_active doubles (out)                  */
+} fmm_request;
+
+/* Build the trees and lists of n_req systems at once (sum of n_active <=
+ * max_n).  Same rules and waiting behaviour as fmm_build. */
+fmm_status fmm_build_batched(fmm_ctx *ctx, int n_req, const fmm_request *reqs, double eps,
+                             double theta);
+
+/* Evaluate the n_req systems of the last fmm_build_batched (same pos, active,
+ * n_total, n_active in the same order, else FMM_ESTALE); masses and outputs
+ * may differ from call to call.  Asynchronous, like fmm_evaluate. */
+fmm_status fmm_evaluate_batched(fmm_ctx *ctx, int n_req, const fmm_request *reqs, int p);
+
+/* fmm_build_batched followed by fmm_evaluate_batched. */
+fmm_status fmm_forces_batched(fmm_ctx *ctx, int n_req, const fmm_request *reqs, double eps,
+                              double theta, int p);
+
+/* Sizes of the current tree (all systems of a batch together): info[0]
+ * n_active, [1] nodes, [2] unordered M2L
  * pairs, [3] unordered P2P leaf pairs (self pairs included), [4] depth,
  * [5] leaves, [6] ordered M2L entries, [7] ordered P2P entries, [8] ordered
  * particle-particle interactions evaluated by P2P. */
@@ -123,7 +158,8 @@ fmm_status fmm_tree_info(fmm_ctx *ctx, int64_t info[9]);
  * implementations: nodes in pre-order (sorted by (begin, level)); perm[i] =
  * active slot of the i-th particle in Morton order; pairs as (a <= b) over
  * pre-order ids, sorted.  All outputs are HOST buffers sized from
- * fmm_tree_info; any pointer may be NULL.  Synchronises the stream. */
+ * fmm_tree_info; any pointer may be NULL.  Synchronises the stream.  Only for
+ * a tree built from a single system (FMM_EINVAL otherwise). */
 fmm_status fmm_export_tree(fmm_ctx *ctx, int64_t *perm, int32_t *level, uint64_t *prefix,
                            int64_t *begin, int64_t *end, int32_t *is_leaf, double *centre,
                            double *half, int64_t *m2l_pairs, int64_t *p2p_pairs, double *box);

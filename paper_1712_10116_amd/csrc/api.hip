@@ -28,11 +28,11 @@ struct fmm_ctx {
   // host copy of the last build
   Header hh;
   bool tree_valid;
-  const double *b_pos;
-  int64_t b_n_total;
-  const int32_t *b_active;
-  int64_t b_n;
+  std::vector<fmm_request> b_reqs;  // requests of the last build
+  int64_t b_n;                      // their active particles in all
   double b_eps, b_theta;
+  std::vector<DevReq> h_reqs;       // staging of the device request table
+  std::vector<int32_t> h_off, h_blk;
   int n_nodes, depth;
   // HHS scratch
   int hhs_levels;
@@ -97,7 +97,7 @@ static bool alloc_nodes(fmm_ctx *c, int64_t cap) {
             dalloc(c, &t.bounds, cap * 8) && dalloc(c, &t.m2l_off, cap) &&
             dalloc(c, &t.m2l_cnt, cap) && dalloc(c, &t.p2p_off, cap) &&
             dalloc(c, &t.p2p_cnt, cap) && dalloc(c, &t.open_off, cap) &&
-            dalloc(c, &t.open_cnt, cap);
+            dalloc(c, &t.open_cnt, cap) && dalloc(c, &t.nreq, cap);
   if (!ok) return false;
   char *m = nullptr, *l = nullptr;
   ok = dalloc(c, &m, (int64_t)(cap * t.kmax * real)) && dalloc(c, &l, (int64_t)(cap * t.kmax * real));
@@ -109,8 +109,21 @@ static bool alloc_nodes(fmm_ctx *c, int64_t cap) {
 static void free_nodes(fmm_ctx *c) {
   DevTree &t = c->t;
   void *ptrs[] = {t.nbeg, t.nend, t.nlev, t.nparent, t.nchild0, t.nnchild, t.ngeo, t.bounds,
-                  t.m2l_off, t.m2l_cnt, t.p2p_off, t.p2p_cnt, t.open_off, t.open_cnt, t.M, t.L};
+                  t.m2l_off, t.m2l_cnt, t.p2p_off, t.p2p_cnt, t.open_off, t.open_cnt, t.M, t.L,
+                  t.nreq};
   for (void *p : ptrs) dfree(c, p);
+}
+
+// request-sized arrays (regrown when a batch holds more requests)
+static bool alloc_reqs(fmm_ctx *c, int cap) {
+  DevTree &t = c->t;
+  void *ptrs[] = {t.reqs, t.req_off, t.blk_off, t.box, t.bbox_part};
+  for (void *p : ptrs) dfree(c, p);
+  t.reqs = nullptr;
+  t.cap_req = cap;
+  return dalloc(c, &t.reqs, cap) && dalloc(c, &t.req_off, cap + 1) &&
+         dalloc(c, &t.blk_off, cap + 1) && dalloc(c, &t.box, cap) &&
+         dalloc(c, &t.bbox_part, (int64_t)cap * 64 * 6);
 }
 
 extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *stream,
@@ -142,11 +155,10 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
             dalloc(c, &t.sz, n) && dalloc(c, &t.lx, n) && dalloc(c, &t.ly, n) &&
             dalloc(c, &t.lz, n) && dalloc(c, &t.sm, n) && dalloc(c, &t.sm32, n) &&
             dalloc(c, &t.leaf_of, n) && dalloc(c, &t.near, 4 * n) &&
-            dalloc(c, &t.scan_part, FMM_SCAN_BLOCKS) && dalloc(c, &t.bbox_part, FMM_SCAN_BLOCKS * 6) &&
+            dalloc(c, &t.scan_part, FMM_SCAN_BLOCKS) && dalloc(c, &t.slot_req, n) &&
             dalloc(c, &t.sort_hist, 256 * ((n + 4095) / 4096) + 256) &&
             dalloc(c, &t.sort_dtot, 256) && dalloc(c, &t.scan_blk, n / 1024 + 64) &&
-            dalloc(c, &t.hdr, 1) &&
-            dalloc(c, &t.box, 1) && alloc_nodes(c, cap_nodes);
+            dalloc(c, &t.hdr, 1) && alloc_reqs(c, 16) && alloc_nodes(c, cap_nodes);
   if (ok) {
     t.cap_m2l = 96 * cap_nodes;
     t.cap_p2p = 32 * cap_nodes;
@@ -192,18 +204,67 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
 
 extern "C" const char *fmm_last_error(const fmm_ctx *c) { return c ? c->err : "null context"; }
 
-static fmm_status check_particles(fmm_ctx *c, const double *pos, int64_t n_total,
-                                  const int32_t *active, int64_t n_active) {
+static fmm_status check_requests(fmm_ctx *c, int n_req, const fmm_request *reqs, bool eval,
+                                 int64_t *n_all) {
   if (!c) return FMM_EINVAL;
-  if (n_active < 0 || n_active > c->max_n)
-    return fail(c, FMM_EINVAL, "n_active=%lld outside [0, max_n=%lld]", (long long)n_active,
+  if (n_req < 1 || !reqs) return fail(c, FMM_EINVAL, "need at least one request");
+  int64_t n = 0;
+  for (int r = 0; r < n_req; ++r) {
+    const fmm_request &q = reqs[r];
+    if (q.n_active < 0 || q.n_total < 0 || q.n_total > (int64_t)INT32_MAX)
+      return fail(c, FMM_EINVAL, "request %d: bad sizes", r);
+    if (q.n_active > 0 && !q.active && q.n_total != q.n_active)
+      return fail(c, FMM_EINVAL, "request %d: n_total=%lld inconsistent with n_active=%lld", r,
+                  (long long)q.n_total, (long long)q.n_active);
+    if (q.n_active > 0 && !q.pos) return fail(c, FMM_EINVAL, "request %d: pos is NULL", r);
+    if (eval && q.n_active > 0 && (!q.mass || !q.acc || !q.pot))
+      return fail(c, FMM_EINVAL, "request %d: NULL mass/acc/pot", r);
+    n += q.n_active;
+  }
+  if (n > c->max_n)
+    return fail(c, FMM_EINVAL, "%lld active particles exceed max_n=%lld", (long long)n,
                 (long long)c->max_n);
-  if (n_total < 0 || (n_active > 0 && !active && n_total != n_active) ||
-      (active && n_total < 1 && n_active > 0))
-    return fail(c, FMM_EINVAL, "n_total=%lld inconsistent with n_active=%lld",
-                (long long)n_total, (long long)n_active);
-  if (n_total > (int64_t)INT32_MAX) return fail(c, FMM_EINVAL, "n_total too large");
-  if (n_active > 0 && !pos) return fail(c, FMM_EINVAL, "pos is NULL");
+  *n_all = n;
+  return FMM_OK;
+}
+
+// upload the request table (pageable staging: the host copy is consumed when
+// the call returns, so the vectors may be reused by the next call)
+static fmm_status upload_requests(fmm_ctx *c, int n_req, const fmm_request *reqs, int *n_blk) {
+  DevTree &t = c->t;
+  if (n_req > t.cap_req && !alloc_reqs(c, std::max(n_req, 2 * t.cap_req)))
+    return fail(c, FMM_ENOMEM, "request table for %d requests", n_req);
+  c->h_reqs.resize(n_req);
+  c->h_off.resize(n_req + 1);
+  c->h_blk.resize(n_req + 1);
+  int off = 0, blk = 0;
+  for (int r = 0; r < n_req; ++r) {
+    const fmm_request &q = reqs[r];
+    DevReq d;
+    d.pos = q.pos;
+    d.active = q.active;
+    d.mass = q.mass;
+    d.acc = q.acc;
+    d.pot = q.pot;
+    d.n_total = q.n_total;
+    d.off = off;
+    d.n = (int32_t)q.n_active;
+    c->h_reqs[r] = d;
+    c->h_off[r] = off;
+    c->h_blk[r] = blk;
+    off += (int)q.n_active;
+    blk += (int)std::min<int64_t>(64, std::max<int64_t>(1, (q.n_active + 4095) / 4096));
+  }
+  c->h_off[n_req] = off;
+  c->h_blk[n_req] = blk;
+  t.n_req = n_req;
+  HIPCHK(c, hipMemcpyAsync(t.reqs, c->h_reqs.data(), sizeof(DevReq) * n_req,
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(t.req_off, c->h_off.data(), sizeof(int32_t) * (n_req + 1),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(t.blk_off, c->h_blk.data(), sizeof(int32_t) * (n_req + 1),
+                           hipMemcpyHostToDevice, c->stream));
+  if (n_blk) *n_blk = blk;
   return FMM_OK;
 }
 
@@ -231,19 +292,21 @@ static fmm_status regrow_lists(fmm_ctx *c, int which, int64_t need) {
   return FMM_OK;
 }
 
-extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
-                                const int32_t *active, int64_t n_active, double eps,
-                                double theta) {
-  fmm_status st = check_particles(c, pos, n_total, active, n_active);
+extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request *reqs,
+                                        double eps, double theta) {
+  int64_t n_all = 0;
+  fmm_status st = check_requests(c, n_req, reqs, false, &n_all);
   if (st != FMM_OK) return st;
   if (!(theta > 0.0) || !(eps >= 0.0) || !std::isfinite(theta) || !std::isfinite(eps))
     return fail(c, FMM_EINVAL, "need theta > 0 and eps >= 0");
   c->tree_valid = false;
+  int n_blk = 0;
+  st = upload_requests(c, n_req, reqs, &n_blk);
+  if (st != FMM_OK) return st;
   BuildArgs a;
-  a.pos = pos;
-  a.n_total = n_total;
-  a.active = active;
-  a.n = (int)n_active;
+  a.n = (int)n_all;
+  a.n_req = n_req;
+  a.n_blk = n_blk;
   a.leaf_size = c->prm.leaf_size;
   a.eps = eps;
   a.theta = theta;
@@ -258,11 +321,16 @@ extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
     if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
     // no cell below level max_prefix + 1 can hold two particles
     const int max_level = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
-    HIPCHK(c, launch_build_tree(c->t, a, max_level, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (!(c->hh.overflow & OVF_NODES)) {
+      HIPCHK(c, launch_build_tree(c->t, a, max_level, c->stream));
+      HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     if (!(c->hh.overflow & OVF_NODES)) break;
-    int64_t need = std::max<int64_t>((int64_t)c->hh.lvl_start[FMM_NLEVELS], 2 * c->t.cap_nodes);
+    int64_t need = std::max<int64_t>(std::max<int64_t>((int64_t)c->hh.lvl_start[FMM_NLEVELS],
+                                                       n_req),
+                                     2 * c->t.cap_nodes);
     free_nodes(c);
     if (!alloc_nodes(c, need + need / 4))
       return fail(c, FMM_ENOMEM, "node workspace regrow to %lld failed", (long long)need);
@@ -301,10 +369,8 @@ extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
     c->n_nodes = h.lvl_start[FMM_NLEVELS];
     c->depth = depth;
     c->tree_valid = true;
-    c->b_pos = pos;
-    c->b_n_total = n_total;
-    c->b_active = active;
-    c->b_n = n_active;
+    c->b_reqs.assign(reqs, reqs + n_req);
+    c->b_n = n_all;
     c->b_eps = eps;
     c->b_theta = theta;
     c->stat_builds++;
@@ -313,45 +379,78 @@ extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
   return fail(c, FMM_EOVERFLOW, "list workspace still too small after regrowth");
 }
 
-extern "C" fmm_status fmm_evaluate(fmm_ctx *c, const double *pos, const double *mass,
-                                   int64_t n_total, const int32_t *active, int64_t n_active, int p,
-                                   double *acc, double *pot) {
-  fmm_status st = check_particles(c, pos, n_total, active, n_active);
+extern "C" fmm_status fmm_evaluate_batched(fmm_ctx *c, int n_req, const fmm_request *reqs, int p) {
+  int64_t n_all = 0;
+  fmm_status st = check_requests(c, n_req, reqs, true, &n_all);
   if (st != FMM_OK) return st;
-  if (!c->tree_valid || pos != c->b_pos || active != c->b_active || n_active != c->b_n ||
-      n_total != c->b_n_total)
-    return fail(c, FMM_ESTALE, "no tree built for these particles");
+  bool same = c->tree_valid && n_req == (int)c->b_reqs.size();
+  for (int r = 0; same && r < n_req; ++r) {
+    const fmm_request &a = reqs[r], &b = c->b_reqs[r];
+    same = a.pos == b.pos && a.active == b.active && a.n_active == b.n_active &&
+           a.n_total == b.n_total;
+  }
+  if (!same) return fail(c, FMM_ESTALE, "no tree built for these particles");
   if (p < 1 || p > c->prm.p_max || !eval_order_supported(p))
     return fail(c, FMM_EINVAL, "order p=%d unsupported (1..%d)", p, std::min(c->prm.p_max, 6));
-  if (n_active > 0 && (!mass || !acc || !pot)) return fail(c, FMM_EINVAL, "NULL mass/acc/pot");
+  st = upload_requests(c, n_req, reqs, nullptr);
+  if (st != FMM_OK) return st;
   EvalArgs e;
-  e.mass = mass;
-  e.active = active;
-  e.n = (int)n_active;
+  e.n = (int)n_all;
   e.n_nodes = c->n_nodes;
   e.p = p;
   e.kernel = c->prm.kernel;
   e.mixed = c->prm.precision == FMM_PREC_MIXED;
   e.eps = c->b_eps;
-  e.acc = acc;
-  e.pot = pot;
   e.lvl_start_host = c->hh.lvl_start;
   e.depth = c->depth;
   e.tm = timer_of(c);
   HIPCHK(c, launch_evaluate(c->t, e, c->stream));
   c->stat_calls++;
-  c->stat_parts += n_active;
+  c->stat_parts += n_all;
   return FMM_OK;
+}
+
+extern "C" fmm_status fmm_forces_batched(fmm_ctx *c, int n_req, const fmm_request *reqs,
+                                         double eps, double theta, int p) {
+  if (c && (p < 1 || p > c->prm.p_max || !eval_order_supported(p)))
+    return fail(c, FMM_EINVAL, "order p=%d unsupported", p);
+  fmm_status st = fmm_build_batched(c, n_req, reqs, eps, theta);
+  if (st != FMM_OK) return st;
+  return fmm_evaluate_batched(c, n_req, reqs, p);
+}
+
+static fmm_request one_request(const double *pos, const double *mass, int64_t n_total,
+                               const int32_t *active, int64_t n_active, double *acc, double *pot) {
+  fmm_request q;
+  q.pos = pos;
+  q.n_total = n_total;
+  q.active = active;
+  q.n_active = n_active;
+  q.mass = mass;
+  q.acc = acc;
+  q.pot = pot;
+  return q;
+}
+
+extern "C" fmm_status fmm_build(fmm_ctx *c, const double *pos, int64_t n_total,
+                                const int32_t *active, int64_t n_active, double eps,
+                                double theta) {
+  fmm_request q = one_request(pos, nullptr, n_total, active, n_active, nullptr, nullptr);
+  return fmm_build_batched(c, 1, &q, eps, theta);
+}
+
+extern "C" fmm_status fmm_evaluate(fmm_ctx *c, const double *pos, const double *mass,
+                                   int64_t n_total, const int32_t *active, int64_t n_active, int p,
+                                   double *acc, double *pot) {
+  fmm_request q = one_request(pos, mass, n_total, active, n_active, acc, pot);
+  return fmm_evaluate_batched(c, 1, &q, p);
 }
 
 extern "C" fmm_status fmm_forces(fmm_ctx *c, const double *pos, const double *mass,
                                  int64_t n_total, const int32_t *active, int64_t n_active,
                                  double eps, double theta, int p, double *acc, double *pot) {
-  if (c && (p < 1 || p > c->prm.p_max || !eval_order_supported(p)))
-    return fail(c, FMM_EINVAL, "order p=%d unsupported", p);
-  fmm_status st = fmm_build(c, pos, n_total, active, n_active, eps, theta);
-  if (st != FMM_OK) return st;
-  return fmm_evaluate(c, pos, mass, n_total, active, n_active, p, acc, pot);
+  fmm_request q = one_request(pos, mass, n_total, active, n_active, acc, pot);
+  return fmm_forces_batched(c, 1, &q, eps, theta, p);
 }
 
 extern "C" fmm_status fmm_tree_info(fmm_ctx *c, int64_t info[9]) {
@@ -359,7 +458,7 @@ extern "C" fmm_status fmm_tree_info(fmm_ctx *c, int64_t info[9]) {
   if (!c->tree_valid) return fail(c, FMM_ESTALE, "no tree");
   const Header &h = c->hh;
   int64_t leaves = h.n_leaves;
-  info[0] = c->b_n;
+  info[0] = c->b_n;  // active particles over all requests
   info[1] = c->n_nodes;
   info[2] = h.m2l_cursor / 2;
   info[3] = ((int64_t)h.p2p_cursor - leaves) / 2 + leaves;
@@ -384,6 +483,7 @@ extern "C" fmm_status fmm_export_tree(fmm_ctx *c, int64_t *perm, int32_t *level,
                                       int64_t *p2p_pairs, double *box) {
   if (!c) return FMM_EINVAL;
   if (!c->tree_valid) return fail(c, FMM_ESTALE, "no tree");
+  if (c->b_reqs.size() != 1) return fail(c, FMM_EINVAL, "export needs a single-request tree");
   const int64_t n = c->b_n, nn = c->n_nodes;
   const DevTree &t = c->t;
   std::vector<int32_t> nbeg, nend, nlev, nnch, slot, moff, mcnt, msrc, poff, pcnt, psrc;
@@ -391,6 +491,7 @@ extern "C" fmm_status fmm_export_tree(fmm_ctx *c, int64_t *perm, int32_t *level,
   std::vector<double4> geo;
   Box hb;
   hipStream_t s = c->stream;
+  // single request: slot == active slot
   HIPCHK(c, d2h(nbeg, t.nbeg, nn, s));
   HIPCHK(c, d2h(nend, t.nend, nn, s));
   HIPCHK(c, d2h(nlev, t.nlev, nn, s));

@@ -49,7 +49,29 @@ struct Box {
   double hi[3];
 };
 
+// One independent particle system of a batched solve.  Its active particles
+// occupy slots [off, off + n) of the batch; positions/masses are read through
+// its own pointers, outputs written to its own acc/pot.
+struct DevReq {
+  const double *pos;      // 3 x n_total SoA
+  const int32_t *active;  // n indices or NULL
+  const double *mass;     // n_total
+  double *acc;            // 3 x n SoA
+  double *pot;            // n
+  int64_t n_total;
+  int32_t off;
+  int32_t n;
+};
+
 struct DevTree {
+  // batch of requests (R = 1 for a plain solve)
+  DevReq *reqs;       // [cap_req]
+  int32_t *req_off;   // [cap_req + 1] slot offsets
+  int32_t *blk_off;   // [cap_req + 1] first bbox block of each request
+  int32_t *slot_req;  // [cap_n] request of each slot
+  int32_t *nreq;      // [cap_nodes] request of each cell
+  int n_req;
+  int cap_req;
   // particles, sorted order
   uint64_t *key, *key2;
   int32_t *slot, *slot2;
@@ -71,12 +93,12 @@ struct DevTree {
   int32_t *open_buf0, *open_buf1;
   // scratch
   int32_t *scan_part;          // [FMM_SCAN_BLOCKS]
-  double *bbox_part;           // [FMM_SCAN_BLOCKS][6]
+  double *bbox_part;           // [bbox blocks][6]
   uint32_t *sort_hist;         // [256][sort blocks]
   uint32_t *sort_dtot;         // [256] digit totals
   uint32_t *scan_blk;          // block sums of the generic scan
   Header *hdr;
-  Box *box;
+  Box *box;  // [cap_req]
   int64_t cap_n, cap_nodes, cap_m2l, cap_p2p, cap_open;
   int kmax;
 };
@@ -161,10 +183,9 @@ struct PhaseTimer {
 // host-side launchers (one translation unit each)
 // ---------------------------------------------------------------------------
 struct BuildArgs {
-  const double *pos;
-  int64_t n_total;
-  const int32_t *active;
-  int n;
+  int n;          // active particles over all requests
+  int n_req;      // requests (roots)
+  int n_blk;      // bbox blocks over all requests
   int leaf_size;
   double eps;
   double theta;
@@ -181,16 +202,12 @@ hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s);
 hipError_t launch_reset_lists(const DevTree &t, hipStream_t s);
 // eval.hip
 struct EvalArgs {
-  const double *mass;
-  const int32_t *active;
   int n;
   int n_nodes;
   int p;
   int kernel;     // 0 Wendland, 1 Plummer
   int mixed;      // 0 FP64, 1 mixed
   double eps;
-  double *acc;
-  double *pot;
   const int32_t *lvl_start_host;  // host copy, FMM_NLEVELS+1 entries
   int depth;
   PhaseTimer *tm;

@@ -17,14 +17,14 @@
 #include "expansion.h"
 
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FMM_BLOCK) void k_gather_mass(DevTree t, const double *__restrict__ mass,
-                                                           const int32_t *__restrict__ active,
-                                                           int n) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_gather_mass(DevTree t, int n) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  int s = t.slot[j];
-  int64_t g = active ? active[s] : s;
-  double m = mass[g];
+  const int s = t.slot[j];
+  const DevReq q = t.reqs[t.slot_req[s]];
+  const int i = s - q.off;
+  int64_t g = q.active ? q.active[i] : i;
+  double m = q.mass[g];
   t.sm[j] = m;
   t.sm32[j] = (float)m;
 }
@@ -168,8 +168,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2l(DevTree t, int s, int e) {
 
 // L2P + near field + un-permute: one thread per Morton-sorted particle
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, double *__restrict__ acc,
-                                                   double *__restrict__ pot) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n) {
   constexpr int K = MI<P>::K;
   const T *L = (const T *)t.L;
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -184,11 +183,13 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, double *__r
   T phi, gx, gy, gz;
   l2p_eval<T, P>(Lt, mono, phi, gx, gy, gz);
   const int s = t.slot[j];
+  const DevReq q = t.reqs[t.slot_req[s]];
+  const int64_t i = s - q.off, nq = q.n;
   const int64_t cap = t.cap_n;
-  acc[s] = t.near[j] - (double)gx * ih;
-  acc[(int64_t)n + s] = t.near[cap + j] - (double)gy * ih;
-  acc[2 * (int64_t)n + s] = t.near[2 * cap + j] - (double)gz * ih;
-  pot[s] = t.near[3 * cap + j] + (double)phi;
+  q.acc[i] = t.near[j] - (double)gx * ih;
+  q.acc[nq + i] = t.near[cap + j] - (double)gy * ih;
+  q.acc[2 * nq + i] = t.near[2 * cap + j] - (double)gz * ih;
+  q.pot[i] = t.near[3 * cap + j] + (double)phi;
 }
 
 // ---------------------------------------------------------------------------
@@ -405,7 +406,7 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
     tm->start(PH_DOWN, s);
   }
   hipLaunchKernelGGL((k_l2p<T, P>), dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
-                     s, t, e.n, e.acc, e.pot);
+                     s, t, e.n);
   if (tm) tm->stop(s);
 }
 
@@ -428,7 +429,7 @@ hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   if (e.n <= 0) return hipSuccess;
   if (e.tm) e.tm->start(PH_UP, s);
   hipLaunchKernelGGL(k_gather_mass, dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0, s,
-                     t, e.mass, e.active, e.n);
+                     t, e.n);
   bool ok;
   if (e.mixed)
     ok = e.kernel == 1 ? dispatch_order<float, 1>(t, e, s) : dispatch_order<float, 0>(t, e, s);

@@ -173,7 +173,8 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
     int ec = 0, c0 = 0;
     if (e < in_cnt) {
       if (l == 0) {
-        ec = 1;  // the pair (root, root)
+        ec = 1;  // the pair (root, root) of this request's tree
+        c0 = P;
       } else {
         const int B = open_in[in_off + e];
         const int nB = t.nnchild[B];
@@ -214,7 +215,8 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
 }
 
 // Level l >= 1: one wavefront per cell P of level l-1 with children; the
-// children are the targets.  Level 0: one wavefront for the root.
+// children are the targets.  Level 0: one wavefront per request root, whose
+// only candidate is itself, so cells of different requests never meet.
 __global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l, int ps, int pe,
                                                                 double th2, double eps) {
   __shared__ WaveLds lds[TRAV_WAVES];
@@ -226,11 +228,12 @@ __global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l
   WaveLds &L = lds[w];
   Sibs S;
   if (l == 0) {
-    // the root is the only target; every sibling slot must hold a valid id
-    // because the slots are read below before the S.n guard applies
+    // a request's root is the only target of its group; every sibling slot
+    // must hold a valid id because the slots are read below before the S.n
+    // guard applies
     S.n = 1;
 #pragma unroll
-    for (int tg = 0; tg < 8; ++tg) S.id[tg] = 0;
+    for (int tg = 0; tg < 8; ++tg) S.id[tg] = P;
   } else {
     const int nc = t.nnchild[P];
     if (nc == 0) return;
@@ -320,7 +323,7 @@ hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s) 
   if (a.tm) a.tm->start(PH_WALK, s);
   for (int l = 0; l <= a.depth; ++l) {
     int ps = l == 0 ? 0 : a.lvl_host[l - 1];
-    int pe = l == 0 ? 1 : a.lvl_host[l];
+    int pe = l == 0 ? a.n_req : a.lvl_host[l];
     int nw = pe - ps;
     if (nw <= 0) continue;
     hipLaunchKernelGGL(k_walk_level, dim3((nw + TRAV_WAVES - 1) / TRAV_WAVES),

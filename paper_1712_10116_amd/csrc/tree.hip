@@ -17,6 +17,8 @@
 // All decisions are the same IEEE double expressions as in the definition
 // above, built with -ffp-contract=off, so keys, octant membership and centres
 // are reproducible bit for bit.
+#include <algorithm>
+
 #include "common.h"
 #include "hhs_kernels.h"
 
@@ -25,19 +27,40 @@
 #define SORT_TILE (SORT_WAVES * 64 * SORT_ITEMS)
 
 // ---------------------------------------------------------------------------
-// root box
+// request of every slot (binary search in the request offsets)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FMM_BLOCK) void k_bbox_partial(const double *__restrict__ pos,
-                                                            int64_t n_total,
-                                                            const int32_t *__restrict__ active,
-                                                            int n, double *part, Header *hdr) {
+__device__ __forceinline__ int upper_index(const int32_t *off, int m, int x) {
+  // largest r in [0, m) with off[r] <= x
+  int lo = 0, hi = m - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_slot_req(DevTree t, int n) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) t.slot_req[s] = upper_index(t.req_off, t.n_req, s);
+}
+
+// ---------------------------------------------------------------------------
+// root box of every request
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(FMM_BLOCK) void k_bbox_partial(DevTree t) {
+  const int r = upper_index(t.blk_off, t.n_req, blockIdx.x);
+  const DevReq q = t.reqs[r];
+  const int lb = blockIdx.x - t.blk_off[r], nbr = t.blk_off[r + 1] - t.blk_off[r];
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   int bad = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    int64_t g = active ? active[i] : i;
+  for (int i = lb * blockDim.x + threadIdx.x; i < q.n; i += nbr * blockDim.x) {
+    int64_t g = q.active ? q.active[i] : i;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      double x = pos[d * n_total + g];
+      double x = q.pos[d * q.n_total + g];
       bad |= !isfinite(x);
       lo[d] = fmin(lo[d], x);
       hi[d] = fmax(hi[d], x);
@@ -49,26 +72,32 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_bbox_partial(const double *__rest
     red[d][threadIdx.x] = lo[d];
     red[3 + d][threadIdx.x] = hi[d];
   }
-  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&hdr->nonfinite, 1);
-  for (int s = FMM_BLOCK / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(&t.hdr->nonfinite, 1);
+  for (int o = FMM_BLOCK / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + s]);
-        red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + s]);
+        red[d][threadIdx.x] = fmin(red[d][threadIdx.x], red[d][threadIdx.x + o]);
+        red[3 + d][threadIdx.x] = fmax(red[3 + d][threadIdx.x], red[3 + d][threadIdx.x + o]);
       }
     }
     __syncthreads();
   }
-  if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 6) t.bbox_part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void k_bbox_final(const double *part, int nblk, int n, Box *box) {
+// one wavefront per request: c = (lo+hi)/2, L = max extent (1 if 0),
+// o = c - L/2, s = 2^21/L
+__global__ __launch_bounds__(FMM_BLOCK) void k_bbox_final(DevTree t) {
+  const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r >= t.n_req) return;
+  const int b0 = t.blk_off[r], b1 = t.blk_off[r + 1];
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = threadIdx.x; b < nblk; b += 64)
+  for (int b = b0 + lane; b < b1; b += 64)
     for (int d = 0; d < 3; ++d) {
-      lo[d] = fmin(lo[d], part[b * 6 + d]);
-      hi[d] = fmax(hi[d], part[b * 6 + 3 + d]);
+      lo[d] = fmin(lo[d], t.bbox_part[b * 6 + d]);
+      hi[d] = fmax(hi[d], t.bbox_part[b * 6 + 3 + d]);
     }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
@@ -77,8 +106,8 @@ __global__ __launch_bounds__(64) void k_bbox_final(const double *part, int nblk,
       lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, 64));
       hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, 64));
     }
-  if (threadIdx.x != 0) return;
-  if (n == 0)
+  if (lane != 0) return;
+  if (t.reqs[r].n == 0)
     for (int d = 0; d < 3; ++d) lo[d] = hi[d] = 0.0;
   double c[3], L = 0.0;
   for (int d = 0; d < 3; ++d) {
@@ -87,13 +116,14 @@ __global__ __launch_bounds__(64) void k_bbox_final(const double *part, int nblk,
     if (e > L) L = e;
   }
   if (L == 0.0) L = 1.0;
+  Box &bx = t.box[r];
   for (int d = 0; d < 3; ++d) {
-    box->o[d] = c[d] - 0.5 * L;
-    box->lo[d] = lo[d];
-    box->hi[d] = hi[d];
+    bx.o[d] = c[d] - 0.5 * L;
+    bx.lo[d] = lo[d];
+    bx.hi[d] = hi[d];
   }
-  box->L = L;
-  box->s = 2097152.0 / L;
+  bx.L = L;
+  bx.s = 2097152.0 / L;
 }
 
 // ---------------------------------------------------------------------------
@@ -127,35 +157,46 @@ __device__ __forceinline__ uint64_t quantise(double x, double o, double s) {
   return (uint64_t)q;
 }
 
-__global__ __launch_bounds__(FMM_BLOCK) void k_keys(const double *__restrict__ pos, int64_t n_total,
-                                                    const int32_t *__restrict__ active, int n,
-                                                    const Box *__restrict__ box,
-                                                    uint64_t *__restrict__ key,
-                                                    int32_t *__restrict__ slot) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int64_t g = active ? active[i] : i;
-  const double s = box->s;
-  uint64_t qx = quantise(pos[g], box->o[0], s);
-  uint64_t qy = quantise(pos[n_total + g], box->o[1], s);
-  uint64_t qz = quantise(pos[2 * n_total + g], box->o[2], s);
-  key[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
-  slot[i] = i;
+__global__ __launch_bounds__(FMM_BLOCK) void k_keys(DevTree t, int n) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int r = t.slot_req[s];
+  const DevReq q = t.reqs[r];
+  const int i = s - q.off;
+  int64_t g = q.active ? q.active[i] : i;
+  const Box &bx = t.box[r];
+  uint64_t qx = quantise(q.pos[g], bx.o[0], bx.s);
+  uint64_t qy = quantise(q.pos[q.n_total + g], bx.o[1], bx.s);
+  uint64_t qz = quantise(q.pos[2 * q.n_total + g], bx.o[2], bx.s);
+  t.key[s] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+  t.slot[s] = s;
 }
 
 // ---------------------------------------------------------------------------
 // stable LSD radix sort, 8-bit digits
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FMM_BLOCK) void k_sort_hist(const uint64_t *__restrict__ key, int n,
-                                                         int shift, uint32_t *__restrict__ hist,
-                                                         int nblk) {
+// digit of element i: bits [shift, shift+8) of its key (by_req = 0) or of the
+// request of its slot (by_req = 1; these passes come last, so the final order
+// is by (request, key, slot))
+__device__ __forceinline__ uint32_t sort_digit(const uint64_t *key, const int32_t *slot,
+                                               const int32_t *slot_req, int i, int shift,
+                                               int by_req) {
+  return by_req ? ((uint32_t)slot_req[slot[i]] >> shift) & 255u
+                : (uint32_t)(key[i] >> shift) & 255u;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_sort_hist(const uint64_t *__restrict__ key,
+                                                         const int32_t *__restrict__ slot,
+                                                         const int32_t *__restrict__ slot_req,
+                                                         int n, int shift, int by_req,
+                                                         uint32_t *__restrict__ hist, int nblk) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
   int base = blockIdx.x * SORT_TILE;
   for (int e = threadIdx.x; e < SORT_TILE; e += FMM_BLOCK) {
     int i = base + e;
-    if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
+    if (i < n) atomicAdd(&h[sort_digit(key, slot, slot_req, i, shift, by_req)], 1u);
   }
   __syncthreads();
   hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
@@ -250,8 +291,8 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_scan_down(uint32_t *v, int m, con
 
 __global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const int32_t *__restrict__ sin, uint64_t *__restrict__ kout,
-    int32_t *__restrict__ sout, int n, int shift, const uint32_t *__restrict__ hist, int nblk,
-    const uint32_t *__restrict__ dtot) {
+    int32_t *__restrict__ sout, const int32_t *__restrict__ slot_req, int n, int shift, int by_req,
+    const uint32_t *__restrict__ hist, int nblk, const uint32_t *__restrict__ dtot) {
   __shared__ uint32_t cnt[SORT_WAVES][256];
   __shared__ uint32_t goff[256];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -283,7 +324,8 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
     bool valid = i < n;
     k[it] = valid ? kin[i] : 0;
     sv[it] = valid ? sin[i] : 0;
-    uint32_t d = (uint32_t)(k[it] >> shift) & 255u;
+    uint32_t d = by_req ? ((uint32_t)slot_req[sv[it]] >> shift) & 255u
+                        : (uint32_t)(k[it] >> shift) & 255u;
     unsigned long long m = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -315,7 +357,8 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
   for (int it = 0; it < SORT_ITEMS; ++it) {
     int i = base + it * 64 + lane;
     if (i < n) {
-      uint32_t d = (uint32_t)(k[it] >> shift) & 255u;
+      uint32_t d = by_req ? ((uint32_t)slot_req[sv[it]] >> shift) & 255u
+                          : (uint32_t)(k[it] >> shift) & 255u;
       uint32_t dst = cnt[w][d] + rank[it];
       kout[dst] = k[it];
       sout[dst] = sv[it];
@@ -325,10 +368,12 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
 
 // deepest level at which two neighbouring sorted keys still share a cell:
 // no cell deeper than that + 1 can hold two particles, so the split stops there
-__global__ __launch_bounds__(FMM_BLOCK) void k_max_common_prefix(const uint64_t *__restrict__ key,
-                                                                 int n, Header *hdr) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_max_common_prefix(DevTree t, int n) {
   int best = 0;
+  const uint64_t *key = t.key;
+  Header *hdr = t.hdr;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += gridDim.x * blockDim.x) {
+    if (t.slot_req[t.slot[i]] != t.slot_req[t.slot[i + 1]]) continue;
     uint64_t x = key[i] ^ key[i + 1];
     int digits = x == 0 ? FMM_MAXLEVEL : (__clzll(x) - 1) / 3;
     best = max(best, digits);
@@ -341,17 +386,16 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_max_common_prefix(const uint64_t 
 // ---------------------------------------------------------------------------
 // sorted particle data
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FMM_BLOCK) void k_gather_sorted(DevTree t, const double *__restrict__ pos,
-                                                             int64_t n_total,
-                                                             const int32_t *__restrict__ active,
-                                                             int n) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_gather_sorted(DevTree t, int n) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  int s = t.slot[j];
-  int64_t g = active ? active[s] : s;
-  t.sx[j] = pos[g];
-  t.sy[j] = pos[n_total + g];
-  t.sz[j] = pos[2 * n_total + g];
+  const int s = t.slot[j];
+  const DevReq q = t.reqs[t.slot_req[s]];
+  const int i = s - q.off;
+  int64_t g = q.active ? q.active[i] : i;
+  t.sx[j] = q.pos[g];
+  t.sy[j] = q.pos[q.n_total + g];
+  t.sz[j] = q.pos[2 * q.n_total + g];
 }
 
 // ---------------------------------------------------------------------------
@@ -368,24 +412,27 @@ __device__ __forceinline__ double4 cell_geometry(const Box &b, uint64_t prefix, 
   return g;
 }
 
-__global__ void k_tree_init(DevTree t, int n) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one root per request, covering its sorted range [off, off + n)
+__global__ __launch_bounds__(FMM_BLOCK) void k_tree_init(DevTree t) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
   Header *h = t.hdr;
-  int root = n > 0 ? 1 : 0;
-  h->lvl_start[0] = 0;
-  for (int l = 1; l < FMM_NLEVELS + 2; ++l) h->lvl_start[l] = root;
-  h->overflow = 0;
-  h->n_leaves = 0;
-  h->max_prefix = 0;
-  if (n > 0) {
-    t.nbeg[0] = 0;
-    t.nend[0] = n;
-    t.nlev[0] = 0;
-    t.nparent[0] = -1;
-    t.nchild0[0] = -1;
-    t.nnchild[0] = 0;
-    t.ngeo[0] = cell_geometry(*t.box, 0ull, 0);
+  const int R = t.n_req;
+  if (r == 0) {
+    h->lvl_start[0] = 0;
+    for (int l = 1; l < FMM_NLEVELS + 2; ++l) h->lvl_start[l] = R;
+    h->overflow = R > t.cap_nodes ? OVF_NODES : 0;
+    h->n_leaves = 0;
+    h->max_prefix = 0;
   }
+  if (r >= R || r >= t.cap_nodes) return;
+  t.nbeg[r] = t.req_off[r];
+  t.nend[r] = t.req_off[r + 1];
+  t.nlev[r] = 0;
+  t.nparent[r] = -1;
+  t.nchild0[r] = -1;
+  t.nnchild[r] = 0;
+  t.nreq[r] = r;
+  t.ngeo[r] = cell_geometry(t.box[r], 0ull, 0);
 }
 
 __device__ __forceinline__ int lower_bound_digit(const uint64_t *__restrict__ key, int b, int e,
@@ -463,7 +510,6 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l) {
   int s, e;
   level_chunk(t.hdr, l, s, e);
   __shared__ int sc[FMM_BLOCK];
-  const Box box = *t.box;
   int run = t.hdr->lvl_start[l + 1] + t.scan_part[blockIdx.x];
   for (int base = s; base < e; base += FMM_BLOCK) {
     int i = base + threadIdx.x;
@@ -481,6 +527,8 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l) {
     __syncthreads();
     if (nc > 0) {
       t.nchild0[i] = first;
+      const int rq = t.nreq[i];
+      const Box box = t.box[rq];
       int c = first;
       for (int o = 0; o < 8; ++o) {
         int b = t.bounds[(int64_t)i * 8 + o];
@@ -493,6 +541,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l) {
             t.nparent[c] = i;
             t.nchild0[c] = -1;
             t.nnchild[c] = 0;
+            t.nreq[c] = rq;
             uint64_t prefix = t.key[b] >> (3 * (FMM_MAXLEVEL - (l + 1)));
             t.ngeo[c] = cell_geometry(box, prefix, l + 1);
           }
@@ -532,33 +581,36 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_mark_leaves(DevTree t) {
 
 hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
   const int n = a.n;
-  int nb = (n + FMM_BLOCK - 1) / FMM_BLOCK;
-  int nbb = nb < FMM_SCAN_BLOCKS ? (nb > 0 ? nb : 1) : FMM_SCAN_BLOCKS;
+  const int nb = (n + FMM_BLOCK - 1) / FMM_BLOCK;
   if (a.tm) a.tm->start(PH_SORT, s);
-  hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(FMM_BLOCK), 0, s, a.pos, a.n_total, a.active,
-                     n, t.bbox_part, t.hdr);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, t.bbox_part, nbb, n, t.box);
-  hipLaunchKernelGGL(k_tree_init, dim3(1), dim3(64), 0, s, t, n);
+  if (n > 0) hipLaunchKernelGGL(k_slot_req, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
+  hipLaunchKernelGGL(k_bbox_partial, dim3(a.n_blk), dim3(FMM_BLOCK), 0, s, t);
+  hipLaunchKernelGGL(k_bbox_final, dim3((a.n_req + 3) / 4), dim3(FMM_BLOCK), 0, s, t);
+  hipLaunchKernelGGL(k_tree_init, dim3((a.n_req + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
+                     s, t);
   if (n > 0) {
-    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(FMM_BLOCK), 0, s, a.pos, a.n_total, a.active, n,
-                       t.box, t.key, t.slot);
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
     const int nblk = (n + SORT_TILE - 1) / SORT_TILE;
     uint64_t *kin = t.key, *kout = t.key2;
     int32_t *sin = t.slot, *sout = t.slot2;
-    for (int pass = 0; pass < 8; ++pass) {
-      int shift = pass * 8;
-      hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, n, shift,
-                         t.sort_hist, nblk);
+    // 8 passes over the 63-bit key, then (several requests) passes over the
+    // request id; an even number of passes leaves the result in key/slot
+    int req_passes = 0;
+    if (a.n_req > 1) req_passes = a.n_req > 65536 ? 4 : (a.n_req > 256 ? 2 : 2);
+    for (int pass = 0; pass < 8 + req_passes; ++pass) {
+      const int by_req = pass >= 8;
+      const int shift = by_req ? (pass - 8) * 8 : pass * 8;
+      hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, sin, t.slot_req, n,
+                         shift, by_req, t.sort_hist, nblk);
       hipLaunchKernelGGL(k_sort_digit_scan, dim3(256), dim3(FMM_BLOCK), 0, s, t.sort_hist, nblk,
                          t.sort_dtot);
       hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, sin, kout, sout,
-                         n, shift, t.sort_hist, nblk, t.sort_dtot);
+                         t.slot_req, n, shift, by_req, t.sort_hist, nblk, t.sort_dtot);
       uint64_t *tk = kin; kin = kout; kout = tk;
       int32_t *ts = sin; sin = sout; sout = ts;
     }
-    hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(FMM_BLOCK), 0, s, t, a.pos, a.n_total,
-                       a.active, n);
-    hipLaunchKernelGGL(k_max_common_prefix, dim3(nbb), dim3(FMM_BLOCK), 0, s, t.key, n, t.hdr);
+    hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
+    hipLaunchKernelGGL(k_max_common_prefix, dim3(std::min(nb, 1024)), dim3(FMM_BLOCK), 0, s, t, n);
   }
   if (a.tm) a.tm->stop(s);
   return hipGetLastError();

@@ -21,7 +21,8 @@ FP64, MIXED = 0, 1
 EXPORTED = (
     "fmm_create", "fmm_destroy", "fmm_last_error", "fmm_build", "fmm_evaluate", "fmm_forces",
     "fmm_tree_info", "fmm_export_tree", "fmm_invariants", "hhs_init", "hhs_step",
-    "fmm_profile_enable", "fmm_profile_read",
+    "fmm_profile_enable", "fmm_profile_read", "fmm_build_batched", "fmm_evaluate_batched",
+    "fmm_forces_batched",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -35,6 +36,13 @@ class FMMError(RuntimeError):
 class _Params(ctypes.Structure):
     _fields_ = [("p_max", ctypes.c_int), ("leaf_size", ctypes.c_int), ("kernel", ctypes.c_int),
                 ("precision", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    """One independent system of a batched solve (fmm_request)."""
+    _fields_ = [("pos", ctypes.c_void_p), ("n_total", ctypes.c_int64), ("active", ctypes.c_void_p),
+                ("n_active", ctypes.c_int64), ("mass", ctypes.c_void_p), ("acc", ctypes.c_void_p),
+                ("pot", ctypes.c_void_p)]
 
 
 class HHSState(ctypes.Structure):
@@ -72,6 +80,9 @@ def lib():
         L.fmm_invariants.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
         L.hhs_init.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams)]
         L.hhs_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
+        L.fmm_build_batched.argtypes = [vp, ci, ctypes.POINTER(Request), dbl, dbl]
+        L.fmm_evaluate_batched.argtypes = [vp, ci, ctypes.POINTER(Request), ci]
+        L.fmm_forces_batched.argtypes = [vp, ci, ctypes.POINTER(Request), dbl, dbl, ci]
         L.fmm_profile_enable.argtypes = [vp, ci]
         L.fmm_profile_read.argtypes = [vp, vp, vp]
         for name in EXPORTED:
@@ -159,6 +170,47 @@ class Solver:
     def forces(self, pos, mass, active=None, *, eps, theta, p, acc=None, pot=None):
         self.build(pos, active, eps=eps, theta=theta)
         return self.evaluate(pos, mass, active, p=p, acc=acc, pot=pot)
+
+    def _requests(self, systems, with_outputs):
+        arr = (Request * len(systems))()
+        outs = []
+        for k, sysd in enumerate(systems):
+            pos = sysd["pos"]
+            n_total = pos.shape[1]
+            _check_dev(pos, torch.float64, (3, n_total), "pos")
+            active = sysd.get("active")
+            n = n_total if active is None else active.shape[0]
+            q = arr[k]
+            q.pos, q.n_total, q.active, q.n_active = pos.data_ptr(), n_total, (
+                None if active is None else active.data_ptr()), n
+            if with_outputs:
+                mass = sysd["mass"]
+                _check_dev(mass, torch.float64, (n_total,), "mass")
+                acc = sysd.get("acc")
+                pot = sysd.get("pot")
+                if acc is None:
+                    acc = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+                if pot is None:
+                    pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+                q.mass, q.acc, q.pot = mass.data_ptr(), acc.data_ptr(), pot.data_ptr()
+                outs.append((acc, pot))
+        return arr, outs
+
+    def build_batched(self, systems, *, eps, theta):
+        """systems: list of dicts with 'pos' (3 x n_total) and optional 'active'."""
+        arr, _ = self._requests(systems, False)
+        self._raise(lib().fmm_build_batched(self._h, len(systems), arr, float(eps), float(theta)))
+
+    def evaluate_batched(self, systems, *, p):
+        """systems as for build_batched plus 'mass' (and optional 'acc', 'pot');
+        returns [(acc, pot), ...]."""
+        arr, outs = self._requests(systems, True)
+        self._raise(lib().fmm_evaluate_batched(self._h, len(systems), arr, int(p)))
+        return outs
+
+    def forces_batched(self, systems, *, eps, theta, p):
+        self.build_batched(systems, eps=eps, theta=theta)
+        return self.evaluate_batched(systems, p=p)
 
     def tree_info(self):
         import numpy as np
