@@ -45,6 +45,26 @@ def m2l_flops_per_pair(p):
 P2P_FLOPS_PER_PAIR = 30.0  # per unordered particle pair (rsqrt counted as 1)
 
 
+def recorded_traffic(kernel, p):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if it was taken for another order or the kernel sources changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_cold_collapse_1M.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"traffic_bytes_per_launch: (.*)", open(path).read())
+    if not m:
+        return None
+    kv = dict(x.split("=", 1) for x in m.group(1).split())
+    csrc = os.path.join(ROOT, "paper_1712_10116_amd", "csrc")
+    sha = hashlib.sha256(open(os.path.join(csrc, "eval.hip"), "rb").read() +
+                         open(os.path.join(csrc, "expansion.h"), "rb").read()).hexdigest()
+    if kv.get("source_sha256") != sha or kv.get("p") != str(p) or kernel not in kv:
+        return None
+    return int(kv[kernel])
+
+
 def force_error(acc, ref):
     mag = np.sqrt((ref * ref).sum(axis=0))
     floor = 1e-6 * np.sqrt((mag * mag).mean())
@@ -179,7 +199,8 @@ def main():
     dom = max(kern, key=lambda k: kern[k]["ms"])
     roof = dict(kernel=dom, bound="alu", achieved=round(kern[dom]["tflops"], 3),
                 peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                frac=round(kern[dom]["tflops"] / PEAK_FP32_TFLOPS, 4), traffic=None)
+                frac=round(kern[dom]["tflops"] / PEAK_FP32_TFLOPS, 4),
+                traffic=recorded_traffic(dom, args.p))
 
     line = {
         "metric": METRIC,
