@@ -128,7 +128,8 @@ typedef struct {
     int64_t n_total;
     const int32_t *active;  /* device int32[n_active], or NULL = all n_total    */
     int64_t n_active;
-    const double *mass;     /* device, n_total doubles                         */
+    const double *mass;     /* device, n_total doubles; NULL in an evaluation:
+                               the system is skipped, acc/pot left untouched   */
     double *acc;            /* device, 3 x n_active doubles (out)              */
     double *pot;            /* device, n_active doubles (out)                  */
 } fmm_request;
@@ -140,7 +141,8 @@ fmm_status fmm_build_batched(fmm_ctx *ctx, int n_req, const fmm_request *reqs, d
 
 /* Evaluate the n_req systems of the last fmm_build_batched (same pos, active,
  * n_total, n_active in the same order, else FMM_ESTALE); masses and outputs
- * may differ from call to call.  Asynchronous, like fmm_evaluate. */
+ * may differ from call to call, and a system with mass == NULL is skipped.
+ * Asynchronous, like fmm_evaluate. */
 fmm_status fmm_evaluate_batched(fmm_ctx *ctx, int n_req, const fmm_request *reqs, int p);
 
 /* fmm_build_batched followed by fmm_evaluate_batched. */
@@ -218,6 +220,34 @@ fmm_status hhs_init(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp);
  * [0] force calls, [1] sum of active particles over the calls, [2] tree builds. */
 fmm_status hhs_step(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp, double dt_top,
                     int64_t stats[3]);
+
+/* Device scratch of one system's integration (rung split lists for every
+ * rung, masked masses, accelerations): about hhs_run_bytes(n, max_levels)
+ * bytes of device memory, owned by the run and freed by hhs_run_destroy
+ * (which waits for the context's stream).  Serves systems of up to n
+ * particles and max_levels rungs.  FMM_EINVAL for n < 1 or max_levels
+ * outside 1..30, FMM_ENOMEM when the device is full (nothing kept). */
+typedef struct hhs_run hhs_run;
+int64_t hhs_run_bytes(int64_t n, int max_levels);
+fmm_status hhs_run_create(fmm_ctx *ctx, int64_t n, int max_levels, hhs_run **out);
+fmm_status hhs_run_destroy(hhs_run *run);
+
+/* hhs_init for n_sys independent systems in one batched force solve; runs[i]
+ * is the scratch of states[i] (distinct runs, distinct state arrays). */
+fmm_status hhs_init_batched(fmm_ctx *ctx, int n_sys, hhs_run *const *runs,
+                            hhs_state *const *states, const hhs_params *hp);
+
+/* One top-level step of each of n_sys independent systems (dt_top[i] for
+ * states[i], dt_top a HOST array), with the semantics of hhs_step.  The
+ * systems advance together: whenever several wait on a KDK (Algorithm 2)
+ * their trees are built in one fmm_build_batched and their kicks evaluated in
+ * two fmm_evaluate_batched calls, so every system ends bit-identical to a
+ * hhs_step of it alone.  The sum of the particles of systems that wait
+ * together must fit max_n.  stats: [0] force evaluations summed over the
+ * systems, [1] sum of active particles over them, [2] batched tree builds. */
+fmm_status hhs_step_batched(fmm_ctx *ctx, int n_sys, hhs_run *const *runs,
+                            hhs_state *const *states, const hhs_params *hp,
+                            const double *dt_top, int64_t stats[3]);
 
 #ifdef __cplusplus
 }

@@ -16,40 +16,12 @@
 
 #include "../../include/fmm355.h"
 #include "common.h"
+#include "context.h"
 #include "hhs_kernels.h"
-
-struct fmm_ctx {
-  fmm_params prm;
-  int64_t max_n;
-  hipStream_t stream;
-  int device;
-  DevTree t;
-  std::vector<void *> allocs;
-  // host copy of the last build
-  Header hh;
-  bool tree_valid;
-  std::vector<fmm_request> b_reqs;  // requests of the last build
-  int64_t b_n;                      // their active particles in all
-  double b_eps, b_theta;
-  std::vector<DevReq> h_reqs;       // staging of the device request table
-  std::vector<int32_t> h_off, h_blk;
-  int n_nodes, depth;
-  // HHS scratch
-  int hhs_levels;
-  int32_t **lv_slow, **lv_slow_pos, **lv_fast, **lv_fast_pos;
-  int32_t *all_idx;
-  uint32_t *flag;
-  int32_t *count;
-  double *mmask, *acc, *pot;
-  double *inv_part;
-  int64_t stat_calls, stat_parts, stat_builds;
-  PhaseTimer timer;
-  char err[512];
-};
 
 static PhaseTimer *timer_of(fmm_ctx *c) { return c->timer.on ? &c->timer : nullptr; }
 
-static fmm_status fail(fmm_ctx *c, fmm_status st, const char *fmt, ...) {
+fmm_status fmm_fail(fmm_ctx *c, fmm_status st, const char *fmt, ...) {
   if (c) {
     va_list ap;
     va_start(ap, fmt);
@@ -68,17 +40,11 @@ static fmm_status fail(fmm_ctx *c, fmm_status st, const char *fmt, ...) {
 
 static int coeffs(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 
-template <typename T>
-static bool dalloc(fmm_ctx *c, T **p, int64_t count) {
-  void *q = nullptr;
-  size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
-  if (hipMalloc(&q, bytes) != hipSuccess) return false;
-  c->allocs.push_back(q);
-  *p = (T *)q;
-  return true;
-}
+#define fail fmm_fail
+#define dalloc fmm_dalloc
+#define dfree fmm_dfree
 
-static void dfree(fmm_ctx *c, void *p) {
+void fmm_dfree(fmm_ctx *c, void *p) {
   if (!p) return;
   auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
   if (it != c->allocs.end()) c->allocs.erase(it);
@@ -166,10 +132,7 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
     ok = dalloc(c, &t.m2l_src, t.cap_m2l) && dalloc(c, &t.p2p_src, t.cap_p2p) &&
          dalloc(c, &t.open_buf0, t.cap_open) && dalloc(c, &t.open_buf1, t.cap_open);
   }
-  // HHS scratch (levels allocated lazily)
-  ok = ok && dalloc(c, &c->all_idx, n) && dalloc(c, &c->flag, n) && dalloc(c, &c->count, 4) &&
-       dalloc(c, &c->mmask, n) && dalloc(c, &c->acc, 3 * n) && dalloc(c, &c->pot, n) &&
-       dalloc(c, &c->inv_part, 512 * 12);
+  ok = ok && dalloc(c, &c->inv_part, 512 * 12);
   if (!ok) {
     fmm_destroy(c);
     return FMM_ENOMEM;
@@ -191,13 +154,8 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
       (void)hipEventDestroy(c->timer.a[i]);
       (void)hipEventDestroy(c->timer.b[i]);
     }
+  if (c->own_run) hhs_run_destroy(c->own_run);
   for (void *p : c->allocs) (void)hipFree(p);
-  if (c->lv_slow) {
-    free(c->lv_slow);
-    free(c->lv_slow_pos);
-    free(c->lv_fast);
-    free(c->lv_fast_pos);
-  }
   delete c;
   return FMM_OK;
 }
@@ -217,8 +175,8 @@ static fmm_status check_requests(fmm_ctx *c, int n_req, const fmm_request *reqs,
       return fail(c, FMM_EINVAL, "request %d: n_total=%lld inconsistent with n_active=%lld", r,
                   (long long)q.n_total, (long long)q.n_active);
     if (q.n_active > 0 && !q.pos) return fail(c, FMM_EINVAL, "request %d: pos is NULL", r);
-    if (eval && q.n_active > 0 && (!q.mass || !q.acc || !q.pot))
-      return fail(c, FMM_EINVAL, "request %d: NULL mass/acc/pot", r);
+    if (eval && q.n_active > 0 && q.mass && (!q.acc || !q.pot))
+      return fail(c, FMM_EINVAL, "request %d: NULL acc/pot", r);
     n += q.n_active;
   }
   if (n > c->max_n)
@@ -406,7 +364,8 @@ extern "C" fmm_status fmm_evaluate_batched(fmm_ctx *c, int n_req, const fmm_requ
   e.tm = timer_of(c);
   HIPCHK(c, launch_evaluate(c->t, e, c->stream));
   c->stat_calls++;
-  c->stat_parts += n_all;
+  for (int r = 0; r < n_req; ++r)
+    if (reqs[r].mass) c->stat_parts += reqs[r].n_active;
   return FMM_OK;
 }
 
@@ -573,162 +532,6 @@ extern "C" fmm_status fmm_invariants(fmm_ctx *c, const double *pos, const double
     for (int b = 0; b < nblk; ++b) s += part[b * 12 + k];
     out[k] = s;
   }
-  return FMM_OK;
-}
-
-// ---------------------------------------------------------------------------
-// HHS integrator: Algorithms 1-3
-// ---------------------------------------------------------------------------
-static fmm_status hhs_alloc(fmm_ctx *c, int levels) {
-  if (c->hhs_levels >= levels) return FMM_OK;
-  int64_t n = c->max_n;
-  int32_t **a = (int32_t **)calloc(levels, sizeof(int32_t *));
-  int32_t **b = (int32_t **)calloc(levels, sizeof(int32_t *));
-  int32_t **d = (int32_t **)calloc(levels, sizeof(int32_t *));
-  int32_t **e = (int32_t **)calloc(levels, sizeof(int32_t *));
-  for (int l = 0; l < c->hhs_levels; ++l) {
-    a[l] = c->lv_slow[l];
-    b[l] = c->lv_slow_pos[l];
-    d[l] = c->lv_fast[l];
-    e[l] = c->lv_fast_pos[l];
-  }
-  for (int l = c->hhs_levels; l < levels; ++l)
-    if (!dalloc(c, &a[l], n) || !dalloc(c, &b[l], n) || !dalloc(c, &d[l], n) ||
-        !dalloc(c, &e[l], n))
-      return fail(c, FMM_ENOMEM, "HHS level buffers");
-  free(c->lv_slow);
-  free(c->lv_slow_pos);
-  free(c->lv_fast);
-  free(c->lv_fast_pos);
-  c->lv_slow = a;
-  c->lv_slow_pos = b;
-  c->lv_fast = d;
-  c->lv_fast_pos = e;
-  c->hhs_levels = levels;
-  return FMM_OK;
-}
-
-struct HHSRun {
-  fmm_ctx *c;
-  hhs_state *st;
-  const hhs_params *hp;
-  double dt_top;
-};
-
-// one kick of Algorithm 3 on `set` (positions setpos inside the joint list)
-static fmm_status hhs_force(HHSRun &r, const int32_t *joint, int n_joint, const double *mass) {
-  fmm_ctx *c = r.c;
-  return fmm_evaluate(c, r.st->pos, mass, r.st->n, joint, n_joint, r.hp->p, c->acc, c->pot);
-}
-
-static fmm_status hhs_kdk(HHSRun &r, int k, const int32_t *sys, int n_sys, const int32_t *slow,
-                          const int32_t *slow_pos, int n_slow, const int32_t *fast,
-                          const int32_t *fast_pos, int n_fast, double dt) {
-  fmm_ctx *c = r.c;
-  hhs_state *st = r.st;
-  const hhs_params *hp = r.hp;
-  const bool s2f = n_fast > 0 && n_slow > 0;
-  fmm_status e;
-  for (int half = 0; half < 2; ++half) {
-    const bool second = half == 1;
-    if (half == 1) hhs_launch_drift(slow, n_slow, st->vel, st->pos, st->n, dt, c->stream);
-    if (!(s2f || n_slow > 0)) continue;
-    e = fmm_build(c, st->pos, st->n, sys, n_sys, hp->eps, hp->theta);
-    if (e != FMM_OK) return e;
-    // kickS2F before kickFS2S on the first half, after it on the second
-    for (int kk = 0; kk < 2; ++kk) {
-      const bool do_s2f = (kk == 0) != second;
-      if (do_s2f) {
-        if (!s2f) continue;
-        hhs_launch_masked_mass(st->mass, st->n, fast, n_fast, c->mmask, c->stream);
-        e = hhs_force(r, sys, n_sys, c->mmask);
-        if (e != FMM_OK) return e;
-        hhs_launch_kick(fast, fast_pos, n_fast, c->acc, n_sys, st->vel, st->n, 0.5 * dt,
-                        second ? st->a_old : nullptr, c->stream);
-      } else {
-        if (n_slow == 0) continue;
-        e = hhs_force(r, sys, n_sys, st->mass);
-        if (e != FMM_OK) return e;
-        hhs_launch_kick(slow, slow_pos, n_slow, c->acc, n_sys, st->vel, st->n, 0.5 * dt,
-                        second ? st->a_cur : nullptr, c->stream);
-      }
-    }
-  }
-  (void)k;
-  return FMM_OK;
-}
-
-static fmm_status hhs_evolve(HHSRun &r, int k, const int32_t *sys, int n_sys, double dt,
-                             bool calc) {
-  fmm_ctx *c = r.c;
-  hhs_state *st = r.st;
-  const hhs_params *hp = r.hp;
-  if (k >= c->hhs_levels) return fail(c, FMM_EINVAL, "rung recursion deeper than max_levels");
-  if (calc && !hp->freeze_rungs)
-    hhs_launch_rungs(sys, n_sys, st->a_old, st->a_cur, st->rung, r.dt_top, hp->eta * hp->eps,
-                     hp->max_levels, c->stream);
-  int32_t *slow = c->lv_slow[k], *slow_pos = c->lv_slow_pos[k];
-  int32_t *fast = c->lv_fast[k], *fast_pos = c->lv_fast_pos[k];
-  hhs_launch_split(sys, n_sys, st->rung, k, c->flag, c->t.scan_blk, slow, slow_pos, fast,
-                   fast_pos, c->count, c->stream);
-  int32_t n_fast = 0;
-  HIPCHK(c, hipMemcpyAsync(&n_fast, c->count, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  const int n_slow = n_sys - n_fast;
-  fmm_status e;
-  if (n_fast > 0) {
-    e = hhs_evolve(r, k + 1, fast, n_fast, 0.5 * dt, false);
-    if (e != FMM_OK) return e;
-  }
-  e = hhs_kdk(r, k, sys, n_sys, slow, slow_pos, n_slow, fast, fast_pos, n_fast, dt);
-  if (e != FMM_OK) return e;
-  if (n_fast > 0) {
-    e = hhs_evolve(r, k + 1, fast, n_fast, 0.5 * dt, true);
-    if (e != FMM_OK) return e;
-  }
-  return FMM_OK;
-}
-
-static fmm_status hhs_check(fmm_ctx *c, hhs_state *st, const hhs_params *hp) {
-  if (!c || !st || !hp) return FMM_EINVAL;
-  if (st->n < 1 || st->n > c->max_n) return fail(c, FMM_EINVAL, "state size outside [1, max_n]");
-  if (!st->pos || !st->vel || !st->mass || !st->a_old || !st->a_cur || !st->rung)
-    return fail(c, FMM_EINVAL, "NULL state array");
-  if (hp->max_levels < 1 || hp->max_levels > 30 || !(hp->eta > 0) || hp->p < 1 ||
-      hp->p > c->prm.p_max)
-    return fail(c, FMM_EINVAL, "bad HHS parameters");
-  return hhs_alloc(c, hp->max_levels + 1);
-}
-
-extern "C" fmm_status hhs_init(fmm_ctx *c, hhs_state *st, const hhs_params *hp) {
-  fmm_status e = hhs_check(c, st, hp);
-  if (e != FMM_OK) return e;
-  e = fmm_forces(c, st->pos, st->mass, st->n, nullptr, st->n, hp->eps, hp->theta, hp->p, c->acc,
-                 c->pot);
-  if (e != FMM_OK) return e;
-  hhs_launch_amag(c->acc, st->n, st->a_cur, st->a_old, c->stream);
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return FMM_OK;
-}
-
-extern "C" fmm_status hhs_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp, double dt_top,
-                               int64_t stats[3]) {
-  fmm_status e = hhs_check(c, st, hp);
-  if (e != FMM_OK) return e;
-  if (!std::isfinite(dt_top) || dt_top == 0.0) return fail(c, FMM_EINVAL, "dt_top");
-  int64_t c0 = c->stat_calls, p0 = c->stat_parts, b0 = c->stat_builds;
-  hhs_launch_iota(c->all_idx, (int)st->n, c->stream);
-  HHSRun r{c, st, hp, dt_top};
-  e = hhs_evolve(r, 0, c->all_idx, (int)st->n, dt_top, true);
-  if (e != FMM_OK) return e;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  st->t += dt_top;
-  if (stats) {
-    stats[0] = c->stat_calls - c0;
-    stats[1] = c->stat_parts - p0;
-    stats[2] = c->stat_builds - b0;
-  }
-  c->tree_valid = false;
   return FMM_OK;
 }
 

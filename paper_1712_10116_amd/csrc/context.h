@@ -1,0 +1,49 @@
+// Solver context shared by the translation units of the C ABI.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/fmm355.h"
+#include "common.h"
+
+struct fmm_ctx {
+  fmm_params prm;
+  int64_t max_n;
+  hipStream_t stream;
+  int device;
+  DevTree t;
+  std::vector<void *> allocs;
+  // host copy of the last build
+  Header hh;
+  bool tree_valid;
+  std::vector<fmm_request> b_reqs;  // requests of the last build
+  int64_t b_n;                      // their active particles in all
+  double b_eps, b_theta;
+  std::vector<DevReq> h_reqs;       // staging of the device request table
+  std::vector<int32_t> h_off, h_blk;
+  int n_nodes, depth;
+  // integrator
+  hhs_run *own_run;       // scratch of hhs_init / hhs_step (one system)
+  int32_t *split_cnt;     // [cap_split] fast-set sizes of pending splits
+  int cap_split;
+  std::vector<int32_t> h_split;
+  double *inv_part;
+  int64_t stat_calls, stat_parts, stat_builds;
+  PhaseTimer timer;
+  char err[512];
+};
+
+
+fmm_status fmm_fail(fmm_ctx *c, fmm_status st, const char *fmt, ...);
+
+template <typename T>
+bool fmm_dalloc(fmm_ctx *c, T **p, int64_t count) {
+  void *q = nullptr;
+  size_t bytes = (size_t)(count > 1 ? count : 1) * sizeof(T);
+  if (hipMalloc(&q, bytes) != hipSuccess) return false;
+  c->allocs.push_back(q);
+  *p = (T *)q;
+  return true;
+}
+void fmm_dfree(fmm_ctx *c, void *p);

@@ -22,6 +22,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_gather_mass(DevTree t, int n) {
   if (j >= n) return;
   const int s = t.slot[j];
   const DevReq q = t.reqs[t.slot_req[s]];
+  if (!q.mass) return;  // system skipped in this evaluation
   const int i = s - q.off;
   int64_t g = q.active ? q.active[i] : i;
   double m = q.mass[g];
@@ -45,13 +46,18 @@ __device__ __forceinline__ void store_row(T *__restrict__ base, int kmax, int no
   for (int t = 0; t < MI<P>::K; ++t) row[t] = v[t];
 }
 
+// a system whose mass pointer is NULL is skipped by this evaluation
+__device__ __forceinline__ bool skipped(const DevTree &t, int node) {
+  return t.reqs[t.nreq[node]].mass == nullptr;
+}
+
 // P2M at leaves: Mt[k] = sum_j m_j (u_j/h)^k/k!  (compensated in FP32)
 template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes) {
   constexpr int K = MI<P>::K;
   T *M = (T *)t.M;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes; i += gridDim.x * blockDim.x) {
-    if (t.nnchild[i] != 0) continue;
+    if (t.nnchild[i] != 0 || skipped(t, i)) continue;
     const double4 g = t.ngeo[i];
     const double ih = 1.0 / g.w;
     T acc[K], cmp[K];
@@ -85,7 +91,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e) {
   T *M = (T *)t.M;
   for (int i = s + blockIdx.x * blockDim.x + threadIdx.x; i < e; i += gridDim.x * blockDim.x) {
     int nc = t.nnchild[i];
-    if (nc == 0) continue;
+    if (nc == 0 || skipped(t, i)) continue;
     const double4 gp = t.ngeo[i];
     const double ih = 1.0 / gp.w;
     T acc[K];
@@ -117,6 +123,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, doubl
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   for (int A = wave; A < n_nodes; A += nwaves) {
+    if (skipped(t, A)) continue;
     const double4 gA = t.ngeo[A];
     const double ih = 1.0 / gA.w;
     const T e2 = KERNEL == 1 ? (T)((eps * ih) * (eps * ih)) : T(0);
@@ -154,6 +161,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2l(DevTree t, int s, int e) {
   constexpr int K = MI<P>::K;
   T *L = (T *)t.L;
   for (int c = s + blockIdx.x * blockDim.x + threadIdx.x; c < e; c += gridDim.x * blockDim.x) {
+    if (skipped(t, c)) continue;
     const int p = t.nparent[c];
     const double4 gp = t.ngeo[p], gc = t.ngeo[c];
     const double ih = 1.0 / gp.w;
@@ -174,6 +182,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int leaf = t.leaf_of[j];
+  if (skipped(t, leaf)) return;
   const double4 g = t.ngeo[leaf];
   const double ih = 1.0 / g.w;
   T mono[K], Lt[K];
@@ -261,7 +270,7 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
   const R inv_eps3 = eps > 0 ? (R)(1.0 / (eps * eps * eps)) : R(0);
   const int64_t cap = t.cap_n;
   for (int A = wave; A < n_nodes; A += nwaves) {
-    if (t.nnchild[A] != 0) continue;
+    if (t.nnchild[A] != 0 || skipped(t, A)) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
     const int nt = nA < 64 ? nA : 64;
     int lg = 0;

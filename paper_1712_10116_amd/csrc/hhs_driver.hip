@@ -1,0 +1,426 @@
+// HHS integrator driver (Sec. 2.2, Algorithms 1-3) for one or many
+// independent systems.
+//
+// Each system's EVOLVE_HOLD recursion is an explicit frame stack.  A system
+// runs on the host until it needs either the size of a slow/fast split (a
+// device count) or a KDK half: the force solve(s) of Algorithm 2 at one set of
+// positions -- one tree over the system, then up to two evaluations
+// (kickS2F with the fast masses zeroed, kickFS2S with all masses) each followed
+// by its kick.  The driver then serves every waiting system at once: one
+// readback for all pending splits, or one batched tree build and two batched
+// evaluation slots for all systems waiting on a half (a system with nothing to
+// evaluate in a slot is skipped).  Kicks of one half act on disjoint particle
+// sets and the evaluations do not read velocities, so every system follows
+// exactly the sequence it would follow alone.
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/fmm355.h"
+#include "common.h"
+#include "context.h"
+#include "hhs_kernels.h"
+
+struct hhs_run {
+  fmm_ctx *ctx;
+  int64_t n;
+  int levels;
+  std::vector<void *> mem;
+  int32_t *all_idx;
+  uint32_t *flag, *scan_part;
+  std::vector<int32_t *> slow, slow_pos, fast, fast_pos;  // per rung
+  double *mmask, *acc, *pot;
+};
+
+template <typename T>
+static bool ralloc(hhs_run *r, T **p, int64_t count) {
+  void *q = nullptr;
+  if (hipMalloc(&q, (size_t)std::max<int64_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
+  r->mem.push_back(q);
+  *p = (T *)q;
+  return true;
+}
+
+extern "C" int64_t hhs_run_bytes(int64_t n, int max_levels) {
+  int64_t lv = (int64_t)(max_levels + 1) * 4 * n * 4;
+  return lv + n * (4 + 4 + 8 + 24 + 8) + (n / 1024 + 64) * 4;
+}
+
+extern "C" fmm_status hhs_run_create(fmm_ctx *c, int64_t n, int max_levels, hhs_run **out) {
+  if (!c || !out || n < 1 || max_levels < 1 || max_levels > 30) return FMM_EINVAL;
+  hhs_run *r = new (std::nothrow) hhs_run();
+  if (!r) return FMM_ENOMEM;
+  r->ctx = c;
+  r->n = n;
+  r->levels = max_levels + 1;
+  bool ok = ralloc(r, &r->all_idx, n) && ralloc(r, &r->flag, n) &&
+            ralloc(r, &r->scan_part, n / 1024 + 64) && ralloc(r, &r->mmask, n) &&
+            ralloc(r, &r->acc, 3 * n) && ralloc(r, &r->pot, n);
+  r->slow.resize(r->levels);
+  r->slow_pos.resize(r->levels);
+  r->fast.resize(r->levels);
+  r->fast_pos.resize(r->levels);
+  for (int l = 0; ok && l < r->levels; ++l)
+    ok = ralloc(r, &r->slow[l], n) && ralloc(r, &r->slow_pos[l], n) && ralloc(r, &r->fast[l], n) &&
+         ralloc(r, &r->fast_pos[l], n);
+  if (!ok) {
+    hhs_run_destroy(r);
+    return FMM_ENOMEM;
+  }
+  hhs_launch_iota(r->all_idx, (int)n, c->stream);
+  *out = r;
+  return FMM_OK;
+}
+
+extern "C" fmm_status hhs_run_destroy(hhs_run *r) {
+  if (!r) return FMM_EINVAL;
+  if (r->ctx) (void)hipStreamSynchronize(r->ctx->stream);
+  for (void *p : r->mem) (void)hipFree(p);
+  delete r;
+  return FMM_OK;
+}
+
+namespace {
+
+struct Frame {
+  int k;
+  const int32_t *sys;
+  int n_sys;
+  double dt;
+  bool calc;
+  int pc;
+  int n_fast, n_slow;
+};
+
+enum SysState { S_RUN, S_WAIT_SPLIT, S_WAIT_HALF, S_DONE };
+
+struct Sys {
+  hhs_run *run;
+  hhs_state *st;
+  double dt_top;
+  std::vector<Frame> stack;
+  SysState state;
+  int half;
+};
+
+// One kick of Algorithm 3 inside a KDK half: which set is kicked, with which
+// masses, and which |a| slot a second kick refreshes.
+struct Kick {
+  bool s2f;     // kickS2F (fast sinks, fast masses zeroed) or kickFS2S
+  bool second;  // second kick of the KDK
+};
+
+int kicks_of_half(const Frame &f, int half, Kick out[2]) {
+  const bool s2f = f.n_fast > 0 && f.n_slow > 0;
+  int n = 0;
+  if (half == 0) {
+    if (s2f) out[n++] = {true, false};
+    if (f.n_slow) out[n++] = {false, false};
+  } else {
+    if (f.n_slow) out[n++] = {false, true};
+    if (s2f) out[n++] = {true, true};
+  }
+  return n;
+}
+
+// Runs system S until it waits on the device or finishes; false when the
+// rung recursion would go deeper than the scratch holds.
+bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
+  hhs_run *r = S.run;
+  hhs_state *st = S.st;
+  while (S.state == S_RUN) {
+    if (S.stack.empty()) {
+      S.state = S_DONE;
+      return true;
+    }
+    Frame &f = S.stack.back();
+    const int k = f.k;
+    if (k >= r->levels) return false;
+    switch (f.pc) {
+      case 0:  // (re)assign rungs, split into slow {rung <= k} and fast {rung > k}
+        if (f.calc && !hp->freeze_rungs)
+          hhs_launch_rungs(f.sys, f.n_sys, st->a_old, st->a_cur, st->rung, S.dt_top,
+                           hp->eta * hp->eps, hp->max_levels, c->stream);
+        hhs_launch_split(f.sys, f.n_sys, st->rung, k, r->flag, r->scan_part, r->slow[k],
+                         r->slow_pos[k], r->fast[k], r->fast_pos[k], c->split_cnt + slot,
+                         c->stream);
+        f.pc = 1;
+        S.state = S_WAIT_SPLIT;
+        return true;
+      case 1: {  // first half of the fast system's evolution
+        f.pc = 2;
+        if (f.n_fast > 0) {
+          Frame ch{k + 1, r->fast[k], f.n_fast, 0.5 * f.dt, false, 0, 0, 0};
+          S.stack.push_back(ch);
+        }
+        break;
+      }
+      case 2:  // KDK, first half: kicks at the current positions
+        f.pc = 3;
+        if ((f.n_fast > 0 && f.n_slow > 0) || f.n_slow > 0) {
+          S.half = 0;
+          S.state = S_WAIT_HALF;
+          return true;
+        }
+        break;
+      case 3:  // drift the slow system, second half of the KDK
+        hhs_launch_drift(r->slow[k], f.n_slow, st->vel, st->pos, st->n, f.dt, c->stream);
+        f.pc = 4;
+        if ((f.n_fast > 0 && f.n_slow > 0) || f.n_slow > 0) {
+          S.half = 1;
+          S.state = S_WAIT_HALF;
+          return true;
+        }
+        break;
+      case 4: {  // second half of the fast system's evolution, rungs recomputed
+        f.pc = 5;
+        if (f.n_fast > 0) {
+          Frame ch{k + 1, r->fast[k], f.n_fast, 0.5 * f.dt, true, 0, 0, 0};
+          S.stack.push_back(ch);
+        }
+        break;
+      }
+      default:
+        S.stack.pop_back();
+        break;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+// The KDK halves of W waiting systems: their trees in one batched build, then
+// the kicks of the half in two batched evaluation slots (a system with no kick
+// in a slot is skipped there), each followed by its systems' kicks.
+static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const hhs_params *hp,
+                             int64_t *kicks) {
+  std::vector<fmm_request> q(W);
+  std::vector<Kick> kk(2 * W, Kick{false, false});
+  std::vector<int> nk(W);
+  for (int w = 0; w < W; ++w) {
+    Sys &S = sys[grp[w]];
+    const Frame &f = S.stack.back();
+    q[w] = fmm_request{S.st->pos, S.st->n, f.sys, f.n_sys, nullptr, S.run->acc, S.run->pot};
+    nk[w] = kicks_of_half(f, S.half, &kk[2 * w]);
+  }
+  fmm_status e = fmm_build_batched(c, W, q.data(), hp->eps, hp->theta);
+  if (e != FMM_OK) return e;
+  for (int slot = 0; slot < 2; ++slot) {
+    bool any = false;
+    for (int w = 0; w < W; ++w) {
+      Sys &S = sys[grp[w]];
+      const Frame &f = S.stack.back();
+      q[w].mass = nullptr;
+      if (slot >= nk[w]) continue;
+      any = true;
+      if (kk[2 * w + slot].s2f) {
+        hhs_launch_masked_mass(S.st->mass, S.st->n, S.run->fast[f.k], f.n_fast, S.run->mmask,
+                               c->stream);
+        q[w].mass = S.run->mmask;
+      } else {
+        q[w].mass = S.st->mass;
+      }
+    }
+    if (!any) continue;
+    e = fmm_evaluate_batched(c, W, q.data(), hp->p);
+    if (e != FMM_OK) return e;
+    for (int w = 0; w < W; ++w) {
+      if (slot >= nk[w]) continue;
+      Sys &S = sys[grp[w]];
+      const Frame &f = S.stack.back();
+      const Kick &K = kk[2 * w + slot];
+      const int k = f.k;
+      if (K.s2f)
+        hhs_launch_kick(S.run->fast[k], S.run->fast_pos[k], f.n_fast, S.run->acc, f.n_sys,
+                        S.st->vel, S.st->n, 0.5 * f.dt, K.second ? S.st->a_old : nullptr,
+                        c->stream);
+      else
+        hhs_launch_kick(S.run->slow[k], S.run->slow_pos[k], f.n_slow, S.run->acc, f.n_sys,
+                        S.st->vel, S.st->n, 0.5 * f.dt, K.second ? S.st->a_cur : nullptr,
+                        c->stream);
+      ++*kicks;
+    }
+  }
+  return FMM_OK;
+}
+
+static fmm_status ensure_split_slots(fmm_ctx *c, int n) {
+  if (n <= c->cap_split) return FMM_OK;
+  if (c->split_cnt) fmm_dfree(c, c->split_cnt);
+  c->split_cnt = nullptr;
+  int cap = std::max(n, 2 * c->cap_split);
+  if (!fmm_dalloc(c, &c->split_cnt, cap)) return fmm_fail(c, FMM_ENOMEM, "split counters");
+  c->cap_split = cap;
+  return FMM_OK;
+}
+
+static fmm_status check_system(fmm_ctx *c, hhs_run *r, hhs_state *st, const hhs_params *hp) {
+  if (!r || !st) return fmm_fail(c, FMM_EINVAL, "NULL system");
+  if (st->n < 1 || st->n > r->n) return fmm_fail(c, FMM_EINVAL, "state larger than its scratch");
+  if (!st->pos || !st->vel || !st->mass || !st->a_old || !st->a_cur || !st->rung)
+    return fmm_fail(c, FMM_EINVAL, "NULL state array");
+  if (hp->max_levels + 1 > r->levels) return fmm_fail(c, FMM_EINVAL, "scratch has too few rungs");
+  return FMM_OK;
+}
+
+static fmm_status check_distinct(fmm_ctx *c, int n_sys, hhs_run *const *runs,
+                                 hhs_state *const *states) {
+  std::vector<const void *> v;
+  for (int i = 0; i < n_sys; ++i) {
+    v.push_back(runs[i]);
+    if (states[i]) v.push_back(states[i]->pos);
+  }
+  std::sort(v.begin(), v.end());
+  if (std::adjacent_find(v.begin(), v.end()) != v.end())
+    return fmm_fail(c, FMM_EINVAL, "systems share a run or a state");
+  return FMM_OK;
+}
+
+static fmm_status check_params(fmm_ctx *c, const hhs_params *hp) {
+  if (!c || !hp) return FMM_EINVAL;
+  if (hp->max_levels < 1 || hp->max_levels > 30 || !(hp->eta > 0) || hp->p < 1 ||
+      hp->p > c->prm.p_max)
+    return fmm_fail(c, FMM_EINVAL, "bad HHS parameters");
+  return FMM_OK;
+}
+
+extern "C" fmm_status hhs_init_batched(fmm_ctx *c, int n_sys, hhs_run *const *runs,
+                                       hhs_state *const *states, const hhs_params *hp) {
+  fmm_status e = check_params(c, hp);
+  if (e != FMM_OK) return e;
+  if (n_sys < 1 || !runs || !states) return fmm_fail(c, FMM_EINVAL, "no systems");
+  e = check_distinct(c, n_sys, runs, states);
+  if (e != FMM_OK) return e;
+  std::vector<fmm_request> q(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    e = check_system(c, runs[i], states[i], hp);
+    if (e != FMM_OK) return e;
+    hhs_state *st = states[i];
+    q[i] = fmm_request{st->pos, st->n, nullptr, st->n, st->mass, runs[i]->acc, runs[i]->pot};
+  }
+  for (int g0 = 0; g0 < n_sys;) {  // groups that fit the context
+    int g1 = g0;
+    int64_t tot = 0;
+    while (g1 < n_sys && (g1 == g0 || tot + q[g1].n_active <= c->max_n)) tot += q[g1++].n_active;
+    e = fmm_forces_batched(c, g1 - g0, q.data() + g0, hp->eps, hp->theta, hp->p);
+    if (e != FMM_OK) return e;
+    g0 = g1;
+  }
+  for (int i = 0; i < n_sys; ++i)
+    hhs_launch_amag(runs[i]->acc, states[i]->n, states[i]->a_cur, states[i]->a_old, c->stream);
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return fmm_fail(c, FMM_EDEVICE, "hhs_init synchronisation failed");
+  return FMM_OK;
+}
+
+extern "C" fmm_status hhs_step_batched(fmm_ctx *c, int n_sys, hhs_run *const *runs,
+                                       hhs_state *const *states, const hhs_params *hp,
+                                       const double *dt_top, int64_t stats[3]) {
+  fmm_status e = check_params(c, hp);
+  if (e != FMM_OK) return e;
+  if (n_sys < 1 || !runs || !states || !dt_top) return fmm_fail(c, FMM_EINVAL, "no systems");
+  e = check_distinct(c, n_sys, runs, states);
+  if (e != FMM_OK) return e;
+  e = ensure_split_slots(c, n_sys);
+  if (e != FMM_OK) return e;
+  std::vector<Sys> sys(n_sys);
+  for (int i = 0; i < n_sys; ++i) {
+    e = check_system(c, runs[i], states[i], hp);
+    if (e != FMM_OK) return e;
+    if (!std::isfinite(dt_top[i]) || dt_top[i] == 0.0)
+      return fmm_fail(c, FMM_EINVAL, "dt_top of system %d", i);
+    Sys &S = sys[i];
+    S.run = runs[i];
+    S.st = states[i];
+    S.dt_top = dt_top[i];
+    S.state = S_RUN;
+    S.half = 0;
+    S.stack.push_back(Frame{0, runs[i]->all_idx, (int)states[i]->n, dt_top[i], true, 0, 0, 0});
+  }
+  const int64_t c0 = c->stat_parts, b0 = c->stat_builds;
+  int64_t kicks = 0;
+  std::vector<int> wait;
+  c->h_split.resize(n_sys);
+  for (;;) {
+    for (int i = 0; i < n_sys; ++i)
+      if (sys[i].state == S_RUN && !advance(c, sys[i], hp, i))
+        return fmm_fail(c, FMM_EINVAL, "system %d: rung recursion deeper than max_levels", i);
+    wait.clear();
+    for (int i = 0; i < n_sys; ++i)
+      if (sys[i].state == S_WAIT_SPLIT) wait.push_back(i);
+    if (!wait.empty()) {  // one readback for every pending split
+      if (hipMemcpyAsync(c->h_split.data(), c->split_cnt, sizeof(int32_t) * n_sys,
+                         hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+          hipStreamSynchronize(c->stream) != hipSuccess)
+        return fmm_fail(c, FMM_EDEVICE, "split readback failed");
+      for (int i : wait) {
+        Frame &f = sys[i].stack.back();
+        f.n_fast = c->h_split[i];
+        f.n_slow = f.n_sys - f.n_fast;
+        sys[i].state = S_RUN;
+      }
+      continue;
+    }
+    for (int i = 0; i < n_sys; ++i)
+      if (sys[i].state == S_WAIT_HALF) wait.push_back(i);
+    if (wait.empty()) break;  // every system finished its top-level step
+    // systems waiting on a KDK half, packed greedily into groups that fit
+    // the context; one batched build and two evaluation slots per group
+    size_t g0 = 0;
+    while (g0 < wait.size()) {
+      size_t g1 = g0;
+      int64_t tot = 0;
+      while (g1 < wait.size()) {
+        const int64_t m = sys[wait[g1]].stack.back().n_sys;
+        if (g1 > g0 && tot + m > c->max_n) break;
+        tot += m;
+        ++g1;
+      }
+      e = serve_half(c, sys.data(), wait.data() + g0, (int)(g1 - g0), hp, &kicks);
+      if (e != FMM_OK) return e;
+      g0 = g1;
+    }
+    for (int i : wait) sys[i].state = S_RUN;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return fmm_fail(c, FMM_EDEVICE, "hhs_step synchronisation failed");
+  for (int i = 0; i < n_sys; ++i) states[i]->t += dt_top[i];
+  if (stats) {
+    stats[0] = kicks;
+    stats[1] = c->stat_parts - c0;
+    stats[2] = c->stat_builds - b0;
+  }
+  c->tree_valid = false;
+  return FMM_OK;
+}
+
+static fmm_status own_run(fmm_ctx *c, hhs_state *st, const hhs_params *hp) {
+  hhs_run *r = c->own_run;
+  if (r && r->n >= st->n && r->levels >= hp->max_levels + 1) return FMM_OK;
+  if (r) hhs_run_destroy(r);
+  c->own_run = nullptr;
+  return hhs_run_create(c, c->max_n, std::max(hp->max_levels, 16), &c->own_run);
+}
+
+extern "C" fmm_status hhs_init(fmm_ctx *c, hhs_state *st, const hhs_params *hp) {
+  fmm_status e = check_params(c, hp);
+  if (e != FMM_OK) return e;
+  if (!st) return FMM_EINVAL;
+  if (st->n < 1 || st->n > c->max_n) return fmm_fail(c, FMM_EINVAL, "state size outside [1, max_n]");
+  e = own_run(c, st, hp);
+  if (e != FMM_OK) return e;
+  return hhs_init_batched(c, 1, &c->own_run, &st, hp);
+}
+
+extern "C" fmm_status hhs_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp, double dt_top,
+                               int64_t stats[3]) {
+  fmm_status e = check_params(c, hp);
+  if (e != FMM_OK) return e;
+  if (!st) return FMM_EINVAL;
+  if (st->n < 1 || st->n > c->max_n) return fmm_fail(c, FMM_EINVAL, "state size outside [1, max_n]");
+  e = own_run(c, st, hp);
+  if (e != FMM_OK) return e;
+  return hhs_step_batched(c, 1, &c->own_run, &st, hp, &dt_top, stats);
+}

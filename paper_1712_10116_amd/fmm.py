@@ -22,7 +22,8 @@ EXPORTED = (
     "fmm_create", "fmm_destroy", "fmm_last_error", "fmm_build", "fmm_evaluate", "fmm_forces",
     "fmm_tree_info", "fmm_export_tree", "fmm_invariants", "hhs_init", "hhs_step",
     "fmm_profile_enable", "fmm_profile_read", "fmm_build_batched", "fmm_evaluate_batched",
-    "fmm_forces_batched",
+    "fmm_forces_batched", "hhs_run_bytes", "hhs_run_create", "hhs_run_destroy",
+    "hhs_init_batched", "hhs_step_batched",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -85,9 +86,19 @@ def lib():
         L.fmm_forces_batched.argtypes = [vp, ci, ctypes.POINTER(Request), dbl, dbl, ci]
         L.fmm_profile_enable.argtypes = [vp, ci]
         L.fmm_profile_read.argtypes = [vp, vp, vp]
+        L.hhs_run_bytes.argtypes = [i64, ci]
+        L.hhs_run_create.argtypes = [vp, i64, ci, ctypes.POINTER(vp)]
+        L.hhs_run_destroy.argtypes = [vp]
+        L.hhs_init_batched.argtypes = [vp, ci, ctypes.POINTER(vp),
+                                       ctypes.POINTER(ctypes.POINTER(HHSState)),
+                                       ctypes.POINTER(HHSParams)]
+        L.hhs_step_batched.argtypes = [vp, ci, ctypes.POINTER(vp),
+                                       ctypes.POINTER(ctypes.POINTER(HHSState)),
+                                       ctypes.POINTER(HHSParams), vp, vp]
         for name in EXPORTED:
-            if name != "fmm_last_error":
+            if name not in ("fmm_last_error", "hhs_run_bytes"):
                 getattr(L, name).restype = ctypes.c_int
+        L.hhs_run_bytes.restype = i64
         _lib = L
     return _lib
 
@@ -264,12 +275,41 @@ class Solver:
         return res
 
 
+class HHSRun:
+    """Device scratch of one system's integration (hhs_run_create)."""
+
+    def __init__(self, solver, n, max_levels):
+        self.solver = solver
+        h = ctypes.c_void_p()
+        solver._raise(lib().hhs_run_create(solver._h, int(n), int(max_levels), ctypes.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def nbytes(n, max_levels):
+        return int(lib().hhs_run_bytes(int(n), int(max_levels)))
+
+    def close(self):
+        if self._h:
+            lib().hhs_run_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class HHS:
-    """Device-resident HHS integrator state driven by hhs_init / hhs_step."""
+    """Device-resident HHS integrator state driven by hhs_init / hhs_step.
+
+    With ``run`` (an HHSRun of at least n particles) the system can take part
+    in hhs_init_batched / hhs_step_batched with other systems."""
 
     def __init__(self, solver, pos, vel, mass, *, eps, theta, p, eta, max_levels,
-                 freeze_rungs=False):
+                 freeze_rungs=False, run=None):
         self.solver = solver
+        self.run = run
         n = pos.shape[1]
         for t, nm, shp in ((pos, "pos", (3, n)), (vel, "vel", (3, n)), (mass, "mass", (n,))):
             _check_dev(t, torch.float64, shp, nm)
@@ -297,3 +337,28 @@ class HHS:
         self.solver._raise(lib().hhs_step(self.solver._h, ctypes.byref(self.state),
                                           ctypes.byref(self.params), float(dt_top), _hptr(stats)))
         return dict(force_calls=int(stats[0]), force_particles=int(stats[1]), builds=int(stats[2]))
+
+
+def _batch_args(systems):
+    n = len(systems)
+    runs = (ctypes.c_void_p * n)(*[s.run._h.value for s in systems])
+    sts = (ctypes.POINTER(HHSState) * n)(*[ctypes.pointer(s.state) for s in systems])
+    return n, runs, sts
+
+
+def hhs_init_batched(solver, systems):
+    """hhs_init of several HHS systems (each with its own ``run``) at once."""
+    n, runs, sts = _batch_args(systems)
+    solver._raise(lib().hhs_init_batched(solver._h, n, runs, sts, ctypes.byref(systems[0].params)))
+
+
+def hhs_step_batched(solver, systems, dt_top):
+    """One top-level step of each system (dt_top: one value or one per system);
+    every system ends as after an hhs_step of it alone."""
+    import numpy as np
+    n, runs, sts = _batch_args(systems)
+    dts = np.broadcast_to(np.asarray(dt_top, dtype=np.float64), (n,)).copy()
+    stats = np.zeros(3, dtype=np.int64)
+    solver._raise(lib().hhs_step_batched(solver._h, n, runs, sts, ctypes.byref(systems[0].params),
+                                         _hptr(dts), _hptr(stats)))
+    return dict(force_calls=int(stats[0]), force_particles=int(stats[1]), builds=int(stats[2]))

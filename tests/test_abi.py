@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "fmm355.h")
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:fmm_status|const char \*)\s*(\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:fmm_status|const char \*|int64_t)\s*(\w+)\s*\(", txt, flags=re.M)))
 
 
 def test_header_declares_the_boundary():

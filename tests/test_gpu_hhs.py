@@ -77,3 +77,59 @@ def test_hhs_momentum_conserved(precision, tol):
     scale = (m * np.sqrt((vel * vel).sum(axis=0))).sum()
     assert np.abs(inv["P"] - P0).max() / scale < tol
     assert sum(s["force_calls"] for s in stats) > 8
+
+
+def _hhs_systems():
+    out = []
+    for k, (gen, n) in enumerate([(W.plummer, 1024), (W.uniform_sphere, 3000),
+                                  (W.plummer, 2048), (W.king, 600)]):
+        pos, vel, m = gen(n, seed=1200 + k)
+        out.append((pos, vel, m))
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("max_n", [None, 4096])
+def test_hhs_batched_equals_solo(precision, max_n):
+    """Several systems stepped together (shared tree builds and evaluations,
+    different top-level steps) end bit-identical to each stepped alone; with
+    max_n = 4096 the waiting systems are split over several batched solves."""
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    prm = dict(PRM0)
+    systems = _hhs_systems()
+    dts = [1.0 / 16, 1.0 / 32, 1.0 / 16, 1.0 / 8]
+    total = sum(m.size for _, _, m in systems)
+    s = F.Solver(max_n or total, p_max=prm["p"], leaf_size=prm["leaf_size"],
+                 kernel=prm["kernel"], precision=precision)
+    kw = dict(eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
+              max_levels=prm["max_levels"])
+    hs = []
+    for pos, vel, m in systems:
+        run = F.HHSRun(s, m.size, prm["max_levels"])
+        hs.append(F.HHS(s, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda(),
+                        torch.from_numpy(m).cuda(), run=run, **kw))
+    F.hhs_init_batched(s, hs)
+    calls = 0
+    for _ in range(2):
+        calls += F.hhs_step_batched(s, hs, dts)["force_calls"]
+    torch.cuda.synchronize()
+    solo_calls = 0
+    for k, (pos, vel, m) in enumerate(systems):
+        t = F.Solver(m.size, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
+                     precision=precision)
+        h = F.HHS(t, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda(),
+                  torch.from_numpy(m).cuda(), **kw)
+        h.init()
+        for _ in range(2):
+            solo_calls += h.step(dts[k])["force_calls"]
+        torch.cuda.synchronize()
+        b = hs[k]
+        for name in ("pos", "vel", "rung", "a_old", "a_cur"):
+            assert torch.equal(getattr(h, name), getattr(b, name)), (k, name)
+        assert h.t == b.t
+        t.close()
+    assert calls == solo_calls
+    for h in hs:
+        h.run.close()
+    s.close()
