@@ -116,6 +116,56 @@ def cpu_leg(args, n, pos, mass, res, line):
                                       f"uniform sphere of the same recipe, {t1 - t0:.1f} s"}
 
 
+def ensemble_leg(args, F, torch, line):
+    """Serving: an ensemble of independent HHS simulations (Plummer / King
+    W0 = 6 in Henon units, N log-uniform in [1024, 262144]) each advanced to
+    t = t_end through the request server.  First a closed loop (all requests
+    at once) measures the saturation rate; then Poisson arrivals at a fraction
+    of it give the p50/p99 latency; a few requests served alone give the
+    latency without contention."""
+    from paper_1712_10116_amd import serving
+    from paper_1712_10116_amd import workloads as W
+    prm = W.PARAMS[4]
+    K = args.ensemble
+    reqs = [W.ensemble_request(i) for i in range(K)]
+    ntot = sum(r[2].size for r in reqs)
+    s = F.Solver(args.ensemble_max_n, p_max=prm["p"], leaf_size=prm["leaf_size"],
+                 kernel=prm["kernel"], precision=F.MIXED)
+
+    def server():
+        return F.Server(s, eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
+                        max_levels=prm["max_levels"], arena_bytes=args.ensemble_arena_gib << 30,
+                        max_slots=args.ensemble_slots)
+
+    srv = server()
+    serving.run(srv, [W.ensemble_request(1000)], args.ensemble_t_end)  # warm-up, untimed
+    res, span = serving.run(srv, reqs, args.ensemble_t_end)
+    closed = serving.summary(res, span)
+    rate = args.ensemble_load * closed["requests_per_s"]
+    arr = serving.poisson_arrivals(K, rate, seed=5999)
+    res, span = serving.run(srv, reqs, args.ensemble_t_end, arrivals=arr)
+    opened = serving.summary(res, span)
+    # latency alone: the smallest, the median-size and the largest request
+    sizes = np.array([r[2].size for r in reqs])
+    pick = sorted({int(np.argmin(sizes)), int(np.argsort(sizes)[K // 2]), int(np.argmax(sizes))})
+    solo = {}
+    for k in pick:
+        rr, sp = serving.run(srv, [reqs[k]], args.ensemble_t_end)
+        solo[int(sizes[k])] = round(rr[0]["latency"], 4)
+    srv.close()
+    s.close()
+    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    line["ensemble"] = {
+        "requests": K, "particles": int(ntot), "t_end": args.ensemble_t_end,
+        "precision": "mixed", "p": prm["p"], "theta": prm["theta"], "eps": prm["eps"],
+        "arena_gib": args.ensemble_arena_gib, "max_slots": args.ensemble_slots,
+        "closed_loop": rnd(closed),
+        "poisson": dict(rnd(opened), rate_per_s=round(rate, 4), load=args.ensemble_load),
+        "p50_latency_s": round(opened["p50_s"], 4), "p99_latency_s": round(opened["p99_s"], 4),
+        "solo_latency_s_by_n": solo,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +183,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=262144, help="particles in the CPU oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hhs", action="store_true")
+    ap.add_argument("--ensemble", type=int, default=64, metavar="K",
+                    help="requests in the serving ensemble (0: skip; the full stream is 512)")
+    ap.add_argument("--ensemble-t-end", type=float, default=1.0)
+    ap.add_argument("--ensemble-load", type=float, default=0.7,
+                    help="Poisson rate as a fraction of the closed-loop saturation rate")
+    ap.add_argument("--ensemble-slots", type=int, default=256)
+    ap.add_argument("--ensemble-arena-gib", type=int, default=16)
+    ap.add_argument("--ensemble-max-n", type=int, default=1 << 22)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -254,6 +312,9 @@ def main():
                        "rung_histogram": rungs}
         s.close()
         del a
+
+    if args.ensemble > 0:
+        ensemble_leg(args, F, torch, line)
 
     if "mixed_config_p" in res:
         r = res["mixed_config_p"]

@@ -249,6 +249,78 @@ fmm_status hhs_step_batched(fmm_ctx *ctx, int n_sys, hhs_run *const *runs,
                             hhs_state *const *states, const hhs_params *hp,
                             const double *dt_top, int64_t stats[3]);
 
+/* ---------------------------------------------------------------------------
+ * Request server: an ensemble of independent HHS simulations with continuous
+ * batching (each request advances one system from t = 0 to t_end with the
+ * integrator above).  Not thread safe: one host thread drives a server.
+ * ------------------------------------------------------------------------- */
+typedef struct fmm_server fmm_server;
+
+typedef struct {
+    int64_t arena_bytes; /* device memory for resident requests, allocated once */
+    int max_slots;       /* at most this many requests resident at a time       */
+    double dt_max;       /* cap on a request's top-level step                   */
+} serve_params;
+
+typedef struct {
+    const double *pos;   /* HOST, 3 x n SoA initial positions                   */
+    const double *vel;   /* HOST, 3 x n SoA initial velocities                  */
+    const double *mass;  /* HOST, n                                             */
+    int64_t n;           /* 1 .. max_n of the context                           */
+    double t_end;        /* > 0                                                 */
+    double *pos_out;     /* HOST, 3 x n: positions at t_end (written when done) */
+    double *vel_out;     /* HOST, 3 x n: velocities at t_end                    */
+} serve_request;
+
+typedef struct {
+    int64_t id, n;
+    int64_t steps;           /* top-level steps taken                            */
+    int64_t force_calls;     /* force evaluations of this request                */
+    int64_t force_particles; /* sum of their active particles                    */
+    double dt_top, t_end;
+    double t_submit, t_admit, t_done; /* seconds on the server's clock           */
+} serve_result;
+
+/* Device bytes one resident request of n particles takes from the arena
+ * (state arrays and integrator scratch); -1 for bad arguments. */
+int64_t serve_footprint(int64_t n, int max_levels);
+
+/* A server on ctx (whose stream and solver parameters it uses; max_n of the
+ * context bounds a request's size and the particles solved in one batched
+ * call) with one set of HHS parameters for all requests.  Allocates the arena
+ * (FMM_ENOMEM if it does not fit). */
+fmm_status serve_create(fmm_ctx *ctx, const hhs_params *hp, const serve_params *sp,
+                        fmm_server **out);
+fmm_status serve_destroy(fmm_server *srv);
+
+/* Queue a request (arrival order is admission order).  The host arrays are
+ * read when the request is admitted and the outputs written when it is done:
+ * they must stay valid until serve_poll returns its result (or it is
+ * cancelled).  FMM_ENOMEM if its footprint exceeds the whole arena.  *id is
+ * the request's id. */
+fmm_status serve_submit(fmm_server *srv, const serve_request *rq, int64_t *id);
+
+/* One scheduling step: admit queued requests in order while a slot and arena
+ * space are free (uploading them, with one batched initial force solve; a
+ * request's top-level step is the largest sqrt(eta eps / |a_i|) at t = 0
+ * rounded down to a power of two, at most dt_max, and its last step is cut to
+ * end at t_end), then advance every resident request by one top-level step in
+ * one hhs_step_batched, and retire those that reached t_end (their outputs
+ * downloaded, their arena space freed).  Synchronous.  A result does not
+ * depend on the other requests served with it.  Outputs (may be NULL): the
+ * resident and queued counts after the step. */
+fmm_status serve_step(fmm_server *srv, int *n_resident, int *n_queued);
+
+/* Up to max_out finished requests, in completion order. */
+fmm_status serve_poll(fmm_server *srv, serve_result *out, int max_out, int *n_out);
+
+/* Drop a queued or resident request (no result); FMM_EINVAL if unknown. */
+fmm_status serve_cancel(fmm_server *srv, int64_t id);
+
+/* info[0] resident, [1] queued, [2] finished not yet polled, [3] arena bytes
+ * in use, [4] arena bytes, [5] serve_step calls that advanced requests. */
+fmm_status serve_info(const fmm_server *srv, int64_t info[6]);
+
 #ifdef __cplusplus
 }
 #endif

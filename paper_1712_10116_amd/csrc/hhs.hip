@@ -2,6 +2,8 @@
 // FP64 conservation reductions.  The host walks the EVOLVE_HOLD recursion;
 // every per-particle step (rung assignment, slow/fast split, mass masking of
 // the fast system for kickS2F, kicks, drifts) runs here in FP64.
+#include <algorithm>
+
 #include "common.h"
 #include "hhs_kernels.h"
 
@@ -108,6 +110,38 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_amag(const double *__restrict__ a
   a_old[i] = 0.0;
 }
 
+// block minima of a[i] + b[i] (grid-stride), then one block reduces them
+__global__ __launch_bounds__(FMM_BLOCK) void k_min_sum_partial(const double *__restrict__ a,
+                                                               const double *__restrict__ b,
+                                                               int64_t n, double *__restrict__ part) {
+  double m = INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = fmin(m, a[i] + b[i]);
+  __shared__ double red[FMM_BLOCK];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = FMM_BLOCK / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_min_final(const double *__restrict__ part, int nb,
+                                                         double *__restrict__ out) {
+  double m = INFINITY;
+  for (int i = threadIdx.x; i < nb; i += FMM_BLOCK) m = fmin(m, part[i]);
+  __shared__ double red[FMM_BLOCK];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = FMM_BLOCK / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
 // per-block FP64 partial sums of the 12 invariants; the host adds the blocks
 // in a fixed order
 __global__ __launch_bounds__(FMM_BLOCK) void k_invariants(const double *__restrict__ pos,
@@ -204,6 +238,14 @@ void hhs_launch_iota(int32_t *v, int n, hipStream_t s) {
 
 void hhs_launch_amag(const double *acc, int64_t n, double *a_cur, double *a_old, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_amag, NB(n), dim3(FMM_BLOCK), 0, s, acc, n, a_cur, a_old);
+}
+
+void hhs_launch_min_sum(const double *a, const double *b, int64_t n, double *part, double *out,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (int)std::min<int64_t>(1024, (n + FMM_BLOCK - 1) / FMM_BLOCK);
+  hipLaunchKernelGGL(k_min_sum_partial, dim3(nb), dim3(FMM_BLOCK), 0, s, a, b, n, part);
+  hipLaunchKernelGGL(k_min_final, dim3(1), dim3(FMM_BLOCK), 0, s, part, nb, out);
 }
 
 void launch_invariants(const double *pos, const double *vel, const double *mass,

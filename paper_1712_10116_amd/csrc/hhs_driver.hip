@@ -15,70 +15,96 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fmm355.h"
 #include "common.h"
 #include "context.h"
+#include "hhs_driver.h"
 #include "hhs_kernels.h"
 
 struct hhs_run {
   fmm_ctx *ctx;
   int64_t n;
   int levels;
-  std::vector<void *> mem;
+  void *owned;  // device block of the run, or NULL when carved from caller memory
   int32_t *all_idx;
   uint32_t *flag, *scan_part;
   std::vector<int32_t *> slow, slow_pos, fast, fast_pos;  // per rung
   double *mmask, *acc, *pot;
 };
 
-template <typename T>
-static bool ralloc(hhs_run *r, T **p, int64_t count) {
-  void *q = nullptr;
-  if (hipMalloc(&q, (size_t)std::max<int64_t>(count, 1) * sizeof(T)) != hipSuccess) return false;
-  r->mem.push_back(q);
-  *p = (T *)q;
-  return true;
+// Lays the run's arrays out in one block (256-byte aligned pieces); returns
+// the block size, and sets the pointers when base is not NULL.
+static int64_t run_layout(hhs_run *r, char *base, int64_t n, int levels) {
+  int64_t off = 0;
+  auto take = [&](auto **p, int64_t count) {
+    using T = std::remove_pointer_t<std::remove_pointer_t<decltype(p)>>;
+    off = (off + 255) & ~(int64_t)255;
+    if (base) *p = (T *)(base + off);
+    off += std::max<int64_t>(count, 1) * (int64_t)sizeof(T);
+  };
+  hhs_run tmp;
+  hhs_run *q = base ? r : &tmp;
+  q->slow.resize(levels);
+  q->slow_pos.resize(levels);
+  q->fast.resize(levels);
+  q->fast_pos.resize(levels);
+  take(&q->all_idx, n);
+  take(&q->flag, n);
+  take(&q->scan_part, n / 1024 + 64);
+  take(&q->mmask, n);
+  take(&q->acc, 3 * n);
+  take(&q->pot, n);
+  for (int l = 0; l < levels; ++l) {
+    take(&q->slow[l], n);
+    take(&q->slow_pos[l], n);
+    take(&q->fast[l], n);
+    take(&q->fast_pos[l], n);
+  }
+  return (off + 255) & ~(int64_t)255;
 }
 
 extern "C" int64_t hhs_run_bytes(int64_t n, int max_levels) {
-  int64_t lv = (int64_t)(max_levels + 1) * 4 * n * 4;
-  return lv + n * (4 + 4 + 8 + 24 + 8) + (n / 1024 + 64) * 4;
+  if (n < 1 || max_levels < 1 || max_levels > 30) return -1;
+  return run_layout(nullptr, nullptr, n, max_levels + 1);
 }
 
-extern "C" fmm_status hhs_run_create(fmm_ctx *c, int64_t n, int max_levels, hhs_run **out) {
-  if (!c || !out || n < 1 || max_levels < 1 || max_levels > 30) return FMM_EINVAL;
+fmm_status hhs_run_create_at(fmm_ctx *c, int64_t n, int max_levels, void *mem, hhs_run **out) {
+  if (!c || !out || n < 1 || n > INT32_MAX || max_levels < 1 || max_levels > 30) return FMM_EINVAL;
   hhs_run *r = new (std::nothrow) hhs_run();
   if (!r) return FMM_ENOMEM;
   r->ctx = c;
   r->n = n;
   r->levels = max_levels + 1;
-  bool ok = ralloc(r, &r->all_idx, n) && ralloc(r, &r->flag, n) &&
-            ralloc(r, &r->scan_part, n / 1024 + 64) && ralloc(r, &r->mmask, n) &&
-            ralloc(r, &r->acc, 3 * n) && ralloc(r, &r->pot, n);
-  r->slow.resize(r->levels);
-  r->slow_pos.resize(r->levels);
-  r->fast.resize(r->levels);
-  r->fast_pos.resize(r->levels);
-  for (int l = 0; ok && l < r->levels; ++l)
-    ok = ralloc(r, &r->slow[l], n) && ralloc(r, &r->slow_pos[l], n) && ralloc(r, &r->fast[l], n) &&
-         ralloc(r, &r->fast_pos[l], n);
-  if (!ok) {
-    hhs_run_destroy(r);
-    return FMM_ENOMEM;
+  if (!mem) {
+    if (hipMalloc(&r->owned, (size_t)run_layout(nullptr, nullptr, n, r->levels)) != hipSuccess) {
+      delete r;
+      return FMM_ENOMEM;
+    }
+    mem = r->owned;
   }
+  run_layout(r, (char *)mem, n, r->levels);
   hhs_launch_iota(r->all_idx, (int)n, c->stream);
   *out = r;
   return FMM_OK;
 }
 
+extern "C" fmm_status hhs_run_create(fmm_ctx *c, int64_t n, int max_levels, hhs_run **out) {
+  return hhs_run_create_at(c, n, max_levels, nullptr, out);
+}
+
 extern "C" fmm_status hhs_run_destroy(hhs_run *r) {
   if (!r) return FMM_EINVAL;
   if (r->ctx) (void)hipStreamSynchronize(r->ctx->stream);
-  for (void *p : r->mem) (void)hipFree(p);
+  if (r->owned) (void)hipFree(r->owned);
   delete r;
   return FMM_OK;
+}
+
+void hhs_run_launch_min_amag(hhs_run *r, const hhs_state *st, double *out) {
+  hhs_launch_min_sum(st->a_old, st->a_cur, st->n, r->pot, out, r->ctx->stream);
 }
 
 namespace {
@@ -102,6 +128,7 @@ struct Sys {
   std::vector<Frame> stack;
   SysState state;
   int half;
+  int64_t kicks, parts;  // force evaluations of this system, and their active particles
 };
 
 // One kick of Algorithm 3 inside a KDK half: which set is kicked, with which
@@ -241,6 +268,8 @@ static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const 
                         S.st->vel, S.st->n, 0.5 * f.dt, K.second ? S.st->a_cur : nullptr,
                         c->stream);
       ++*kicks;
+      ++S.kicks;
+      S.parts += f.n_sys;
     }
   }
   return FMM_OK;
@@ -315,9 +344,9 @@ extern "C" fmm_status hhs_init_batched(fmm_ctx *c, int n_sys, hhs_run *const *ru
   return FMM_OK;
 }
 
-extern "C" fmm_status hhs_step_batched(fmm_ctx *c, int n_sys, hhs_run *const *runs,
-                                       hhs_state *const *states, const hhs_params *hp,
-                                       const double *dt_top, int64_t stats[3]) {
+fmm_status hhs_step_batched_ex(fmm_ctx *c, int n_sys, hhs_run *const *runs,
+                               hhs_state *const *states, const hhs_params *hp,
+                               const double *dt_top, int64_t stats[3], int64_t *sys_stats) {
   fmm_status e = check_params(c, hp);
   if (e != FMM_OK) return e;
   if (n_sys < 1 || !runs || !states || !dt_top) return fmm_fail(c, FMM_EINVAL, "no systems");
@@ -337,6 +366,7 @@ extern "C" fmm_status hhs_step_batched(fmm_ctx *c, int n_sys, hhs_run *const *ru
     S.dt_top = dt_top[i];
     S.state = S_RUN;
     S.half = 0;
+    S.kicks = S.parts = 0;
     S.stack.push_back(Frame{0, runs[i]->all_idx, (int)states[i]->n, dt_top[i], true, 0, 0, 0});
   }
   const int64_t c0 = c->stat_parts, b0 = c->stat_builds;
@@ -392,8 +422,19 @@ extern "C" fmm_status hhs_step_batched(fmm_ctx *c, int n_sys, hhs_run *const *ru
     stats[1] = c->stat_parts - c0;
     stats[2] = c->stat_builds - b0;
   }
+  if (sys_stats)
+    for (int i = 0; i < n_sys; ++i) {
+      sys_stats[2 * i] = sys[i].kicks;
+      sys_stats[2 * i + 1] = sys[i].parts;
+    }
   c->tree_valid = false;
   return FMM_OK;
+}
+
+extern "C" fmm_status hhs_step_batched(fmm_ctx *c, int n_sys, hhs_run *const *runs,
+                                       hhs_state *const *states, const hhs_params *hp,
+                                       const double *dt_top, int64_t stats[3]) {
+  return hhs_step_batched_ex(c, n_sys, runs, states, hp, dt_top, stats, nullptr);
 }
 
 static fmm_status own_run(fmm_ctx *c, hhs_state *st, const hhs_params *hp) {

@@ -19,6 +19,10 @@ void hhs_launch_drift(const int32_t *set, int n_set, const double *vel, double *
                       double dt, hipStream_t s);
 void hhs_launch_iota(int32_t *v, int n, hipStream_t s);
 void hhs_launch_amag(const double *acc, int64_t n, double *a_cur, double *a_old, hipStream_t s);
+// out[0] = min_i (a[i] + b[i]) over n >= 1 values; part holds
+// min(1024, ceil(n / 256)) doubles of scratch
+void hhs_launch_min_sum(const double *a, const double *b, int64_t n, double *part, double *out,
+                        hipStream_t s);
 void launch_invariants(const double *pos, const double *vel, const double *mass,
                        const double *acc, const double *pot, int64_t n, double *part, int nblk,
                        hipStream_t s);

@@ -23,7 +23,8 @@ EXPORTED = (
     "fmm_tree_info", "fmm_export_tree", "fmm_invariants", "hhs_init", "hhs_step",
     "fmm_profile_enable", "fmm_profile_read", "fmm_build_batched", "fmm_evaluate_batched",
     "fmm_forces_batched", "hhs_run_bytes", "hhs_run_create", "hhs_run_destroy",
-    "hhs_init_batched", "hhs_step_batched",
+    "hhs_init_batched", "hhs_step_batched", "serve_footprint", "serve_create", "serve_destroy",
+    "serve_submit", "serve_step", "serve_poll", "serve_cancel", "serve_info",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -32,6 +33,25 @@ class FMMError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"fmm status {status}: {msg}")
         self.status = status
+
+
+class ServeParams(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int),
+                ("dt_max", ctypes.c_double)]
+
+
+class ServeRequest(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("vel", ctypes.c_void_p), ("mass", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("t_end", ctypes.c_double), ("pos_out", ctypes.c_void_p),
+                ("vel_out", ctypes.c_void_p)]
+
+
+class ServeResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("n", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("force_calls", ctypes.c_int64), ("force_particles", ctypes.c_int64),
+                ("dt_top", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
 
 class _Params(ctypes.Structure):
@@ -95,10 +115,20 @@ def lib():
         L.hhs_step_batched.argtypes = [vp, ci, ctypes.POINTER(vp),
                                        ctypes.POINTER(ctypes.POINTER(HHSState)),
                                        ctypes.POINTER(HHSParams), vp, vp]
+        L.serve_footprint.argtypes = [i64, ci]
+        L.serve_create.argtypes = [vp, ctypes.POINTER(HHSParams), ctypes.POINTER(ServeParams),
+                                   ctypes.POINTER(vp)]
+        L.serve_destroy.argtypes = [vp]
+        L.serve_submit.argtypes = [vp, ctypes.POINTER(ServeRequest), ctypes.POINTER(i64)]
+        L.serve_step.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+        L.serve_poll.argtypes = [vp, ctypes.POINTER(ServeResult), ci, ctypes.POINTER(ci)]
+        L.serve_cancel.argtypes = [vp, i64]
+        L.serve_info.argtypes = [vp, vp]
         for name in EXPORTED:
-            if name not in ("fmm_last_error", "hhs_run_bytes"):
+            if name not in ("fmm_last_error", "hhs_run_bytes", "serve_footprint"):
                 getattr(L, name).restype = ctypes.c_int
         L.hhs_run_bytes.restype = i64
+        L.serve_footprint.restype = i64
         _lib = L
     return _lib
 
@@ -362,3 +392,86 @@ def hhs_step_batched(solver, systems, dt_top):
     solver._raise(lib().hhs_step_batched(solver._h, n, runs, sts, ctypes.byref(systems[0].params),
                                          _hptr(dts), _hptr(stats)))
     return dict(force_calls=int(stats[0]), force_particles=int(stats[1]), builds=int(stats[2]))
+
+
+class Server:
+    """Request server for ensembles of HHS simulations (serve_* in the C ABI).
+
+    ``submit`` takes host float64 arrays (pos and vel 3 x n, mass n) and keeps
+    them, with the output arrays, alive until the request's result is polled."""
+
+    def __init__(self, solver, *, eps, theta, p, eta, max_levels, arena_bytes, max_slots,
+                 dt_max=1.0 / 16):
+        self.solver = solver
+        self.params = HHSParams(float(eps), float(theta), int(p), float(eta), int(max_levels), 0)
+        sp = ServeParams(int(arena_bytes), int(max_slots), float(dt_max))
+        h = ctypes.c_void_p()
+        solver._raise(lib().serve_create(solver._h, ctypes.byref(self.params), ctypes.byref(sp),
+                                         ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+
+    @staticmethod
+    def footprint(n, max_levels):
+        return int(lib().serve_footprint(int(n), int(max_levels)))
+
+    def submit(self, pos, vel, mass, t_end):
+        import numpy as np
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        n = mass.size
+        if pos.shape != (3, n) or vel.shape != (3, n):
+            raise ValueError("pos and vel must be 3 x n")
+        out_p = np.empty((3, n))
+        out_v = np.empty((3, n))
+        rq = ServeRequest(pos.ctypes.data, vel.ctypes.data, mass.ctypes.data, n, float(t_end),
+                          out_p.ctypes.data, out_v.ctypes.data)
+        rid = ctypes.c_int64()
+        self.solver._raise(lib().serve_submit(self._h, ctypes.byref(rq), ctypes.byref(rid)))
+        self._live[rid.value] = (pos, vel, mass, out_p, out_v)
+        return rid.value
+
+    def step(self):
+        nr, nq = ctypes.c_int(), ctypes.c_int()
+        self.solver._raise(lib().serve_step(self._h, ctypes.byref(nr), ctypes.byref(nq)))
+        return nr.value, nq.value
+
+    def poll(self, max_out=64):
+        """Finished requests: list of dicts with the result fields and the
+        final ``pos`` and ``vel``."""
+        buf = (ServeResult * max_out)()
+        k = ctypes.c_int()
+        out = []
+        while True:
+            self.solver._raise(lib().serve_poll(self._h, buf, max_out, ctypes.byref(k)))
+            for i in range(k.value):
+                r = buf[i]
+                d = {f: getattr(r, f) for f, _ in ServeResult._fields_}
+                keep = self._live.pop(r.id)
+                d["pos"], d["vel"] = keep[3], keep[4]
+                out.append(d)
+            if k.value < max_out:
+                return out
+
+    def cancel(self, rid):
+        self.solver._raise(lib().serve_cancel(self._h, int(rid)))
+        self._live.pop(rid, None)
+
+    def info(self):
+        import numpy as np
+        v = np.zeros(6, dtype=np.int64)
+        self.solver._raise(lib().serve_info(self._h, _hptr(v)))
+        return dict(resident=int(v[0]), queued=int(v[1]), finished=int(v[2]),
+                    arena_used=int(v[3]), arena_bytes=int(v[4]), steps=int(v[5]))
+
+    def close(self):
+        if self._h:
+            lib().serve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,6 +12,8 @@ zoom generators below draw particle sets of the same kind and size class.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 
 _N_CONFIG = {0: 4096, 1: 1 << 20, 2: 1 << 22, 3: 1 << 24}
@@ -138,15 +140,12 @@ def clustered_zoom(n=1 << 24, seed=1003, n_halos=2000):
     return pos, vel, mass
 
 
-def king(n, seed=5001, w0=6.0):
-    """King (1966) model with central dimensionless potential W0, drawn from
-    its distribution function f(E) ~ exp(W - v^2/2) - 1 (sigma = 1, King radius
-    1), then rescaled to unit total mass with G = 1.  Radii follow the tabulated
-    cumulative mass of the integrated Poisson equation
-    W'' + (2/r) W' = -9 rho(W)/rho0; speeds are drawn by vectorised rejection
-    sampling of v^2 (exp(W - v^2/2) - 1) on [0, sqrt(2W)]."""
+@functools.lru_cache(maxsize=8)
+def _king_profile(w0):
+    """Tabulated King model: radius, dimensionless potential W and cumulative
+    mass (in units of 9 int r^2 rho/rho0 dr) from the Poisson equation
+    W'' + (2/r) W' = -9 rho(W)/rho0 (fourth-order Runge-Kutta)."""
     from math import erf
-    rng = np.random.default_rng(seed)
 
     def rho_of_w(w):
         if w <= 0:
@@ -169,7 +168,20 @@ def king(n, seed=5001, w0=6.0):
         y = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
         r += h
         rs.append(r); ws.append(max(float(y[0]), 0.0)); ms.append(m)
-    rs, ws, ms = np.array(rs), np.array(ws), np.array(ms)
+    return np.array(rs), np.array(ws), np.array(ms)
+
+
+def king(n, seed=5001, w0=6.0, henon=False):
+    """King (1966) model with central dimensionless potential W0, drawn from
+    its distribution function f(E) ~ exp(W - v^2/2) - 1 (sigma = 1, King radius
+    1), then rescaled to unit total mass with G = 1.  Radii follow the tabulated
+    cumulative mass of the integrated Poisson equation
+    W'' + (2/r) W' = -9 rho(W)/rho0; speeds are drawn by vectorised rejection
+    sampling of v^2 (exp(W - v^2/2) - 1) on [0, sqrt(2W)].  With henon=True
+    lengths and velocities are rescaled to Henon units (potential energy -1/2
+    for M = G = 1), the potential energy taken from the tabulated profile."""
+    rng = np.random.default_rng(seed)
+    rs, ws, ms = _king_profile(float(w0))
     radii = np.interp(rng.uniform(0, 1, n) * ms[-1], ms, rs)
     W = np.interp(radii, rs, ws)
     vmax = np.sqrt(2.0 * W)
@@ -188,8 +200,28 @@ def king(n, seed=5001, w0=6.0):
     # with G = sigma = r0 = 1 the model mass is 9 * int r^2 rho/rho0 dr; scale
     # velocities by sqrt(M_new / M_model) to reach unit mass at fixed radii
     vel *= 1.0 / np.sqrt(9.0 * ms[-1])
+    if henon:
+        # W = -int G M(r) / r dM over the unit-mass profile; Henon units have
+        # W = -1/2, reached by r -> r (-2 W) and v -> v / sqrt(-2 W)
+        mm = ms / ms[-1]
+        rm = 0.5 * (rs[1:] + rs[:-1])
+        wpot = -np.sum(0.5 * (mm[1:] + mm[:-1]) / rm * np.diff(mm))
+        scale = -2.0 * wpot
+        pos = pos * scale
+        vel = vel / np.sqrt(scale)
     pos, vel = _recentre(pos, vel, mass)
     return pos, vel, mass
+
+
+def ensemble_request(i, n_min=1024, n_max=262144):
+    """Request i of the serving ensemble: N log-uniform in [n_min, n_max]
+    (seed 5000 + i), a Plummer sphere for even i and a King W0 = 6 model for
+    odd i, both in Henon units (Plummer scale length 3 pi / 16)."""
+    seed = 5000 + i
+    n = int(round(np.exp(np.random.default_rng(seed).uniform(np.log(n_min), np.log(n_max)))))
+    if i % 2 == 0:
+        return plummer(n, seed=seed, a=3.0 * np.pi / 16.0)
+    return king(n, seed=seed, henon=True)
 
 
 def config(idx, n=None):
