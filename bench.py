@@ -2,16 +2,23 @@
 """FMM force-solve benchmark on one MI355X.
 
 Workload: cold collapse -- 1,048,576 equal-mass particles uniform in the unit
-sphere (G = M = R = 1), Wendland C2 softening eps = 0.005, expansion order
-p = 4, leaf size 16.  One step = one complete force solve of all particles
-(root box, Morton keys and sort, tree, symmetric dual walk, P2M/M2M, M2L,
-P2P, L2L/L2P) through the C ABI, inputs resident in HBM.
+sphere (G = M = R = 1), Wendland C2 softening eps = 0.005.  One step = one
+complete force solve of all particles (root box, Morton keys and sort, tree,
+symmetric dual walk, P2M/M2M, M2L, P2P, L2L/L2P) through the C ABI, inputs
+resident in HBM.
+
+The leaf size, opening angle and order are picked first by the autotuner (the
+fastest mixed-precision solve whose rms force error over all particles, against
+a high-accuracy FP64 solve, is within the target); the plain FP64 path runs at
+the same parameters, so both have the same truncation error.  The workload's
+own parameters (p 4, theta 0.5, leaf 16) are timed beside them.
 
 Prints one JSON line: particles/s of the mixed-precision path (the headline),
-the plain FP64 path beside it, force errors of both against FP64 direct
-summation on a seeded sample of sinks (CPU oracle), momentum balance, per-phase
-HIP-event times, the roofline of the dominant kernel, the CPU oracle timed on
-a bounded sample, and one HHS top-level step.
+the FP64 path beside it, force errors (all particles against the reference
+solve; a seeded sample of sinks against FP64 direct summation by the CPU
+oracle), momentum balance, per-phase HIP-event times, the roofline of the
+dominant kernel, the CPU oracle timed on a bounded sample, one HHS top-level
+step and the serving ensemble.
 """
 from __future__ import annotations
 
@@ -45,9 +52,9 @@ def m2l_flops_per_pair(p):
 P2P_FLOPS_PER_PAIR = 30.0  # per unordered particle pair (rsqrt counted as 1)
 
 
-def recorded_traffic(kernel, p):
+def recorded_traffic(kernel, prm):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None if it was taken for another order or the kernel sources changed since."""
+    None if it was taken for other parameters or the kernel sources changed since."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_traffic_cold_collapse_1M.md")
@@ -60,7 +67,9 @@ def recorded_traffic(kernel, p):
     csrc = os.path.join(ROOT, "paper_1712_10116_amd", "csrc")
     sha = hashlib.sha256(open(os.path.join(csrc, "eval.hip"), "rb").read() +
                          open(os.path.join(csrc, "expansion.h"), "rb").read()).hexdigest()
-    if kv.get("source_sha256") != sha or kv.get("p") != str(p) or kernel not in kv:
+    same = (kv.get("p") == str(prm["p"]) and kv.get("theta") == str(prm["theta"]) and
+            kv.get("leaf") == str(prm["leaf_size"]))
+    if kv.get("source_sha256") != sha or not same or kernel not in kv:
         return None
     return int(kv[kernel])
 
@@ -90,10 +99,10 @@ def time_solver(F, torch, s, tp, tm, acc, pot, prm, steps, warmup, profile):
     return (t1 - t0) / steps, phases
 
 
-def cpu_leg(args, n, pos, mass, res, line):
-    """CPU side: the oracle timed on a bounded sample of the same workload, and
-    FP64 direct summation (oracle) on seeded sinks as the force-error reference
-    for the GPU results."""
+def cpu_leg(args, n, pos, mass, res, prm, line):
+    """CPU side: FP64 direct summation (oracle) on a seeded sample of sinks as
+    the force-error reference of every GPU result, and the oracle FMM timed on
+    a bounded sample of the same workload."""
     from oracle import oracle as O
     from paper_1712_10116_amd import workloads as W
     rng = np.random.default_rng(2024)
@@ -101,19 +110,21 @@ def cpu_leg(args, n, pos, mass, res, line):
     ref, _ = O.direct(pos, mass, O.WENDLAND, 0.005, sinks=sinks)
     for name, r in res.items():
         e = force_error(r["acc"][:, sinks], ref)
-        line["force_err"][f"{name}_vs_direct"] = {"rms": e[0], "p99": e[1], "p": r["p"]}
-    line["force_err"]["sinks"] = int(len(sinks))
+        line["force_err"]["vs_direct_sample"][name] = {"rms": e[0], "p99": e[1]}
+    line["force_err"]["vs_direct_sample"]["sinks"] = int(len(sinks))
     ns = min(args.cpu_sample, n)
     spos, _, smass = W.uniform_sphere(ns, seed=1001)
-    kw = dict(p=args.p, theta=args.theta, eps=0.005, leaf_size=args.leaf, kernel=O.WENDLAND)
+    kw = dict(p=prm["p"], theta=prm["theta"], eps=0.005, leaf_size=prm["leaf_size"],
+              kernel=O.WENDLAND)
     t0 = time.perf_counter()
     O.fmm(spos, smass, **kw)
     t1 = time.perf_counter()
     line["cpu_baseline"] = {"value": round(ns / (t1 - t0), 1), "unit": "particles/s", "cores": 1,
                             "kind": "oracle",
-                            "sample": f"one oracle FMM force solve (FP64, single thread, p={args.p}, "
-                                      f"theta={args.theta}, leaf {args.leaf}) on a {ns}-particle "
-                                      f"uniform sphere of the same recipe, {t1 - t0:.1f} s"}
+                            "sample": f"one oracle FMM force solve (FP64, single thread, "
+                                      f"p={prm['p']}, theta={prm['theta']}, leaf "
+                                      f"{prm['leaf_size']}) on a {ns}-particle uniform sphere of "
+                                      f"the same recipe, {t1 - t0:.1f} s"}
 
 
 def ensemble_leg(args, F, torch, line):
@@ -172,17 +183,18 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1 << 20)
-    # the workload names theta = 0.5, p = 4; at N = 2^20 that gives ~2e-3 rms force
-    # error, so the headline uses the cheapest setting measured to reach the
-    # metric's 1e-3 (theta = 0.5, p = 5, leaf 32); the named p = 4 is reported beside it
+    ap.add_argument("--target", type=float, default=1e-3, help="rms force error to reach")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner and use --p/--theta/--leaf")
     ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--p", type=int, default=5)
-    ap.add_argument("--leaf", type=int, default=32)
-    ap.add_argument("--config-p", type=int, default=4, help="order named by the workload")
-    ap.add_argument("--sample", type=int, default=2048, help="sinks checked against direct sum")
+    ap.add_argument("--p", type=int, default=6)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--sample", type=int, default=4096, help="sinks checked against direct sum")
     ap.add_argument("--cpu-sample", type=int, default=262144, help="particles in the CPU oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hhs", action="store_true")
+    ap.add_argument("--no-named", action="store_true",
+                    help="skip the run at the workload's own parameters (p 4, theta 0.5, leaf 16)")
     ap.add_argument("--ensemble", type=int, default=64, metavar="K",
                     help="requests in the serving ensemble (0: skip; the full stream is 512)")
     ap.add_argument("--ensemble-t-end", type=float, default=1.0)
@@ -212,35 +224,60 @@ def main():
 
     import torch
     import paper_1712_10116_amd.fmm as F
+    from paper_1712_10116_amd import autotune
     from paper_1712_10116_amd import workloads as W
 
     dev = torch.device("cuda:0")
     n = args.n
-    prm = dict(p=args.p, theta=args.theta, eps=0.005, leaf_size=args.leaf, kernel=F.WENDLAND)
+    eps = 0.005
     pos, vel, mass = W.uniform_sphere(n, seed=1001)
     tp = torch.from_numpy(pos).to(dev)
     tm = torch.from_numpy(mass).to(dev)
-    out = {}
+    line_tune = None
+    if args.no_tune:
+        prm = dict(p=args.p, theta=args.theta, eps=eps, leaf_size=args.leaf)
+    else:
+        t0 = time.perf_counter()
+        tr = autotune.tune(tp, tm, eps=eps, kernel=F.WENDLAND, precision=F.MIXED,
+                           target=args.target, leaf_sizes=(16, 24, 32, 48, 64, 96),
+                           orders=(4, 5, 6), thetas=(0.4, 0.45, 0.5), reps=3)
+        b = tr["best"]
+        prm = dict(p=b["p"], theta=b["theta"], eps=eps, leaf_size=b["leaf_size"])
+        ok = sorted((r for r in tr["table"] if r["ms"] is not None), key=lambda r: r["ms"])
+        line_tune = {"target_rms": args.target, "candidates": len(tr["table"]),
+                     "passing": len(ok), "seconds": round(time.perf_counter() - t0, 2),
+                     "reference": tr["reference"],
+                     "best": {k: (round(v, 6) if isinstance(v, float) else v) for k, v in b.items()},
+                     "runners_up": [{k: (round(v, 6) if isinstance(v, float) else v)
+                                     for k, v in r.items()} for r in ok[1:4]]}
+    # the same (theta, p, leaf) for both precisions: equal truncation error
+    runs = [("mixed", F.MIXED, prm), ("fp64", F.FP64, prm)]
+    named = dict(p=4, theta=0.5, eps=eps, leaf_size=16)
+    if not args.no_named and named != prm:
+        runs.append(("mixed_named", F.MIXED, named))
     res = {}
-    runs = [("mixed", F.MIXED, args.p), ("fp64", F.FP64, args.p)]
-    if args.config_p != args.p:
-        runs.append(("mixed_config_p", F.MIXED, args.config_p))
-    for name, prec, pp in runs:
-        prm = dict(prm, p=pp)
-        s = F.Solver(n, p_max=pp, leaf_size=args.leaf, kernel=F.WENDLAND, precision=prec)
+    for name, prec, pr in runs:
+        s = F.Solver(n, p_max=pr["p"], leaf_size=pr["leaf_size"], kernel=F.WENDLAND,
+                     precision=prec)
         acc = torch.empty((3, n), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev)
-        sec, phases = time_solver(F, torch, s, tp, tm, acc, pot, prm, args.steps, args.warmup,
+        sec, phases = time_solver(F, torch, s, tp, tm, acc, pot, pr, args.steps, args.warmup,
                                   profile=True)
         info = s.tree_info()
         inv = s.invariants(mass=tm, acc=acc)
-        res[name] = dict(sec=sec, phases=phases, info=info, acc=acc.cpu().numpy(), p=pp,
+        res[name] = dict(sec=sec, phases=phases, info=info, acc=acc.cpu().numpy(), prm=pr,
                          momentum=float(np.abs(inv["F"]).max() / inv["Fabs"]))
         s.close()
         del acc, pot
         torch.cuda.synchronize()
+    # force error of every run over all particles against a high-accuracy
+    # FP64 solve of the same particles
+    rp = autotune.REFERENCE
+    s = F.Solver(n, p_max=rp["p"], leaf_size=rp["leaf_size"], kernel=F.WENDLAND, precision=F.FP64)
+    a_ref, _ = s.forces(tp, tm, eps=eps, theta=rp["theta"], p=rp["p"])
+    a_ref = a_ref.cpu().numpy()
+    s.close()
 
-    prm = dict(prm, p=args.p)
     mixed, fp64 = res["mixed"], res["fp64"]
     e_mf = force_error(mixed["acc"], fp64["acc"])
     ph = mixed["phases"]
@@ -251,14 +288,14 @@ def main():
     p2p_ms = ph["p2p"][0] / max(ph["p2p"][1], 1)
     m2l_ms = ph["m2l"][0] / max(ph["m2l"][1], 1)
     p2p_flops = P2P_FLOPS_PER_PAIR * info["p2p_interactions"] / 2.0
-    m2l_flops = m2l_flops_per_pair(args.p) * info["m2l"]
+    m2l_flops = m2l_flops_per_pair(prm["p"]) * info["m2l"]
     kern["p2p"] = dict(ms=p2p_ms, flops=p2p_flops, tflops=p2p_flops / (p2p_ms * 1e-3) / 1e12)
     kern["m2l"] = dict(ms=m2l_ms, flops=m2l_flops, tflops=m2l_flops / (m2l_ms * 1e-3) / 1e12)
     dom = max(kern, key=lambda k: kern[k]["ms"])
     roof = dict(kernel=dom, bound="alu", achieved=round(kern[dom]["tflops"], 3),
                 peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                 frac=round(kern[dom]["tflops"] / PEAK_FP32_TFLOPS, 4),
-                traffic=recorded_traffic(dom, args.p))
+                traffic=recorded_traffic(dom, prm))
 
     line = {
         "metric": METRIC,
@@ -273,12 +310,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"cold collapse, uniform unit sphere, N={n}, Wendland C2 eps=0.005, "
-                               f"p={args.p}, theta={args.theta}, leaf {args.leaf}, mixed FP32/FP64",
-                   "n": n, "p": args.p, "theta": args.theta, "eps": 0.005, "leaf_size": args.leaf,
-                   "parallelism": "single GPU"},
+        "config": {"workload": f"cold collapse, uniform unit sphere, N={n}, Wendland C2 "
+                               f"eps={eps}, p={prm['p']}, theta={prm['theta']}, leaf "
+                               f"{prm['leaf_size']} (autotuned for rms force error <= "
+                               f"{args.target}), mixed FP32/FP64",
+                   "n": n, "p": prm["p"], "theta": prm["theta"], "eps": eps,
+                   "leaf_size": prm["leaf_size"], "parallelism": "single GPU"},
         "roofline": roof,
-        "force_err": {"mixed_vs_fp64_gpu": {"rms": e_mf[0], "p99": e_mf[1]}},
+        "force_err": {"mixed_vs_fp64_gpu": {"rms": e_mf[0], "p99": e_mf[1]},
+                      "vs_reference_all": {}, "vs_direct_sample": {},
+                      "reference": dict(rp, precision="fp64")},
         "fp64": {"value": round(n / fp64["sec"], 1), "ms_per_step": round(fp64["sec"] * 1e3, 4),
                  "phases_ms": {k: round(v[0] / steps, 4) for k, v in fp64["phases"].items()}},
         "momentum_rel": {"mixed": mixed["momentum"], "fp64": fp64["momentum"]},
@@ -289,17 +330,22 @@ def main():
         "interactions_per_s": {"p2p_ordered": round(info["p2p_interactions"] / mixed["sec"], 1),
                                "m2l_ordered": round(info["m2l_directed"] / mixed["sec"], 1)},
     }
+    for name, r in res.items():
+        e = force_error(r["acc"], a_ref)
+        line["force_err"]["vs_reference_all"][name] = {"rms": e[0], "p99": e[1]}
+    if line_tune:
+        line["autotune"] = line_tune
 
     if not args.no_hhs:
         # one HHS top-level step of the same particles (mixed precision)
-        s = F.Solver(n, p_max=args.p, leaf_size=args.leaf, kernel=F.WENDLAND, precision=F.MIXED)
+        s = F.Solver(n, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=F.WENDLAND,
+                     precision=F.MIXED)
         tpp = tp.clone()
         tv = torch.from_numpy(vel).to(dev)
-        h = F.HHS(s, tpp, tv, tm, eps=prm["eps"], theta=prm["theta"], p=args.p, eta=0.0025,
+        h = F.HHS(s, tpp, tv, tm, eps=eps, theta=prm["theta"], p=prm["p"], eta=0.0025,
                   max_levels=10)
         h.init()
-        a = torch.sqrt(h.a_cur.max() / 1.0)
-        dtmax = float(np.sqrt(0.0025 * prm["eps"] / max(float(h.a_cur[h.a_cur > 0].min()), 1e-30)))
+        dtmax = float(np.sqrt(0.0025 * eps / max(float(h.a_cur[h.a_cur > 0].min()), 1e-30)))
         dt_top = min(2.0 ** np.floor(np.log2(dtmax)), 2.0 ** -4)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -311,18 +357,18 @@ def main():
                        "particles_per_s": round(st["force_particles"] / (t1 - t0), 1),
                        "rung_histogram": rungs}
         s.close()
-        del a
+
+    if "mixed_named" in res:
+        r = res["mixed_named"]
+        line["named_config"] = {**{k: v for k, v in r["prm"].items() if k != "eps"},
+                                "value": round(n / r["sec"], 1),
+                                "ms_per_step": round(r["sec"] * 1e3, 4)}
 
     if args.ensemble > 0:
         ensemble_leg(args, F, torch, line)
 
-    if "mixed_config_p" in res:
-        r = res["mixed_config_p"]
-        line["config_order"] = {"p": r["p"], "value": round(n / r["sec"], 1),
-                                "ms_per_step": round(r["sec"] * 1e3, 4)}
-
     if not args.no_cpu_baseline:
-        cpu_leg(args, n, pos, mass, res, line)
+        cpu_leg(args, n, pos, mass, res, prm, line)
     print(json.dumps(line))
 
 

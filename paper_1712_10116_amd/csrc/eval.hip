@@ -230,14 +230,20 @@ struct PairKernel {
 };
 
 // One wavefront per target leaf A.  The particles of every leaf in A's P2P
-// list (A itself included) are staged into LDS as one flattened stream --
-// FP32 offsets from A's centre in the mixed form, absolute FP64 positions in
-// the FP64 form -- in windows of SRC particles.  Lanes = (target particle,
-// phase): LP = smallest power of two >= n_A lanes per phase, 64/LP phases each
-// taking every (64/LP)-th source of the window.  FP32 partial sums are added
-// into FP64 accumulators every 8 sources.  The self term is excluded by its
-// position in the stream (coincident distinct particles still interact).
+// list (A itself included) form one stream, staged into LDS in windows of up
+// to SRC particles -- FP32 offsets from A's centre in the mixed form, absolute
+// FP64 positions in the FP64 form.  Staging is cooperative: the lane holding a
+// source leaf writes the particle index of each of its slots into an LDS table,
+// then consecutive lanes load consecutive slots.  Lanes = (target particle, phase): LP >= 4 lanes per phase (the
+// smallest power of two >= n_A), nph = 64/LP phases, phase ph taking sources
+// ph, ph + nph, ...  A window is padded to a multiple of UNROLL*nph with
+// massless sources far away, so every lane runs the same number of unrolled
+// blocks with no bounds test.  FP32 partial sums are added into FP64
+// accumulators after every block of UNROLL sources.  The self term is excluded
+// by its position in the stream (coincident distinct particles interact).
 #define P2P_WAVES 4
+#define P2P_UNROLL 8
+#define P2P_MINLP 4  // at most 16 phases, so a window pads to a multiple of 128
 
 template <bool MIXED>
 struct P2PTypes;
@@ -245,13 +251,15 @@ template <>
 struct P2PTypes<true> {
   typedef float R;
   typedef float4 R4;
-  static constexpr int SRC = 512;
+  static constexpr int SRC = 384;  // multiple of P2P_UNROLL * 64 / P2P_MINLP
+  __device__ static R4 far() { return make_float4(1e15f, 1e15f, 1e15f, 0.f); }
 };
 template <>
 struct P2PTypes<false> {
   typedef double R;
   typedef double4 R4;
   static constexpr int SRC = 256;
+  __device__ static R4 far() { return make_double4(1e150, 1e150, 1e150, 0.0); }
 };
 
 template <bool MIXED, int KERNEL>
@@ -259,10 +267,13 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
   typedef typename P2PTypes<MIXED>::R R;
   typedef typename P2PTypes<MIXED>::R4 R4;
   constexpr int SRC = P2PTypes<MIXED>::SRC;
+  static_assert(SRC % (P2P_UNROLL * 64 / P2P_MINLP) == 0, "window must hold its padding");
   __shared__ R4 src_all[P2P_WAVES][SRC];
+  __shared__ int idx_all[P2P_WAVES][SRC];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   R4 *src = src_all[w];
+  int *idx = idx_all[w];
   const int wave = blockIdx.x * P2P_WAVES + w;
   const int nwaves = gridDim.x * P2P_WAVES;
   const R eps2 = (R)(eps * eps);
@@ -273,11 +284,12 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
     if (t.nnchild[A] != 0 || skipped(t, A)) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
     const int nt = nA < 64 ? nA : 64;
-    int lg = 0;
+    int lg = 2;  // log2 of P2P_MINLP
     while ((1 << lg) < nt) ++lg;
     const int LP = 1 << lg;           // lanes per phase
     const int nph = 64 >> lg;         // phases
     const int ph = lane >> lg, ti = lane & (LP - 1);
+    const int blk = P2P_UNROLL * nph; // sources per unrolled block of all phases
     const double4 gA = t.ngeo[A];
     const int off = t.p2p_off[A], cnt = t.p2p_cnt[A];
     for (int tb = 0; tb < nA; tb += LP) {
@@ -302,52 +314,63 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
         const int bB = t.nbeg[B];
         const int nb = vq ? t.nend[B] - bB : 0;
         int total;
-        const int pos = wave_excl_scan_int(nb, &total);
+        const int pos = wave_excl_scan_int(nb, &total);  // lanes past cnt hold pos = total
         const unsigned long long selfm = __ballot(vq && B == A);
         const int self_lane = selfm ? (int)__ffsll((long long)selfm) - 1 : 0;
         const int self_start = selfm ? __shfl(pos, self_lane, 64) : -(1 << 30);
         for (int w0 = 0; w0 < total; w0 += SRC) {
           const int W = min(SRC, total - w0);
-          const int k0 = max(0, w0 - pos), k1 = min(nb, w0 + W - pos);
-          for (int k = k0; k < k1; ++k) {
-            const int j = bB + k;
-            R4 v;
-            if (MIXED) {
-              v.x = (R)(t.sx[j] - gA.x);
-              v.y = (R)(t.sy[j] - gA.y);
-              v.z = (R)(t.sz[j] - gA.z);
-              v.w = t.sm32[j];
-            } else {
-              v.x = t.sx[j];
-              v.y = t.sy[j];
-              v.z = t.sz[j];
-              v.w = t.sm[j];
+          const int Wr = (W + blk - 1) / blk * blk;
+          // particle index of every slot of the window, written by the lane
+          // that holds its source leaf
+          {
+            const int a0 = max(pos, w0), a1 = min(pos + nb, w0 + W);
+            for (int s = a0; s < a1; ++s) idx[s - w0] = bB + (s - pos);
+          }
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          for (int j = lane; j < Wr; j += 64) {
+            R4 v = P2PTypes<MIXED>::far();
+            if (j < W) {
+              const int k = idx[j];
+              if (MIXED) {
+                v.x = (R)(t.sx[k] - gA.x);
+                v.y = (R)(t.sy[k] - gA.y);
+                v.z = (R)(t.sz[k] - gA.z);
+                v.w = t.sm32[k];
+              } else {
+                v.x = t.sx[k];
+                v.y = t.sy[k];
+                v.z = t.sz[k];
+                v.w = t.sm[k];
+              }
             }
-            src[pos + k - w0] = v;
+            src[j] = v;
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
           const int self_idx = self_start + i - w0;
-          for (int f0 = ph; f0 < W; f0 += 8 * nph) {
+          for (int f0 = ph; f0 < Wr; f0 += blk) {
             R sx = 0, sy = 0, sz = 0, sp = 0;
+            R4 svs[P2P_UNROLL];  // the block's sources, read before any use
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < P2P_UNROLL; ++u) svs[u] = src[f0 + u * nph];
+#pragma unroll
+            for (int u = 0; u < P2P_UNROLL; ++u) {
               const int f = f0 + u * nph;
-              if (f < W) {
-                const R4 sv = src[f];
-                const R dx = sv.x - xi, dy = sv.y - yi, dz = sv.z - zi;
-                const bool self = f == self_idx;
-                R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-                r2 = self ? R(1) : r2;
-                const R mj = self ? R(0) : sv.w;
-                R g, phi;
-                PairKernel<R, KERNEL>::eval(r2, eps2, inv_eps, inv_eps3, g, phi);
-                const R mg = mj * g;
-                sx = fma(mg, dx, sx);
-                sy = fma(mg, dy, sy);
-                sz = fma(mg, dz, sz);
-                sp = fma(mj, phi, sp);
-              }
+              const R4 sv = svs[u];
+              const R dx = sv.x - xi, dy = sv.y - yi, dz = sv.z - zi;
+              const bool self = f == self_idx;
+              R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+              r2 = self ? R(1) : r2;
+              const R mj = self ? R(0) : sv.w;
+              R g, phi;
+              PairKernel<R, KERNEL>::eval(r2, eps2, inv_eps, inv_eps3, g, phi);
+              const R mg = mj * g;
+              sx = fma(mg, dx, sx);
+              sy = fma(mg, dy, sy);
+              sz = fma(mg, dz, sz);
+              sp = fma(mj, phi, sp);
             }
             ax += (double)sx;
             ay += (double)sy;

@@ -27,6 +27,10 @@
 #define TRAV_WAVES 4
 #define TRAV_CAND 512   // expanded candidates of one block of 64 open-list entries
 #define TRAV_STACK 2048 // descent items (target tag in the top 3 bits)
+// Room kept free for single-item (depth-first) pops: each pops one item and
+// pushes at most its 8 children, one level deeper, so a depth-first run from
+// any state grows the stack by at most 7 per level below it.
+#define TRAV_RESERVE (7 * (FMM_MAXLEVEL + 1))
 #define TRAV_TAG 28
 
 enum { CAT_NONE = 0, CAT_M2L = 1, CAT_P2P = 2, CAT_OPEN = 3, CAT_DEEPEN = 4 };
@@ -104,14 +108,16 @@ __device__ __forceinline__ void push_item(const DevTree &t, WaveLds &L, int &sp,
 }
 
 // Descents of leaf targets into non-leaf cells, LIFO.  A popped item (tg, C)
-// makes the children of C candidates of target tg; each may push one item,
-// so popping take <= (TRAV_STACK - sp) / 7 items can never overflow.
+// makes the children of C candidates of target tg; each may push one item.
+// Batches of take <= (TRAV_STACK - TRAV_RESERVE - sp) / 7 items keep sp below
+// TRAV_STACK - TRAV_RESERVE; once that room is used up, items are popped one
+// at a time (depth first), which the reserve absorbs.
 template <bool WRITE>
 __device__ void drain(const DevTree &t, Sibs &S, WaveLds &L, int &sp, int *open_out, double th2,
                       double eps, unsigned long long &pairs) {
   const int lane = __lane_id();
   while (sp > 0) {
-    const int room = (TRAV_STACK - sp) / 7;
+    const int room = (TRAV_STACK - TRAV_RESERVE - sp) / 7;
     const int take = min(sp, max(1, min(64, room)));
     const bool vp = lane < take;
     const int item = vp ? L.stack[sp - take + lane] : 0;
@@ -187,8 +193,9 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
     for (int q = 0; q < ec; ++q) L.cand[pos + q] = c0 + q;
     __builtin_amdgcn_wave_barrier();
     for (int cb = 0; cb < total; cb += 64) {
-      // a chunk pushes at most 64 items per target, 512 in all
-      if (sp > TRAV_STACK - 512) drain<WRITE>(t, S, L, sp, open_out, th2, eps, pairs);
+      // a chunk pushes at most 64 items per target, 512 in all, and must leave
+      // the depth-first reserve free
+      if (sp > TRAV_STACK - TRAV_RESERVE - 512) drain<WRITE>(t, S, L, sp, open_out, th2, eps, pairs);
       const bool valid = cb + lane < total;
       const int C = valid ? L.cand[cb + lane] : 0;
       double4 gC = make_double4(0, 0, 0, 0);
