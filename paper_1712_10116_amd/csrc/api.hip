@@ -65,10 +65,12 @@ static bool alloc_nodes(fmm_ctx *c, int64_t cap) {
             dalloc(c, &t.p2p_cnt, cap) && dalloc(c, &t.open_off, cap) &&
             dalloc(c, &t.open_cnt, cap) && dalloc(c, &t.nreq, cap);
   if (!ok) return false;
-  char *m = nullptr, *l = nullptr;
-  ok = dalloc(c, &m, (int64_t)(cap * t.kmax * real)) && dalloc(c, &l, (int64_t)(cap * t.kmax * real));
+  char *m = nullptr, *l = nullptr, *mh = nullptr;
+  ok = dalloc(c, &m, (int64_t)(cap * t.kmax * real)) && dalloc(c, &l, (int64_t)(cap * t.kmax * real)) &&
+       dalloc(c, &mh, (int64_t)(cap * t.khmax * real));
   t.M = m;
   t.L = l;
+  t.Mh = mh;
   return ok;
 }
 
@@ -76,7 +78,7 @@ static void free_nodes(fmm_ctx *c) {
   DevTree &t = c->t;
   void *ptrs[] = {t.nbeg, t.nend, t.nlev, t.nparent, t.nchild0, t.nnchild, t.ngeo, t.bounds,
                   t.m2l_off, t.m2l_cnt, t.p2p_off, t.p2p_cnt, t.open_off, t.open_cnt, t.M, t.L,
-                  t.nreq};
+                  t.Mh, t.nreq};
   for (void *p : ptrs) dfree(c, p);
 }
 
@@ -113,6 +115,7 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   DevTree &t = c->t;
   memset(&t, 0, sizeof(t));
   t.kmax = coeffs(prm->p_max);
+  t.khmax = (prm->p_max + 1) * (prm->p_max + 1);
   t.cap_n = max_n;
   int64_t n = max_n;
   int64_t cap_nodes = 8 * n / prm->leaf_size + 1024;

@@ -86,6 +86,7 @@ struct DevTree {
   double4 *ngeo;
   int32_t *bounds;  // [cap_nodes][8]
   void *M, *L;      // [cap_nodes][Kmax] of float or double
+  void *Mh;         // [cap_nodes][KHmax]: moments folded onto z-degree <= 1 (harmonic far field)
   // lists
   int32_t *m2l_off, *m2l_cnt, *m2l_src;
   int32_t *p2p_off, *p2p_cnt, *p2p_src;
@@ -100,7 +101,7 @@ struct DevTree {
   Header *hdr;
   Box *box;  // [cap_req]
   int64_t cap_n, cap_nodes, cap_m2l, cap_p2p, cap_open;
-  int kmax;
+  int kmax, khmax;
 };
 
 // ---------------------------------------------------------------------------

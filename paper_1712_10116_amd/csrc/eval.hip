@@ -46,6 +46,16 @@ __device__ __forceinline__ void store_row(T *__restrict__ base, int kmax, int no
   for (int t = 0; t < MI<P>::K; ++t) row[t] = v[t];
 }
 
+// folded moments of a cell (harmonic far field), stride khmax
+template <typename T, int P>
+__device__ __forceinline__ void store_folded(const DevTree &t, int node, const T (&M)[MI<P>::K]) {
+  T h[HI<P>::KH];
+  fold_moments<T, P>(M, h);
+  T *row = (T *)t.Mh + (size_t)node * t.khmax;
+#pragma unroll
+  for (int j = 0; j < HI<P>::KH; ++j) row[j] = h[j];
+}
+
 // a system whose mass pointer is NULL is skipped by this evaluation
 __device__ __forceinline__ bool skipped(const DevTree &t, int node) {
   return t.reqs[t.nreq[node]].mass == nullptr;
@@ -53,7 +63,7 @@ __device__ __forceinline__ bool skipped(const DevTree &t, int node) {
 
 // P2M at leaves: Mt[k] = sum_j m_j (u_j/h)^k/k!  (compensated in FP32)
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes, bool harm) {
   constexpr int K = MI<P>::K;
   T *M = (T *)t.M;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes; i += gridDim.x * blockDim.x) {
@@ -81,12 +91,13 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes) {
       }
     }
     store_row<T, P>(M, t.kmax, i, acc);
+    if (harm) store_folded<T, P>(t, i, acc);
   }
 }
 
 // M2M for the cells of one level that have children
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e, bool harm) {
   constexpr int K = MI<P>::K;
   T *M = (T *)t.M;
   for (int i = s + blockIdx.x * blockDim.x + threadIdx.x; i < e; i += gridDim.x * blockDim.x) {
@@ -107,17 +118,25 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e) {
       m2m_shift<T, P>(Mc, (T)(gc.w * ih), q, acc);
     }
     store_row<T, P>(M, t.kmax, i, acc);
+    if (harm) store_folded<T, P>(t, i, acc);
   }
 }
 
 // M2L: one wavefront per target cell A, lanes over A's list of sources B.
 // With rho = h_A:  Lt_A[n] = (1/h_A) sum_m (-1)^|m| beta^|m| Mt_B[m]
 //                             D^{n+m} psi_{eps/h_A}((zA - zB)/h_A),  beta = h_B/h_A.
+// For the Wendland kernel the far field is exactly -1/r (the lists only hold
+// pairs separated by more than eps), so the harmonic form is used: folded
+// moments, contraction onto n_z <= 1, unfolding after the wave reduction.
 template <typename T, int P, int KERNEL>
 __global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, double eps) {
   constexpr int K = MI<P>::K;
+  constexpr int KH = HI<P>::KH;
   constexpr MI<P> mi{};
+  constexpr HI<P> hi{};
+  constexpr bool HARM = KERNEL == 0;
   const T *M = (const T *)t.M;
+  const T *Mh = (const T *)t.Mh;
   T *L = (T *)t.L;
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -128,29 +147,51 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, doubl
     const double ih = 1.0 / gA.w;
     const T e2 = KERNEL == 1 ? (T)((eps * ih) * (eps * ih)) : T(0);
     const int off = t.m2l_off[A], cnt = t.m2l_cnt[A];
-    T acc[K];
+    T acc[K];  // in the harmonic form the n_z >= 2 entries are set by the unfolding
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = T(0);
+    for (int k = 0; k < K; ++k)
+      if (!HARM || mi.z[k] <= 1) acc[k] = T(0);
     for (int q = lane; q < cnt; q += 64) {
       const int B = t.m2l_src[off + q];
       const double4 gB = t.ngeo[B];
-      T D[K], Ms[K];
-      derivatives<T, P>((T)((gA.x - gB.x) * ih), (T)((gA.y - gB.y) * ih), (T)((gA.z - gB.z) * ih),
-                        e2, D);
-      load_row<T, P>(M, t.kmax, B, Ms);
+      const T X = (T)((gA.x - gB.x) * ih), Y = (T)((gA.y - gB.y) * ih),
+              Z = (T)((gA.z - gB.z) * ih);
       const T beta = (T)(gB.w * ih);
-      T bp = T(1);
+      T D[K];
+      if (HARM) {
+        derivatives<T, P, 2>(X, Y, Z, e2, D);
+        T Ms[KH];
+        const T *row = Mh + (size_t)B * t.khmax;
 #pragma unroll
-      for (int d = 0; d <= P; ++d) {
+        for (int j = 0; j < KH; ++j) Ms[j] = row[j];
+        T bp = T(1);
 #pragma unroll
-        for (int m = 0; m < K; ++m)
-          if (mi.deg[m] == d) Ms[m] *= (d & 1) ? -bp : bp;
-        bp *= beta;
+        for (int d = 0; d <= P; ++d) {
+#pragma unroll
+          for (int j = 0; j < KH; ++j)
+            if (mi.deg[hi.full[j]] == d) Ms[j] *= (d & 1) ? -bp : bp;
+          bp *= beta;
+        }
+        m2l_contract_h<T, P>(Ms, D, acc);
+      } else {
+        derivatives<T, P>(X, Y, Z, e2, D);
+        T Ms[K];
+        load_row<T, P>(M, t.kmax, B, Ms);
+        T bp = T(1);
+#pragma unroll
+        for (int d = 0; d <= P; ++d) {
+#pragma unroll
+          for (int m = 0; m < K; ++m)
+            if (mi.deg[m] == d) Ms[m] *= (d & 1) ? -bp : bp;
+          bp *= beta;
+        }
+        m2l_contract<T, P>(Ms, D, acc);
       }
-      m2l_contract<T, P>(Ms, D, acc);
     }
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = wave_sum(acc[k]) * (T)ih;
+    for (int k = 0; k < K; ++k)
+      if (!HARM || mi.z[k] <= 1) acc[k] = wave_sum(acc[k]) * (T)ih;
+    if (HARM) unfold_locals<T, P>(acc);
     if (lane == 0) store_row<T, P>(L, t.kmax, A, acc);
   }
 }
@@ -403,12 +444,13 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   const int nn = e.n_nodes;
   const int nb_nodes = (nn + FMM_BLOCK - 1) / FMM_BLOCK;
   PhaseTimer *tm = e.tm;
-  hipLaunchKernelGGL((k_p2m<T, P>), dim3(nb_nodes), dim3(FMM_BLOCK), 0, s, t, nn);
+  const bool harm = KERNEL == 0;  // folded moments feed the harmonic M2L
+  hipLaunchKernelGGL((k_p2m<T, P>), dim3(nb_nodes), dim3(FMM_BLOCK), 0, s, t, nn, harm);
   for (int l = e.depth - 1; l >= 0; --l) {
     int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
     if (le > ls)
       hipLaunchKernelGGL((k_m2m<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
-                         dim3(FMM_BLOCK), 0, s, t, ls, le);
+                         dim3(FMM_BLOCK), 0, s, t, ls, le, harm);
   }
   const int wave_blocks = (nn + 3) / 4;
   if (tm) {

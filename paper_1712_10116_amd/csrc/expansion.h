@@ -88,8 +88,10 @@ __device__ __forceinline__ double fast_rsqrt<double>(double s) {
   return y;
 }
 
-// D[t] = d^{k_t} psi / dR^{k_t}, psi = -(|R|^2 + e2)^(-1/2)
-template <typename T, int P>
+// D[t] = d^{k_t} psi / dR^{k_t}, psi = -(|R|^2 + e2)^(-1/2), for the k_t with
+// z-degree <= ZMAX (the recursion for such k only uses such k; other entries
+// of D are left unset)
+template <typename T, int P, int ZMAX = P>
 __device__ __forceinline__ void derivatives(T X, T Y, T Z, T e2, T (&D)[MI<P>::K]) {
   constexpr MI<P> mi{};
   constexpr int K = MI<P>::K;
@@ -107,7 +109,7 @@ __device__ __forceinline__ void derivatives(T X, T Y, T Z, T e2, T (&D)[MI<P>::K
 #pragma unroll
     for (int t = 0; t < K; ++t) {
       const int d = mi.deg[t];
-      if (d > P - n) continue;
+      if (d > P - n || mi.z[t] > ZMAX) continue;
       if (d == 0) {
         Rn[n][t] = G[n];
         continue;
@@ -129,7 +131,8 @@ __device__ __forceinline__ void derivatives(T X, T Y, T Z, T e2, T (&D)[MI<P>::K
     }
   }
 #pragma unroll
-  for (int t = 0; t < K; ++t) D[t] = Rn[0][t];
+  for (int t = 0; t < K; ++t)
+    if (mi.z[t] <= ZMAX) D[t] = Rn[0][t];
 }
 
 // Compile-time term lists: only the (n, m) index pairs that occur, so every
@@ -192,6 +195,108 @@ __device__ __forceinline__ void m2l_contract(const T (&Ms)[MI<P>::K], const T (&
   constexpr M2LTerms<P> tt{};
 #pragma unroll
   for (int q = 0; q < M2LTerms<P>::NT; ++q) Lacc[tt.n[q]] = fma(Ms[tt.m[q]], D[tt.nm[q]], Lacc[tt.n[q]]);
+}
+
+// ---------------------------------------------------------------------------
+// Harmonic far field.  For psi = -1/|R| the derivative tensors satisfy
+// Laplace's equation, D[k + 2e_z] = -D[k + 2e_x] - D[k + 2e_y], so in
+//   L[n] = sum_m M[m] D[n+m]
+// every moment with m_z >= 2 can be moved onto two moments of the same degree
+// with m_z lowered by 2 ("folding"), leaving the 2d+1 moments of each degree d
+// with m_z <= 1.  The local coefficients obey the same relation, so only the
+// 2d+1 with n_z <= 1 need the contraction; the rest follow by "unfolding".
+// Per pair this costs sum_{a+b<=P} (2a+1)(2b+1) multiply-adds instead of
+// C(P+6,6) (532 instead of 924 at P = 6), with derivatives of z-degree <= 2.
+// ---------------------------------------------------------------------------
+template <int P>
+struct HI {  // the multi-indices with z-degree <= 1, in MI order
+  static constexpr int KH = (P + 1) * (P + 1);
+  int full[KH];            // compact -> MI index
+  int compact[MI<P>::K];   // MI index -> compact index, or -1
+  constexpr HI() : full(), compact() {
+    constexpr MI<P> mi{};
+    int c = 0;
+    for (int t = 0; t < MI<P>::K; ++t) {
+      compact[t] = mi.z[t] <= 1 ? c : -1;
+      if (mi.z[t] <= 1) full[c++] = t;
+    }
+  }
+};
+
+// moments folded onto z-degree <= 1: Mh[compact(m)] for m_z <= 1
+template <typename T, int P>
+__device__ __forceinline__ void fold_moments(const T (&M)[MI<P>::K], T (&Mh)[HI<P>::KH]) {
+  constexpr MI<P> mi{};
+  constexpr HI<P> hi{};
+  T w[MI<P>::K];
+#pragma unroll
+  for (int t = 0; t < MI<P>::K; ++t) w[t] = M[t];
+  // within each degree, highest z first, so folded values cascade down by 2
+#pragma unroll
+  for (int d = 2; d <= P; ++d)
+#pragma unroll
+    for (int c = d; c >= 2; --c)
+#pragma unroll
+      for (int b = 0; b <= d - c; ++b) {
+        const int a = d - c - b;
+        const int t = mi.at(a, b, c);
+        w[mi.at(a + 2, b, c - 2)] -= w[t];
+        w[mi.at(a, b + 2, c - 2)] -= w[t];
+      }
+#pragma unroll
+  for (int j = 0; j < HI<P>::KH; ++j) Mh[j] = w[hi.full[j]];
+}
+
+// local coefficients with n_z >= 2 from those with lower n_z (same degree)
+template <typename T, int P>
+__device__ __forceinline__ void unfold_locals(T (&L)[MI<P>::K]) {
+  constexpr MI<P> mi{};
+#pragma unroll
+  for (int d = 2; d <= P; ++d)
+#pragma unroll
+    for (int c = 2; c <= d; ++c)
+#pragma unroll
+      for (int b = 0; b <= d - c; ++b) {
+        const int a = d - c - b;
+        L[mi.at(a, b, c)] = -L[mi.at(a + 2, b, c - 2)] - L[mi.at(a, b + 2, c - 2)];
+      }
+}
+
+template <int P>
+struct M2LHTerms {  // (n, m) with n_z, m_z <= 1 and |n| + |m| <= P: (n, compact m, n+m)
+  static constexpr int count() {
+    constexpr MI<P> mi{};
+    int c = 0;
+    for (int n = 0; n < MI<P>::K; ++n)
+      for (int m = 0; m < MI<P>::K; ++m)
+        c += mi.z[n] <= 1 && mi.z[m] <= 1 && mi.deg[n] + mi.deg[m] <= P;
+    return c;
+  }
+  static constexpr int NT = count();
+  int n[NT], mc[NT], nm[NT];
+  constexpr M2LHTerms() : n(), mc(), nm() {
+    constexpr MI<P> mi{};
+    constexpr HI<P> hi{};
+    int c = 0;
+    for (int a = 0; a < MI<P>::K; ++a)
+      for (int b = 0; b < MI<P>::K; ++b)
+        if (mi.z[a] <= 1 && mi.z[b] <= 1 && mi.deg[a] + mi.deg[b] <= P) {
+          n[c] = a;
+          mc[c] = hi.compact[b];
+          nm[c] = mi.at(mi.x[a] + mi.x[b], mi.y[a] + mi.y[b], mi.z[a] + mi.z[b]);
+          ++c;
+        }
+  }
+};
+
+// Lacc[n] += sum_m Mh[m] D[n+m] over n_z, m_z <= 1 (Lacc entries with n_z >= 2 untouched)
+template <typename T, int P>
+__device__ __forceinline__ void m2l_contract_h(const T (&Mh)[HI<P>::KH], const T (&D)[MI<P>::K],
+                                               T (&Lacc)[MI<P>::K]) {
+  constexpr M2LHTerms<P> tt{};
+#pragma unroll
+  for (int q = 0; q < M2LHTerms<P>::NT; ++q)
+    Lacc[tt.n[q]] = fma(Mh[tt.mc[q]], D[tt.nm[q]], Lacc[tt.n[q]]);
 }
 
 // Multipole shift to the parent: Mp[m] += sum_{k<=m} beta^|k| Mc[k] q[m-k],
