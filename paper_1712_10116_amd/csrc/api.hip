@@ -82,16 +82,37 @@ static void free_nodes(fmm_ctx *c) {
   for (void *p : ptrs) dfree(c, p);
 }
 
-// request-sized arrays (regrown when a batch holds more requests)
+// Request-sized arrays (regrown when a batch holds more requests).  The
+// request table, its particle offsets and its block offsets share one device
+// region, mirrored by pinned host staging slots, so a table is sent in one copy.
+static size_t req_region_bytes(int cap) {
+  return sizeof(DevReq) * (size_t)cap + 2 * sizeof(int32_t) * (size_t)(cap + 1);
+}
+
 static bool alloc_reqs(fmm_ctx *c, int cap) {
   DevTree &t = c->t;
-  void *ptrs[] = {t.reqs, t.req_off, t.blk_off, t.box, t.bbox_part};
+  for (int k = 0; k < fmm_ctx::UP_SLOTS; ++k)
+    if (c->up_ev_set[k]) (void)hipEventSynchronize(c->up_ev[k]);
+  void *ptrs[] = {t.reqs, t.box, t.bbox_part};
   for (void *p : ptrs) dfree(c, p);
   t.reqs = nullptr;
   t.cap_req = cap;
-  return dalloc(c, &t.reqs, cap) && dalloc(c, &t.req_off, cap + 1) &&
-         dalloc(c, &t.blk_off, cap + 1) && dalloc(c, &t.box, cap) &&
-         dalloc(c, &t.bbox_part, (int64_t)cap * 64 * 6);
+  const size_t bytes = req_region_bytes(cap);
+  char *region = nullptr;
+  if (!dalloc(c, &region, (int64_t)bytes) || !dalloc(c, &t.box, cap) ||
+      !dalloc(c, &t.bbox_part, (int64_t)cap * FMM_BBOX_BLOCKS * 6))
+    return false;
+  t.reqs = (DevReq *)region;
+  t.req_off = (int32_t *)(region + sizeof(DevReq) * (size_t)cap);
+  t.blk_off = t.req_off + cap + 1;
+  for (int k = 0; k < fmm_ctx::UP_SLOTS; ++k) {
+    if (c->up_pin[k]) (void)hipHostFree(c->up_pin[k]);
+    c->up_pin[k] = nullptr;
+    if (hipHostMalloc((void **)&c->up_pin[k], bytes) != hipSuccess) return false;
+  }
+  c->up_bytes = bytes;
+  c->up_valid = false;
+  return true;
 }
 
 extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *stream,
@@ -114,6 +135,13 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   }
   DevTree &t = c->t;
   memset(&t, 0, sizeof(t));
+  bool pins = hipHostMalloc((void **)&c->pin_hdr, sizeof(Header)) == hipSuccess;
+  for (int k = 0; pins && k < fmm_ctx::UP_SLOTS; ++k)
+    pins = hipEventCreateWithFlags(&c->up_ev[k], hipEventDisableTiming) == hipSuccess;
+  if (!pins) {
+    fmm_destroy(c);
+    return FMM_ENOMEM;
+  }
   t.kmax = coeffs(prm->p_max);
   t.khmax = (prm->p_max + 1) * (prm->p_max + 1);
   t.cap_n = max_n;
@@ -121,8 +149,7 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   int64_t cap_nodes = 8 * n / prm->leaf_size + 1024;
   bool ok = dalloc(c, &t.key, n) && dalloc(c, &t.key2, n) && dalloc(c, &t.slot, n) &&
             dalloc(c, &t.slot2, n) && dalloc(c, &t.sx, n) && dalloc(c, &t.sy, n) &&
-            dalloc(c, &t.sz, n) && dalloc(c, &t.lx, n) && dalloc(c, &t.ly, n) &&
-            dalloc(c, &t.lz, n) && dalloc(c, &t.sm, n) && dalloc(c, &t.sm32, n) &&
+            dalloc(c, &t.sz, n) && dalloc(c, &t.sm, n) && dalloc(c, &t.sm32, n) &&
             dalloc(c, &t.leaf_of, n) && dalloc(c, &t.near, 4 * n) &&
             dalloc(c, &t.scan_part, FMM_SCAN_BLOCKS) && dalloc(c, &t.slot_req, n) &&
             dalloc(c, &t.sort_hist, 256 * ((n + 4095) / 4096) + 256) &&
@@ -159,6 +186,11 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
     }
   if (c->own_run) hhs_run_destroy(c->own_run);
   for (void *p : c->allocs) (void)hipFree(p);
+  for (int k = 0; k < fmm_ctx::UP_SLOTS; ++k) {
+    if (c->up_pin[k]) (void)hipHostFree(c->up_pin[k]);
+    if (c->up_ev[k]) (void)hipEventDestroy(c->up_ev[k]);
+  }
+  if (c->pin_hdr) (void)hipHostFree(c->pin_hdr);
   delete c;
   return FMM_OK;
 }
@@ -189,43 +221,57 @@ static fmm_status check_requests(fmm_ctx *c, int n_req, const fmm_request *reqs,
   return FMM_OK;
 }
 
-// upload the request table (pageable staging: the host copy is consumed when
-// the call returns, so the vectors may be reused by the next call)
+// Stage the request table in the next pinned slot and send it in one copy,
+// unless it equals the table last sent.  Blocks per request for the box
+// reduction: ceil(n / 2048), at least 1 and at most FMM_BBOX_BLOCKS.
 static fmm_status upload_requests(fmm_ctx *c, int n_req, const fmm_request *reqs, int *n_blk) {
   DevTree &t = c->t;
   if (n_req > t.cap_req && !alloc_reqs(c, std::max(n_req, 2 * t.cap_req)))
     return fail(c, FMM_ENOMEM, "request table for %d requests", n_req);
-  c->h_reqs.resize(n_req);
-  c->h_off.resize(n_req + 1);
-  c->h_blk.resize(n_req + 1);
+  const int k = c->up_next;
+  if (c->up_ev_set[k]) HIPCHK(c, hipEventSynchronize(c->up_ev[k]));
+  char *stage = c->up_pin[k];
+  memset(stage, 0, c->up_bytes);
+  DevReq *hr = (DevReq *)stage;
+  int32_t *ho = (int32_t *)(stage + sizeof(DevReq) * (size_t)t.cap_req);
+  int32_t *hb = ho + t.cap_req + 1;
   int off = 0, blk = 0;
   for (int r = 0; r < n_req; ++r) {
     const fmm_request &q = reqs[r];
-    DevReq d;
-    d.pos = q.pos;
-    d.active = q.active;
-    d.mass = q.mass;
-    d.acc = q.acc;
-    d.pot = q.pot;
-    d.n_total = q.n_total;
-    d.off = off;
-    d.n = (int32_t)q.n_active;
-    c->h_reqs[r] = d;
-    c->h_off[r] = off;
-    c->h_blk[r] = blk;
+    hr[r].pos = q.pos;
+    hr[r].active = q.active;
+    hr[r].mass = q.mass;
+    hr[r].acc = q.acc;
+    hr[r].pot = q.pot;
+    hr[r].n_total = q.n_total;
+    hr[r].off = off;
+    hr[r].n = (int32_t)q.n_active;
+    ho[r] = off;
+    hb[r] = blk;
     off += (int)q.n_active;
-    blk += (int)std::min<int64_t>(64, std::max<int64_t>(1, (q.n_active + 4095) / 4096));
+    blk += (int)std::min<int64_t>(FMM_BBOX_BLOCKS, std::max<int64_t>(1, (q.n_active + 2047) / 2048));
   }
-  c->h_off[n_req] = off;
-  c->h_blk[n_req] = blk;
+  ho[n_req] = off;
+  hb[n_req] = blk;
   t.n_req = n_req;
-  HIPCHK(c, hipMemcpyAsync(t.reqs, c->h_reqs.data(), sizeof(DevReq) * n_req,
-                           hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(t.req_off, c->h_off.data(), sizeof(int32_t) * (n_req + 1),
-                           hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(t.blk_off, c->h_blk.data(), sizeof(int32_t) * (n_req + 1),
-                           hipMemcpyHostToDevice, c->stream));
+  if (!(c->up_valid && c->up_last.size() == c->up_bytes &&
+        memcmp(c->up_last.data(), stage, c->up_bytes) == 0)) {
+    HIPCHK(c, hipMemcpyAsync(t.reqs, stage, c->up_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(c->up_ev[k], c->stream));
+    c->up_ev_set[k] = true;
+    c->up_next = (k + 1) % fmm_ctx::UP_SLOTS;
+    c->up_last.assign(stage, stage + c->up_bytes);
+    c->up_valid = true;
+  }
   if (n_blk) *n_blk = blk;
+  return FMM_OK;
+}
+
+// header readback through pinned memory; waits for the stream
+static fmm_status read_header(fmm_ctx *c) {
+  HIPCHK(c, hipMemcpyAsync(c->pin_hdr, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  memcpy(&c->hh, c->pin_hdr, sizeof(Header));
   return FMM_OK;
 }
 
@@ -275,18 +321,16 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
   // 1. tree; one readback of the level sizes (exact launches for the walk)
   for (int attempt = 0;; ++attempt) {
     if (attempt == 4) return fail(c, FMM_EOVERFLOW, "node workspace still too small");
-    HIPCHK(c, hipMemsetAsync(&c->t.hdr->nonfinite, 0, sizeof(int32_t), c->stream));
     HIPCHK(c, launch_sort(c->t, a, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    st = read_header(c);
+    if (st != FMM_OK) return st;
     if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
-    // no cell below level max_prefix + 1 can hold two particles
+    // no cell below level split_depth + 1 holds more than leaf_size particles
     const int max_level = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
     if (!(c->hh.overflow & OVF_NODES)) {
       HIPCHK(c, launch_build_tree(c->t, a, max_level, c->stream));
-      HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost,
-                               c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
+      st = read_header(c);
+      if (st != FMM_OK) return st;
     }
     if (!(c->hh.overflow & OVF_NODES)) break;
     int64_t need = std::max<int64_t>(std::max<int64_t>((int64_t)c->hh.lvl_start[FMM_NLEVELS],
@@ -306,8 +350,8 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
   // 2. symmetric walk; regrow a list buffer that turned out too small
   for (int attempt = 0; attempt < 4; ++attempt) {
     HIPCHK(c, launch_traverse(c->t, a, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&c->hh, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    st = read_header(c);
+    if (st != FMM_OK) return st;
     const Header &h = c->hh;
     if (h.overflow & OVF_STACK) return fail(c, FMM_EOVERFLOW, "walk descent stack overflow");
     if (h.overflow & (OVF_M2L | OVF_P2P | OVF_OPEN)) {

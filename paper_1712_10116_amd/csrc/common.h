@@ -20,6 +20,7 @@
 #define FMM_NLEVELS (FMM_MAXLEVEL + 1)
 #define FMM_BLOCK 256
 #define FMM_SCAN_BLOCKS 256
+#define FMM_BBOX_BLOCKS 256  // box-reduction blocks per request, at most
 
 // error bits latched in Header::overflow
 #define OVF_NODES 1
@@ -37,7 +38,7 @@ struct Header {
   int32_t nonfinite;                   // an input position was not finite
   unsigned long long p2p_pairs;        // ordered particle interactions in P2P
   int32_t n_leaves;
-  int32_t max_prefix;  // longest common key prefix (levels) of sorted neighbours
+  int32_t max_prefix;  // deepest level of a cell holding more than leaf_size particles
 };
 
 // Box: o[3] (origin), L (side), s = 2^21/L, lo[3], hi[3]
@@ -76,7 +77,6 @@ struct DevTree {
   uint64_t *key, *key2;
   int32_t *slot, *slot2;
   double *sx, *sy, *sz;
-  float *lx, *ly, *lz;
   double *sm;
   float *sm32;
   int32_t *leaf_of;

@@ -20,8 +20,18 @@ struct fmm_ctx {
   std::vector<fmm_request> b_reqs;  // requests of the last build
   int64_t b_n;                      // their active particles in all
   double b_eps, b_theta;
-  std::vector<DevReq> h_reqs;       // staging of the device request table
-  std::vector<int32_t> h_off, h_blk;
+  // request table uploads: a ring of pinned staging slots (each reused only
+  // after the copy from it has completed) and the last table sent, so an
+  // unchanged table is not sent again
+  static constexpr int UP_SLOTS = 8;
+  char *up_pin[UP_SLOTS];
+  hipEvent_t up_ev[UP_SLOTS];
+  bool up_ev_set[UP_SLOTS];
+  int up_next;
+  size_t up_bytes;                  // bytes of one slot = device request region
+  std::vector<char> up_last;
+  bool up_valid;
+  Header *pin_hdr;                  // pinned destination of header readbacks
   int n_nodes, depth;
   // integrator
   hhs_run *own_run;       // scratch of hhs_init / hhs_step (one system)

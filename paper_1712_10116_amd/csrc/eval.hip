@@ -74,6 +74,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes, bool 
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = cmp[k] = T(0);
     for (int j = t.nbeg[i]; j < t.nend[i]; ++j) {
+      t.leaf_of[j] = i;
       T mono[K];
       monomials<T, P>((T)((t.sx[j] - g.x) * ih), (T)((t.sy[j] - g.y) * ih),
                       (T)((t.sz[j] - g.z) * ih), mono);

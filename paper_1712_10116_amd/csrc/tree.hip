@@ -42,8 +42,14 @@ __device__ __forceinline__ int upper_index(const int32_t *off, int m, int x) {
   return lo;
 }
 
+// request of every active slot; also clears the header counters that the
+// following kernels accumulate into (non-finite flag, leaf count)
 __global__ __launch_bounds__(FMM_BLOCK) void k_slot_req(DevTree t, int n) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0) {
+    t.hdr->nonfinite = 0;
+    t.hdr->n_leaves = 0;
+  }
   if (s < n) t.slot_req[s] = upper_index(t.req_off, t.n_req, s);
 }
 
@@ -366,15 +372,21 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
   }
 }
 
-// deepest level at which two neighbouring sorted keys still share a cell:
-// no cell deeper than that + 1 can hold two particles, so the split stops there
-__global__ __launch_bounds__(FMM_BLOCK) void k_max_common_prefix(DevTree t, int n) {
+// Deepest level at which a cell holds more than leaf_size particles: a cell
+// holds more than leaf_size particles exactly when some sorted key and the key
+// leaf_size positions later (same request) share its prefix.  Cells below that
+// level are leaves, so the split stops there.
+__global__ __launch_bounds__(FMM_BLOCK) void k_split_depth(DevTree t, int n, int stride) {
   int best = 0;
   const uint64_t *key = t.key;
   Header *hdr = t.hdr;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += gridDim.x * blockDim.x) {
-    if (t.slot_req[t.slot[i]] != t.slot_req[t.slot[i + 1]]) continue;
-    uint64_t x = key[i] ^ key[i + 1];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i + stride < n;
+       i += gridDim.x * blockDim.x) {
+    if (t.n_req > 1) {  // sorted positions are grouped by request, in request order
+      const int r = upper_index(t.req_off, t.n_req, i);
+      if (i + stride >= t.req_off[r + 1]) continue;
+    }
+    uint64_t x = key[i] ^ key[i + stride];
     int digits = x == 0 ? FMM_MAXLEVEL : (__clzll(x) - 1) / 3;
     best = max(best, digits);
   }
@@ -413,7 +425,7 @@ __device__ __forceinline__ double4 cell_geometry(const Box &b, uint64_t prefix, 
 }
 
 // one root per request, covering its sorted range [off, off + n)
-__global__ __launch_bounds__(FMM_BLOCK) void k_tree_init(DevTree t) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_tree_init(DevTree t, int leaf_size) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   Header *h = t.hdr;
   const int R = t.n_req;
@@ -421,7 +433,6 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_init(DevTree t) {
     h->lvl_start[0] = 0;
     for (int l = 1; l < FMM_NLEVELS + 2; ++l) h->lvl_start[l] = R;
     h->overflow = R > t.cap_nodes ? OVF_NODES : 0;
-    h->n_leaves = 0;
     h->max_prefix = 0;
   }
   if (r >= R || r >= t.cap_nodes) return;
@@ -433,6 +444,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_init(DevTree t) {
   t.nnchild[r] = 0;
   t.nreq[r] = r;
   t.ngeo[r] = cell_geometry(t.box[r], 0ull, 0);
+  if (t.req_off[r + 1] - t.req_off[r] <= leaf_size) atomicAdd((int *)&h->n_leaves, 1);
 }
 
 __device__ __forceinline__ int lower_bound_digit(const uint64_t *__restrict__ key, int b, int e,
@@ -506,7 +518,10 @@ __global__ __launch_bounds__(FMM_SCAN_BLOCKS) void k_tree_scan(DevTree t, int l)
   }
 }
 
-__global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l) {
+// Children of the splitting cells of level l; a child is a leaf when it holds
+// at most leaf_size particles or sits at the deepest level, and leaves are
+// counted here.
+__global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l, int leaf_size) {
   int s, e;
   level_chunk(t.hdr, l, s, e);
   __shared__ int sc[FMM_BLOCK];
@@ -525,6 +540,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l) {
     int first = run + sc[threadIdx.x] - nc;
     int total = sc[FMM_BLOCK - 1];
     __syncthreads();
+    int leaves = 0;
     if (nc > 0) {
       t.nchild0[i] = first;
       const int rq = t.nreq[i];
@@ -545,49 +561,27 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l) {
             uint64_t prefix = t.key[b] >> (3 * (FMM_MAXLEVEL - (l + 1)));
             t.ngeo[c] = cell_geometry(box, prefix, l + 1);
           }
+          leaves += (en - b <= leaf_size || l + 1 == FMM_MAXLEVEL);
           ++c;
         }
       }
     } else if (i < e && i < t.cap_nodes) {
       t.nchild0[i] = -1;
     }
+    if (leaves) atomicAdd((int *)&t.hdr->n_leaves, leaves);
     run += total;
   }
-}
-
-// leaf id and FP32 cell-local offsets of every particle: one wavefront per
-// leaf, lanes over its particles
-__global__ __launch_bounds__(FMM_BLOCK) void k_mark_leaves(DevTree t) {
-  const Header *h = t.hdr;
-  const int nn = min((int)t.cap_nodes, h->lvl_start[FMM_NLEVELS]);
-  const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int nwaves = (gridDim.x * blockDim.x) >> 6;
-  int leaves = 0;
-  for (int i = wave; i < nn; i += nwaves) {
-    if (t.nnchild[i] != 0) continue;
-    ++leaves;
-    const double4 g = t.ngeo[i];
-    const int e = t.nend[i];
-    for (int j = t.nbeg[i] + lane; j < e; j += 64) {
-      t.leaf_of[j] = i;
-      t.lx[j] = (float)(t.sx[j] - g.x);
-      t.ly[j] = (float)(t.sy[j] - g.y);
-      t.lz[j] = (float)(t.sz[j] - g.z);
-    }
-  }
-  if (lane == 0 && leaves) atomicAdd((int *)&t.hdr->n_leaves, leaves);
 }
 
 hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
   const int n = a.n;
   const int nb = (n + FMM_BLOCK - 1) / FMM_BLOCK;
   if (a.tm) a.tm->start(PH_SORT, s);
-  if (n > 0) hipLaunchKernelGGL(k_slot_req, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
+  hipLaunchKernelGGL(k_slot_req, dim3(std::max(nb, 1)), dim3(FMM_BLOCK), 0, s, t, n);
   hipLaunchKernelGGL(k_bbox_partial, dim3(a.n_blk), dim3(FMM_BLOCK), 0, s, t);
   hipLaunchKernelGGL(k_bbox_final, dim3((a.n_req + 3) / 4), dim3(FMM_BLOCK), 0, s, t);
   hipLaunchKernelGGL(k_tree_init, dim3((a.n_req + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
-                     s, t);
+                     s, t, a.leaf_size);
   if (n > 0) {
     hipLaunchKernelGGL(k_keys, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
     const int nblk = (n + SORT_TILE - 1) / SORT_TILE;
@@ -610,7 +604,8 @@ hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
       int32_t *ts = sin; sin = sout; sout = ts;
     }
     hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
-    hipLaunchKernelGGL(k_max_common_prefix, dim3(std::min(nb, 1024)), dim3(FMM_BLOCK), 0, s, t, n);
+    hipLaunchKernelGGL(k_split_depth, dim3(std::min(nb, 1024)), dim3(FMM_BLOCK), 0, s, t, n,
+                       a.leaf_size);
   }
   if (a.tm) a.tm->stop(s);
   return hipGetLastError();
@@ -625,9 +620,9 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, int max_level
       hipLaunchKernelGGL(k_tree_count, dim3(FMM_SCAN_BLOCKS), dim3(FMM_BLOCK), 0, s, t, l,
                          a.leaf_size);
       hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(FMM_SCAN_BLOCKS), 0, s, t, l);
-      hipLaunchKernelGGL(k_tree_emit, dim3(FMM_SCAN_BLOCKS), dim3(FMM_BLOCK), 0, s, t, l);
+      hipLaunchKernelGGL(k_tree_emit, dim3(FMM_SCAN_BLOCKS), dim3(FMM_BLOCK), 0, s, t, l,
+                         a.leaf_size);
     }
-    hipLaunchKernelGGL(k_mark_leaves, dim3(1024), dim3(FMM_BLOCK), 0, s, t);
   }
   if (a.tm) a.tm->stop(s);
   return hipGetLastError();
