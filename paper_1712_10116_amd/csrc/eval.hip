@@ -249,23 +249,27 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n) {
 // ---------------------------------------------------------------------------
 template <typename R, int KERNEL>
 struct PairKernel {
-  // acceleration factor g = psi'(r)/r and potential psi for squared distance r2
-  __device__ __forceinline__ static void eval(R r2, R eps2, R inv_eps, R inv_eps3, R &g, R &phi) {
+  // For a source of mass m at squared distance r2: mg = m psi'(r)/r (the
+  // acceleration factor) and t = -m psi(r) (the potential, sign flipped).
+  // Plummer: psi = -(r2 + eps2)^(-1/2).  Wendland C2 (Eq. 8): psi = -1/r for
+  // r >= eps, the polynomial in u = r/eps inside.
+  __device__ __forceinline__ static void eval(R r2, R m, R eps2, R inv_eps, R inv_eps3, R &mg,
+                                              R &t) {
     if (KERNEL == 1) {
-      R rinv = fast_rsqrt<R>(r2 + eps2);
-      g = rinv * rinv * rinv;
-      phi = -rinv;
+      const R rinv = fast_rsqrt<R>(r2 + eps2);
+      t = m * rinv;
+      mg = t * (rinv * rinv);
     } else {
-      R rinv = fast_rsqrt<R>(r2);
-      g = rinv * rinv * rinv;
-      phi = -rinv;
+      const R rinv = fast_rsqrt<R>(r2);
+      t = m * rinv;
+      mg = t * (rinv * rinv);
       if (r2 < eps2) {
         R r = r2 > R(0) ? r2 * rinv : R(0);
         R u = r * inv_eps;
         R u2 = u * u;
-        g = fma(fma(fma(fma(R(21), u, R(-90)), u, R(140)), u, R(-84)), u2, R(14)) * inv_eps3;
-        phi = fma(u2, fma(fma(fma(fma(R(3), u, R(-15)), u, R(28)), u, R(-21)), u2, R(7)), R(-3)) *
-              inv_eps;
+        mg = m * (fma(fma(fma(fma(R(21), u, R(-90)), u, R(140)), u, R(-84)), u2, R(14)) * inv_eps3);
+        t = m * (fma(u2, fma(fma(fma(fma(R(-3), u, R(15)), u, R(-28)), u, R(21)), u2, R(-7)),
+                     R(3)) * inv_eps);
       }
     }
   }
@@ -304,7 +308,40 @@ struct P2PTypes<false> {
   __device__ static R4 far() { return make_double4(1e150, 1e150, 1e150, 0.0); }
 };
 
-template <bool MIXED, int KERNEL>
+// One block of UNROLL sources per phase, NPH phases (NPH = 0: nph at run time).
+template <typename R, typename R4, int KERNEL, bool SELF, int NPH>
+__device__ __forceinline__ void p2p_block(const R4 *src, int f0, int nph, int self_idx, R xi, R yi,
+                                          R zi, R eps2, R inv_eps, R inv_eps3, R &sx, R &sy,
+                                          R &sz, R &sp) {
+  const int step = NPH > 0 ? NPH : nph;
+  R4 svs[P2P_UNROLL];  // the block's sources, read before any use
+#pragma unroll
+  for (int u = 0; u < P2P_UNROLL; ++u) svs[u] = src[f0 + u * step];
+#pragma unroll
+  for (int u = 0; u < P2P_UNROLL; ++u) {
+    const R4 sv = svs[u];
+    const R dx = sv.x - xi, dy = sv.y - yi, dz = sv.z - zi;
+    R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    R mj = sv.w;
+    if (SELF) {
+      const bool self = f0 + u * step == self_idx;
+      r2 = self ? R(1) : r2;
+      mj = self ? R(0) : mj;
+    }
+    R mg, tp;
+    PairKernel<R, KERNEL>::eval(r2, mj, eps2, inv_eps, inv_eps3, mg, tp);
+    sx = fma(mg, dx, sx);
+    sy = fma(mg, dy, sy);
+    sz = fma(mg, dz, sz);
+    sp += tp;
+  }
+}
+
+// SELF: exclude the self pair by its stream position (needed when eps = 0);
+// otherwise the self pair is evaluated -- its acceleration term is exactly
+// zero (dx = 0) -- and its potential term, reproduced bit for bit, is taken
+// off once per sink.
+template <bool MIXED, int KERNEL, bool SELF>
 __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, double eps) {
   typedef typename P2PTypes<MIXED>::R R;
   typedef typename P2PTypes<MIXED>::R4 R4;
@@ -394,30 +431,16 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
           const int self_idx = self_start + i - w0;
           for (int f0 = ph; f0 < Wr; f0 += blk) {
             R sx = 0, sy = 0, sz = 0, sp = 0;
-            R4 svs[P2P_UNROLL];  // the block's sources, read before any use
-#pragma unroll
-            for (int u = 0; u < P2P_UNROLL; ++u) svs[u] = src[f0 + u * nph];
-#pragma unroll
-            for (int u = 0; u < P2P_UNROLL; ++u) {
-              const int f = f0 + u * nph;
-              const R4 sv = svs[u];
-              const R dx = sv.x - xi, dy = sv.y - yi, dz = sv.z - zi;
-              const bool self = f == self_idx;
-              R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-              r2 = self ? R(1) : r2;
-              const R mj = self ? R(0) : sv.w;
-              R g, phi;
-              PairKernel<R, KERNEL>::eval(r2, eps2, inv_eps, inv_eps3, g, phi);
-              const R mg = mj * g;
-              sx = fma(mg, dx, sx);
-              sy = fma(mg, dy, sy);
-              sz = fma(mg, dz, sz);
-              sp = fma(mj, phi, sp);
-            }
+            if (nph == 1)
+              p2p_block<R, R4, KERNEL, SELF, 1>(src, f0, 1, self_idx, xi, yi, zi, eps2, inv_eps,
+                                                inv_eps3, sx, sy, sz, sp);
+            else
+              p2p_block<R, R4, KERNEL, SELF, 0>(src, f0, nph, self_idx, xi, yi, zi, eps2, inv_eps,
+                                                inv_eps3, sx, sy, sz, sp);
             ax += (double)sx;
             ay += (double)sy;
             az += (double)sz;
-            pp += (double)sp;
+            pp -= (double)sp;
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -428,6 +451,12 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
         ay += __shfl_xor(ay, o, 64);
         az += __shfl_xor(az, o, 64);
         pp += __shfl_xor(pp, o, 64);
+      }
+      if (!SELF) {  // the self pair's potential term, as the loop computed it
+        R mg0, t0;
+        PairKernel<R, KERNEL>::eval(R(0), MIXED ? (R)t.sm32[gi] : (R)t.sm[gi], eps2, inv_eps,
+                                    inv_eps3, mg0, t0);
+        if (ph == 0) pp += (double)t0;
       }
       if (vi && ph == 0) {
         t.near[gi] = ax;
@@ -474,8 +503,14 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
     tm->stop(s);
     tm->start(PH_P2P, s);
   }
-  hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL>), dim3((nn + P2P_WAVES - 1) / P2P_WAVES),
-                     dim3(P2P_WAVES * 64), 0, s, t, nn, e.eps);
+  if (e.eps > 0)
+    hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL, false>),
+                       dim3((nn + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, s, t, nn,
+                       e.eps);
+  else
+    hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL, true>),
+                       dim3((nn + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, s, t, nn,
+                       e.eps);
   if (tm) {
     tm->stop(s);
     tm->start(PH_DOWN, s);
