@@ -121,6 +121,22 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin in
+// blockIdx order.  xcd_block maps blockIdx to a logical block index so that
+// each XCD runs chunks of C consecutive logical blocks (the chunks themselves
+// dealt round-robin): neighbouring cells, which share most of their sources,
+// meet in one L2, while every XCD still gets a mix of the whole range.  A
+// bijection on [0, G): the blocks past the last whole round of 8 C keep their
+// index.
+#define FMM_XCDS 8
+template <int C>
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  const int full = G / (FMM_XCDS * C) * (FMM_XCDS * C);
+  if (b >= full) return b;
+  const int x = b % FMM_XCDS, k = b / FMM_XCDS;
+  return ((k / C) * FMM_XCDS + x) * C + k % C;
+}
+
 __device__ __forceinline__ int wave_excl_scan_int(int v, int *total) {
   // inclusive Hillis-Steele over 64 lanes
   int x = v;

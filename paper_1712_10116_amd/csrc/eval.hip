@@ -140,7 +140,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, doubl
   const T *Mh = (const T *)t.Mh;
   T *L = (T *)t.L;
   const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int wave = (xcd_block<32>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (skipped(t, A)) continue;
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
   const int w = threadIdx.x >> 6;
   R4 *src = src_all[w];
   int *idx = idx_all[w];
-  const int wave = blockIdx.x * P2P_WAVES + w;
+  const int wave = xcd_block<32>(blockIdx.x, gridDim.x) * P2P_WAVES + w;
   const int nwaves = gridDim.x * P2P_WAVES;
   const R eps2 = (R)(eps * eps);
   const R inv_eps = eps > 0 ? (R)(1.0 / eps) : R(0);

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   Header *h = t.hdr;
-  const int P = ps + blockIdx.x * TRAV_WAVES + w;
+  const int P = ps + xcd_block<32>(blockIdx.x, gridDim.x) * TRAV_WAVES + w;
   if (P >= pe) return;
   WaveLds &L = lds[w];
   Sibs S;
