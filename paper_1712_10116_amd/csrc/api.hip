@@ -135,7 +135,10 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   }
   DevTree &t = c->t;
   memset(&t, 0, sizeof(t));
-  bool pins = hipHostMalloc((void **)&c->pin_hdr, sizeof(Header)) == hipSuccess;
+  bool pins = hipHostMalloc((void **)&c->pin_hdr, sizeof(Header)) == hipSuccess &&
+              hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess;
   for (int k = 0; pins && k < fmm_ctx::UP_SLOTS; ++k)
     pins = hipEventCreateWithFlags(&c->up_ev[k], hipEventDisableTiming) == hipSuccess;
   if (!pins) {
@@ -191,6 +194,12 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
     if (c->up_ev[k]) (void)hipEventDestroy(c->up_ev[k]);
   }
   if (c->pin_hdr) (void)hipHostFree(c->pin_hdr);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
+  if (c->join) (void)hipEventDestroy(c->join);
   delete c;
   return FMM_OK;
 }
@@ -409,6 +418,9 @@ extern "C" fmm_status fmm_evaluate_batched(fmm_ctx *c, int n_req, const fmm_requ
   e.lvl_start_host = c->hh.lvl_start;
   e.depth = c->depth;
   e.tm = timer_of(c);
+  e.side = c->side;
+  e.fork = c->fork;
+  e.join = c->join;
   HIPCHK(c, launch_evaluate(c->t, e, c->stream));
   c->stat_calls++;
   for (int r = 0; r < n_req; ++r)

@@ -169,25 +169,29 @@ struct PhaseTimer {
   bool ready = false;
   hipEvent_t a[CAP], b[CAP];
   int ph[CAP];
-  int n = 0;
+  int n = 0, cur = -1;
   double ms[PH_N] = {0};
   long long cnt[PH_N] = {0};
-  void start(int p, hipStream_t s) {
-    if (!on) return;
+  // an interval of phase p on stream s (intervals on different streams may overlap)
+  int begin(int p, hipStream_t s) {
+    if (!on) return -1;
     if (n == CAP) flush();
     hipEventRecord(a[n], s);
     ph[n] = p;
+    return n++;
   }
+  void end(int k, hipStream_t s) {
+    if (on && k >= 0) hipEventRecord(b[k], s);
+  }
+  void start(int p, hipStream_t s) { cur = begin(p, s); }
   void stop(hipStream_t s) {
-    if (!on) return;
-    hipEventRecord(b[n], s);
-    ++n;
+    end(cur, s);
+    cur = -1;
   }
   void flush() {
-    if (n == 0) return;
-    hipEventSynchronize(b[n - 1]);
     for (int i = 0; i < n; ++i) {
       float t = 0.f;
+      hipEventSynchronize(b[i]);
       hipEventElapsedTime(&t, a[i], b[i]);
       ms[ph[i]] += t;
       cnt[ph[i]] += 1;
@@ -219,6 +223,8 @@ hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s);
 hipError_t launch_reset_lists(const DevTree &t, hipStream_t s);
 // eval.hip
 struct EvalArgs {
+  hipStream_t side;         // P2P runs here, concurrently with the multipole passes
+  hipEvent_t fork, join;
   int n;
   int n_nodes;
   int p;

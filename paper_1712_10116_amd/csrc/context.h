@@ -11,6 +11,8 @@ struct fmm_ctx {
   fmm_params prm;
   int64_t max_n;
   hipStream_t stream;
+  hipStream_t side;        // library-owned second stream (P2P beside the multipole passes)
+  hipEvent_t fork, join;
   int device;
   DevTree t;
   std::vector<void *> allocs;

@@ -469,12 +469,28 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
 }
 
 // ---------------------------------------------------------------------------
+// Launch order: P2P goes to the side stream (after the mass gather, by an
+// event) and runs concurrently with P2M, M2M, M2L and L2L on the main stream,
+// which waits for it (second event) before L2P adds the near field.
 template <typename T, int P, int KERNEL>
 static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   const int nn = e.n_nodes;
   const int nb_nodes = (nn + FMM_BLOCK - 1) / FMM_BLOCK;
   PhaseTimer *tm = e.tm;
   const bool harm = KERNEL == 0;  // folded moments feed the harmonic M2L
+  hipEventRecord(e.fork, s);
+  hipStreamWaitEvent(e.side, e.fork, 0);
+  const int tp = tm ? tm->begin(PH_P2P, e.side) : -1;
+  if (e.eps > 0)
+    hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL, false>),
+                       dim3((nn + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, e.side,
+                       t, nn, e.eps);
+  else
+    hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL, true>),
+                       dim3((nn + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, e.side,
+                       t, nn, e.eps);
+  if (tm) tm->end(tp, e.side);
+  hipEventRecord(e.join, e.side);
   hipLaunchKernelGGL((k_p2m<T, P>), dim3(nb_nodes), dim3(FMM_BLOCK), 0, s, t, nn, harm);
   for (int l = e.depth - 1; l >= 0; --l) {
     int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
@@ -499,22 +515,7 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
       hipLaunchKernelGGL((k_l2l<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
                          dim3(FMM_BLOCK), 0, s, t, ls, le);
   }
-  if (tm) {
-    tm->stop(s);
-    tm->start(PH_P2P, s);
-  }
-  if (e.eps > 0)
-    hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL, false>),
-                       dim3((nn + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, s, t, nn,
-                       e.eps);
-  else
-    hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL, true>),
-                       dim3((nn + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, s, t, nn,
-                       e.eps);
-  if (tm) {
-    tm->stop(s);
-    tm->start(PH_DOWN, s);
-  }
+  hipStreamWaitEvent(s, e.join, 0);
   hipLaunchKernelGGL((k_l2p<T, P>), dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
                      s, t, e.n);
   if (tm) tm->stop(s);
