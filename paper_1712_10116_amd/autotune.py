@@ -56,16 +56,20 @@ def tune(pos, mass, *, eps, kernel=F.WENDLAND, precision=F.MIXED, target=1e-3,
 
     pos: device float64 (3, n); mass: device float64 (n,).  Returns a dict
     with the winner (leaf_size, theta, p, ms, err) and ``table``, one entry
-    per candidate (ms is None for those that missed the target)."""
+    per candidate (ms is None for those that missed the target).  With
+    target None every candidate is timed and no error is measured (for when
+    theta and p are fixed by the caller and only the leaf size is free)."""
     n = pos.shape[1]
     dev = pos.device
     acc = torch.empty((3, n), dtype=torch.float64, device=dev)
     pot = torch.empty((n,), dtype=torch.float64, device=dev)
-    ref = F.Solver(n, p_max=REFERENCE["p"], leaf_size=REFERENCE["leaf_size"], kernel=kernel,
-                   precision=F.FP64)
-    a_ref, _ = ref.forces(pos, mass, eps=eps, theta=REFERENCE["theta"], p=REFERENCE["p"])
-    torch.cuda.synchronize()
-    ref.close()
+    a_ref = None
+    if target is not None:
+        ref = F.Solver(n, p_max=REFERENCE["p"], leaf_size=REFERENCE["leaf_size"], kernel=kernel,
+                       precision=F.FP64)
+        a_ref, _ = ref.forces(pos, mass, eps=eps, theta=REFERENCE["theta"], p=REFERENCE["p"])
+        torch.cuda.synchronize()
+        ref.close()
     table = []
     best = None
     for leaf in leaf_sizes:
@@ -73,9 +77,9 @@ def tune(pos, mass, *, eps, kernel=F.WENDLAND, precision=F.MIXED, target=1e-3,
         for p in orders:
             for th in thetas:
                 s.forces(pos, mass, eps=eps, theta=th, p=p, acc=acc, pot=pot)
-                err = _rel_rms(acc, a_ref)
+                err = _rel_rms(acc, a_ref) if a_ref is not None else None
                 ms = None
-                if err <= target:
+                if target is None or err <= target:
                     ms = 1e3 * _time(s, pos, mass, eps, th, p, acc, pot, reps)
                     if best is None or ms < best["ms"]:
                         best = dict(leaf_size=leaf, theta=th, p=p, ms=ms, err=err)

@@ -392,7 +392,13 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_split_depth(DevTree t, int n, int
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off, 64));
-  if ((threadIdx.x & 63) == 0 && best > 0) atomicMax(&hdr->max_prefix, best);
+  __shared__ int wbest[FMM_BLOCK / 64];
+  if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one atomic per block
+    for (int w = 1; w < FMM_BLOCK / 64; ++w) best = max(best, wbest[w]);
+    if (best > 0) atomicMax(&hdr->max_prefix, best);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -604,7 +610,7 @@ hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
       int32_t *ts = sin; sin = sout; sout = ts;
     }
     hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
-    hipLaunchKernelGGL(k_split_depth, dim3(std::min(nb, 1024)), dim3(FMM_BLOCK), 0, s, t, n,
+    hipLaunchKernelGGL(k_split_depth, dim3(std::min(nb, 512)), dim3(FMM_BLOCK), 0, s, t, n,
                        a.leaf_size);
   }
   if (a.tm) a.tm->stop(s);
