@@ -141,14 +141,23 @@ def ensemble_leg(args, F, torch, line):
     K = args.ensemble
     reqs = [W.ensemble_request(i) for i in range(K)]
     ntot = sum(r[2].size for r in reqs)
-    # leaf size by the autotuner on a median-size request (theta and p are the workload's)
-    sizes = np.array([r[2].size for r in reqs])
-    med = reqs[int(np.argsort(sizes)[K // 2])]
-    tr = autotune.tune(torch.from_numpy(med[0]).cuda(), torch.from_numpy(med[2]).cuda(),
-                       eps=prm["eps"], kernel=prm["kernel"], precision=F.MIXED, target=None,
-                       leaf_sizes=(8, 16, 24, 32, 48, 64), orders=(prm["p"],),
-                       thetas=(prm["theta"],), reps=5)
-    prm["leaf_size"] = tr["best"]["leaf_size"]
+    # leaf size by the autotuner on the serving workload itself: a short closed
+    # loop (the first 16 requests, one top-level step each) per candidate
+    probe = reqs[:16]
+
+    def probe_run(leaf):
+        sv = F.Solver(args.ensemble_max_n, p_max=prm["p"], leaf_size=leaf, kernel=prm["kernel"],
+                      precision=F.MIXED)
+        srv = F.Server(sv, eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
+                       max_levels=prm["max_levels"], arena_bytes=args.ensemble_arena_gib << 30,
+                       max_slots=args.ensemble_slots)
+        _, span = serving.run(srv, probe, 1.0 / 16)
+        srv.close()
+        sv.close()
+        return span
+
+    tl = autotune.fastest((8, 16, 32, 64), probe_run)
+    prm["leaf_size"] = tl["best"]
     s = F.Solver(args.ensemble_max_n, p_max=prm["p"], leaf_size=prm["leaf_size"],
                  kernel=prm["kernel"], precision=F.MIXED)
 
@@ -178,7 +187,8 @@ def ensemble_leg(args, F, torch, line):
     line["ensemble"] = {
         "requests": K, "particles": int(ntot), "t_end": args.ensemble_t_end,
         "precision": "mixed", "p": prm["p"], "theta": prm["theta"], "eps": prm["eps"],
-        "leaf_size": prm["leaf_size"], "leaf_tuned_on_n": int(med[2].size),
+        "leaf_size": prm["leaf_size"],
+        "leaf_tuning_s": {str(r["candidate"]): round(r["seconds"], 4) for r in tl["table"]},
         "arena_gib": args.ensemble_arena_gib, "max_slots": args.ensemble_slots,
         "closed_loop": rnd(closed),
         "poisson": dict(rnd(opened), rate_per_s=round(rate, 4), load=args.ensemble_load),

@@ -90,3 +90,16 @@ def tune(pos, mass, *, eps, kernel=F.WENDLAND, precision=F.MIXED, target=1e-3,
     del a_ref
     return dict(best=best, table=table, target=target, n=n, eps=eps, kernel=kernel,
                 precision=precision, reference=dict(REFERENCE))
+
+
+def fastest(candidates, run, reps=2):
+    """The candidate whose ``run(candidate)`` (returning seconds) is smallest,
+    best of ``reps`` runs each, with the table of all timings.  Used where the
+    cost is not a single solve, e.g. the leaf size of a request server, timed
+    on a short closed-loop run of its own workload."""
+    table = []
+    for c in candidates:
+        t = min(run(c) for _ in range(reps))
+        table.append(dict(candidate=c, seconds=t))
+    best = min(table, key=lambda r: r["seconds"])
+    return dict(best=best["candidate"], table=table)
