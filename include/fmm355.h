@@ -156,6 +156,12 @@ fmm_status fmm_forces_batched(fmm_ctx *ctx, int n_req, const fmm_request *reqs, 
  * particle-particle interactions evaluated by P2P. */
 fmm_status fmm_tree_info(fmm_ctx *ctx, int64_t info[9]);
 
+/* Builds of at most 8192 active particles (all systems of a batch together)
+ * run as two single-workgroup launches with one readback; enable = 0 forces
+ * the multi-workgroup path (same trees, lists and results; for comparison
+ * and tests).  On by default. */
+fmm_status fmm_set_small_path(fmm_ctx *ctx, int enable);
+
 /* Canonical host copy of the current tree, for comparison with other
  * implementations: nodes in pre-order (sorted by (begin, level)); perm[i] =
  * active slot of the i-th particle in Morton order; pairs as (a <= b) over

@@ -128,6 +128,7 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   if (!c) return FMM_ENOMEM;
   c->prm = *prm;
   c->max_n = max_n;
+  c->small_path = true;
   c->stream = (hipStream_t)stream;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -205,6 +206,12 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
 }
 
 extern "C" const char *fmm_last_error(const fmm_ctx *c) { return c ? c->err : "null context"; }
+
+extern "C" fmm_status fmm_set_small_path(fmm_ctx *c, int enable) {
+  if (!c) return FMM_EINVAL;
+  c->small_path = enable != 0;
+  return FMM_OK;
+}
 
 static fmm_status check_requests(fmm_ctx *c, int n_req, const fmm_request *reqs, bool eval,
                                  int64_t *n_all) {
@@ -327,6 +334,34 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
   a.eps = eps;
   a.theta = theta;
   a.tm = timer_of(c);
+  auto finish = [&](int depth) {
+    c->n_nodes = c->hh.lvl_start[FMM_NLEVELS];
+    c->depth = depth;
+    c->tree_valid = true;
+    c->b_reqs.assign(reqs, reqs + n_req);
+    c->b_n = n_all;
+    c->b_eps = eps;
+    c->b_theta = theta;
+    c->stat_builds++;
+    return FMM_OK;
+  };
+  auto tree_depth = [&]() {
+    int depth = 0;
+    for (int l = 0; l < FMM_NLEVELS; ++l)
+      if (c->hh.lvl_start[l + 1] > c->hh.lvl_start[l]) depth = l;
+    return depth;
+  };
+  // 0. small batches: build and walk in two single-workgroup launches and one
+  // readback; anything that needs more room falls through to the general path
+  if (n_all <= SMALL_N && c->small_path) {
+    HIPCHK(c, launch_build_small(c->t, a, c->stream));
+    HIPCHK(c, launch_traverse_small(c->t, a, c->stream));
+    st = read_header(c);
+    if (st != FMM_OK) return st;
+    if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
+    if (c->hh.overflow & OVF_STACK) return fail(c, FMM_EOVERFLOW, "walk descent stack overflow");
+    if (!(c->hh.overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN))) return finish(tree_depth());
+  }
   // 1. tree; one readback of the level sizes (exact launches for the walk)
   for (int attempt = 0;; ++attempt) {
     if (attempt == 4) return fail(c, FMM_EOVERFLOW, "node workspace still too small");
@@ -349,9 +384,7 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
     if (!alloc_nodes(c, need + need / 4))
       return fail(c, FMM_ENOMEM, "node workspace regrow to %lld failed", (long long)need);
   }
-  int depth = 0;
-  for (int l = 0; l < FMM_NLEVELS; ++l)
-    if (c->hh.lvl_start[l + 1] > c->hh.lvl_start[l]) depth = l;
+  const int depth = tree_depth();
   int32_t lvl[FMM_NLEVELS + 2];
   memcpy(lvl, c->hh.lvl_start, sizeof(lvl));
   a.lvl_host = lvl;
@@ -380,15 +413,7 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
       }
       continue;
     }
-    c->n_nodes = h.lvl_start[FMM_NLEVELS];
-    c->depth = depth;
-    c->tree_valid = true;
-    c->b_reqs.assign(reqs, reqs + n_req);
-    c->b_n = n_all;
-    c->b_eps = eps;
-    c->b_theta = theta;
-    c->stat_builds++;
-    return FMM_OK;
+    return finish(depth);
   }
   return fail(c, FMM_EOVERFLOW, "list workspace still too small after regrowth");
 }

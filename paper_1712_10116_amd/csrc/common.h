@@ -21,6 +21,11 @@
 #define FMM_BLOCK 256
 #define FMM_SCAN_BLOCKS 256
 #define FMM_BBOX_BLOCKS 256  // box-reduction blocks per request, at most
+// single-workgroup ("small") build, walk and level passes
+#define SMALL_WAVES 8
+#define SMALL_THREADS (SMALL_WAVES * 64)
+#define SMALL_N (SMALL_THREADS * 16)  // active particles of a batch, at most
+#define SMALL_NODES 2048              // cells of a tree whose M2M / L2L levels run in one workgroup
 
 // error bits latched in Header::overflow
 #define OVF_NODES 1
@@ -217,9 +222,13 @@ struct BuildArgs {
 
 // tree.hip
 hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s);
+// whole build up to the walk in one workgroup (a.n <= SMALL_N)
+hipError_t launch_build_small(const DevTree &t, const BuildArgs &a, hipStream_t s);
 hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, int max_level, hipStream_t s);
 // traverse.hip
 hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s);
+// all walk levels in one workgroup, level sizes read on the device
+hipError_t launch_traverse_small(const DevTree &t, const BuildArgs &a, hipStream_t s);
 hipError_t launch_reset_lists(const DevTree &t, hipStream_t s);
 // eval.hip
 struct EvalArgs {

@@ -35,6 +35,7 @@ struct fmm_ctx {
   bool up_valid;
   Header *pin_hdr;                  // pinned destination of header readbacks
   int n_nodes, depth;
+  bool small_path;         // single-workgroup build and walk for small batches
   // integrator
   hhs_run *own_run;       // scratch of hhs_init / hhs_step (one system)
   int32_t *split_cnt;     // [cap_split] fast-set sizes of pending splits

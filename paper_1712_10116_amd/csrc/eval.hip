@@ -98,29 +98,33 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes, bool 
 
 // M2M for the cells of one level that have children
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e, bool harm) {
+__device__ __forceinline__ void m2m_cell(const DevTree &t, int i, bool harm) {
   constexpr int K = MI<P>::K;
   T *M = (T *)t.M;
-  for (int i = s + blockIdx.x * blockDim.x + threadIdx.x; i < e; i += gridDim.x * blockDim.x) {
-    int nc = t.nnchild[i];
-    if (nc == 0 || skipped(t, i)) continue;
-    const double4 gp = t.ngeo[i];
-    const double ih = 1.0 / gp.w;
-    T acc[K];
+  int nc = t.nnchild[i];
+  if (nc == 0 || skipped(t, i)) return;
+  const double4 gp = t.ngeo[i];
+  const double ih = 1.0 / gp.w;
+  T acc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = T(0);
-    int c0 = t.nchild0[i];
-    for (int c = c0; c < c0 + nc; ++c) {
-      const double4 gc = t.ngeo[c];
-      T q[K], Mc[K];
-      monomials<T, P>((T)((gc.x - gp.x) * ih), (T)((gc.y - gp.y) * ih), (T)((gc.z - gp.z) * ih),
-                      q);
-      load_row<T, P>(M, t.kmax, c, Mc);
-      m2m_shift<T, P>(Mc, (T)(gc.w * ih), q, acc);
-    }
-    store_row<T, P>(M, t.kmax, i, acc);
-    if (harm) store_folded<T, P>(t, i, acc);
+  for (int k = 0; k < K; ++k) acc[k] = T(0);
+  int c0 = t.nchild0[i];
+  for (int c = c0; c < c0 + nc; ++c) {
+    const double4 gc = t.ngeo[c];
+    T q[K], Mc[K];
+    monomials<T, P>((T)((gc.x - gp.x) * ih), (T)((gc.y - gp.y) * ih), (T)((gc.z - gp.z) * ih),
+                    q);
+    load_row<T, P>(M, t.kmax, c, Mc);
+    m2m_shift<T, P>(Mc, (T)(gc.w * ih), q, acc);
   }
+  store_row<T, P>(M, t.kmax, i, acc);
+  if (harm) store_folded<T, P>(t, i, acc);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e, bool harm) {
+  for (int i = s + blockIdx.x * blockDim.x + threadIdx.x; i < e; i += gridDim.x * blockDim.x)
+    m2m_cell<T, P>(t, i, harm);
 }
 
 // M2L: one wavefront per target cell A, lanes over A's list of sources B.
@@ -199,20 +203,46 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, doubl
 
 // L2L for the cells of one level: Lt_c += shift of the parent's Lt
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_l2l(DevTree t, int s, int e) {
+__device__ __forceinline__ void l2l_cell(const DevTree &t, int c) {
   constexpr int K = MI<P>::K;
   T *L = (T *)t.L;
-  for (int c = s + blockIdx.x * blockDim.x + threadIdx.x; c < e; c += gridDim.x * blockDim.x) {
-    if (skipped(t, c)) continue;
-    const int p = t.nparent[c];
-    const double4 gp = t.ngeo[p], gc = t.ngeo[c];
-    const double ih = 1.0 / gp.w;
-    T q[K], Lp[K], Lc[K];
-    monomials<T, P>((T)((gc.x - gp.x) * ih), (T)((gc.y - gp.y) * ih), (T)((gc.z - gp.z) * ih), q);
-    load_row<T, P>(L, t.kmax, p, Lp);
-    load_row<T, P>(L, t.kmax, c, Lc);
-    l2l_shift<T, P>(Lp, (T)(gc.w * ih), q, Lc);
-    store_row<T, P>(L, t.kmax, c, Lc);
+  if (skipped(t, c)) return;
+  const int p = t.nparent[c];
+  const double4 gp = t.ngeo[p], gc = t.ngeo[c];
+  const double ih = 1.0 / gp.w;
+  T q[K], Lp[K], Lc[K];
+  monomials<T, P>((T)((gc.x - gp.x) * ih), (T)((gc.y - gp.y) * ih), (T)((gc.z - gp.z) * ih), q);
+  load_row<T, P>(L, t.kmax, p, Lp);
+  load_row<T, P>(L, t.kmax, c, Lc);
+  l2l_shift<T, P>(Lp, (T)(gc.w * ih), q, Lc);
+  store_row<T, P>(L, t.kmax, c, Lc);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_l2l(DevTree t, int s, int e) {
+  for (int c = s + blockIdx.x * blockDim.x + threadIdx.x; c < e; c += gridDim.x * blockDim.x)
+    l2l_cell<T, P>(t, c);
+}
+
+// Small trees: all M2M levels (deepest first) or all L2L levels (root first)
+// in one workgroup, a barrier between levels.
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_m2m_small(DevTree t, int depth, bool harm) {
+  const Header *h = t.hdr;
+  for (int l = depth - 1; l >= 0; --l) {
+    for (int i = h->lvl_start[l] + threadIdx.x; i < h->lvl_start[l + 1]; i += blockDim.x)
+      m2m_cell<T, P>(t, i, harm);
+    __syncthreads();
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_l2l_small(DevTree t, int depth) {
+  const Header *h = t.hdr;
+  for (int l = 1; l <= depth; ++l) {
+    for (int c = h->lvl_start[l] + threadIdx.x; c < h->lvl_start[l + 1]; c += blockDim.x)
+      l2l_cell<T, P>(t, c);
+    __syncthreads();
   }
 }
 
@@ -492,11 +522,16 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   if (tm) tm->end(tp, e.side);
   hipEventRecord(e.join, e.side);
   hipLaunchKernelGGL((k_p2m<T, P>), dim3(nb_nodes), dim3(FMM_BLOCK), 0, s, t, nn, harm);
-  for (int l = e.depth - 1; l >= 0; --l) {
-    int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
-    if (le > ls)
-      hipLaunchKernelGGL((k_m2m<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
-                         dim3(FMM_BLOCK), 0, s, t, ls, le, harm);
+  const bool small = nn <= SMALL_NODES;
+  if (small && e.depth > 0) {
+    hipLaunchKernelGGL((k_m2m_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth, harm);
+  } else {
+    for (int l = e.depth - 1; l >= 0; --l) {
+      int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
+      if (le > ls)
+        hipLaunchKernelGGL((k_m2m<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
+                           dim3(FMM_BLOCK), 0, s, t, ls, le, harm);
+    }
   }
   const int wave_blocks = (nn + 3) / 4;
   if (tm) {
@@ -509,11 +544,15 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
     tm->stop(s);
     tm->start(PH_DOWN, s);
   }
-  for (int l = 1; l <= e.depth; ++l) {
-    int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
-    if (le > ls)
-      hipLaunchKernelGGL((k_l2l<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
-                         dim3(FMM_BLOCK), 0, s, t, ls, le);
+  if (small && e.depth > 0) {
+    hipLaunchKernelGGL((k_l2l_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth);
+  } else {
+    for (int l = 1; l <= e.depth; ++l) {
+      int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
+      if (le > ls)
+        hipLaunchKernelGGL((k_l2l<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
+                           dim3(FMM_BLOCK), 0, s, t, ls, le);
+    }
   }
   hipStreamWaitEvent(s, e.join, 0);
   hipLaunchKernelGGL((k_l2p<T, P>), dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,

@@ -224,15 +224,9 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
 // Level l >= 1: one wavefront per cell P of level l-1 with children; the
 // children are the targets.  Level 0: one wavefront per request root, whose
 // only candidate is itself, so cells of different requests never meet.
-__global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l, int ps, int pe,
-                                                                double th2, double eps) {
-  __shared__ WaveLds lds[TRAV_WAVES];
-  const int w = threadIdx.x >> 6;
+__device__ void walk_parent(const DevTree &t, int l, int P, double th2, double eps, WaveLds &L) {
   const int lane = threadIdx.x & 63;
   Header *h = t.hdr;
-  const int P = ps + xcd_block<32>(blockIdx.x, gridDim.x) * TRAV_WAVES + w;
-  if (P >= pe) return;
-  WaveLds &L = lds[w];
   Sibs S;
   if (l == 0) {
     // a request's root is the only target of its group; every sibling slot
@@ -307,6 +301,31 @@ __global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l
   if (lane == 0 && pairs) atomicAdd(&h->p2p_pairs, pairs);
 }
 
+__global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l, int ps, int pe,
+                                                                double th2, double eps) {
+  __shared__ WaveLds lds[TRAV_WAVES];
+  const int w = threadIdx.x >> 6;
+  const int P = ps + xcd_block<32>(blockIdx.x, gridDim.x) * TRAV_WAVES + w;
+  if (P >= pe) return;
+  walk_parent(t, l, P, th2, eps, lds[w]);
+}
+
+// All levels of the walk in one workgroup (small trees): the waves share the
+// parents of a level, and a barrier separates levels (a level reads the open
+// lists the previous one wrote).  Level sizes come from the tree header.
+__global__ __launch_bounds__(SMALL_THREADS) void k_walk_small(DevTree t, double th2, double eps) {
+  __shared__ WaveLds lds[SMALL_WAVES];
+  const int w = threadIdx.x >> 6;
+  const Header *h = t.hdr;
+  for (int l = 0; l <= FMM_MAXLEVEL; ++l) {
+    const int ps = l == 0 ? 0 : h->lvl_start[l - 1];
+    const int pe = l == 0 ? t.n_req : h->lvl_start[l];
+    if (l > 0 && h->lvl_start[l + 1] <= h->lvl_start[l]) break;  // no cells at level l
+    for (int P = ps + w; P < pe; P += SMALL_WAVES) walk_parent(t, l, P, th2, eps, lds[w]);
+    __syncthreads();
+  }
+}
+
 __global__ void k_reset_lists(Header *h) {
   int i = threadIdx.x;
   if (i == 0) {
@@ -320,6 +339,16 @@ __global__ void k_reset_lists(Header *h) {
 
 hipError_t launch_reset_lists(const DevTree &t, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_lists, dim3(1), dim3(64), 0, s, t.hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_traverse_small(const DevTree &t, const BuildArgs &a, hipStream_t s) {
+  launch_reset_lists(t, s);
+  if (a.n <= 0) return hipGetLastError();
+  if (a.tm) a.tm->start(PH_WALK, s);
+  hipLaunchKernelGGL(k_walk_small, dim3(1), dim3(SMALL_THREADS), 0, s, t, a.theta * a.theta,
+                     a.eps);
+  if (a.tm) a.tm->stop(s);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@
 #define SORT_WAVES 4
 #define SORT_ITEMS 16
 #define SORT_TILE (SORT_WAVES * 64 * SORT_ITEMS)
+#define SMALL_ITEMS 16
 
 // ---------------------------------------------------------------------------
 // request of every slot (binary search in the request offsets)
@@ -92,8 +93,27 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_bbox_partial(DevTree t) {
   if (threadIdx.x < 6) t.bbox_part[blockIdx.x * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// one wavefront per request: c = (lo+hi)/2, L = max extent (1 if 0),
-// o = c - L/2, s = 2^21/L
+// c = (lo+hi)/2, L = max extent (1 if 0), o = c - L/2, s = 2^21/L
+__device__ __forceinline__ void finish_box(Box &bx, double lo[3], double hi[3], bool empty) {
+  if (empty)
+    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = 0.0;
+  double c[3], L = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    c[d] = 0.5 * (lo[d] + hi[d]);
+    double e = hi[d] - lo[d];
+    if (e > L) L = e;
+  }
+  if (L == 0.0) L = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    bx.o[d] = c[d] - 0.5 * L;
+    bx.lo[d] = lo[d];
+    bx.hi[d] = hi[d];
+  }
+  bx.L = L;
+  bx.s = 2097152.0 / L;
+}
+
+// one wavefront per request
 __global__ __launch_bounds__(FMM_BLOCK) void k_bbox_final(DevTree t) {
   const int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -113,23 +133,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_bbox_final(DevTree t) {
       hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, 64));
     }
   if (lane != 0) return;
-  if (t.reqs[r].n == 0)
-    for (int d = 0; d < 3; ++d) lo[d] = hi[d] = 0.0;
-  double c[3], L = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    c[d] = 0.5 * (lo[d] + hi[d]);
-    double e = hi[d] - lo[d];
-    if (e > L) L = e;
-  }
-  if (L == 0.0) L = 1.0;
-  Box &bx = t.box[r];
-  for (int d = 0; d < 3; ++d) {
-    bx.o[d] = c[d] - 0.5 * L;
-    bx.lo[d] = lo[d];
-    bx.hi[d] = hi[d];
-  }
-  bx.L = L;
-  bx.s = 2097152.0 / L;
+  finish_box(t.box[r], lo, hi, t.reqs[r].n == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -163,9 +167,7 @@ __device__ __forceinline__ uint64_t quantise(double x, double o, double s) {
   return (uint64_t)q;
 }
 
-__global__ __launch_bounds__(FMM_BLOCK) void k_keys(DevTree t, int n) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+__device__ __forceinline__ void make_key(const DevTree &t, int s) {
   const int r = t.slot_req[s];
   const DevReq q = t.reqs[r];
   const int i = s - q.off;
@@ -176,6 +178,11 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_keys(DevTree t, int n) {
   uint64_t qz = quantise(q.pos[2 * q.n_total + g], bx.o[2], bx.s);
   t.key[s] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
   t.slot[s] = s;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_keys(DevTree t, int n) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) make_key(t, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,9 +411,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_split_depth(DevTree t, int n, int
 // ---------------------------------------------------------------------------
 // sorted particle data
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(FMM_BLOCK) void k_gather_sorted(DevTree t, int n) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+__device__ __forceinline__ void gather_at(const DevTree &t, int j) {
   const int s = t.slot[j];
   const DevReq q = t.reqs[t.slot_req[s]];
   const int i = s - q.off;
@@ -414,6 +419,11 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_gather_sorted(DevTree t, int n) {
   t.sx[j] = q.pos[g];
   t.sy[j] = q.pos[q.n_total + g];
   t.sz[j] = q.pos[2 * q.n_total + g];
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_gather_sorted(DevTree t, int n) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) gather_at(t, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -430,18 +440,19 @@ __device__ __forceinline__ double4 cell_geometry(const Box &b, uint64_t prefix, 
   return g;
 }
 
-// one root per request, covering its sorted range [off, off + n)
-__global__ __launch_bounds__(FMM_BLOCK) void k_tree_init(DevTree t, int leaf_size) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+// header of a new tree (one thread) and the root of request r, covering its
+// sorted range [off, off + n)
+__device__ __forceinline__ void header_init(const DevTree &t) {
   Header *h = t.hdr;
   const int R = t.n_req;
-  if (r == 0) {
-    h->lvl_start[0] = 0;
-    for (int l = 1; l < FMM_NLEVELS + 2; ++l) h->lvl_start[l] = R;
-    h->overflow = R > t.cap_nodes ? OVF_NODES : 0;
-    h->max_prefix = 0;
-  }
-  if (r >= R || r >= t.cap_nodes) return;
+  h->lvl_start[0] = 0;
+  for (int l = 1; l < FMM_NLEVELS + 2; ++l) h->lvl_start[l] = R;
+  h->overflow = R > t.cap_nodes ? OVF_NODES : 0;
+  h->max_prefix = 0;
+}
+
+__device__ __forceinline__ void root_init(const DevTree &t, int r, int leaf_size) {
+  if (r >= t.cap_nodes) return;
   t.nbeg[r] = t.req_off[r];
   t.nend[r] = t.req_off[r + 1];
   t.nlev[r] = 0;
@@ -450,7 +461,13 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_init(DevTree t, int leaf_siz
   t.nnchild[r] = 0;
   t.nreq[r] = r;
   t.ngeo[r] = cell_geometry(t.box[r], 0ull, 0);
-  if (t.req_off[r + 1] - t.req_off[r] <= leaf_size) atomicAdd((int *)&h->n_leaves, 1);
+  if (t.req_off[r + 1] - t.req_off[r] <= leaf_size) atomicAdd((int *)&t.hdr->n_leaves, 1);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_tree_init(DevTree t, int leaf_size) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0) header_init(t);
+  if (r < t.n_req) root_init(t, r, leaf_size);
 }
 
 __device__ __forceinline__ int lower_bound_digit(const uint64_t *__restrict__ key, int b, int e,
@@ -473,27 +490,67 @@ __device__ __forceinline__ void level_chunk(const Header *h, int l, int &s, int 
   e = min(le, s + per);
 }
 
+// children of node i of level l: octant boundaries of its key range into
+// bounds[i][0..8), the number of non-empty octants into nnchild[i]
+__device__ __forceinline__ int count_node(const DevTree &t, int i, int l, int leaf_size) {
+  const int shift = 3 * (FMM_MAXLEVEL - (l + 1));
+  int b = t.nbeg[i], en = t.nend[i];
+  int nc = 0;
+  if (en - b > leaf_size && l < FMM_MAXLEVEL) {
+    int bd[9];
+    bd[0] = b;
+    bd[8] = en;
+    for (uint32_t o = 1; o < 8; ++o) bd[o] = lower_bound_digit(t.key, bd[o - 1], en, shift, o);
+    for (int o = 0; o < 8; ++o) {
+      t.bounds[(int64_t)i * 8 + o] = bd[o];
+      nc += bd[o + 1] > bd[o];
+    }
+  }
+  t.nnchild[i] = nc;
+  return nc;
+}
+
+// emit the nc children of node i (level l) at ids first, first+1, ...;
+// returns how many of them are leaves
+__device__ __forceinline__ int emit_node(const DevTree &t, int i, int l, int nc, int first,
+                                         int leaf_size) {
+  if (nc == 0) {
+    t.nchild0[i] = -1;
+    return 0;
+  }
+  int leaves = 0;
+  t.nchild0[i] = first;
+  const int rq = t.nreq[i];
+  const Box box = t.box[rq];
+  int c = first;
+  for (int o = 0; o < 8; ++o) {
+    int b = t.bounds[(int64_t)i * 8 + o];
+    int en = o < 7 ? t.bounds[(int64_t)i * 8 + o + 1] : t.nend[i];
+    if (en > b) {
+      if (c < t.cap_nodes) {
+        t.nbeg[c] = b;
+        t.nend[c] = en;
+        t.nlev[c] = l + 1;
+        t.nparent[c] = i;
+        t.nchild0[c] = -1;
+        t.nnchild[c] = 0;
+        t.nreq[c] = rq;
+        uint64_t prefix = t.key[b] >> (3 * (FMM_MAXLEVEL - (l + 1)));
+        t.ngeo[c] = cell_geometry(box, prefix, l + 1);
+      }
+      leaves += (en - b <= leaf_size || l + 1 == FMM_MAXLEVEL);
+      ++c;
+    }
+  }
+  return leaves;
+}
+
 __global__ __launch_bounds__(FMM_BLOCK) void k_tree_count(DevTree t, int l, int leaf_size) {
   int s, e;
   level_chunk(t.hdr, l, s, e);
   int sum = 0;
-  const int shift = 3 * (FMM_MAXLEVEL - (l + 1));
-  for (int i = s + threadIdx.x; i < e && i < t.cap_nodes; i += blockDim.x) {
-    int b = t.nbeg[i], en = t.nend[i];
-    int nc = 0;
-    if (en - b > leaf_size && l < FMM_MAXLEVEL) {
-      int bd[9];
-      bd[0] = b;
-      bd[8] = en;
-      for (uint32_t o = 1; o < 8; ++o) bd[o] = lower_bound_digit(t.key, bd[o - 1], en, shift, o);
-      for (int o = 0; o < 8; ++o) {
-        t.bounds[(int64_t)i * 8 + o] = bd[o];
-        nc += bd[o + 1] > bd[o];
-      }
-    }
-    t.nnchild[i] = nc;
-    sum += nc;
-  }
+  for (int i = s + threadIdx.x; i < e && i < t.cap_nodes; i += blockDim.x)
+    sum += count_node(t, i, l, leaf_size);
   __shared__ int red[FMM_BLOCK];
   red[threadIdx.x] = sum;
   __syncthreads();
@@ -547,36 +604,216 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l, int l
     int total = sc[FMM_BLOCK - 1];
     __syncthreads();
     int leaves = 0;
-    if (nc > 0) {
-      t.nchild0[i] = first;
-      const int rq = t.nreq[i];
-      const Box box = t.box[rq];
-      int c = first;
-      for (int o = 0; o < 8; ++o) {
-        int b = t.bounds[(int64_t)i * 8 + o];
-        int en = o < 7 ? t.bounds[(int64_t)i * 8 + o + 1] : t.nend[i];
-        if (en > b) {
-          if (c < t.cap_nodes) {
-            t.nbeg[c] = b;
-            t.nend[c] = en;
-            t.nlev[c] = l + 1;
-            t.nparent[c] = i;
-            t.nchild0[c] = -1;
-            t.nnchild[c] = 0;
-            t.nreq[c] = rq;
-            uint64_t prefix = t.key[b] >> (3 * (FMM_MAXLEVEL - (l + 1)));
-            t.ngeo[c] = cell_geometry(box, prefix, l + 1);
-          }
-          leaves += (en - b <= leaf_size || l + 1 == FMM_MAXLEVEL);
-          ++c;
-        }
-      }
-    } else if (i < e && i < t.cap_nodes) {
-      t.nchild0[i] = -1;
-    }
+    if (i < e && i < t.cap_nodes) leaves = emit_node(t, i, l, nc, first, leaf_size);
     if (leaves) atomicAdd((int *)&t.hdr->n_leaves, leaves);
     run += total;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Small batches (at most SMALL_N active particles in all): the whole build up
+// to the walk -- slots, boxes, roots, keys, every sort pass, sorted gather,
+// split depth and every split level -- in one workgroup, one launch, with no
+// host round trip.  Each step is the same per-element code as the multi-block
+// path, so the tree is the same bit for bit.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int block_sum_small(int v, int *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  int s = 0;
+  for (int k = 0; k < SMALL_WAVES; ++k) s += red[k];
+  return s;
+}
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_build_small(DevTree t, int n, int leaf_size,
+                                                               int req_passes) {
+  __shared__ uint32_t cnt[SMALL_WAVES][256];
+  __shared__ uint32_t dbase[256];
+  __shared__ double bred[6][SMALL_WAVES];
+  __shared__ int ired[SMALL_WAVES];
+  __shared__ int sc[SMALL_THREADS];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int T = SMALL_THREADS;
+  Header *h = t.hdr;
+  if (tid == 0) {
+    h->nonfinite = 0;
+    h->n_leaves = 0;
+    header_init(t);
+  }
+  for (int q = tid; q < n; q += T) t.slot_req[q] = upper_index(t.req_off, t.n_req, q);
+  __syncthreads();
+  // root box of every request
+  int bad = 0;
+  for (int r = 0; r < t.n_req; ++r) {
+    const DevReq q = t.reqs[r];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = tid; i < q.n; i += T) {
+      int64_t g = q.active ? q.active[i] : i;
+      for (int d = 0; d < 3; ++d) {
+        double x = q.pos[d * q.n_total + g];
+        bad |= !isfinite(x);
+        lo[d] = fmin(lo[d], x);
+        hi[d] = fmax(hi[d], x);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, 64));
+        hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, 64));
+      }
+    if (lane == 0)
+      for (int d = 0; d < 3; ++d) {
+        bred[d][w] = lo[d];
+        bred[3 + d][w] = hi[d];
+      }
+    __syncthreads();
+    if (tid == 0) {
+      for (int k = 1; k < SMALL_WAVES; ++k)
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = fmin(lo[d], bred[d][k]);
+          hi[d] = fmax(hi[d], bred[3 + d][k]);
+        }
+      finish_box(t.box[r], lo, hi, q.n == 0);
+    }
+    __syncthreads();
+  }
+  if (__syncthreads_or(bad) && tid == 0) h->nonfinite = 1;
+  for (int r = tid; r < t.n_req; r += T) root_init(t, r, leaf_size);
+  for (int q = tid; q < n; q += T) make_key(t, q);
+  __syncthreads();
+  // stable LSD radix sort, 8-bit digits: 8 key passes, then request passes
+  uint64_t *kin = t.key, *kout = t.key2;
+  int32_t *sin = t.slot, *sout = t.slot2;
+  const unsigned long long below = lanes_below_mask();
+  for (int pass = 0; pass < 8 + req_passes; ++pass) {
+    const int by_req = pass >= 8;
+    const int shift = by_req ? (pass - 8) * 8 : pass * 8;
+    for (int d = tid; d < SMALL_WAVES * 256; d += T) (&cnt[0][0])[d] = 0;
+    __syncthreads();
+    const int base = w * 64 * SMALL_ITEMS;
+    uint64_t k[SMALL_ITEMS];
+    int32_t sv[SMALL_ITEMS];
+    uint32_t rank[SMALL_ITEMS], dg[SMALL_ITEMS];
+#pragma unroll
+    for (int it = 0; it < SMALL_ITEMS; ++it) {
+      int i = base + it * 64 + lane;
+      bool valid = i < n;
+      k[it] = valid ? kin[i] : 0;
+      sv[it] = valid ? sin[i] : 0;
+      uint32_t d = by_req ? ((uint32_t)t.slot_req[sv[it]] >> shift) & 255u
+                          : (uint32_t)(k[it] >> shift) & 255u;
+      dg[it] = d;
+      unsigned long long m = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        unsigned long long bal = __ballot((d >> b) & 1u);
+        m &= ((d >> b) & 1u) ? bal : ~bal;
+      }
+      uint32_t prior = cnt[w][d];
+      rank[it] = prior + (uint32_t)__popcll(m & below);
+      __builtin_amdgcn_wave_barrier();
+      if (valid && (m & below) == 0) cnt[w][d] = prior + (uint32_t)__popcll(m);
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    if (tid < 256) {  // digit totals, then exclusive scan over digits
+      uint32_t tot = 0;
+      for (int ww = 0; ww < SMALL_WAVES; ++ww) tot += cnt[ww][tid];
+      dbase[tid] = tot;
+    }
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      uint32_t y = (tid < 256 && tid >= off) ? dbase[tid - off] : 0u;
+      __syncthreads();
+      if (tid < 256) dbase[tid] += y;
+      __syncthreads();
+    }
+    if (tid < 256) {
+      uint32_t run = 0, tot = 0;
+      for (int ww = 0; ww < SMALL_WAVES; ++ww) tot += cnt[ww][tid];
+      run = dbase[tid] - tot;  // exclusive
+      for (int ww = 0; ww < SMALL_WAVES; ++ww) {
+        const uint32_t c = cnt[ww][tid];
+        cnt[ww][tid] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SMALL_ITEMS; ++it) {
+      int i = base + it * 64 + lane;
+      if (i < n) {
+        uint32_t dst = cnt[w][dg[it]] + rank[it];
+        kout[dst] = k[it];
+        sout[dst] = sv[it];
+      }
+    }
+    __syncthreads();
+    uint64_t *tk = kin; kin = kout; kout = tk;
+    int32_t *ts = sin; sin = sout; sout = ts;
+  }
+  // sorted positions; split depth (keys leaf_size apart, same request)
+  int best = 0;
+  for (int i = tid; i < n; i += T) {
+    gather_at(t, i);
+    if (i + leaf_size < n) {
+      const int r = t.n_req > 1 ? upper_index(t.req_off, t.n_req, i) : 0;
+      if (t.n_req == 1 || i + leaf_size < t.req_off[r + 1]) {
+        uint64_t x = t.key[i] ^ t.key[i + leaf_size];
+        best = max(best, x == 0 ? FMM_MAXLEVEL : (__clzll(x) - 1) / 3);
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off, 64));
+  if (lane == 0) ired[w] = best;
+  __syncthreads();
+  for (int k2 = 0; k2 < SMALL_WAVES; ++k2) best = max(best, ired[k2]);
+  if (tid == 0) h->max_prefix = best;
+  const int max_level = min(FMM_MAXLEVEL, best + 1);
+  __syncthreads();
+  // level-by-level split
+  int leaves = 0;
+  for (int l = 0; l < max_level; ++l) {
+    const int ls = h->lvl_start[l], le = min(h->lvl_start[l + 1], (int)t.cap_nodes);
+    int run = h->lvl_start[l + 1];
+    for (int b0 = ls; b0 < le; b0 += T) {
+      const int i = b0 + tid;
+      const int nc = i < le ? count_node(t, i, l, leaf_size) : 0;
+      sc[tid] = nc;
+      __syncthreads();
+      for (int off = 1; off < T; off <<= 1) {
+        int y = tid >= off ? sc[tid - off] : 0;
+        __syncthreads();
+        sc[tid] += y;
+        __syncthreads();
+      }
+      const int first = run + sc[tid] - nc;
+      const int total = sc[T - 1];
+      __syncthreads();
+      if (i < le) leaves += emit_node(t, i, l, nc, first, leaf_size);
+      run += total;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int k2 = l + 2; k2 < FMM_NLEVELS + 2; ++k2) h->lvl_start[k2] = run;
+      if (run > t.cap_nodes) h->overflow |= OVF_NODES;
+    }
+    __syncthreads();
+  }
+  leaves = block_sum_small(leaves, ired);
+  if (tid == 0 && leaves) atomicAdd((int *)&h->n_leaves, leaves);
+}
+
+hipError_t launch_build_small(const DevTree &t, const BuildArgs &a, hipStream_t s) {
+  if (a.tm) a.tm->start(PH_TREE, s);
+  const int req_passes = a.n_req > 1 ? (a.n_req > 65536 ? 4 : 2) : 0;
+  hipLaunchKernelGGL(k_build_small, dim3(1), dim3(SMALL_THREADS), 0, s, t, a.n, a.leaf_size,
+                     req_passes);
+  if (a.tm) a.tm->stop(s);
+  return hipGetLastError();
 }
 
 hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {

@@ -60,3 +60,39 @@ def test_batched_equals_solo(oracle, precision, kernel):
             assert e.max() < 1e-12
     assert info["nodes"] == nodes
     s.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_batch_paths_identical(precision):
+    """A batch small enough for the single-workgroup build (several requests,
+    so the sort also orders by request) equals the multi-workgroup build bit
+    for bit, and each system equals its solo solve."""
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    sizes = [1500, 0, 1, 2000, 700, 3000, 2]
+    dev = []
+    for (p, m, _), n in zip(_systems(), sizes):
+        if n == 0:  # an empty system: active set of size zero
+            dev.append(dict(pos=torch.from_numpy(np.ascontiguousarray(p)).cuda(),
+                            mass=torch.from_numpy(np.ascontiguousarray(m)).cuda(),
+                            active=torch.zeros(0, dtype=torch.int32, device="cuda")))
+            continue
+        dev.append(dict(pos=torch.from_numpy(np.ascontiguousarray(p[:, :n])).cuda(),
+                        mass=torch.from_numpy(np.ascontiguousarray(m[:n])).cuda(), active=None))
+    total = sum(d["mass"].numel() if d["active"] is None else 0 for d in dev)
+    assert total <= 8192
+    res = []
+    for small in (True, False):
+        s = F.Solver(total, p_max=4, leaf_size=16, kernel=0, precision=precision)
+        s.set_small_path(small)
+        outs = s.forces_batched(dev, eps=0.01, theta=0.5, p=4)
+        torch.cuda.synchronize()
+        res.append([(a.cpu().numpy(), p.cpu().numpy()) for a, p in outs])
+        if small:
+            for k, d in enumerate(dev):
+                a, pt = s.forces(d["pos"], d["mass"], d["active"], eps=0.01, theta=0.5, p=4)
+                torch.cuda.synchronize()
+                assert np.array_equal(a.cpu().numpy(), res[0][k][0]), k
+        s.close()
+    for (a1, p1), (a2, p2) in zip(*res):
+        assert np.array_equal(a1, a2) and np.array_equal(p1, p2)

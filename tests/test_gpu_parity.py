@@ -228,3 +228,32 @@ def test_run_to_run_bit_identical(precision):
     r1 = gpu_solve(pos, m, p=4, theta=0.5, eps=0.005, leaf_size=16, kernel=0, precision=precision)
     r2 = gpu_solve(pos, m, p=4, theta=0.5, eps=0.005, leaf_size=16, kernel=0, precision=precision)
     assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[1], r2[1])
+
+
+@pytest.mark.parametrize("label", ["plummer4096", "subset", "zoom7003", "leaf1", "leaf64"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_small_and_general_paths_identical(label, precision):
+    """Batches of at most 8192 particles are built and walked by one workgroup
+    each; forcing the multi-workgroup path gives the same tree, lists and
+    forces bit for bit."""
+    torch, F = _torch(), _F()
+    pos, m, active, leaf, theta, eps = _inputs(_case(label))
+    out = []
+    for small in (True, False):
+        n = pos.shape[1] if active is None else len(active)
+        s = F.Solver(n, p_max=4, leaf_size=leaf, kernel=F.WENDLAND, precision=precision)
+        s.set_small_path(small)
+        tp = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+        tm = torch.from_numpy(np.ascontiguousarray(m)).cuda()
+        ta = None if active is None else torch.from_numpy(active).cuda()
+        s.build(tp, ta, eps=eps, theta=theta)
+        ex = s.export_tree()
+        a, pt = s.evaluate(tp, tm, ta, p=4)
+        torch.cuda.synchronize()
+        out.append((ex, a.cpu().numpy(), pt.cpu().numpy(), s.tree_info()))
+        s.close()
+    (e1, a1, p1, i1), (e2, a2, p2, i2) = out
+    assert i1 == i2
+    for k in e1:
+        np.testing.assert_array_equal(e1[k], e2[k], err_msg=k)
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
