@@ -617,24 +617,31 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l, int l
 // host round trip.  Each step is the same per-element code as the multi-block
 // path, so the tree is the same bit for bit.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int block_sum_small(int v, int *red) {
-  v = wave_sum(v);
+// block-wide exclusive scan of one int per thread (wave shuffles, then the
+// wave totals through LDS); *total gets the sum
+__device__ __forceinline__ int block_excl_scan_small(int v, int *wsum, int *total) {
   const int w = threadIdx.x >> 6;
+  int wt;
+  const int x = wave_excl_scan_int(v, &wt);
+  if ((threadIdx.x & 63) == 0) wsum[w] = wt;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
+  int off = 0, tot = 0;
+  for (int k = 0; k < SMALL_WAVES; ++k) {
+    off += k < w ? wsum[k] : 0;
+    tot += wsum[k];
+  }
   __syncthreads();
-  int s = 0;
-  for (int k = 0; k < SMALL_WAVES; ++k) s += red[k];
-  return s;
+  *total = tot;
+  return off + x;
 }
 
 __global__ __launch_bounds__(SMALL_THREADS) void k_build_small(DevTree t, int n, int leaf_size,
                                                                int req_passes) {
   __shared__ uint32_t cnt[SMALL_WAVES][256];
   __shared__ uint32_t dbase[256];
-  __shared__ double bred[6][SMALL_WAVES];
-  __shared__ int ired[SMALL_WAVES];
-  __shared__ int sc[SMALL_THREADS];
+  __shared__ uint64_t skey[SMALL_THREADS];
+  __shared__ int sord[SMALL_THREADS];
+  __shared__ int wsum[SMALL_WAVES];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int T = SMALL_THREADS;
   Header *h = t.hdr;
@@ -644,13 +651,12 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_build_small(DevTree t, int n,
     header_init(t);
   }
   for (int q = tid; q < n; q += T) t.slot_req[q] = upper_index(t.req_off, t.n_req, q);
-  __syncthreads();
-  // root box of every request
+  // root box of every request: one wavefront per request
   int bad = 0;
-  for (int r = 0; r < t.n_req; ++r) {
+  for (int r = w; r < t.n_req; r += SMALL_WAVES) {
     const DevReq q = t.reqs[r];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int i = tid; i < q.n; i += T) {
+    for (int i = lane; i < q.n; i += 64) {
       int64_t g = q.active ? q.active[i] : i;
       for (int d = 0; d < 3; ++d) {
         double x = q.pos[d * q.n_total + g];
@@ -664,96 +670,110 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_build_small(DevTree t, int n,
         lo[d] = fmin(lo[d], __shfl_xor(lo[d], off, 64));
         hi[d] = fmax(hi[d], __shfl_xor(hi[d], off, 64));
       }
-    if (lane == 0)
-      for (int d = 0; d < 3; ++d) {
-        bred[d][w] = lo[d];
-        bred[3 + d][w] = hi[d];
-      }
-    __syncthreads();
-    if (tid == 0) {
-      for (int k = 1; k < SMALL_WAVES; ++k)
-        for (int d = 0; d < 3; ++d) {
-          lo[d] = fmin(lo[d], bred[d][k]);
-          hi[d] = fmax(hi[d], bred[3 + d][k]);
-        }
-      finish_box(t.box[r], lo, hi, q.n == 0);
-    }
-    __syncthreads();
+    if (lane == 0) finish_box(t.box[r], lo, hi, q.n == 0);
   }
   if (__syncthreads_or(bad) && tid == 0) h->nonfinite = 1;
   for (int r = tid; r < t.n_req; r += T) root_init(t, r, leaf_size);
   for (int q = tid; q < n; q += T) make_key(t, q);
   __syncthreads();
-  // stable LSD radix sort, 8-bit digits: 8 key passes, then request passes
-  uint64_t *kin = t.key, *kout = t.key2;
-  int32_t *sin = t.slot, *sout = t.slot2;
-  const unsigned long long below = lanes_below_mask();
-  for (int pass = 0; pass < 8 + req_passes; ++pass) {
-    const int by_req = pass >= 8;
-    const int shift = by_req ? (pass - 8) * 8 : pass * 8;
-    for (int d = tid; d < SMALL_WAVES * 256; d += T) (&cnt[0][0])[d] = 0;
+  if (n <= T) {
+    // at most one particle per thread: the rank of (request, key, slot) among
+    // all of them is its place in the stable sorted order
+    uint64_t k = 0;
+    int r = 0;
+    if (tid < n) {
+      k = t.key[tid];
+      r = t.slot_req[tid];
+      skey[tid] = k;
+      sord[tid] = r;
+    }
     __syncthreads();
+    if (tid < n) {
+      int rank = 0;
+      for (int j = 0; j < n; ++j) {
+        const int rj = sord[j];
+        const uint64_t kj = skey[j];
+        rank += (rj < r) || (rj == r && (kj < k || (kj == k && j < tid)));
+      }
+      t.key[rank] = k;
+      t.slot[rank] = tid;  // slots are still in input order
+    }
+    __syncthreads();
+  } else {
+    // stable LSD radix sort, 8-bit digits: 8 key passes, then request passes
+    uint64_t *kin = t.key, *kout = t.key2;
+    int32_t *sin = t.slot, *sout = t.slot2;
+    const unsigned long long below = lanes_below_mask();
     const int base = w * 64 * SMALL_ITEMS;
-    uint64_t k[SMALL_ITEMS];
-    int32_t sv[SMALL_ITEMS];
-    uint32_t rank[SMALL_ITEMS], dg[SMALL_ITEMS];
-#pragma unroll
-    for (int it = 0; it < SMALL_ITEMS; ++it) {
-      int i = base + it * 64 + lane;
-      bool valid = i < n;
-      k[it] = valid ? kin[i] : 0;
-      sv[it] = valid ? sin[i] : 0;
-      uint32_t d = by_req ? ((uint32_t)t.slot_req[sv[it]] >> shift) & 255u
-                          : (uint32_t)(k[it] >> shift) & 255u;
-      dg[it] = d;
-      unsigned long long m = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        unsigned long long bal = __ballot((d >> b) & 1u);
-        m &= ((d >> b) & 1u) ? bal : ~bal;
-      }
-      uint32_t prior = cnt[w][d];
-      rank[it] = prior + (uint32_t)__popcll(m & below);
-      __builtin_amdgcn_wave_barrier();
-      if (valid && (m & below) == 0) cnt[w][d] = prior + (uint32_t)__popcll(m);
-      __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    if (tid < 256) {  // digit totals, then exclusive scan over digits
-      uint32_t tot = 0;
-      for (int ww = 0; ww < SMALL_WAVES; ++ww) tot += cnt[ww][tid];
-      dbase[tid] = tot;
-    }
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      uint32_t y = (tid < 256 && tid >= off) ? dbase[tid - off] : 0u;
+    const int items = min(SMALL_ITEMS, max(0, (n - base + 63) / 64));  // uniform per wave
+    for (int pass = 0; pass < 8 + req_passes; ++pass) {
+      const int by_req = pass >= 8;
+      const int shift = by_req ? (pass - 8) * 8 : pass * 8;
+      for (int d = tid; d < SMALL_WAVES * 256; d += T) (&cnt[0][0])[d] = 0;
       __syncthreads();
-      if (tid < 256) dbase[tid] += y;
-      __syncthreads();
-    }
-    if (tid < 256) {
-      uint32_t run = 0, tot = 0;
-      for (int ww = 0; ww < SMALL_WAVES; ++ww) tot += cnt[ww][tid];
-      run = dbase[tid] - tot;  // exclusive
-      for (int ww = 0; ww < SMALL_WAVES; ++ww) {
-        const uint32_t c = cnt[ww][tid];
-        cnt[ww][tid] = run;
-        run += c;
-      }
-    }
-    __syncthreads();
+      uint64_t k[SMALL_ITEMS];
+      int32_t sv[SMALL_ITEMS];
+      uint32_t rank[SMALL_ITEMS], dg[SMALL_ITEMS];
 #pragma unroll
-    for (int it = 0; it < SMALL_ITEMS; ++it) {
-      int i = base + it * 64 + lane;
-      if (i < n) {
-        uint32_t dst = cnt[w][dg[it]] + rank[it];
-        kout[dst] = k[it];
-        sout[dst] = sv[it];
+      for (int it = 0; it < SMALL_ITEMS; ++it) {
+        if (it >= items) continue;  // wave-uniform
+        int i = base + it * 64 + lane;
+        bool valid = i < n;
+        k[it] = valid ? kin[i] : 0;
+        sv[it] = valid ? sin[i] : 0;
+        uint32_t d = by_req ? ((uint32_t)t.slot_req[sv[it]] >> shift) & 255u
+                            : (uint32_t)(k[it] >> shift) & 255u;
+        dg[it] = d;
+        unsigned long long m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          unsigned long long bal = __ballot((d >> b) & 1u);
+          m &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        uint32_t prior = cnt[w][d];
+        rank[it] = prior + (uint32_t)__popcll(m & below);
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (m & below) == 0) cnt[w][d] = prior + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
       }
+      __syncthreads();
+      if (w == 0) {  // digit bases: lane l scans digits 4l .. 4l+3
+        uint32_t tt[4], sum = 0;
+        for (int q = 0; q < 4; ++q) {
+          tt[q] = 0;
+          for (int ww = 0; ww < SMALL_WAVES; ++ww) tt[q] += cnt[ww][4 * lane + q];
+          sum += tt[q];
+        }
+        int tot;
+        uint32_t run = (uint32_t)wave_excl_scan_int((int)sum, &tot);
+        for (int q = 0; q < 4; ++q) {
+          dbase[4 * lane + q] = run;
+          run += tt[q];
+        }
+      }
+      __syncthreads();
+      if (tid < 256) {
+        uint32_t run = dbase[tid];
+        for (int ww = 0; ww < SMALL_WAVES; ++ww) {
+          const uint32_t c = cnt[ww][tid];
+          cnt[ww][tid] = run;
+          run += c;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < SMALL_ITEMS; ++it) {
+        int i = base + it * 64 + lane;
+        if (it < items && i < n) {
+          uint32_t dst = cnt[w][dg[it]] + rank[it];
+          kout[dst] = k[it];
+          sout[dst] = sv[it];
+        }
+      }
+      __syncthreads();
+      uint64_t *tk = kin; kin = kout; kout = tk;
+      int32_t *ts = sin; sin = sout; sout = ts;
     }
-    __syncthreads();
-    uint64_t *tk = kin; kin = kout; kout = tk;
-    int32_t *ts = sin; sin = sout; sout = ts;
   }
   // sorted positions; split depth (keys leaf_size apart, same request)
   int best = 0;
@@ -768,43 +788,37 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_build_small(DevTree t, int n,
     }
   }
   for (int off = 32; off > 0; off >>= 1) best = max(best, __shfl_xor(best, off, 64));
-  if (lane == 0) ired[w] = best;
+  if (lane == 0) wsum[w] = best;
   __syncthreads();
-  for (int k2 = 0; k2 < SMALL_WAVES; ++k2) best = max(best, ired[k2]);
+  for (int k2 = 0; k2 < SMALL_WAVES; ++k2) best = max(best, wsum[k2]);
   if (tid == 0) h->max_prefix = best;
   const int max_level = min(FMM_MAXLEVEL, best + 1);
   __syncthreads();
   // level-by-level split
   int leaves = 0;
+  int ls = 0, run = t.n_req;  // level l occupies [ls, run) when its split starts
   for (int l = 0; l < max_level; ++l) {
-    const int ls = h->lvl_start[l], le = min(h->lvl_start[l + 1], (int)t.cap_nodes);
-    int run = h->lvl_start[l + 1];
+    const int le = min(run, (int)t.cap_nodes);
+    int next = run;
     for (int b0 = ls; b0 < le; b0 += T) {
       const int i = b0 + tid;
       const int nc = i < le ? count_node(t, i, l, leaf_size) : 0;
-      sc[tid] = nc;
-      __syncthreads();
-      for (int off = 1; off < T; off <<= 1) {
-        int y = tid >= off ? sc[tid - off] : 0;
-        __syncthreads();
-        sc[tid] += y;
-        __syncthreads();
-      }
-      const int first = run + sc[tid] - nc;
-      const int total = sc[T - 1];
-      __syncthreads();
+      int total;
+      const int first = next + block_excl_scan_small(nc, wsum, &total);
       if (i < le) leaves += emit_node(t, i, l, nc, first, leaf_size);
-      run += total;
+      next += total;
     }
-    __syncthreads();
     if (tid == 0) {
-      for (int k2 = l + 2; k2 < FMM_NLEVELS + 2; ++k2) h->lvl_start[k2] = run;
-      if (run > t.cap_nodes) h->overflow |= OVF_NODES;
+      for (int k2 = l + 2; k2 < FMM_NLEVELS + 2; ++k2) h->lvl_start[k2] = next;
+      if (next > t.cap_nodes) h->overflow |= OVF_NODES;
     }
+    ls = run;
+    run = next;
     __syncthreads();
   }
-  leaves = block_sum_small(leaves, ired);
-  if (tid == 0 && leaves) atomicAdd((int *)&h->n_leaves, leaves);
+  int total;
+  block_excl_scan_small(leaves, wsum, &total);
+  if (tid == 0 && total) atomicAdd((int *)&h->n_leaves, total);
 }
 
 hipError_t launch_build_small(const DevTree &t, const BuildArgs &a, hipStream_t s) {
