@@ -197,6 +197,34 @@ def ensemble_leg(args, F, torch, line):
     }
 
 
+def hhs_request_leg(args):
+    """Top-level HHS steps (dt 1/16) of one ensemble request, after one
+    untimed step; prints one JSON line."""
+    import torch
+    import paper_1712_10116_amd.fmm as F
+    from paper_1712_10116_amd import workloads as W
+    prm = W.PARAMS[4]
+    pos, vel, m = W.ensemble_request(args.hhs_request)
+    s = F.Solver(m.size, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
+                 precision=F.MIXED)
+    h = F.HHS(s, torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda(),
+              torch.from_numpy(m).cuda(), eps=prm["eps"], theta=prm["theta"], p=prm["p"],
+              eta=prm["eta"], max_levels=prm["max_levels"])
+    h.init()
+    h.step(1.0 / 16)
+    torch.cuda.synchronize()
+    steps = []
+    for _ in range(args.hhs_steps):
+        t0 = time.perf_counter()
+        st = h.step(1.0 / 16)
+        torch.cuda.synchronize()
+        steps.append(dict(ms=round((time.perf_counter() - t0) * 1e3, 3), **st))
+    rungs = torch.bincount(h.rung.long()).cpu().numpy().tolist()
+    print(json.dumps({"request": args.hhs_request, "n": int(m.size), "leaf_size": prm["leaf_size"],
+                      "rung_histogram": rungs, "steps": steps}))
+    s.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +253,10 @@ def main():
     ap.add_argument("--ensemble-slots", type=int, default=256)
     ap.add_argument("--ensemble-arena-gib", type=int, default=16)
     ap.add_argument("--ensemble-max-n", type=int, default=1 << 22)
+    ap.add_argument("--hhs-request", type=int, default=-1, metavar="I",
+                    help="only time top-level HHS steps of ensemble request I (mixed, the "
+                         "ensemble parameters) and exit; used for kernel traces of small systems")
+    ap.add_argument("--hhs-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -238,6 +270,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}))
+        return
+    if args.hhs_request >= 0:
+        hhs_request_leg(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
