@@ -38,6 +38,11 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X FP64 vector (published)
 METRIC = "FMM force particles/s at 1e-3 force err (mixed vs FP64); ensemble p99 latency"
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def coeffs(p):
     return (p + 1) * (p + 2) * (p + 3) // 6
 
@@ -168,10 +173,12 @@ def ensemble_leg(args, F, torch, line):
 
     srv = server()
     serving.run(srv, [W.ensemble_request(1000)], args.ensemble_t_end)  # warm-up, untimed
+    progress("  closed loop")
     res, span = serving.run(srv, reqs, args.ensemble_t_end)
     closed = serving.summary(res, span)
     rate = args.ensemble_load * closed["requests_per_s"]
     arr = serving.poisson_arrivals(K, rate, seed=5999)
+    progress(f"  Poisson arrivals at {rate:.3f} per s")
     res, span = serving.run(srv, reqs, args.ensemble_t_end, arrivals=arr)
     opened = serving.summary(res, span)
     # latency alone: the smallest, the median-size and the largest request
@@ -195,6 +202,107 @@ def ensemble_leg(args, F, torch, line):
         "p50_latency_s": round(opened["p50_s"], 4), "p99_latency_s": round(opened["p99_s"], 4),
         "solo_latency_s_by_n": solo,
     }
+
+
+def configs_leg(args, F, torch, line):
+    """Every named workload at its own p and theta (leaf size by the
+    autotuner): one timed solve, force error over all particles against the
+    high-accuracy FP64 solve and on seeded sinks against FP64 direct summation
+    (CPU oracle), momentum balance; HHS runs on the Plummer sphere (8 steps,
+    FP64) and the cold collapse (to two free-fall times, mixed) with the drift
+    of total momentum and angular momentum."""
+    from paper_1712_10116_amd import autotune
+    from paper_1712_10116_amd import workloads as W
+    names = {0: "plummer_4096", 1: "cold_collapse_2^20", 2: "disk_galaxy_2^22",
+             3: "clustered_zoom_2^24"}
+    precision = {0: F.FP64, 1: F.MIXED, 2: F.MIXED, 3: F.MIXED}
+    sinks_n = {0: 4096, 1: 1024, 2: 512, 3: 256}
+    dev = torch.device("cuda:0")
+    out = {}
+    for c in args.configs:
+        progress(f"config {names[c]}")
+        prm = W.PARAMS[c]
+        pos, vel, m = W.config(c)
+        n = m.size
+        tp = torch.from_numpy(pos).to(dev)
+        tm = torch.from_numpy(m).to(dev)
+        tr = autotune.tune(tp, tm, eps=prm["eps"], kernel=prm["kernel"], precision=precision[c],
+                           target=None, leaf_sizes=(16, 32, 64, 96), orders=(prm["p"],),
+                           thetas=(prm["theta"],), reps=3)
+        leaf = tr["best"]["leaf_size"]
+        s = F.Solver(n, p_max=prm["p"], leaf_size=leaf, kernel=prm["kernel"],
+                     precision=precision[c])
+        acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+        pot = torch.empty((n,), dtype=torch.float64, device=dev)
+        pr = dict(p=prm["p"], theta=prm["theta"], eps=prm["eps"])
+        sec, _ = time_solver(F, torch, s, tp, tm, acc, pot, pr, 5, 1, profile=False)
+        inv = s.invariants(mass=tm, acc=acc)
+        a = acc.cpu().numpy()
+        s.close()
+        rp = autotune.REFERENCE
+        r = F.Solver(n, p_max=rp["p"], leaf_size=rp["leaf_size"], kernel=prm["kernel"],
+                     precision=F.FP64)
+        a_ref, _ = r.forces(tp, tm, eps=prm["eps"], theta=rp["theta"], p=rp["p"])
+        a_ref = a_ref.cpu().numpy()
+        r.close()
+        e_all = force_error(a, a_ref)
+        row = {"n": n, "p": prm["p"], "theta": prm["theta"], "eps": prm["eps"], "leaf_size": leaf,
+               "kernel": "plummer" if prm["kernel"] == F.PLUMMER else "wendland_c2",
+               "precision": "fp64" if precision[c] == F.FP64 else "mixed",
+               "ms_per_solve": round(sec * 1e3, 4), "particles_per_s": round(n / sec, 1),
+               "force_err_vs_reference_all": {"rms": e_all[0], "p99": e_all[1]},
+               "momentum_rel": float(np.abs(inv["F"]).max() / inv["Fabs"])}
+        if not args.no_cpu_baseline:
+            from oracle import oracle as O
+            rng = np.random.default_rng(3000 + c)
+            sk = np.sort(rng.choice(n, size=min(sinks_n[c], n), replace=False))
+            d, _ = O.direct(pos, m, O.PLUMMER if prm["kernel"] == F.PLUMMER else O.WENDLAND,
+                            prm["eps"], sinks=sk)
+            e = force_error(a[:, sk], d)
+            row["force_err_vs_direct_sample"] = {"rms": e[0], "p99": e[1], "sinks": int(len(sk))}
+        steps, t_end = {0: (8, None), 1: (None, args.collapse_t_end)}.get(c, (0, None))
+        if steps or t_end:
+            s = F.Solver(n, p_max=prm["p"], leaf_size=leaf, kernel=prm["kernel"],
+                         precision=precision[c])
+            tv = torch.from_numpy(vel).to(dev)
+            tpp = tp.clone()
+            h = F.HHS(s, tpp, tv, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"],
+                      eta=prm["eta"], max_levels=prm["max_levels"])
+            h.init()
+            dtmax = float(np.sqrt(prm["eta"] * prm["eps"] /
+                                  max(float(h.a_cur[h.a_cur > 0].min()), 1e-30)))
+            dt_top = min(2.0 ** np.floor(np.log2(dtmax)), 2.0 ** -4)
+            i0 = s.invariants(pos=tpp, vel=tv, mass=tm)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = 0
+            calls = parts = 0
+            while (steps and k < steps) or (t_end and h.t < t_end - 1e-12):
+                dt = dt_top if not t_end else min(dt_top, t_end - h.t)
+                st = h.step(dt)
+                calls += st["force_calls"]
+                parts += st["force_particles"]
+                k += 1
+                progress(f"  {names[c]} HHS step {k}: t = {h.t:.4f}, {st['force_calls']} calls")
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            i1 = s.invariants(pos=tpp, vel=tv, mass=tm)
+            pscale = float(np.sum(m * np.sqrt((vel * vel).sum(axis=0)))) or 1.0
+            lscale = float(np.sum(m * np.sqrt((pos * pos).sum(axis=0)) *
+                                  np.sqrt((vel * vel).sum(axis=0)))) or 1.0
+            row["hhs"] = {"steps": k, "t": h.t, "dt_top": dt_top, "seconds": round(wall, 3),
+                          "force_calls": calls, "particles_per_s": round(parts / wall, 1),
+                          "momentum_drift": float(np.abs(i1["P"] - i0["P"]).max()),
+                          "momentum_scale": pscale if c == 0 else None,
+                          "angular_momentum_drift": float(np.abs(i1["L"] - i0["L"]).max()),
+                          "kinetic_energy": [i0["T"], i1["T"]]}
+            if c != 0:  # a cold start has no momentum scale of its own: use m |a| dt
+                row["hhs"]["momentum_scale"] = float(inv["Fabs"]) * h.t
+            s.close()
+        out[names[c]] = row
+        del tp, tm, acc, pot
+        torch.cuda.empty_cache()
+    line["configs"] = out
 
 
 def hhs_request_leg(args):
@@ -253,6 +361,11 @@ def main():
     ap.add_argument("--ensemble-slots", type=int, default=256)
     ap.add_argument("--ensemble-arena-gib", type=int, default=16)
     ap.add_argument("--ensemble-max-n", type=int, default=1 << 22)
+    ap.add_argument("--configs", type=int, nargs="*", default=[0, 1, 2, 3],
+                    help="named workloads measured in the per-configuration leg")
+    ap.add_argument("--no-configs", action="store_true")
+    ap.add_argument("--collapse-t-end", type=float, default=0.25,
+                    help="end time of the cold-collapse HHS run (two free-fall times: 2.2214)")
     ap.add_argument("--hhs-request", type=int, default=-1, metavar="I",
                     help="only time top-level HHS steps of ensemble request I (mixed, the "
                          "ensemble parameters) and exit; used for kernel traces of small systems")
@@ -294,6 +407,7 @@ def main():
     if args.no_tune:
         prm = dict(p=args.p, theta=args.theta, eps=eps, leaf_size=args.leaf)
     else:
+        progress("autotuner")
         t0 = time.perf_counter()
         tr = autotune.tune(tp, tm, eps=eps, kernel=F.WENDLAND, precision=F.MIXED,
                            target=args.target, leaf_sizes=(16, 24, 32, 48, 64, 96),
@@ -314,6 +428,7 @@ def main():
         runs.append(("mixed_named", F.MIXED, named))
     res = {}
     for name, prec, pr in runs:
+        progress(f"timed solves: {name}")
         s = F.Solver(n, p_max=pr["p"], leaf_size=pr["leaf_size"], kernel=F.WENDLAND,
                      precision=prec)
         acc = torch.empty((3, n), dtype=torch.float64, device=dev)
@@ -398,6 +513,7 @@ def main():
         line["autotune"] = line_tune
 
     if not args.no_hhs:
+        progress("HHS step")
         # one HHS top-level step of the same particles (mixed precision)
         s = F.Solver(n, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=F.WENDLAND,
                      precision=F.MIXED)
@@ -426,9 +542,14 @@ def main():
                                 "ms_per_step": round(r["sec"] * 1e3, 4)}
 
     if args.ensemble > 0:
+        progress("serving ensemble")
         ensemble_leg(args, F, torch, line)
 
+    if not args.no_configs:
+        configs_leg(args, F, torch, line)
+
     if not args.no_cpu_baseline:
+        progress("CPU oracle")
         cpu_leg(args, n, pos, mass, res, prm, line)
     print(json.dumps(line))
 

@@ -291,9 +291,13 @@ static fmm_status read_header(fmm_ctx *c) {
   return FMM_OK;
 }
 
+// Regrow the list buffer that overflowed.  A walk that overflows stops
+// writing, so `need` (the entries it tried to place) can undercount what the
+// whole walk needs: the capacity at least doubles each time.
 static fmm_status regrow_lists(fmm_ctx *c, int which, int64_t need) {
   DevTree &t = c->t;
-  int64_t cap = need + need / 4 + 1024;
+  const int64_t old = which == OVF_M2L ? t.cap_m2l : which == OVF_P2P ? t.cap_p2p : t.cap_open;
+  int64_t cap = std::max(need + need / 4 + 1024, 2 * old);
   if (which == OVF_M2L) {
     dfree(c, t.m2l_src);
     t.m2l_src = nullptr;
@@ -390,7 +394,7 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
   a.lvl_host = lvl;
   a.depth = depth;
   // 2. symmetric walk; regrow a list buffer that turned out too small
-  for (int attempt = 0; attempt < 4; ++attempt) {
+  for (int attempt = 0; attempt < 10; ++attempt) {
     HIPCHK(c, launch_traverse(c->t, a, c->stream));
     st = read_header(c);
     if (st != FMM_OK) return st;
