@@ -174,12 +174,14 @@ def ensemble_leg(args, F, torch, line):
     srv = server()
     serving.run(srv, [W.ensemble_request(1000)], args.ensemble_t_end)  # warm-up, untimed
     progress("  closed loop")
-    res, span = serving.run(srv, reqs, args.ensemble_t_end)
+    res, span = serving.run(srv, reqs, args.ensemble_t_end,
+                            log=lambda m: progress("    " + m) if K > 64 else None)
     closed = serving.summary(res, span)
     rate = args.ensemble_load * closed["requests_per_s"]
     arr = serving.poisson_arrivals(K, rate, seed=5999)
     progress(f"  Poisson arrivals at {rate:.3f} per s")
-    res, span = serving.run(srv, reqs, args.ensemble_t_end, arrivals=arr)
+    res, span = serving.run(srv, reqs, args.ensemble_t_end, arrivals=arr,
+                            log=lambda m: progress("    " + m) if K > 64 else None)
     opened = serving.summary(res, span)
     # latency alone: the smallest, the median-size and the largest request
     sizes = np.array([r[2].size for r in reqs])

@@ -18,7 +18,7 @@ def poisson_arrivals(n, rate, seed):
     return np.cumsum(rng.exponential(1.0 / rate, n))
 
 
-def run(server, requests, t_end, arrivals=None, clock=time.perf_counter):
+def run(server, requests, t_end, arrivals=None, clock=time.perf_counter, log=None):
     """Serve ``requests`` (a list of (pos, vel, mass) host arrays) to ``t_end``.
 
     arrivals: seconds after the start at which request k arrives (None: all at
@@ -35,6 +35,7 @@ def run(server, requests, t_end, arrivals=None, clock=time.perf_counter):
     results = [None] * n
     start = clock()
     outstanding = 0
+    steps = 0
     while nxt < n or outstanding:
         now = clock() - start
         while nxt < n and arr[order[nxt]] <= now:
@@ -45,7 +46,10 @@ def run(server, requests, t_end, arrivals=None, clock=time.perf_counter):
             outstanding += 1
             nxt += 1
         if outstanding:
-            server.step()
+            nr, nq = server.step()
+            steps += 1
+            if log is not None:
+                log(f"step {steps}: {nr} resident, {nq} queued, {clock() - start:.1f} s")
             for r in server.poll():
                 k, t_sub = ids.pop(r["id"])
                 # server clock: t_done - t_submit; driver clock: hand-over delay
