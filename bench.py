@@ -307,6 +307,49 @@ def configs_leg(args, F, torch, line):
     line["configs"] = out
 
 
+def collapse_run_leg(args):
+    """The cold collapse (uniform sphere at rest, Wendland eps = 0.005, p 4,
+    theta 0.5, HHS with 10 rungs) integrated to t = collapse_t_end with N =
+    collapse_run particles, in mixed precision and in FP64: total momentum and
+    angular momentum drift, kinetic energy, force calls; prints one JSON line."""
+    import torch
+    import paper_1712_10116_amd.fmm as F
+    from paper_1712_10116_amd import workloads as W
+    prm = W.PARAMS[1]
+    n = args.collapse_run
+    pos, vel, m = W.uniform_sphere(n, seed=1001)
+    out = {"n": n, "t_end": args.collapse_t_end, "p": prm["p"], "theta": prm["theta"],
+           "eps": prm["eps"], "leaf_size": args.leaf}
+    for name, prec in (("mixed", F.MIXED), ("fp64", F.FP64)):
+        s = F.Solver(n, p_max=prm["p"], leaf_size=args.leaf, kernel=prm["kernel"], precision=prec)
+        tp = torch.from_numpy(pos.copy()).cuda()
+        tv = torch.from_numpy(vel.copy()).cuda()
+        tm = torch.from_numpy(m).cuda()
+        h = F.HHS(s, tp, tv, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
+                  max_levels=prm["max_levels"])
+        h.init()
+        dtmax = float(np.sqrt(prm["eta"] * prm["eps"] /
+                              max(float(h.a_cur[h.a_cur > 0].min()), 1e-30)))
+        dt_top = min(2.0 ** np.floor(np.log2(dtmax)), 2.0 ** -4)
+        fabs = s.invariants(mass=tm, acc=s.forces(tp, tm, eps=prm["eps"], theta=prm["theta"],
+                                                  p=prm["p"])[0])["Fabs"]
+        t0 = time.perf_counter()
+        k = calls = 0
+        while h.t < args.collapse_t_end - 1e-12:
+            st = h.step(min(dt_top, args.collapse_t_end - h.t))
+            calls += st["force_calls"]
+            k += 1
+            progress(f"{name} collapse step {k}: t = {h.t:.4f}, {st['force_calls']} calls")
+        torch.cuda.synchronize()
+        inv = s.invariants(pos=tp, vel=tv, mass=tm)
+        out[name] = {"steps": k, "dt_top": dt_top, "seconds": round(time.perf_counter() - t0, 2),
+                     "force_calls": calls, "momentum": inv["P"].tolist(),
+                     "momentum_rel": float(np.abs(inv["P"]).max() / (fabs * h.t)),
+                     "angular_momentum": inv["L"].tolist(), "kinetic_energy": float(inv["T"])}
+        s.close()
+    print(json.dumps(out))
+
+
 def hhs_request_leg(args):
     """Top-level HHS steps (dt 1/16) of one ensemble request, after one
     untimed step; prints one JSON line."""
@@ -368,6 +411,9 @@ def main():
     ap.add_argument("--no-configs", action="store_true")
     ap.add_argument("--collapse-t-end", type=float, default=0.25,
                     help="end time of the cold-collapse HHS run (two free-fall times: 2.2214)")
+    ap.add_argument("--collapse-run", type=int, default=0, metavar="N",
+                    help="only integrate a cold collapse of N particles to --collapse-t-end "
+                         "(both precisions) and exit")
     ap.add_argument("--hhs-request", type=int, default=-1, metavar="I",
                     help="only time top-level HHS steps of ensemble request I (mixed, the "
                          "ensemble parameters) and exit; used for kernel traces of small systems")
@@ -388,6 +434,9 @@ def main():
         return
     if args.hhs_request >= 0:
         hhs_request_leg(args)
+        return
+    if args.collapse_run > 0:
+        collapse_run_leg(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
