@@ -310,16 +310,24 @@ struct PairKernel {
 // to SRC particles -- FP32 offsets from A's centre in the mixed form, absolute
 // FP64 positions in the FP64 form.  Staging is cooperative: the lane holding a
 // source leaf writes the particle index of each of its slots into an LDS table,
-// then consecutive lanes load consecutive slots.  Lanes = (target particle, phase): LP >= 4 lanes per phase (the
-// smallest power of two >= n_A), nph = 64/LP phases, phase ph taking sources
-// ph, ph + nph, ...  A window is padded to a multiple of UNROLL*nph with
-// massless sources far away, so every lane runs the same number of unrolled
-// blocks with no bounds test.  FP32 partial sums are added into FP64
-// accumulators after every block of UNROLL sources.  The self term is excluded
-// by its position in the stream (coincident distinct particles interact).
+// then consecutive lanes load consecutive slots.
+//
+// Lanes = (sink, phase), lane = ti * nph + ph: LP = 64 / nph sinks at a time,
+// phase ph taking window slots ph, ph + nph, ...  The sinks of A are taken 64
+// at a time ("super passes"); within one, `passes` = ceil(ns / LP) passes over
+// each staged window cover its ns sinks, LP chosen per leaf so that few lanes
+// idle (a leaf of 40 runs 5 passes of 8 sinks x 8 phases rather than one pass
+// with 24 of 64 lanes idle).  With one pass a lane accumulates its phase for
+// the whole stream and the phases are summed at the end; with several, the
+// phases of a pass are summed after every window (DPP within the group of nph
+// lanes) and kept by the lane of phase p, the home lane of sink p * LP + ti.
+// A window is padded to a multiple of UNROLL*nph with massless sources far
+// away, so every lane runs the same number of unrolled blocks with no bounds
+// test.  FP32 partial sums are added into FP64 accumulators after every block
+// of UNROLL sources.
 #define P2P_WAVES 4
 #define P2P_UNROLL 8
-#define P2P_MINLP 4  // at most 16 phases, so a window pads to a multiple of 128
+#define P2P_MAXPH 16  // at most 16 phases, so a window pads to a multiple of 128
 
 template <bool MIXED>
 struct P2PTypes;
@@ -327,7 +335,7 @@ template <>
 struct P2PTypes<true> {
   typedef float R;
   typedef float4 R4;
-  static constexpr int SRC = 384;  // multiple of P2P_UNROLL * 64 / P2P_MINLP
+  static constexpr int SRC = 384;  // multiple of P2P_UNROLL * P2P_MAXPH
   __device__ static R4 far() { return make_float4(1e15f, 1e15f, 1e15f, 0.f); }
 };
 template <>
@@ -338,15 +346,14 @@ struct P2PTypes<false> {
   __device__ static R4 far() { return make_double4(1e150, 1e150, 1e150, 0.0); }
 };
 
-// One block of UNROLL sources per phase, NPH phases (NPH = 0: nph at run time).
+// One block of UNROLL sources of one phase (stride NPH between them).
 template <typename R, typename R4, int KERNEL, bool SELF, int NPH>
-__device__ __forceinline__ void p2p_block(const R4 *src, int f0, int nph, int self_idx, R xi, R yi,
-                                          R zi, R eps2, R inv_eps, R inv_eps3, R &sx, R &sy,
-                                          R &sz, R &sp) {
-  const int step = NPH > 0 ? NPH : nph;
+__device__ __forceinline__ void p2p_block(const R4 *src, int f0, int self_idx, R xi, R yi, R zi,
+                                          R eps2, R inv_eps, R inv_eps3, R &sx, R &sy, R &sz,
+                                          R &sp) {
   R4 svs[P2P_UNROLL];  // the block's sources, read before any use
 #pragma unroll
-  for (int u = 0; u < P2P_UNROLL; ++u) svs[u] = src[f0 + u * step];
+  for (int u = 0; u < P2P_UNROLL; ++u) svs[u] = src[f0 + u * NPH];
 #pragma unroll
   for (int u = 0; u < P2P_UNROLL; ++u) {
     const R4 sv = svs[u];
@@ -354,7 +361,7 @@ __device__ __forceinline__ void p2p_block(const R4 *src, int f0, int nph, int se
     R r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     R mj = sv.w;
     if (SELF) {
-      const bool self = f0 + u * step == self_idx;
+      const bool self = f0 + u * NPH == self_idx;
       r2 = self ? R(1) : r2;
       mj = self ? R(0) : mj;
     }
@@ -367,6 +374,92 @@ __device__ __forceinline__ void p2p_block(const R4 *src, int f0, int nph, int se
   }
 }
 
+// One phase of one staged window (Wr slots, a multiple of UNROLL * NPH) for
+// one sink, added into (bx, by, bz, bp).
+template <typename R, typename R4, int KERNEL, bool SELF, int NPH>
+__device__ __forceinline__ void p2p_window(const R4 *src, int ph, int Wr, int self_idx, R xi,
+                                           R yi, R zi, R eps2, R inv_eps, R inv_eps3, double &bx,
+                                           double &by, double &bz, double &bp) {
+  for (int f0 = ph; f0 < Wr; f0 += P2P_UNROLL * NPH) {
+    R sx = 0, sy = 0, sz = 0, sp = 0;
+    p2p_block<R, R4, KERNEL, SELF, NPH>(src, f0, self_idx, xi, yi, zi, eps2, inv_eps, inv_eps3,
+                                        sx, sy, sz, sp);
+    bx += (double)sx;
+    by += (double)sy;
+    bz += (double)sz;
+    bp -= (double)sp;
+  }
+}
+
+template <typename R, typename R4, int KERNEL, bool SELF>
+__device__ __forceinline__ void p2p_window_any(int nph, const R4 *src, int ph, int Wr,
+                                               int self_idx, R xi, R yi, R zi, R eps2, R inv_eps,
+                                               R inv_eps3, double &bx, double &by, double &bz,
+                                               double &bp) {
+  switch (nph) {
+    case 1:
+      p2p_window<R, R4, KERNEL, SELF, 1>(src, ph, Wr, self_idx, xi, yi, zi, eps2, inv_eps,
+                                         inv_eps3, bx, by, bz, bp);
+      break;
+    case 2:
+      p2p_window<R, R4, KERNEL, SELF, 2>(src, ph, Wr, self_idx, xi, yi, zi, eps2, inv_eps,
+                                         inv_eps3, bx, by, bz, bp);
+      break;
+    case 4:
+      p2p_window<R, R4, KERNEL, SELF, 4>(src, ph, Wr, self_idx, xi, yi, zi, eps2, inv_eps,
+                                         inv_eps3, bx, by, bz, bp);
+      break;
+    case 8:
+      p2p_window<R, R4, KERNEL, SELF, 8>(src, ph, Wr, self_idx, xi, yi, zi, eps2, inv_eps,
+                                         inv_eps3, bx, by, bz, bp);
+      break;
+    default:
+      p2p_window<R, R4, KERNEL, SELF, 16>(src, ph, Wr, self_idx, xi, yi, zi, eps2, inv_eps,
+                                          inv_eps3, bx, by, bz, bp);
+      break;
+  }
+}
+
+// Value of v in another lane of the same DPP row (CTRL: a DPP16 control).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each aligned group of nph consecutive lanes (nph = 1, 2, 4, 8, 16),
+// every lane of a group ending with the same value: quad swaps (lane ^ 1,
+// lane ^ 2), then the mirror within 8 and within 16 lanes, each pairing a lane
+// with one of the other half whose partial is already the other half's sum.
+// All lanes must be active.
+__device__ __forceinline__ double group_sum(double v, int nph) {
+  if (nph > 1) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (nph > 2) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (nph > 4) v += dpp_d<0x141>(v);  // row_half_mirror
+  if (nph > 8) v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+
+// log2 of the sinks per pass for a super pass of ns sinks: the fewest
+// lane-slots ceil(ns / LP) * LP, weighted by the cost of the per-window phase
+// sums when there is more than one pass; ties go to the larger LP.
+__device__ __forceinline__ int p2p_lanes_log2(int ns) {
+  int best_lg = 6, best = 1 << 30;
+  for (int lg = 6; lg >= 2; --lg) {
+    const int LP = 1 << lg, nph = 64 >> lg;
+    const int passes = (ns + LP - 1) >> lg;
+    const int ovh = passes > 1 ? (nph == 16 ? 8 : nph == 8 ? 3 : nph == 4 ? 1 : 0) : 0;
+    const int cost = passes * LP * (64 + ovh);
+    if (cost < best) {
+      best = cost;
+      best_lg = lg;
+    }
+  }
+  return best_lg;
+}
+
 // SELF: exclude the self pair by its stream position (needed when eps = 0);
 // otherwise the self pair is evaluated -- its acceleration term is exactly
 // zero (dx = 0) -- and its potential term, reproduced bit for bit, is taken
@@ -376,7 +469,7 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
   typedef typename P2PTypes<MIXED>::R R;
   typedef typename P2PTypes<MIXED>::R4 R4;
   constexpr int SRC = P2PTypes<MIXED>::SRC;
-  static_assert(SRC % (P2P_UNROLL * 64 / P2P_MINLP) == 0, "window must hold its padding");
+  static_assert(SRC % (P2P_UNROLL * P2P_MAXPH) == 0, "window must hold its padding");
   __shared__ R4 src_all[P2P_WAVES][SRC];
   __shared__ int idx_all[P2P_WAVES][SRC];
   const int lane = threadIdx.x & 63;
@@ -392,28 +485,30 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (t.nnchild[A] != 0 || skipped(t, A)) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
-    const int nt = nA < 64 ? nA : 64;
-    int lg = 2;  // log2 of P2P_MINLP
-    while ((1 << lg) < nt) ++lg;
-    const int LP = 1 << lg;           // lanes per phase
-    const int nph = 64 >> lg;         // phases
-    const int ph = lane >> lg, ti = lane & (LP - 1);
-    const int blk = P2P_UNROLL * nph; // sources per unrolled block of all phases
     const double4 gA = t.ngeo[A];
     const int off = t.p2p_off[A], cnt = t.p2p_cnt[A];
-    for (int tb = 0; tb < nA; tb += LP) {
-      const int i = tb + ti;
-      const bool vi = i < nA;
-      const int gi = bA + (vi ? i : 0);
-      R xi, yi, zi;
+    for (int tb = 0; tb < nA; tb += 64) {
+      const int ns = min(64, nA - tb);
+      const int lg = p2p_lanes_log2(ns);
+      const int LP = 1 << lg;                  // sinks per pass
+      const int nph = 64 >> lg;                // phases
+      const int passes = (ns + LP - 1) >> lg;
+      const int ti = lane >> (6 - lg), ph = lane & (nph - 1);
+      const int blk = P2P_UNROLL * nph;        // slots per unrolled block of all phases
+      // home sink of this lane: with one pass sink ti (summed at the end,
+      // written by phase 0), else sink ph * LP + ti
+      const int hs = passes > 1 ? ph * LP + ti : ti;
+      const bool hv = hs < ns && (passes > 1 || ph == 0);
+      const int gi = bA + tb + (hs < ns ? hs : 0);
+      R xh, yh, zh;
       if (MIXED) {
-        xi = (R)(t.sx[gi] - gA.x);
-        yi = (R)(t.sy[gi] - gA.y);
-        zi = (R)(t.sz[gi] - gA.z);
+        xh = (R)(t.sx[gi] - gA.x);
+        yh = (R)(t.sy[gi] - gA.y);
+        zh = (R)(t.sz[gi] - gA.z);
       } else {
-        xi = t.sx[gi];
-        yi = t.sy[gi];
-        zi = t.sz[gi];
+        xh = t.sx[gi];
+        yh = t.sy[gi];
+        zh = t.sz[gi];
       }
       double ax = 0, ay = 0, az = 0, pp = 0;
       for (int qb = 0; qb < cnt; qb += 64) {
@@ -458,37 +553,47 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          const int self_idx = self_start + i - w0;
-          for (int f0 = ph; f0 < Wr; f0 += blk) {
-            R sx = 0, sy = 0, sz = 0, sp = 0;
-            if (nph == 1)
-              p2p_block<R, R4, KERNEL, SELF, 1>(src, f0, 1, self_idx, xi, yi, zi, eps2, inv_eps,
-                                                inv_eps3, sx, sy, sz, sp);
-            else
-              p2p_block<R, R4, KERNEL, SELF, 0>(src, f0, nph, self_idx, xi, yi, zi, eps2, inv_eps,
-                                                inv_eps3, sx, sy, sz, sp);
-            ax += (double)sx;
-            ay += (double)sy;
-            az += (double)sz;
-            pp -= (double)sp;
+          if (passes == 1) {
+            p2p_window_any<R, R4, KERNEL, SELF>(nph, src, ph, Wr, self_start + tb + ti - w0, xh,
+                                                yh, zh, eps2, inv_eps, inv_eps3, ax, ay, az, pp);
+          } else {
+            for (int p = 0; p < passes; ++p) {
+              const int from = ti * nph + p;  // home lane of sink p * LP + ti
+              const R xi = __shfl(xh, from, 64), yi = __shfl(yh, from, 64),
+                      zi = __shfl(zh, from, 64);
+              double bx = 0, by = 0, bz = 0, bp = 0;
+              p2p_window_any<R, R4, KERNEL, SELF>(nph, src, ph, Wr,
+                                                  self_start + tb + p * LP + ti - w0, xi, yi, zi,
+                                                  eps2, inv_eps, inv_eps3, bx, by, bz, bp);
+              bx = group_sum(bx, nph);
+              by = group_sum(by, nph);
+              bz = group_sum(bz, nph);
+              bp = group_sum(bp, nph);
+              if (ph == p) {
+                ax += bx;
+                ay += by;
+                az += bz;
+                pp += bp;
+              }
+            }
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
       }
-      for (int o = LP; o < 64; o <<= 1) {
-        ax += __shfl_xor(ax, o, 64);
-        ay += __shfl_xor(ay, o, 64);
-        az += __shfl_xor(az, o, 64);
-        pp += __shfl_xor(pp, o, 64);
+      if (passes == 1) {
+        ax = group_sum(ax, nph);
+        ay = group_sum(ay, nph);
+        az = group_sum(az, nph);
+        pp = group_sum(pp, nph);
       }
       if (!SELF) {  // the self pair's potential term, as the loop computed it
         R mg0, t0;
         PairKernel<R, KERNEL>::eval(R(0), MIXED ? (R)t.sm32[gi] : (R)t.sm[gi], eps2, inv_eps,
                                     inv_eps3, mg0, t0);
-        if (ph == 0) pp += (double)t0;
+        pp += (double)t0;
       }
-      if (vi && ph == 0) {
+      if (hv) {
         t.near[gi] = ax;
         t.near[cap + gi] = ay;
         t.near[2 * cap + gi] = az;
