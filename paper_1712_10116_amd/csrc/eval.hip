@@ -61,55 +61,95 @@ __device__ __forceinline__ bool skipped(const DevTree &t, int node) {
   return t.reqs[t.nreq[node]].mass == nullptr;
 }
 
-// P2M at leaves: Mt[k] = sum_j m_j (u_j/h)^k/k!  (compensated in FP32)
+// Value of v in another lane of the same DPP row (CTRL: a DPP16 control).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each aligned group of 8 lanes, every lane of the group ending with
+// the same value: quad swaps (lane ^ 1, lane ^ 2), then the mirror within 8
+// lanes, which pairs a lane with one of the other quad.  The 8 lanes of the
+// group must be active.
+template <typename T>
+__device__ __forceinline__ T sum8(T v) {
+  v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f<0x141>(v);  // row_half_mirror
+  return v;
+}
+
+// The far-field cell kernels give each cell an aligned group of 8 lanes;
+// g8 = lane & 7 is the lane's place in it.  Branches on the cell are uniform
+// over the group, so its 8 lanes are active at every group sum.
+
+// P2M at leaves: Mt[k] = sum_j m_j (u_j/h)^k/k!, lane g8 summing particles
+// g8, g8 + 8, ... of the leaf (compensated in FP32, then the lanes' partial
+// sums and compensations added in FP64 and rounded once).
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes, bool harm) {
+__device__ __forceinline__ void p2m_cell8(const DevTree &t, int i, int g8, bool harm) {
   constexpr int K = MI<P>::K;
   T *M = (T *)t.M;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_nodes; i += gridDim.x * blockDim.x) {
-    if (t.nnchild[i] != 0 || skipped(t, i)) continue;
-    const double4 g = t.ngeo[i];
-    const double ih = 1.0 / g.w;
-    T acc[K], cmp[K];
+  if (t.nnchild[i] != 0 || skipped(t, i)) return;
+  const double4 g = t.ngeo[i];
+  const double ih = 1.0 / g.w;
+  T acc[K], cmp[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = cmp[k] = T(0);
-    for (int j = t.nbeg[i]; j < t.nend[i]; ++j) {
-      t.leaf_of[j] = i;
-      T mono[K];
-      monomials<T, P>((T)((t.sx[j] - g.x) * ih), (T)((t.sy[j] - g.y) * ih),
-                      (T)((t.sz[j] - g.z) * ih), mono);
-      const T m = (T)t.sm[j];
+  for (int k = 0; k < K; ++k) acc[k] = cmp[k] = T(0);
+  for (int j = t.nbeg[i] + g8; j < t.nend[i]; j += 8) {
+    t.leaf_of[j] = i;
+    T mono[K];
+    monomials<T, P>((T)((t.sx[j] - g.x) * ih), (T)((t.sy[j] - g.y) * ih),
+                    (T)((t.sz[j] - g.z) * ih), mono);
+    const T m = (T)t.sm[j];
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        if (sizeof(T) == 4) {  // Kahan-Babuska summation of the FP32 moments
-          T y = m * mono[k] - cmp[k];
-          T s = acc[k] + y;
-          cmp[k] = (s - acc[k]) - y;
-          acc[k] = s;
-        } else {
-          acc[k] = fma(m, mono[k], acc[k]);
-        }
+    for (int k = 0; k < K; ++k) {
+      if (sizeof(T) == 4) {  // Kahan-Babuska summation of the FP32 moments
+        T y = m * mono[k] - cmp[k];
+        T s = acc[k] + y;
+        cmp[k] = (s - acc[k]) - y;
+        acc[k] = s;
+      } else {
+        acc[k] = fma(m, mono[k], acc[k]);
       }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = (T)sum8<double>((double)acc[k] - (double)cmp[k]);
+  if (g8 == 0) {
     store_row<T, P>(M, t.kmax, i, acc);
     if (harm) store_folded<T, P>(t, i, acc);
   }
 }
 
-// M2M for the cells of one level that have children
 template <typename T, int P>
-__device__ __forceinline__ void m2m_cell(const DevTree &t, int i, bool harm) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes, bool harm) {
+  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+  if (i < n_nodes) p2m_cell8<T, P>(t, i, threadIdx.x & 7, harm);
+}
+
+// M2M for a cell with children, lane g8 shifting child g8 (if any); the
+// shifted children are summed over the group.
+template <typename T, int P>
+__device__ __forceinline__ void m2m_cell8(const DevTree &t, int i, int g8, bool harm) {
   constexpr int K = MI<P>::K;
   T *M = (T *)t.M;
-  int nc = t.nnchild[i];
+  const int nc = t.nnchild[i];
   if (nc == 0 || skipped(t, i)) return;
-  const double4 gp = t.ngeo[i];
-  const double ih = 1.0 / gp.w;
   T acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = T(0);
-  int c0 = t.nchild0[i];
-  for (int c = c0; c < c0 + nc; ++c) {
+  if (g8 < nc) {
+    const double4 gp = t.ngeo[i];
+    const double ih = 1.0 / gp.w;
+    const int c = t.nchild0[i] + g8;
     const double4 gc = t.ngeo[c];
     T q[K], Mc[K];
     monomials<T, P>((T)((gc.x - gp.x) * ih), (T)((gc.y - gp.y) * ih), (T)((gc.z - gp.z) * ih),
@@ -117,14 +157,18 @@ __device__ __forceinline__ void m2m_cell(const DevTree &t, int i, bool harm) {
     load_row<T, P>(M, t.kmax, c, Mc);
     m2m_shift<T, P>(Mc, (T)(gc.w * ih), q, acc);
   }
-  store_row<T, P>(M, t.kmax, i, acc);
-  if (harm) store_folded<T, P>(t, i, acc);
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = sum8<T>(acc[k]);
+  if (g8 == 0) {
+    store_row<T, P>(M, t.kmax, i, acc);
+    if (harm) store_folded<T, P>(t, i, acc);
+  }
 }
 
 template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e, bool harm) {
-  for (int i = s + blockIdx.x * blockDim.x + threadIdx.x; i < e; i += gridDim.x * blockDim.x)
-    m2m_cell<T, P>(t, i, harm);
+  const int i = s + ((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
+  if (i < e) m2m_cell8<T, P>(t, i, threadIdx.x & 7, harm);
 }
 
 // M2L: one wavefront per target cell A, lanes over A's list of sources B.
@@ -230,8 +274,9 @@ template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_m2m_small(DevTree t, int depth, bool harm) {
   const Header *h = t.hdr;
   for (int l = depth - 1; l >= 0; --l) {
-    for (int i = h->lvl_start[l] + threadIdx.x; i < h->lvl_start[l + 1]; i += blockDim.x)
-      m2m_cell<T, P>(t, i, harm);
+    for (int i = h->lvl_start[l] + (threadIdx.x >> 3); i < h->lvl_start[l + 1];
+         i += blockDim.x >> 3)
+      m2m_cell8<T, P>(t, i, threadIdx.x & 7, harm);
     __syncthreads();
   }
 }
@@ -420,25 +465,16 @@ __device__ __forceinline__ void p2p_window_any(int nph, const R4 *src, int ph, i
   }
 }
 
-// Value of v in another lane of the same DPP row (CTRL: a DPP16 control).
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Sum over each aligned group of nph consecutive lanes (nph = 1, 2, 4, 8, 16),
 // every lane of a group ending with the same value: quad swaps (lane ^ 1,
 // lane ^ 2), then the mirror within 8 and within 16 lanes, each pairing a lane
 // with one of the other half whose partial is already the other half's sum.
 // All lanes must be active.
 __device__ __forceinline__ double group_sum(double v, int nph) {
-  if (nph > 1) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
-  if (nph > 2) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
-  if (nph > 4) v += dpp_d<0x141>(v);  // row_half_mirror
-  if (nph > 8) v += dpp_d<0x140>(v);  // row_mirror
+  if (nph > 1) v += dpp_f<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (nph > 2) v += dpp_f<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (nph > 4) v += dpp_f<0x141>(v);  // row_half_mirror
+  if (nph > 8) v += dpp_f<0x140>(v);  // row_mirror
   return v;
 }
 
@@ -610,7 +646,6 @@ __global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, 
 template <typename T, int P, int KERNEL>
 static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   const int nn = e.n_nodes;
-  const int nb_nodes = (nn + FMM_BLOCK - 1) / FMM_BLOCK;
   PhaseTimer *tm = e.tm;
   const bool harm = KERNEL == 0;  // folded moments feed the harmonic M2L
   hipEventRecord(e.fork, s);
@@ -626,7 +661,9 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
                        t, nn, e.eps);
   if (tm) tm->end(tp, e.side);
   hipEventRecord(e.join, e.side);
-  hipLaunchKernelGGL((k_p2m<T, P>), dim3(nb_nodes), dim3(FMM_BLOCK), 0, s, t, nn, harm);
+  // far-field cell kernels: 8 lanes per cell
+  hipLaunchKernelGGL((k_p2m<T, P>), dim3((8 * nn + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
+                     s, t, nn, harm);
   const bool small = nn <= SMALL_NODES;
   if (small && e.depth > 0) {
     hipLaunchKernelGGL((k_m2m_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth, harm);
@@ -634,7 +671,7 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
     for (int l = e.depth - 1; l >= 0; --l) {
       int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
       if (le > ls)
-        hipLaunchKernelGGL((k_m2m<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
+        hipLaunchKernelGGL((k_m2m<T, P>), dim3((8 * (le - ls) + FMM_BLOCK - 1) / FMM_BLOCK),
                            dim3(FMM_BLOCK), 0, s, t, ls, le, harm);
     }
   }
