@@ -22,9 +22,10 @@
 #include "common.h"
 #include "hhs_kernels.h"
 
-#define SORT_WAVES 4
-#define SORT_ITEMS 16
-#define SORT_TILE (SORT_WAVES * 64 * SORT_ITEMS)
+#define SORT_TILE 4096                         // keys per radix tile (one histogram column)
+#define SORT_WAVES 16                          // wavefronts per tile
+#define SORT_ITEMS (SORT_TILE / (SORT_WAVES * 64))
+#define SORT_THREADS (SORT_WAVES * 64)
 #define SMALL_ITEMS 16
 
 // ---------------------------------------------------------------------------
@@ -198,21 +199,23 @@ __device__ __forceinline__ uint32_t sort_digit(const uint64_t *key, const int32_
                 : (uint32_t)(key[i] >> shift) & 255u;
 }
 
-__global__ __launch_bounds__(FMM_BLOCK) void k_sort_hist(const uint64_t *__restrict__ key,
-                                                         const int32_t *__restrict__ slot,
-                                                         const int32_t *__restrict__ slot_req,
-                                                         int n, int shift, int by_req,
-                                                         uint32_t *__restrict__ hist, int nblk) {
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__restrict__ key,
+                                                            const int32_t *__restrict__ slot,
+                                                            const int32_t *__restrict__ slot_req,
+                                                            int n, int shift, int by_req,
+                                                            uint32_t *__restrict__ hist,
+                                                            int nblk) {
   __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
+  if (threadIdx.x < 256) h[threadIdx.x] = 0;
   __syncthreads();
-  int base = blockIdx.x * SORT_TILE;
-  for (int e = threadIdx.x; e < SORT_TILE; e += FMM_BLOCK) {
-    int i = base + e;
+  const int base = blockIdx.x * SORT_TILE;
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const int i = base + it * SORT_THREADS + threadIdx.x;
     if (i < n) atomicAdd(&h[sort_digit(key, slot, slot_req, i, shift, by_req)], 1u);
   }
   __syncthreads();
-  hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < 256) hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
 // Per-digit exclusive scan over the blocks: hist[d][0..nblk) in place, digit
@@ -302,79 +305,115 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_scan_down(uint32_t *v, int m, con
   }
 }
 
-__global__ __launch_bounds__(FMM_BLOCK) void k_sort_scatter(
+// Exclusive scan of one value per thread over threads 0..255 of a block
+// (the others pass 0 and get 0); every thread of the block must call it.
+__device__ __forceinline__ uint32_t scan256(uint32_t v, uint32_t *wsum) {
+  const int w = threadIdx.x >> 6;
+  uint32_t ex = 0;
+  if (threadIdx.x < 256) {
+    int tot;
+    ex = (uint32_t)wave_excl_scan_int((int)v, &tot);
+    if ((threadIdx.x & 63) == 0) wsum[w] = (uint32_t)tot;
+  }
+  __syncthreads();
+  if (threadIdx.x < 256)
+    for (int ww = 0; ww < w; ++ww) ex += wsum[ww];
+  __syncthreads();
+  return ex;
+}
+
+// One radix pass over a tile of SORT_TILE keys: every key's rank among the
+// tile's keys of its digit (8 ballots per 64 keys, waves in index order, so
+// the pass is stable), the tile reordered by digit in LDS, then written out
+// in tile order so that consecutive threads store consecutive addresses of a
+// digit's run.
+__global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const int32_t *__restrict__ sin, uint64_t *__restrict__ kout,
     int32_t *__restrict__ sout, const int32_t *__restrict__ slot_req, int n, int shift, int by_req,
     const uint32_t *__restrict__ hist, int nblk, const uint32_t *__restrict__ dtot) {
-  __shared__ uint32_t cnt[SORT_WAVES][256];
-  __shared__ uint32_t goff[256];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int d = threadIdx.x; d < SORT_WAVES * 256; d += FMM_BLOCK) (&cnt[0][0])[d] = 0;
-  // digit base = exclusive scan of the digit totals
-  {
-    uint32_t x = dtot[threadIdx.x];
-    goff[threadIdx.x] = x;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-      uint32_t y = threadIdx.x >= off ? goff[threadIdx.x - off] : 0u;
-      __syncthreads();
-      goff[threadIdx.x] += y;
-      __syncthreads();
-    }
-    uint32_t base = goff[threadIdx.x] - x;
-    __syncthreads();
-    goff[threadIdx.x] = base + hist[threadIdx.x * nblk + blockIdx.x];
-  }
-  __syncthreads();
-  const int base = blockIdx.x * SORT_TILE + w * 64 * SORT_ITEMS;
+  // keys | slots | digits of the reordered tile; the per-wave digit counters
+  // of the ranking step live in the front of the same space before that
+  __shared__ __align__(16) unsigned char smem[SORT_TILE * 13];
+  __shared__ uint32_t lstart[256], gbase[256], wsum[SORT_WAVES];
+  uint64_t *skey = (uint64_t *)smem;
+  int32_t *sslot = (int32_t *)(smem + 8 * SORT_TILE);
+  uint8_t *sdig = smem + 12 * SORT_TILE;
+  uint32_t(*cnt)[256] = (uint32_t(*)[256])smem;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  for (int d = tid; d < SORT_WAVES * 256; d += SORT_THREADS) (&cnt[0][0])[d] = 0;
+  // global start of each digit: exclusive scan of the digit totals, plus the
+  // counts of the earlier tiles
+  const uint32_t dbase = scan256(tid < 256 ? dtot[tid] : 0u, wsum);
+  const int tile = blockIdx.x * SORT_TILE;
+  const int base = tile + w * 64 * SORT_ITEMS;
   uint64_t k[SORT_ITEMS];
   int32_t sv[SORT_ITEMS];
-  uint32_t rank[SORT_ITEMS];
+  uint32_t dg[SORT_ITEMS], rank[SORT_ITEMS];
   const unsigned long long below = lanes_below_mask();
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
-    int i = base + it * 64 + lane;
-    bool valid = i < n;
+    const int i = base + it * 64 + lane;
+    const bool valid = i < n;
     k[it] = valid ? kin[i] : 0;
     sv[it] = valid ? sin[i] : 0;
-    uint32_t d = by_req ? ((uint32_t)slot_req[sv[it]] >> shift) & 255u
-                        : (uint32_t)(k[it] >> shift) & 255u;
+  }
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    const int i = base + it * 64 + lane;
+    const bool valid = i < n;
+    const uint32_t d = by_req ? (valid ? ((uint32_t)slot_req[sv[it]] >> shift) & 255u : 0u)
+                              : (uint32_t)(k[it] >> shift) & 255u;
+    dg[it] = d;
     unsigned long long m = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      unsigned long long bal = __ballot((d >> b) & 1u);
+      const unsigned long long bal = __ballot((d >> b) & 1u);
       m &= ((d >> b) & 1u) ? bal : ~bal;
     }
-    uint32_t prior = cnt[w][d];
+    const uint32_t prior = cnt[w][d];
     rank[it] = prior + (uint32_t)__popcll(m & below);
     __builtin_amdgcn_wave_barrier();
     if (valid && (m & below) == 0) cnt[w][d] = prior + (uint32_t)__popcll(m);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // per-digit offsets of the earlier waves of this block
-  uint32_t woff[SORT_WAVES];
-  {
-    uint32_t run = 0;
+  // per digit: offsets of the waves inside the tile (in place), tile count
+  uint32_t tcount = 0;
+  if (tid < 256) {
 #pragma unroll
     for (int ww = 0; ww < SORT_WAVES; ++ww) {
-      woff[ww] = run;
-      run += cnt[ww][threadIdx.x];
+      const uint32_t c = cnt[ww][tid];
+      cnt[ww][tid] = tcount;
+      tcount += c;
+    }
+  }
+  const uint32_t ls = scan256(tcount, wsum);
+  if (tid < 256) {
+    lstart[tid] = ls;
+    gbase[tid] = dbase + hist[tid * nblk + blockIdx.x] - ls;
+  }
+  __syncthreads();
+  int lpos[SORT_ITEMS];
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) lpos[it] = (int)(lstart[dg[it]] + cnt[w][dg[it]] + rank[it]);
+  __syncthreads();  // the counters are overwritten below
+#pragma unroll
+  for (int it = 0; it < SORT_ITEMS; ++it) {
+    if (base + it * 64 + lane < n) {
+      skey[lpos[it]] = k[it];
+      sslot[lpos[it]] = sv[it];
+      sdig[lpos[it]] = (uint8_t)dg[it];
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int ww = 0; ww < SORT_WAVES; ++ww) cnt[ww][threadIdx.x] = woff[ww] + goff[threadIdx.x];
-  __syncthreads();
+  const int tn = min(SORT_TILE, n - tile);
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
-    int i = base + it * 64 + lane;
-    if (i < n) {
-      uint32_t d = by_req ? ((uint32_t)slot_req[sv[it]] >> shift) & 255u
-                          : (uint32_t)(k[it] >> shift) & 255u;
-      uint32_t dst = cnt[w][d] + rank[it];
-      kout[dst] = k[it];
-      sout[dst] = sv[it];
+    const int j = it * SORT_THREADS + tid;
+    if (j < tn) {
+      const uint32_t dst = gbase[sdig[j]] + (uint32_t)j;
+      kout[dst] = skey[j];
+      sout[dst] = sslot[j];
     }
   }
 }
@@ -851,11 +890,11 @@ hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
     for (int pass = 0; pass < 8 + req_passes; ++pass) {
       const int by_req = pass >= 8;
       const int shift = by_req ? (pass - 8) * 8 : pass * 8;
-      hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, sin, t.slot_req, n,
+      hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, sin, t.slot_req, n,
                          shift, by_req, t.sort_hist, nblk);
       hipLaunchKernelGGL(k_sort_digit_scan, dim3(256), dim3(FMM_BLOCK), 0, s, t.sort_hist, nblk,
                          t.sort_dtot);
-      hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(FMM_BLOCK), 0, s, kin, sin, kout, sout,
+      hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, sin, kout, sout,
                          t.slot_req, n, shift, by_req, t.sort_hist, nblk, t.sort_dtot);
       uint64_t *tk = kin; kin = kout; kout = tk;
       int32_t *ts = sin; sin = sout; sout = ts;
