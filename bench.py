@@ -87,21 +87,33 @@ def force_error(acc, ref):
 
 
 def time_solver(F, torch, s, tp, tm, acc, pot, prm, steps, warmup, profile):
+    """Seconds per solve over `steps` timed solves.  With `profile`: HIP events
+    around the M2L and P2P kernels inside the timed region (their launch
+    durations, for the roofline), and the per-phase event times of a further
+    `steps` solves outside it (events between every phase lengthen a solve).
+    Returns (seconds, phases summed over the profiled solves, kernel times
+    summed over the timed solves)."""
     for _ in range(warmup):
         s.forces(tp, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], acc=acc, pot=pot)
     torch.cuda.synchronize()
     if profile:
-        s.profile(True)
+        s.profile(True, kernels_only=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         s.forces(tp, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], acc=acc, pot=pot)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    phases = s.profile_read() if profile else None
+    phases = kern = None
     if profile:
+        kern = s.profile_read()
+        s.profile(True)
+        for _ in range(steps):
+            s.forces(tp, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], acc=acc, pot=pot)
+        torch.cuda.synchronize()
+        phases = s.profile_read()
         s.profile(False)
-    return (t1 - t0) / steps, phases
+    return (t1 - t0) / steps, phases, kern
 
 
 def cpu_leg(args, n, pos, mass, res, prm, line):
@@ -237,7 +249,7 @@ def configs_leg(args, F, torch, line):
         acc = torch.empty((3, n), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev)
         pr = dict(p=prm["p"], theta=prm["theta"], eps=prm["eps"])
-        sec, _ = time_solver(F, torch, s, tp, tm, acc, pot, pr, 5, 1, profile=False)
+        sec, _, _ = time_solver(F, torch, s, tp, tm, acc, pot, pr, 5, 1, profile=False)
         inv = s.invariants(mass=tm, acc=acc)
         a = acc.cpu().numpy()
         s.close()
@@ -484,11 +496,11 @@ def main():
                      precision=prec)
         acc = torch.empty((3, n), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev)
-        sec, phases = time_solver(F, torch, s, tp, tm, acc, pot, pr, args.steps, args.warmup,
-                                  profile=True)
+        sec, phases, kt = time_solver(F, torch, s, tp, tm, acc, pot, pr, args.steps,
+                                      args.warmup, profile=True)
         info = s.tree_info()
         inv = s.invariants(mass=tm, acc=acc)
-        res[name] = dict(sec=sec, phases=phases, info=info, acc=acc.cpu().numpy(), prm=pr,
+        res[name] = dict(sec=sec, phases=phases, kt=kt, info=info, acc=acc.cpu().numpy(), prm=pr,
                          momentum=float(np.abs(inv["F"]).max() / inv["Fabs"]))
         s.close()
         del acc, pot
@@ -509,10 +521,12 @@ def main():
     ph = mixed["phases"]
     info = mixed["info"]
     steps = args.steps
-    # dominant evaluation kernel and its algorithmic work per launch
+    # dominant evaluation kernel and its algorithmic work per launch; launch
+    # durations from the events around the two kernels in the timed region
     kern = {}
-    p2p_ms = ph["p2p"][0] / max(ph["p2p"][1], 1)
-    m2l_ms = ph["m2l"][0] / max(ph["m2l"][1], 1)
+    kt = mixed["kt"]
+    p2p_ms = kt["p2p"][0] / max(kt["p2p"][1], 1)
+    m2l_ms = kt["m2l"][0] / max(kt["m2l"][1], 1)
     p2p_flops = P2P_FLOPS_PER_PAIR * info["p2p_interactions"] / 2.0
     m2l_flops = m2l_flops_per_pair(prm["p"]) * info["m2l"]
     kern["p2p"] = dict(ms=p2p_ms, flops=p2p_flops, tflops=p2p_flops / (p2p_ms * 1e-3) / 1e12)

@@ -180,8 +180,9 @@ fmm_status fmm_invariants(fmm_ctx *ctx, const double *pos, const double *vel, co
                           const double *acc, const double *pot, int64_t n, double out[12]);
 
 /* Per-phase timing with HIP events recorded on the context's stream between
- * launch groups (nothing else changes).  enable != 0 starts recording and
- * clears the totals; 0 stops. */
+ * launch groups (nothing else changes).  enable = 1 starts recording every
+ * phase, enable = 2 only the M2L and P2P kernels (one event pair each per
+ * evaluation, on the stream each runs on); both clear the totals; 0 stops. */
 fmm_status fmm_profile_enable(fmm_ctx *ctx, int enable);
 
 /* Totals since enabling: ms[k] milliseconds and calls[k] timed launch groups

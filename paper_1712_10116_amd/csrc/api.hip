@@ -635,6 +635,7 @@ extern "C" fmm_status fmm_profile_enable(fmm_ctx *c, int enable) {
   }
   if (tm.on) tm.flush();
   tm.on = enable != 0;
+  tm.mask = enable == 2 ? (1u << PH_M2L | 1u << PH_P2P) : ~0u;
   tm.n = 0;
   for (int k = 0; k < PH_N; ++k) {
     tm.ms[k] = 0.0;

@@ -172,6 +172,7 @@ struct PhaseTimer {
   static const int CAP = 512;
   bool on = false;
   bool ready = false;
+  unsigned mask = ~0u;  // phases recorded (bit p for phase p)
   hipEvent_t a[CAP], b[CAP];
   int ph[CAP];
   int n = 0, cur = -1;
@@ -179,7 +180,7 @@ struct PhaseTimer {
   long long cnt[PH_N] = {0};
   // an interval of phase p on stream s (intervals on different streams may overlap)
   int begin(int p, hipStream_t s) {
-    if (!on) return -1;
+    if (!on || !(mask >> p & 1u)) return -1;
     if (n == CAP) flush();
     hipEventRecord(a[n], s);
     ph[n] = p;

@@ -284,9 +284,11 @@ class Solver:
             "box")]))
         return out
 
-    def profile(self, enable=True):
-        """Start (clearing totals) or stop per-phase HIP-event timing."""
-        self._raise(lib().fmm_profile_enable(self._h, int(bool(enable))))
+    def profile(self, enable=True, kernels_only=False):
+        """Start (clearing totals) or stop per-phase HIP-event timing; with
+        kernels_only only the M2L and P2P kernels are timed."""
+        mode = (2 if kernels_only else 1) if enable else 0
+        self._raise(lib().fmm_profile_enable(self._h, mode))
 
     def profile_read(self):
         """{phase: (milliseconds, timed launch groups)} since profile(True)."""
