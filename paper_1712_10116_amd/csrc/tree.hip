@@ -584,12 +584,36 @@ __device__ __forceinline__ int emit_node(const DevTree &t, int i, int l, int nc,
   return leaves;
 }
 
+// count_node with its searches spread over an aligned group of 8 lanes: lane
+// o finds the first particle of octant >= o in the whole key range of the
+// cell (its keys are sorted by octant, so this is the bound the sequential
+// search finds), and the group counts the non-empty octants.  Same bounds
+// and count as count_node.
+__device__ __forceinline__ int count_node8(const DevTree &t, int i, int l, int leaf_size, int o) {
+  const int shift = 3 * (FMM_MAXLEVEL - (l + 1));
+  const int b = t.nbeg[i], en = t.nend[i];
+  int nc = 0;
+  if (en - b > leaf_size && l < FMM_MAXLEVEL) {
+    const int bd = o == 0 ? b : lower_bound_digit(t.key, b, en, shift, (uint32_t)o);
+    t.bounds[(int64_t)i * 8 + o] = bd;
+    const int nx = __shfl_down(bd, 1, 8);  // lane o + 1's bound (o = 7: its own)
+    const bool nonempty = o < 7 ? nx > bd : en > bd;
+    const unsigned long long m = __ballot(nonempty);
+    nc = __popcll((m >> (__lane_id() & 56)) & 0xFFull);
+  }
+  if (o == 0) t.nnchild[i] = nc;
+  return nc;
+}
+
 __global__ __launch_bounds__(FMM_BLOCK) void k_tree_count(DevTree t, int l, int leaf_size) {
   int s, e;
   level_chunk(t.hdr, l, s, e);
+  const int o = threadIdx.x & 7;
   int sum = 0;
-  for (int i = s + threadIdx.x; i < e && i < t.cap_nodes; i += blockDim.x)
-    sum += count_node(t, i, l, leaf_size);
+  for (int i = s + (threadIdx.x >> 3); i < e && i < t.cap_nodes; i += blockDim.x >> 3) {
+    const int nc = count_node8(t, i, l, leaf_size, o);
+    if (o == 0) sum += nc;
+  }
   __shared__ int red[FMM_BLOCK];
   red[threadIdx.x] = sum;
   __syncthreads();

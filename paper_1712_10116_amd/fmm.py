@@ -211,8 +211,22 @@ class Solver:
         return acc, pot
 
     def forces(self, pos, mass, active=None, *, eps, theta, p, acc=None, pot=None):
-        self.build(pos, active, eps=eps, theta=theta)
-        return self.evaluate(pos, mass, active, p=p, acc=acc, pot=pot)
+        """Build and evaluate in one call (fmm_forces)."""
+        n_total = pos.shape[1]
+        _check_dev(pos, torch.float64, (3, n_total), "pos")
+        n = n_total if active is None else active.shape[0]
+        if active is not None:
+            _check_dev(active, torch.int32, None, "active")
+        _check_dev(mass, torch.float64, (n_total,), "mass")
+        if acc is None:
+            acc = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        if pot is None:
+            pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        _check_dev(acc, torch.float64, (3, n), "acc")
+        _check_dev(pot, torch.float64, (n,), "pot")
+        self._raise(lib().fmm_forces(self._h, _ptr(pos), _ptr(mass), n_total, _ptr(active), n,
+                                     float(eps), float(theta), int(p), _ptr(acc), _ptr(pot)))
+        return acc, pot
 
     def _requests(self, systems, with_outputs):
         arr = (Request * len(systems))()
