@@ -162,6 +162,15 @@ fmm_status fmm_tree_info(fmm_ctx *ctx, int64_t info[9]);
  * and tests).  On by default. */
 fmm_status fmm_set_small_path(fmm_ctx *ctx, int enable);
 
+/* Multi-workgroup builds queue the tree and the walk for the deepest split
+ * level of the last four builds on this context, behind the sort, and read
+ * the tree header once at the end (instead of after the split-depth search,
+ * after the tree and after the walk); a build whose tree needs more levels,
+ * or whose workspace overflows, is redone the classic way.  Trees, lists and
+ * forces are the same either way.  enable = 0 always takes the classic
+ * sequence; on by default; either call forgets the recorded levels. */
+fmm_status fmm_set_level_prediction(fmm_ctx *ctx, int enable);
+
 /* Canonical host copy of the current tree, for comparison with other
  * implementations: nodes in pre-order (sorted by (begin, level)); perm[i] =
  * active slot of the i-th particle in Morton order; pairs as (a <= b) over

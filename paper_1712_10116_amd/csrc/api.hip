@@ -129,6 +129,8 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   c->prm = *prm;
   c->max_n = max_n;
   c->small_path = true;
+  c->predict_levels = true;
+  c->lvl_hist_n = 0;
   c->stream = (hipStream_t)stream;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
@@ -211,6 +213,25 @@ extern "C" fmm_status fmm_set_small_path(fmm_ctx *c, int enable) {
   if (!c) return FMM_EINVAL;
   c->small_path = enable != 0;
   return FMM_OK;
+}
+
+extern "C" fmm_status fmm_set_level_prediction(fmm_ctx *c, int enable) {
+  if (!c) return FMM_EINVAL;
+  c->predict_levels = enable != 0;
+  c->lvl_hist_n = 0;
+  return FMM_OK;
+}
+
+// split levels of the recent builds (0: none recorded)
+static int predicted_levels(const fmm_ctx *c) {
+  int m = 0;
+  for (int i = 0; i < std::min(c->lvl_hist_n, fmm_ctx::LEVEL_HIST); ++i) m = std::max(m, c->lvl_hist[i]);
+  return m;
+}
+
+static void record_levels(fmm_ctx *c, int levels) {
+  c->lvl_hist[c->lvl_hist_n % fmm_ctx::LEVEL_HIST] = levels;
+  c->lvl_hist_n++;
 }
 
 static fmm_status check_requests(fmm_ctx *c, int n_req, const fmm_request *reqs, bool eval,
@@ -366,7 +387,27 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
     if (c->hh.overflow & OVF_STACK) return fail(c, FMM_EOVERFLOW, "walk descent stack overflow");
     if (!(c->hh.overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN))) return finish(tree_depth());
   }
+  // 1a. split levels predicted from recent builds: tree and walk queued behind
+  // the sort, one readback.  The tree equals the one built below whenever the
+  // prediction covers the split depth (levels past it split nothing); if it
+  // does not, or a workspace overflowed, the classic sequence runs.
+  const int pred = c->predict_levels ? predicted_levels(c) : 0;
+  if (pred > 0) {
+    HIPCHK(c, launch_sort(c->t, a, c->stream));
+    HIPCHK(c, launch_build_tree(c->t, a, pred, c->stream));
+    HIPCHK(c, launch_traverse_dev(c->t, a, pred, c->stream));
+    st = read_header(c);
+    if (st != FMM_OK) return st;
+    if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
+    const int need = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
+    if (need <= pred &&
+        !(c->hh.overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN | OVF_STACK))) {
+      record_levels(c, need);
+      return finish(tree_depth());
+    }
+  }
   // 1. tree; one readback of the level sizes (exact launches for the walk)
+  int max_level = 0;
   for (int attempt = 0;; ++attempt) {
     if (attempt == 4) return fail(c, FMM_EOVERFLOW, "node workspace still too small");
     HIPCHK(c, launch_sort(c->t, a, c->stream));
@@ -374,7 +415,7 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
     if (st != FMM_OK) return st;
     if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
     // no cell below level split_depth + 1 holds more than leaf_size particles
-    const int max_level = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
+    max_level = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
     if (!(c->hh.overflow & OVF_NODES)) {
       HIPCHK(c, launch_build_tree(c->t, a, max_level, c->stream));
       st = read_header(c);
@@ -417,6 +458,7 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
       }
       continue;
     }
+    record_levels(c, max_level);
     return finish(depth);
   }
   return fail(c, FMM_EOVERFLOW, "list workspace still too small after regrowth");

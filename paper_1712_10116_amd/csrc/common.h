@@ -228,6 +228,8 @@ hipError_t launch_build_small(const DevTree &t, const BuildArgs &a, hipStream_t 
 hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, int max_level, hipStream_t s);
 // traverse.hip
 hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s);
+// levels 0..levels, level bounds read on the device (tree sizes not yet known)
+hipError_t launch_traverse_dev(const DevTree &t, const BuildArgs &a, int levels, hipStream_t s);
 // all walk levels in one workgroup, level sizes read on the device
 hipError_t launch_traverse_small(const DevTree &t, const BuildArgs &a, hipStream_t s);
 hipError_t launch_reset_lists(const DevTree &t, hipStream_t s);

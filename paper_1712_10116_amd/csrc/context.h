@@ -36,6 +36,14 @@ struct fmm_ctx {
   Header *pin_hdr;                  // pinned destination of header readbacks
   int n_nodes, depth;
   bool small_path;         // single-workgroup build and walk for small batches
+  // split levels of recent multi-workgroup builds: the next build queues the
+  // tree and the walk for the deepest of them behind the sort, with one
+  // readback at the end, and falls back to reading the split depth first when
+  // its tree needed more levels
+  static constexpr int LEVEL_HIST = 4;
+  int lvl_hist[LEVEL_HIST];
+  int lvl_hist_n;
+  bool predict_levels;
   // integrator
   hhs_run *own_run;       // scratch of hhs_init / hhs_step (one system)
   int32_t *split_cnt;     // [cap_split] fast-set sizes of pending splits

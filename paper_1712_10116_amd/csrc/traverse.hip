@@ -22,6 +22,8 @@
 // Sec. 2.3, written in IEEE double without contraction:
 //   d2 = (dx*dx + dy*dy) + dz*dz,  S = hA + hB,
 //   d2*(theta*theta) > S*S  and  d2 > (eps + sqrt(3)*S)^2.
+#include <algorithm>
+
 #include "common.h"
 
 #define TRAV_WAVES 4
@@ -310,6 +312,22 @@ __global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level(DevTree t, int l
   walk_parent(t, l, P, th2, eps, lds[w]);
 }
 
+// Level l with its bounds read from the tree header (queued before the
+// level sizes are known on the host): the waves of the grid stride over the
+// parents; nothing is done on a tree whose node workspace overflowed.
+__global__ __launch_bounds__(TRAV_WAVES * 64) void k_walk_level_dev(DevTree t, int l, double th2,
+                                                                    double eps) {
+  __shared__ WaveLds lds[TRAV_WAVES];
+  const Header *h = t.hdr;
+  if (h->overflow & OVF_NODES) return;
+  const int ps = l == 0 ? 0 : h->lvl_start[l - 1];
+  const int pe = l == 0 ? t.n_req : h->lvl_start[l];
+  const int w = threadIdx.x >> 6;
+  const int nw = gridDim.x * TRAV_WAVES;
+  for (int P = ps + xcd_block<32>(blockIdx.x, gridDim.x) * TRAV_WAVES + w; P < pe; P += nw)
+    walk_parent(t, l, P, th2, eps, lds[w]);
+}
+
 // All levels of the walk in one workgroup (small trees): the waves share the
 // parents of a level, and a barrier separates levels (a level reads the open
 // lists the previous one wrote).  Level sizes come from the tree header.
@@ -365,6 +383,21 @@ hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s) 
     hipLaunchKernelGGL(k_walk_level, dim3((nw + TRAV_WAVES - 1) / TRAV_WAVES),
                        dim3(TRAV_WAVES * 64), 0, s, t, l, ps, pe, th2, a.eps);
   }
+  if (a.tm) a.tm->stop(s);
+  return hipGetLastError();
+}
+
+// Levels 0..levels with the bounds of each read on the device (see
+// k_walk_level_dev); the grid fills the chip for large trees.
+hipError_t launch_traverse_dev(const DevTree &t, const BuildArgs &a, int levels, hipStream_t s) {
+  launch_reset_lists(t, s);
+  if (a.n <= 0) return hipGetLastError();
+  const double th2 = a.theta * a.theta;
+  const int blocks = std::min(2048, std::max(16, a.n / 512));
+  if (a.tm) a.tm->start(PH_WALK, s);
+  for (int l = 0; l <= levels && l <= FMM_MAXLEVEL; ++l)
+    hipLaunchKernelGGL(k_walk_level_dev, dim3(blocks), dim3(TRAV_WAVES * 64), 0, s, t, l, th2,
+                       a.eps);
   if (a.tm) a.tm->stop(s);
   return hipGetLastError();
 }

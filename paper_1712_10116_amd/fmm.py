@@ -25,7 +25,7 @@ EXPORTED = (
     "fmm_forces_batched", "hhs_run_bytes", "hhs_run_create", "hhs_run_destroy",
     "hhs_init_batched", "hhs_step_batched", "serve_footprint", "serve_create", "serve_destroy",
     "serve_submit", "serve_step", "serve_poll", "serve_cancel", "serve_info",
-    "fmm_set_small_path",
+    "fmm_set_small_path", "fmm_set_level_prediction",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -106,6 +106,7 @@ def lib():
         L.fmm_evaluate_batched.argtypes = [vp, ci, ctypes.POINTER(Request), ci]
         L.fmm_forces_batched.argtypes = [vp, ci, ctypes.POINTER(Request), dbl, dbl, ci]
         L.fmm_set_small_path.argtypes = [vp, ci]
+        L.fmm_set_level_prediction.argtypes = [vp, ci]
         L.fmm_profile_enable.argtypes = [vp, ci]
         L.fmm_profile_read.argtypes = [vp, vp, vp]
         L.hhs_run_bytes.argtypes = [i64, ci]
@@ -273,6 +274,12 @@ class Solver:
         """Single-workgroup build and walk for batches of at most 8192 particles
         (on by default; off forces the multi-workgroup path)."""
         self._raise(lib().fmm_set_small_path(self._h, int(bool(enable))))
+
+    def set_level_prediction(self, enable):
+        """Queue tree and walk for the split depth of recent builds, one header
+        readback (on by default; off reads the split depth first).  Same trees,
+        lists and results either way."""
+        self._raise(lib().fmm_set_level_prediction(self._h, int(bool(enable))))
 
     def tree_info(self):
         import numpy as np

@@ -257,3 +257,38 @@ def test_small_and_general_paths_identical(label, precision):
     for k in e1:
         np.testing.assert_array_equal(e1[k], e2[k], err_msg=k)
     assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+
+
+def test_level_prediction_identical():
+    """Builds that queue tree and walk for the split depth of recent builds
+    (one readback) give the same trees, lists and forces as the classic
+    sequence: first build (no history), a deeper system after a shallow one
+    (prediction too shallow: redone), a shallow one after a deep one (extra
+    empty levels), and a repeat."""
+    torch, F = _torch(), _F()
+    seq = [W.uniform_sphere(30000, seed=41), W.plummer(30000, seed=42),
+           W.uniform_sphere(20000, seed=43), W.uniform_sphere(20000, seed=43)]
+    kw = dict(p_max=4, leaf_size=16, kernel=F.WENDLAND, precision=1)
+    pred = F.Solver(30000, **kw)
+    for k, (pos, _, m) in enumerate(seq):
+        tp = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+        tm = torch.from_numpy(np.ascontiguousarray(m)).cuda()
+        out = []
+        for s in (pred, None):
+            own = s is None
+            if own:
+                s = F.Solver(30000, **kw)
+                s.set_level_prediction(False)
+            s.build(tp, eps=0.01, theta=0.5)
+            ex = s.export_tree()
+            a, pt = s.evaluate(tp, tm, p=4)
+            torch.cuda.synchronize()
+            out.append((ex, a.cpu().numpy(), pt.cpu().numpy(), s.tree_info()))
+            if own:
+                s.close()
+        (e1, a1, p1, i1), (e2, a2, p2, i2) = out
+        assert i1 == i2, k
+        for key in e1:
+            np.testing.assert_array_equal(e1[key], e2[key], err_msg=f"{k} {key}")
+        assert np.array_equal(a1, a2) and np.array_equal(p1, p2), k
+    pred.close()
