@@ -473,8 +473,8 @@ def main():
         progress("autotuner")
         t0 = time.perf_counter()
         tr = autotune.tune(tp, tm, eps=eps, kernel=F.WENDLAND, precision=F.MIXED,
-                           target=args.target, leaf_sizes=(16, 24, 32, 48, 64, 96),
-                           orders=(4, 5, 6), thetas=(0.4, 0.45, 0.5), reps=3)
+                           target=args.target, leaf_sizes=(24, 32, 48, 64, 96, 128),
+                           orders=(4, 5, 6), thetas=(0.4, 0.45, 0.5, 0.55, 0.6), reps=3)
         b = tr["best"]
         prm = dict(p=b["p"], theta=b["theta"], eps=eps, leaf_size=b["leaf_size"])
         ok = sorted((r for r in tr["table"] if r["ms"] is not None), key=lambda r: r["ms"])

@@ -391,12 +391,55 @@ struct P2PTypes<false> {
   __device__ static R4 far() { return make_double4(1e150, 1e150, 1e150, 0.0); }
 };
 
-// One block of UNROLL sources of one phase (stride NPH between them).
+// One block of UNROLL sources of one phase (stride NPH between them).  For
+// the Wendland kernel a block in which no pair of the whole wavefront lies
+// inside the kernel radius (the common case: such pairs are a tiny fraction)
+// takes the -1/r form without a per-pair test; otherwise every pair goes
+// through PairKernel, whose outside branch is the same expressions, so the
+// sums are the same either way.
 template <typename R, typename R4, int KERNEL, bool SELF, int NPH>
 __device__ __forceinline__ void p2p_block(const R4 *src, int f0, int self_idx, R xi, R yi, R zi,
                                           R eps2, R inv_eps, R inv_eps3, R &sx, R &sy, R &sz,
                                           R &sp) {
-  R4 svs[P2P_UNROLL];  // the block's sources, read before any use
+  if (KERNEL == 0) {
+    R dx[P2P_UNROLL], dy[P2P_UNROLL], dz[P2P_UNROLL], r2[P2P_UNROLL], mj[P2P_UNROLL];
+    {
+      R4 svs[P2P_UNROLL];  // the block's sources, read before any use
+#pragma unroll
+      for (int u = 0; u < P2P_UNROLL; ++u) svs[u] = src[f0 + u * NPH];
+#pragma unroll
+      for (int u = 0; u < P2P_UNROLL; ++u) {
+        dx[u] = svs[u].x - xi;
+        dy[u] = svs[u].y - yi;
+        dz[u] = svs[u].z - zi;
+        r2[u] = fma(dx[u], dx[u], fma(dy[u], dy[u], dz[u] * dz[u]));
+        mj[u] = svs[u].w;
+        if (SELF) {
+          const bool self = f0 + u * NPH == self_idx;
+          r2[u] = self ? R(1) : r2[u];
+          mj[u] = self ? R(0) : mj[u];
+        }
+      }
+    }
+    R rmin = r2[0];
+#pragma unroll
+    for (int u = 1; u < P2P_UNROLL; ++u) rmin = fmin(rmin, r2[u]);
+    if (__ballot(rmin < eps2) == 0ull) {
+#pragma unroll
+      for (int u = 0; u < P2P_UNROLL; ++u) {
+        const R rinv = fast_rsqrt<R>(r2[u]);
+        const R t = mj[u] * rinv;
+        const R mg = t * (rinv * rinv);
+        sx = fma(mg, dx[u], sx);
+        sy = fma(mg, dy[u], sy);
+        sz = fma(mg, dz[u], sz);
+        sp += t;
+      }
+      return;
+    }
+  }
+  // every pair through PairKernel (the block's sources read again)
+  R4 svs[P2P_UNROLL];
 #pragma unroll
   for (int u = 0; u < P2P_UNROLL; ++u) svs[u] = src[f0 + u * NPH];
 #pragma unroll
@@ -501,7 +544,7 @@ __device__ __forceinline__ int p2p_lanes_log2(int ns) {
 // zero (dx = 0) -- and its potential term, reproduced bit for bit, is taken
 // off once per sink.
 template <bool MIXED, int KERNEL, bool SELF>
-__global__ __launch_bounds__(P2P_WAVES * 64) void k_p2p(DevTree t, int n_nodes, double eps) {
+__global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t, int n_nodes, double eps) {
   typedef typename P2PTypes<MIXED>::R R;
   typedef typename P2PTypes<MIXED>::R4 R4;
   constexpr int SRC = P2PTypes<MIXED>::SRC;
