@@ -158,7 +158,7 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
             dalloc(c, &t.sz, n) && dalloc(c, &t.sm, n) && dalloc(c, &t.sm32, n) &&
             dalloc(c, &t.leaf_of, n) && dalloc(c, &t.near, 4 * n) &&
             dalloc(c, &t.scan_part, FMM_SCAN_BLOCKS) && dalloc(c, &t.slot_req, n) &&
-            dalloc(c, &t.sort_hist, 256 * ((n + 4095) / 4096) + 256) &&
+            dalloc(c, &t.sort_hist, 256 * ((n + SORT_TILE - 1) / SORT_TILE) + 256) &&
             dalloc(c, &t.sort_dtot, 256) && dalloc(c, &t.scan_blk, n / 1024 + 64) &&
             dalloc(c, &t.hdr, 1) && alloc_reqs(c, 16) && alloc_nodes(c, cap_nodes);
   if (ok) {

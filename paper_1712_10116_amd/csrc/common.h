@@ -21,6 +21,7 @@
 #define FMM_BLOCK 256
 #define FMM_SCAN_BLOCKS 256
 #define FMM_BBOX_BLOCKS 256  // box-reduction blocks per request, at most
+#define SORT_TILE 4096       // keys per radix-sort tile (one histogram column)
 // single-workgroup ("small") build, walk and level passes
 #define SMALL_WAVES 8
 #define SMALL_THREADS (SMALL_WAVES * 64)
@@ -112,6 +113,20 @@ struct DevTree {
 // ---------------------------------------------------------------------------
 // wavefront helpers (wave64)
 // ---------------------------------------------------------------------------
+// largest r in [0, m) with off[r] <= x (request of a slot, or of a sorted
+// position: both lie in the request's [off[r], off[r + 1]))
+__device__ __forceinline__ int upper_index(const int32_t *off, int m, int x) {
+  int lo = 0, hi = m - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ unsigned long long lanes_below_mask() {

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_gather_mass(DevTree t, int n) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int s = t.slot[j];
-  const DevReq q = t.reqs[t.slot_req[s]];
+  const DevReq q = t.reqs[upper_index(t.req_off, t.n_req, j)];
   if (!q.mass) return;  // system skipped in this evaluation
   const int i = s - q.off;
   int64_t g = q.active ? q.active[i] : i;
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n) {
   T phi, gx, gy, gz;
   l2p_eval<T, P>(Lt, mono, phi, gx, gy, gz);
   const int s = t.slot[j];
-  const DevReq q = t.reqs[t.slot_req[s]];
+  const DevReq q = t.reqs[upper_index(t.req_off, t.n_req, j)];
   const int64_t i = s - q.off, nq = q.n;
   const int64_t cap = t.cap_n;
   q.acc[i] = t.near[j] - (double)gx * ih;

@@ -22,8 +22,7 @@
 #include "common.h"
 #include "hhs_kernels.h"
 
-#define SORT_TILE 4096                         // keys per radix tile (one histogram column)
-#define SORT_WAVES 16                          // wavefronts per tile
+#define SORT_WAVES 16                          // wavefronts per radix tile
 #define SORT_ITEMS (SORT_TILE / (SORT_WAVES * 64))
 #define SORT_THREADS (SORT_WAVES * 64)
 #define SMALL_ITEMS 16
@@ -31,18 +30,6 @@
 // ---------------------------------------------------------------------------
 // request of every slot (binary search in the request offsets)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int upper_index(const int32_t *off, int m, int x) {
-  // largest r in [0, m) with off[r] <= x
-  int lo = 0, hi = m - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= x)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
 
 // request of every active slot; also clears the header counters that the
 // following kernels accumulate into (non-finite flag, leaf count)
@@ -450,9 +437,12 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_split_depth(DevTree t, int n, int
 // ---------------------------------------------------------------------------
 // sorted particle data
 // ---------------------------------------------------------------------------
+// Sorted position j of request r lies in [req_off[r], req_off[r + 1]) as
+// its active slot did (the sort orders by request first), so the request
+// comes from the offsets rather than a random read of slot_req.
 __device__ __forceinline__ void gather_at(const DevTree &t, int j) {
   const int s = t.slot[j];
-  const DevReq q = t.reqs[t.slot_req[s]];
+  const DevReq q = t.reqs[upper_index(t.req_off, t.n_req, j)];
   const int i = s - q.off;
   int64_t g = q.active ? q.active[i] : i;
   t.sx[j] = q.pos[g];
