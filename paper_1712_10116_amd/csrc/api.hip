@@ -351,7 +351,7 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
   int n_blk = 0;
   st = upload_requests(c, n_req, reqs, &n_blk);
   if (st != FMM_OK) return st;
-  BuildArgs a;
+  BuildArgs a = {};
   a.n = (int)n_all;
   a.n_req = n_req;
   a.n_blk = n_blk;
