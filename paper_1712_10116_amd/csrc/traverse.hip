@@ -73,6 +73,8 @@ struct WaveLds {
   int dcand[TRAV_CAND];  // children of popped descent items
   int stack[TRAV_STACK]; // descent items: (target tag << TRAV_TAG) | cell
   double4 geo[8];
+  int sid[8];            // target cells and their leaf flags, for per-lane lookup
+  int sleaf[8];
 };
 
 template <bool WRITE>
@@ -145,13 +147,16 @@ __device__ void drain(const DevTree &t, Sibs &S, WaveLds &L, int &sp, int *open_
         nC = t.nnchild[C];
         npC = t.nend[C] - t.nbeg[C];
       }
+      // each lane's item belongs to one target: classify once against it
+      const int lcat = valid ? classify(L.sid[tgl], L.geo[tgl], L.sleaf[tgl] != 0, C, gC,
+                                        nC == 0, th2, eps)
+                             : CAT_NONE;
 #pragma unroll
       for (int tg = 0; tg < 8; ++tg) {
         if (tg < S.n) {
           const bool mine = valid && tgl == tg;
-          const int cat = mine ? classify(S.id[tg], L.geo[tg], S.leaf[tg], C, gC, nC == 0, th2,
-                                          eps)
-                               : CAT_NONE;
+          if (__ballot(mine) == 0ull) continue;  // no item of this target in the chunk
+          const int cat = mine ? lcat : CAT_NONE;
           emit<WRITE>(t, S, tg, cat, mine, C, npC, open_out, pairs);
           push_item(t, L, sp, cat == CAT_DEEPEN, tg, C);
         }
@@ -253,10 +258,16 @@ __device__ void walk_parent(const DevTree &t, int l, int P, double th2, double e
   }
   if (lane < 8) {
     int A = S.id[0];
+    bool lf = S.leaf[0];
 #pragma unroll
     for (int tg = 1; tg < 8; ++tg)
-      if (lane == tg) A = S.id[tg];
+      if (lane == tg) {
+        A = S.id[tg];
+        lf = S.leaf[tg];
+      }
     L.geo[lane] = t.ngeo[A];
+    L.sid[lane] = A;
+    L.sleaf[lane] = lf ? 1 : 0;
   }
   __builtin_amdgcn_wave_barrier();
   const int *open_in = (l & 1) ? t.open_buf0 : t.open_buf1;
