@@ -86,6 +86,37 @@ __device__ __forceinline__ T sum8(T v) {
   return v;
 }
 
+// Value of v from the lane a row-broadcast DPP control names (0x142: lane 15
+// of each row into the next row; 0x143: lane 31 into rows 2 and 3), in the
+// rows of ROWS; 0 in the other rows.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the whole wavefront, valid in lane 63: each row of 16 lanes is
+// summed with DPP (quad swaps, mirror within 8, mirror within 16), then row 1
+// adds row 0 and row 3 adds row 2 (lane 15 / 47 broadcast), and row 3 adds
+// rows 0 + 1 (lane 31 broadcast).  No LDS traffic.  All 64 lanes must be
+// active.
+template <typename T>
+__device__ __forceinline__ T wave_total_last(T v) {
+  v += dpp_f<0xB1>(v);
+  v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
+  v += dpp_bcast<0x142, 0xA>(v);
+  v += dpp_bcast<0x143, 0xC>(v);
+  return v;
+}
+
 // The far-field cell kernels give each cell an aligned group of 8 lanes;
 // g8 = lane & 7 is the lane's place in it.  Branches on the cell are uniform
 // over the group, so its 8 lanes are active at every group sum.
@@ -239,9 +270,9 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, doubl
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (!HARM || mi.z[k] <= 1) acc[k] = wave_sum(acc[k]) * (T)ih;
+      if (!HARM || mi.z[k] <= 1) acc[k] = wave_total_last(acc[k]) * (T)ih;
     if (HARM) unfold_locals<T, P>(acc);
-    if (lane == 0) store_row<T, P>(L, t.kmax, A, acc);
+    if (lane == 63) store_row<T, P>(L, t.kmax, A, acc);
   }
 }
 
