@@ -141,7 +141,8 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   bool pins = hipHostMalloc((void **)&c->pin_hdr, sizeof(Header)) == hipSuccess &&
               hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->hdr_ev, hipEventDisableTiming) == hipSuccess;
   for (int k = 0; pins && k < fmm_ctx::UP_SLOTS; ++k)
     pins = hipEventCreateWithFlags(&c->up_ev[k], hipEventDisableTiming) == hipSuccess;
   if (!pins) {
@@ -203,6 +204,7 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
   }
   if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->join) (void)hipEventDestroy(c->join);
+  if (c->hdr_ev) (void)hipEventDestroy(c->hdr_ev);
   delete c;
   return FMM_OK;
 }
@@ -340,10 +342,34 @@ static fmm_status regrow_lists(fmm_ctx *c, int which, int64_t need) {
   return FMM_OK;
 }
 
-extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request *reqs,
-                                        double eps, double theta) {
+static void set_eval_args(fmm_ctx *c, EvalArgs &e, int64_t n_all, int p, double eps) {
+  e.n = (int)n_all;
+  e.p = p;
+  e.kernel = c->prm.kernel;
+  e.mixed = c->prm.precision == FMM_PREC_MIXED;
+  e.eps = eps;
+  e.tm = timer_of(c);
+  e.side = c->side;
+  e.fork = c->fork;
+  e.join = c->join;
+}
+
+static void count_evaluation(fmm_ctx *c, int n_req, const fmm_request *reqs) {
+  c->stat_calls++;
+  for (int r = 0; r < n_req; ++r)
+    if (reqs[r].mass) c->stat_parts += reqs[r].n_active;
+}
+
+// Build (and, with p_fused > 0, evaluate at order p_fused): when the
+// predicted sequence runs, the evaluation is queued behind the walk before the
+// host reads the tree header, with the tree's sizes taken on the device; if
+// the header then shows that the prediction fell short or a workspace
+// overflowed, the build is redone the classic way and *evaluated stays false
+// (the caller evaluates again, overwriting whatever the queued kernels wrote).
+static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, double eps,
+                             double theta, int p_fused, bool *evaluated) {
   int64_t n_all = 0;
-  fmm_status st = check_requests(c, n_req, reqs, false, &n_all);
+  fmm_status st = check_requests(c, n_req, reqs, p_fused > 0, &n_all);
   if (st != FMM_OK) return st;
   if (!(theta > 0.0) || !(eps >= 0.0) || !std::isfinite(theta) || !std::isfinite(eps))
     return fail(c, FMM_EINVAL, "need theta > 0 and eps >= 0");
@@ -393,17 +419,37 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
   // does not, or a workspace overflowed, the classic sequence runs.
   const int pred = c->predict_levels ? predicted_levels(c) : 0;
   if (pred > 0) {
+    int32_t prev[FMM_NLEVELS + 2];  // level starts of the last tree: grid estimates
+    memcpy(prev, c->hh.lvl_start, sizeof(prev));
+    const int prev_nodes = c->n_nodes;
     HIPCHK(c, launch_sort(c->t, a, c->stream));
     HIPCHK(c, launch_build_tree(c->t, a, pred, c->stream));
     HIPCHK(c, launch_traverse_dev(c->t, a, pred, c->stream));
-    st = read_header(c);
-    if (st != FMM_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(c->pin_hdr, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipEventRecord(c->hdr_ev, c->stream));
+    if (p_fused > 0) {
+      EvalArgs e = {};
+      set_eval_args(c, e, n_all, p_fused, eps);
+      e.n_nodes = std::max(prev_nodes, 1);
+      e.lvl_start_host = prev;
+      e.depth = pred;
+      e.dev = true;
+      HIPCHK(c, launch_evaluate(c->t, e, c->stream));
+    }
+    HIPCHK(c, hipEventSynchronize(c->hdr_ev));
+    memcpy(&c->hh, c->pin_hdr, sizeof(Header));
     if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
     const int need = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
     if (need <= pred &&
         !(c->hh.overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN | OVF_STACK))) {
       record_levels(c, need);
-      return finish(tree_depth());
+      st = finish(tree_depth());
+      if (st == FMM_OK && p_fused > 0) {
+        count_evaluation(c, n_req, reqs);
+        *evaluated = true;
+      }
+      return st;
     }
   }
   // 1. tree; one readback of the level sizes (exact launches for the walk)
@@ -464,6 +510,11 @@ extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request
   return fail(c, FMM_EOVERFLOW, "list workspace still too small after regrowth");
 }
 
+extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request *reqs,
+                                        double eps, double theta) {
+  return build_impl(c, n_req, reqs, eps, theta, 0, nullptr);
+}
+
 extern "C" fmm_status fmm_evaluate_batched(fmm_ctx *c, int n_req, const fmm_request *reqs, int p) {
   int64_t n_all = 0;
   fmm_status st = check_requests(c, n_req, reqs, true, &n_all);
@@ -479,23 +530,13 @@ extern "C" fmm_status fmm_evaluate_batched(fmm_ctx *c, int n_req, const fmm_requ
     return fail(c, FMM_EINVAL, "order p=%d unsupported (1..%d)", p, std::min(c->prm.p_max, 6));
   st = upload_requests(c, n_req, reqs, nullptr);
   if (st != FMM_OK) return st;
-  EvalArgs e;
-  e.n = (int)n_all;
+  EvalArgs e = {};
+  set_eval_args(c, e, n_all, p, c->b_eps);
   e.n_nodes = c->n_nodes;
-  e.p = p;
-  e.kernel = c->prm.kernel;
-  e.mixed = c->prm.precision == FMM_PREC_MIXED;
-  e.eps = c->b_eps;
   e.lvl_start_host = c->hh.lvl_start;
   e.depth = c->depth;
-  e.tm = timer_of(c);
-  e.side = c->side;
-  e.fork = c->fork;
-  e.join = c->join;
   HIPCHK(c, launch_evaluate(c->t, e, c->stream));
-  c->stat_calls++;
-  for (int r = 0; r < n_req; ++r)
-    if (reqs[r].mass) c->stat_parts += reqs[r].n_active;
+  count_evaluation(c, n_req, reqs);
   return FMM_OK;
 }
 
@@ -503,8 +544,9 @@ extern "C" fmm_status fmm_forces_batched(fmm_ctx *c, int n_req, const fmm_reques
                                          double eps, double theta, int p) {
   if (c && (p < 1 || p > c->prm.p_max || !eval_order_supported(p)))
     return fail(c, FMM_EINVAL, "order p=%d unsupported", p);
-  fmm_status st = fmm_build_batched(c, n_req, reqs, eps, theta);
-  if (st != FMM_OK) return st;
+  bool evaluated = false;
+  fmm_status st = build_impl(c, n_req, reqs, eps, theta, p, &evaluated);
+  if (st != FMM_OK || evaluated) return st;
   return fmm_evaluate_batched(c, n_req, reqs, p);
 }
 

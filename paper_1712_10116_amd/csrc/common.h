@@ -261,6 +261,10 @@ struct EvalArgs {
   const int32_t *lvl_start_host;  // host copy, FMM_NLEVELS+1 entries
   int depth;
   PhaseTimer *tm;
+  // queued before the host read the tree header: n_nodes, lvl_start_host and
+  // depth are estimates (grid sizes, loop bounds) and the kernels take the
+  // tree's sizes from the header
+  bool dev;
 };
 hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s);
 bool eval_order_supported(int p);

@@ -34,6 +34,7 @@ struct fmm_ctx {
   std::vector<char> up_last;
   bool up_valid;
   Header *pin_hdr;                  // pinned destination of header readbacks
+  hipEvent_t hdr_ev;                // recorded after a queued header readback
   int n_nodes, depth;
   bool small_path;         // single-workgroup build and walk for small batches
   // split levels of recent multi-workgroup builds: the next build queues the

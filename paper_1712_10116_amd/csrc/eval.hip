@@ -61,6 +61,31 @@ __device__ __forceinline__ bool skipped(const DevTree &t, int node) {
   return t.reqs[t.nreq[node]].mass == nullptr;
 }
 
+// Node range of an evaluation.  n >= 0: the host's count.  n < 0: queued
+// before the host read the tree header (the tree is checked afterwards and
+// the evaluation redone if it fails): the count comes from the header, and
+// nothing is evaluated on a tree or lists whose build overflowed a
+// workspace (node arrays, list buffers or descent stack).
+__device__ __forceinline__ bool tree_incomplete(const DevTree &t) {
+  return (t.hdr->overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN | OVF_STACK)) != 0;
+}
+__device__ __forceinline__ int node_count(const DevTree &t, int n) {
+  if (n >= 0) return n;
+  return tree_incomplete(t) ? 0 : min(t.hdr->lvl_start[FMM_NLEVELS], (int)t.cap_nodes);
+}
+// cells of one level: [s, e) from the host, or s = -1 - l for level l read
+// from the header as above
+__device__ __forceinline__ void level_range(const DevTree &t, int &s, int &e) {
+  if (s >= 0) return;
+  const int l = -1 - s;
+  if (tree_incomplete(t)) {
+    s = e = 0;
+    return;
+  }
+  s = t.hdr->lvl_start[l];
+  e = t.hdr->lvl_start[l + 1];
+}
+
 // Value of v in another lane of the same DPP row (CTRL: a DPP16 control).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
@@ -162,8 +187,10 @@ __device__ __forceinline__ void p2m_cell8(const DevTree &t, int i, int g8, bool 
 
 template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes, bool harm) {
-  const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-  if (i < n_nodes) p2m_cell8<T, P>(t, i, threadIdx.x & 7, harm);
+  n_nodes = node_count(t, n_nodes);
+  const int stride = (gridDim.x * blockDim.x) >> 3;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < n_nodes; i += stride)
+    p2m_cell8<T, P>(t, i, threadIdx.x & 7, harm);
 }
 
 // M2M for a cell with children, lane g8 shifting child g8 (if any); the
@@ -198,8 +225,10 @@ __device__ __forceinline__ void m2m_cell8(const DevTree &t, int i, int g8, bool 
 
 template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_m2m(DevTree t, int s, int e, bool harm) {
-  const int i = s + ((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
-  if (i < e) m2m_cell8<T, P>(t, i, threadIdx.x & 7, harm);
+  level_range(t, s, e);
+  const int stride = (gridDim.x * blockDim.x) >> 3;
+  for (int i = s + ((blockIdx.x * blockDim.x + threadIdx.x) >> 3); i < e; i += stride)
+    m2m_cell8<T, P>(t, i, threadIdx.x & 7, harm);
 }
 
 // M2L: one wavefront per target cell A, lanes over A's list of sources B.
@@ -221,6 +250,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, doubl
   const int lane = threadIdx.x & 63;
   const int wave = (xcd_block<32>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  n_nodes = node_count(t, n_nodes);
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (skipped(t, A)) continue;
     const double4 gA = t.ngeo[A];
@@ -295,6 +325,7 @@ __device__ __forceinline__ void l2l_cell(const DevTree &t, int c) {
 
 template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_l2l(DevTree t, int s, int e) {
+  level_range(t, s, e);
   for (int c = s + blockIdx.x * blockDim.x + threadIdx.x; c < e; c += gridDim.x * blockDim.x)
     l2l_cell<T, P>(t, c);
 }
@@ -304,6 +335,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2l(DevTree t, int s, int e) {
 template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_m2m_small(DevTree t, int depth, bool harm) {
   const Header *h = t.hdr;
+  if (tree_incomplete(t)) return;
   for (int l = depth - 1; l >= 0; --l) {
     for (int i = h->lvl_start[l] + (threadIdx.x >> 3); i < h->lvl_start[l + 1];
          i += blockDim.x >> 3)
@@ -315,6 +347,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2m_small(DevTree t, int depth, b
 template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_l2l_small(DevTree t, int depth) {
   const Header *h = t.hdr;
+  if (tree_incomplete(t)) return;
   for (int l = 1; l <= depth; ++l) {
     for (int c = h->lvl_start[l] + threadIdx.x; c < h->lvl_start[l + 1]; c += blockDim.x)
       l2l_cell<T, P>(t, c);
@@ -324,13 +357,16 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2l_small(DevTree t, int depth) {
 
 // L2P + near field + un-permute: one thread per Morton-sorted particle
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, bool dev) {
   constexpr int K = MI<P>::K;
   const T *L = (const T *)t.L;
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  if (dev && tree_incomplete(t)) return;  // leaf_of not written by this build
+  // the system first: leaf_of is written only for systems this evaluation covers
+  const DevReq q = t.reqs[upper_index(t.req_off, t.n_req, j)];
+  if (!q.mass) return;
   const int leaf = t.leaf_of[j];
-  if (skipped(t, leaf)) return;
   const double4 g = t.ngeo[leaf];
   const double ih = 1.0 / g.w;
   T mono[K], Lt[K];
@@ -340,7 +376,6 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n) {
   T phi, gx, gy, gz;
   l2p_eval<T, P>(Lt, mono, phi, gx, gy, gz);
   const int s = t.slot[j];
-  const DevReq q = t.reqs[upper_index(t.req_off, t.n_req, j)];
   const int64_t i = s - q.off, nq = q.n;
   const int64_t cap = t.cap_n;
   q.acc[i] = t.near[j] - (double)gx * ih;
@@ -592,6 +627,7 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
   const R inv_eps = eps > 0 ? (R)(1.0 / eps) : R(0);
   const R inv_eps3 = eps > 0 ? (R)(1.0 / (eps * eps * eps)) : R(0);
   const int64_t cap = t.cap_n;
+  n_nodes = node_count(t, n_nodes);
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (t.nnchild[A] != 0 || skipped(t, A)) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
@@ -719,7 +755,9 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
 // which waits for it (second event) before L2P adds the near field.
 template <typename T, int P, int KERNEL>
 static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
-  const int nn = e.n_nodes;
+  const int nn = e.n_nodes;  // exact, or (e.dev) an estimate that sets grid sizes
+  const int ga = e.dev ? nn + nn / 4 + 64 : nn;
+  const int narg = e.dev ? -1 : nn;  // -1: node count read on the device
   PhaseTimer *tm = e.tm;
   const bool harm = KERNEL == 0;  // folded moments feed the harmonic M2L
   hipEventRecord(e.fork, s);
@@ -727,34 +765,49 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   const int tp = tm ? tm->begin(PH_P2P, e.side) : -1;
   if (e.eps > 0)
     hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL, false>),
-                       dim3((nn + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, e.side,
-                       t, nn, e.eps);
+                       dim3((ga + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, e.side,
+                       t, narg, e.eps);
   else
     hipLaunchKernelGGL((k_p2p<(sizeof(T) == 4), KERNEL, true>),
-                       dim3((nn + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, e.side,
-                       t, nn, e.eps);
+                       dim3((ga + P2P_WAVES - 1) / P2P_WAVES), dim3(P2P_WAVES * 64), 0, e.side,
+                       t, narg, e.eps);
   if (tm) tm->end(tp, e.side);
   hipEventRecord(e.join, e.side);
   // far-field cell kernels: 8 lanes per cell
-  hipLaunchKernelGGL((k_p2m<T, P>), dim3((8 * nn + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
-                     s, t, nn, harm);
+  hipLaunchKernelGGL((k_p2m<T, P>), dim3((8 * ga + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
+                     s, t, narg, harm);
+  // cells of level l for a launch: exact, or (e.dev) an estimated grid and
+  // bounds read on the device
+  auto level = [&](int l, int per_cell, int &blocks, int &a0, int &a1) {
+    const int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
+    const int cnt = le - ls;
+    if (!e.dev) {
+      blocks = cnt > 0 ? (per_cell * cnt + FMM_BLOCK - 1) / FMM_BLOCK : 0;
+      a0 = ls;
+      a1 = le;
+    } else {
+      blocks = (per_cell * (cnt + cnt / 4 + 32) + FMM_BLOCK - 1) / FMM_BLOCK;
+      a0 = -1 - l;
+      a1 = 0;
+    }
+  };
   const bool small = nn <= SMALL_NODES;
   if (small && e.depth > 0) {
     hipLaunchKernelGGL((k_m2m_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth, harm);
   } else {
     for (int l = e.depth - 1; l >= 0; --l) {
-      int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
-      if (le > ls)
-        hipLaunchKernelGGL((k_m2m<T, P>), dim3((8 * (le - ls) + FMM_BLOCK - 1) / FMM_BLOCK),
-                           dim3(FMM_BLOCK), 0, s, t, ls, le, harm);
+      int blocks, a0, a1;
+      level(l, 8, blocks, a0, a1);
+      if (blocks > 0)
+        hipLaunchKernelGGL((k_m2m<T, P>), dim3(blocks), dim3(FMM_BLOCK), 0, s, t, a0, a1, harm);
     }
   }
-  const int wave_blocks = (nn + 3) / 4;
+  const int wave_blocks = (ga + 3) / 4;
   if (tm) {
     tm->stop(s);
     tm->start(PH_M2L, s);
   }
-  hipLaunchKernelGGL((k_m2l<T, P, KERNEL>), dim3(wave_blocks), dim3(FMM_BLOCK), 0, s, t, nn,
+  hipLaunchKernelGGL((k_m2l<T, P, KERNEL>), dim3(wave_blocks), dim3(FMM_BLOCK), 0, s, t, narg,
                      e.eps);
   if (tm) {
     tm->stop(s);
@@ -764,15 +817,15 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
     hipLaunchKernelGGL((k_l2l_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth);
   } else {
     for (int l = 1; l <= e.depth; ++l) {
-      int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
-      if (le > ls)
-        hipLaunchKernelGGL((k_l2l<T, P>), dim3((le - ls + FMM_BLOCK - 1) / FMM_BLOCK),
-                           dim3(FMM_BLOCK), 0, s, t, ls, le);
+      int blocks, a0, a1;
+      level(l, 1, blocks, a0, a1);
+      if (blocks > 0)
+        hipLaunchKernelGGL((k_l2l<T, P>), dim3(blocks), dim3(FMM_BLOCK), 0, s, t, a0, a1);
     }
   }
   hipStreamWaitEvent(s, e.join, 0);
   hipLaunchKernelGGL((k_l2p<T, P>), dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
-                     s, t, e.n);
+                     s, t, e.n, e.dev);
   if (tm) tm->stop(s);
 }
 

@@ -282,16 +282,20 @@ __device__ void walk_parent(const DevTree &t, int l, int P, double th2, double e
 #pragma unroll
       for (int k = 0; k < 3; ++k) mine[k] = S.cnt[tg][k];
   int o[3] = {0, 0, 0};
-  bool ovf = false;
+  int bits = 0;
   if (lane < S.n) {
     o[0] = (int)atomicAdd(&h->m2l_cursor, (unsigned)mine[0]);
     o[1] = (int)atomicAdd(&h->p2p_cursor, (unsigned)mine[1]);
     o[2] = (int)atomicAdd(&h->open_cursor[l], (unsigned)mine[2]);
-    int bits = 0;
     if ((int64_t)o[0] + mine[0] > t.cap_m2l) bits |= OVF_M2L;
     if ((int64_t)o[1] + mine[1] > t.cap_p2p) bits |= OVF_P2P;
     if ((int64_t)o[2] + mine[2] > t.cap_open) bits |= OVF_OPEN;
-    ovf = bits != 0;
+  }
+  // if any target's lists do not fit, the wavefront writes none of them and
+  // every one of its targets gets empty lists: no count ever covers entries
+  // that were not written (the host regrows and rebuilds)
+  const bool ovf = __ballot(bits != 0) != 0ull;
+  if (lane < S.n) {
     int A = S.id[0];
 #pragma unroll
     for (int tg = 1; tg < 8; ++tg)
@@ -302,9 +306,9 @@ __device__ void walk_parent(const DevTree &t, int l, int P, double th2, double e
     t.p2p_cnt[A] = ovf ? 0 : mine[1];
     t.open_off[A] = o[2];
     t.open_cnt[A] = ovf ? 0 : mine[2];
-    if (ovf) atomicOr(&h->overflow, bits);
+    if (bits) atomicOr(&h->overflow, bits);
   }
-  if (__ballot(ovf) != 0ull) return;  // lists incomplete; the host regrows and rebuilds
+  if (ovf) return;
 #pragma unroll
   for (int tg = 0; tg < 8; ++tg)
 #pragma unroll

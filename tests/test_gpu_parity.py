@@ -292,3 +292,32 @@ def test_level_prediction_identical():
             np.testing.assert_array_equal(e1[key], e2[key], err_msg=f"{k} {key}")
         assert np.array_equal(a1, a2) and np.array_equal(p1, p2), k
     pred.close()
+
+
+def test_fused_forces_identical():
+    """forces() on a context with recent builds queues the evaluation behind
+    the walk before the tree header is read; the result equals a classic
+    build + evaluate bit for bit, also when the tree needs more levels than
+    predicted, when the lists outgrow their workspace (theta lowered) and on
+    a repeat."""
+    torch, F = _torch(), _F()
+    seq = [(W.uniform_sphere(30000, seed=51), 0.5), (W.uniform_sphere(30000, seed=52), 0.5),
+           (W.plummer(30000, seed=53), 0.5), (W.plummer(30000, seed=53), 0.25),
+           (W.plummer(30000, seed=53), 0.25)]
+    for precision in (0, 1):
+        kw = dict(p_max=4, leaf_size=16, kernel=F.WENDLAND, precision=precision)
+        fused = F.Solver(30000, **kw)
+        for k, ((pos, _, m), theta) in enumerate(seq):
+            tp = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+            tm = torch.from_numpy(np.ascontiguousarray(m)).cuda()
+            a1, p1 = fused.forces(tp, tm, eps=0.01, theta=theta, p=4)
+            i1 = fused.tree_info()
+            ref = F.Solver(30000, **kw)
+            ref.set_level_prediction(False)
+            ref.build(tp, eps=0.01, theta=theta)
+            a2, p2 = ref.evaluate(tp, tm, p=4)
+            torch.cuda.synchronize()
+            assert i1 == ref.tree_info(), (precision, k)
+            assert torch.equal(a1, a2) and torch.equal(p1, p2), (precision, k)
+            ref.close()
+        fused.close()
