@@ -156,19 +156,24 @@ fmm_status fmm_forces_batched(fmm_ctx *ctx, int n_req, const fmm_request *reqs, 
  * particle-particle interactions evaluated by P2P. */
 fmm_status fmm_tree_info(fmm_ctx *ctx, int64_t info[9]);
 
-/* Builds of at most 8192 active particles (all systems of a batch together)
- * run as two single-workgroup launches with one readback; enable = 0 forces
- * the multi-workgroup path (same trees, lists and results; for comparison
- * and tests).  On by default. */
+/* Builds of few active particles (all systems of a batch together) run as
+ * two single-workgroup launches with one readback: enable = 1 (the default)
+ * up to 1024 particles, beyond which the multi-workgroup path is faster;
+ * enable = 2 up to 8192, the most those launches hold; enable = 0 never.
+ * Trees, lists and results are the same either way (for comparison and
+ * tests).  Other values: FMM_EINVAL. */
 fmm_status fmm_set_small_path(fmm_ctx *ctx, int enable);
 
-/* Multi-workgroup builds queue the tree and the walk for the deepest split
- * level of the last four builds on this context, behind the sort, and read
- * the tree header once at the end (instead of after the split-depth search,
- * after the tree and after the walk); a build whose tree needs more levels,
- * or whose workspace overflows, is redone the classic way.  Trees, lists and
- * forces are the same either way.  enable = 0 always takes the classic
- * sequence; on by default; either call forgets the recorded levels. */
+/* enable = 1: multi-workgroup builds queue the tree and the walk for the
+ * deepest split level of the last four builds on this context, behind the
+ * sort, and read the tree header once at the end (instead of after the
+ * split-depth search, after the tree and after the walk); fmm_forces also
+ * queues the evaluation before that read when the batch holds the same
+ * systems as the last build within a quarter of its size.  A build whose
+ * tree needs more levels, or whose workspace overflows, is redone the
+ * classic way (and re-evaluated).  Trees, lists and forces are the same
+ * either way.  enable = 0 (the default): the classic sequence.  Either call
+ * forgets the recorded levels. */
 fmm_status fmm_set_level_prediction(fmm_ctx *ctx, int enable);
 
 /* Canonical host copy of the current tree, for comparison with other

@@ -128,8 +128,8 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   if (!c) return FMM_ENOMEM;
   c->prm = *prm;
   c->max_n = max_n;
-  c->small_path = true;
-  c->predict_levels = true;
+  c->small_max = SMALL_AUTO_N;
+  c->predict_levels = false;
   c->lvl_hist_n = 0;
   c->stream = (hipStream_t)stream;
   if (hipGetDevice(&c->device) != hipSuccess) {
@@ -212,8 +212,8 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
 extern "C" const char *fmm_last_error(const fmm_ctx *c) { return c ? c->err : "null context"; }
 
 extern "C" fmm_status fmm_set_small_path(fmm_ctx *c, int enable) {
-  if (!c) return FMM_EINVAL;
-  c->small_path = enable != 0;
+  if (!c || enable < 0 || enable > 2) return FMM_EINVAL;
+  c->small_max = enable == 0 ? -1 : enable == 1 ? SMALL_AUTO_N : SMALL_N;
   return FMM_OK;
 }
 
@@ -404,7 +404,7 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
   };
   // 0. small batches: build and walk in two single-workgroup launches and one
   // readback; anything that needs more room falls through to the general path
-  if (n_all <= SMALL_N && c->small_path) {
+  if (n_all <= c->small_max) {
     HIPCHK(c, launch_build_small(c->t, a, c->stream));
     HIPCHK(c, launch_traverse_small(c->t, a, c->stream));
     st = read_header(c);
@@ -428,7 +428,11 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
     HIPCHK(c, hipMemcpyAsync(c->pin_hdr, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost,
                              c->stream));
     HIPCHK(c, hipEventRecord(c->hdr_ev, c->stream));
-    if (p_fused > 0) {
+    // the evaluation's grids come from the last tree: only for a batch of
+    // the same systems within a quarter of its size
+    const bool fuse = p_fused > 0 && n_req == (int)c->b_reqs.size() && 4 * n_all >= 3 * c->b_n &&
+                      4 * n_all <= 5 * c->b_n;
+    if (fuse) {
       EvalArgs e = {};
       set_eval_args(c, e, n_all, p_fused, eps);
       e.n_nodes = std::max(prev_nodes, 1);
@@ -445,7 +449,7 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
         !(c->hh.overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN | OVF_STACK))) {
       record_levels(c, need);
       st = finish(tree_depth());
-      if (st == FMM_OK && p_fused > 0) {
+      if (st == FMM_OK && fuse) {
         count_evaluation(c, n_req, reqs);
         *evaluated = true;
       }

@@ -26,6 +26,8 @@
 #define SMALL_WAVES 8
 #define SMALL_THREADS (SMALL_WAVES * 64)
 #define SMALL_N (SMALL_THREADS * 16)  // active particles of a batch, at most
+#define SMALL_AUTO_N 1024             // the small path's default reach (beyond it the
+                                      // multi-workgroup path is faster)
 #define SMALL_NODES 2048              // cells of a tree whose M2M / L2L levels run in one workgroup
 
 // error bits latched in Header::overflow

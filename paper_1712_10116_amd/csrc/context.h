@@ -36,7 +36,7 @@ struct fmm_ctx {
   Header *pin_hdr;                  // pinned destination of header readbacks
   hipEvent_t hdr_ev;                // recorded after a queued header readback
   int n_nodes, depth;
-  bool small_path;         // single-workgroup build and walk for small batches
+  int small_max;           // single-workgroup build and walk for batches of at most this many particles
   // split levels of recent multi-workgroup builds: the next build queues the
   // tree and the walk for the deepest of them behind the sort, with one
   // readback at the end, and falls back to reading the split depth first when

@@ -271,14 +271,16 @@ class Solver:
         return self.evaluate_batched(systems, p=p)
 
     def set_small_path(self, enable):
-        """Single-workgroup build and walk for batches of at most 8192 particles
-        (on by default; off forces the multi-workgroup path)."""
-        self._raise(lib().fmm_set_small_path(self._h, int(bool(enable))))
+        """Single-workgroup build and walk for small batches: True (default)
+        up to 1024 particles, 2 up to 8192 (the most those launches hold),
+        False never; same trees, lists and results either way."""
+        mode = 2 if enable == 2 else int(bool(enable))
+        self._raise(lib().fmm_set_small_path(self._h, mode))
 
     def set_level_prediction(self, enable):
-        """Queue tree and walk for the split depth of recent builds, one header
-        readback (on by default; off reads the split depth first).  Same trees,
-        lists and results either way."""
+        """Queue tree and walk (and in forces() the evaluation) for the split
+        depth of recent builds, one header readback (off by default: the split
+        depth is read first).  Same trees, lists and results either way."""
         self._raise(lib().fmm_set_level_prediction(self._h, int(bool(enable))))
 
     def tree_info(self):

@@ -84,7 +84,7 @@ def test_small_batch_paths_identical(precision):
     res = []
     for small in (True, False):
         s = F.Solver(total, p_max=4, leaf_size=16, kernel=0, precision=precision)
-        s.set_small_path(small)
+        s.set_small_path(2 if small else False)
         outs = s.forces_batched(dev, eps=0.01, theta=0.5, p=4)
         torch.cuda.synchronize()
         res.append([(a.cpu().numpy(), p.cpu().numpy()) for a, p in outs])

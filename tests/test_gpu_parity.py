@@ -242,7 +242,7 @@ def test_small_and_general_paths_identical(label, precision):
     for small in (True, False):
         n = pos.shape[1] if active is None else len(active)
         s = F.Solver(n, p_max=4, leaf_size=leaf, kernel=F.WENDLAND, precision=precision)
-        s.set_small_path(small)
+        s.set_small_path(2 if small else False)
         tp = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
         tm = torch.from_numpy(np.ascontiguousarray(m)).cuda()
         ta = None if active is None else torch.from_numpy(active).cuda()
@@ -270,6 +270,7 @@ def test_level_prediction_identical():
            W.uniform_sphere(20000, seed=43), W.uniform_sphere(20000, seed=43)]
     kw = dict(p_max=4, leaf_size=16, kernel=F.WENDLAND, precision=1)
     pred = F.Solver(30000, **kw)
+    pred.set_level_prediction(True)
     for k, (pos, _, m) in enumerate(seq):
         tp = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
         tm = torch.from_numpy(np.ascontiguousarray(m)).cuda()
@@ -307,6 +308,7 @@ def test_fused_forces_identical():
     for precision in (0, 1):
         kw = dict(p_max=4, leaf_size=16, kernel=F.WENDLAND, precision=precision)
         fused = F.Solver(30000, **kw)
+        fused.set_level_prediction(True)
         for k, ((pos, _, m), theta) in enumerate(seq):
             tp = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
             tm = torch.from_numpy(np.ascontiguousarray(m)).cuda()
