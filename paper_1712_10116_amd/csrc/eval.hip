@@ -534,7 +534,21 @@ template <typename R, typename R4, int KERNEL, bool SELF, int NPH>
 __device__ __forceinline__ void p2p_window(const R4 *src, int ph, int Wr, int self_idx, R xi,
                                            R yi, R zi, R eps2, R inv_eps, R inv_eps3, double &bx,
                                            double &by, double &bz, double &bp) {
-  for (int f0 = ph; f0 < Wr; f0 += P2P_UNROLL * NPH) {
+  constexpr int B = P2P_UNROLL * NPH;  // slots per block of all phases
+  int f0 = ph;
+  // two blocks per update of the FP64 sums, then the odd block if any
+  for (; f0 + B < Wr; f0 += 2 * B) {
+    R sx = 0, sy = 0, sz = 0, sp = 0;
+    p2p_block<R, R4, KERNEL, SELF, NPH>(src, f0, self_idx, xi, yi, zi, eps2, inv_eps, inv_eps3,
+                                        sx, sy, sz, sp);
+    p2p_block<R, R4, KERNEL, SELF, NPH>(src, f0 + B, self_idx, xi, yi, zi, eps2, inv_eps,
+                                        inv_eps3, sx, sy, sz, sp);
+    bx += (double)sx;
+    by += (double)sy;
+    bz += (double)sz;
+    bp -= (double)sp;
+  }
+  if (f0 < Wr) {
     R sx = 0, sy = 0, sz = 0, sp = 0;
     p2p_block<R, R4, KERNEL, SELF, NPH>(src, f0, self_idx, xi, yi, zi, eps2, inv_eps, inv_eps3,
                                         sx, sy, sz, sp);
