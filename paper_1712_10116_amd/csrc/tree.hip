@@ -314,10 +314,15 @@ __device__ __forceinline__ uint32_t scan256(uint32_t v, uint32_t *wsum) {
 // the pass is stable), the tile reordered by digit in LDS, then written out
 // in tile order so that consecutive threads store consecutive addresses of a
 // digit's run.
+// raw = 1 (at most SORT_RAW_TILES tiles): hist holds the tiles' raw digit
+// counts and each tile sums what it needs itself (no digit-scan launch);
+// raw = 0: hist holds each digit's exclusive prefix over the tiles and dtot
+// the digit totals.
+#define SORT_RAW_TILES 16
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const int32_t *__restrict__ sin, uint64_t *__restrict__ kout,
     int32_t *__restrict__ sout, const int32_t *__restrict__ slot_req, int n, int shift, int by_req,
-    const uint32_t *__restrict__ hist, int nblk, const uint32_t *__restrict__ dtot) {
+    const uint32_t *__restrict__ hist, int nblk, const uint32_t *__restrict__ dtot, int raw) {
   // keys | slots | digits of the reordered tile; the per-wave digit counters
   // of the ranking step live in the front of the same space before that
   __shared__ __align__(16) unsigned char smem[SORT_TILE * 13];
@@ -330,7 +335,20 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
   for (int d = tid; d < SORT_WAVES * 256; d += SORT_THREADS) (&cnt[0][0])[d] = 0;
   // global start of each digit: exclusive scan of the digit totals, plus the
   // counts of the earlier tiles
-  const uint32_t dbase = scan256(tid < 256 ? dtot[tid] : 0u, wsum);
+  uint32_t dtotal = 0, tprefix = 0;
+  if (tid < 256) {
+    if (raw) {
+      for (int b = 0; b < nblk; ++b) {
+        const uint32_t c = hist[tid * nblk + b];
+        dtotal += c;
+        tprefix += b < (int)blockIdx.x ? c : 0u;
+      }
+    } else {
+      dtotal = dtot[tid];
+      tprefix = hist[tid * nblk + blockIdx.x];
+    }
+  }
+  const uint32_t dbase = scan256(dtotal, wsum);
   const int tile = blockIdx.x * SORT_TILE;
   const int base = tile + w * 64 * SORT_ITEMS;
   uint64_t k[SORT_ITEMS];
@@ -377,7 +395,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
   const uint32_t ls = scan256(tcount, wsum);
   if (tid < 256) {
     lstart[tid] = ls;
-    gbase[tid] = dbase + hist[tid * nblk + blockIdx.x] - ls;
+    gbase[tid] = dbase + tprefix - ls;
   }
   __syncthreads();
   int lpos[SORT_ITEMS];
@@ -614,34 +632,41 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_count(DevTree t, int l, int 
   if (threadIdx.x == 0) t.scan_part[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(FMM_SCAN_BLOCKS) void k_tree_scan(DevTree t, int l) {
-  __shared__ int v[FMM_SCAN_BLOCKS];
-  int x = t.scan_part[threadIdx.x];
-  v[threadIdx.x] = x;
-  __syncthreads();
-  for (int off = 1; off < FMM_SCAN_BLOCKS; off <<= 1) {
-    int y = threadIdx.x >= off ? v[threadIdx.x - off] : 0;
-    __syncthreads();
-    v[threadIdx.x] += y;
-    __syncthreads();
-  }
-  t.scan_part[threadIdx.x] = v[threadIdx.x] - x;
-  if (threadIdx.x == FMM_SCAN_BLOCKS - 1) {
-    Header *h = t.hdr;
-    int next = h->lvl_start[l + 1] + v[threadIdx.x];
-    for (int k = l + 2; k < FMM_NLEVELS + 2; ++k) h->lvl_start[k] = next;
-    if (next > t.cap_nodes) h->overflow |= OVF_NODES;
-  }
-}
 
 // Children of the splitting cells of level l; a child is a leaf when it holds
 // at most leaf_size particles or sits at the deepest level, and leaves are
 // counted here.
+// Sum of v over a block of FMM_BLOCK threads (all of them call it).
+__device__ __forceinline__ int block_sum(int v, int *part) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int tot = 0;
+#pragma unroll
+  for (int w = 0; w < FMM_BLOCK / 64; ++w) tot += part[w];
+  __syncthreads();
+  return tot;
+}
+
+// Each block first takes its offset among the children of the level (the
+// child counts of the earlier blocks, from k_tree_count) and the level's
+// total; block 0 records where the next level ends.
 __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l, int leaf_size) {
+  static_assert(FMM_SCAN_BLOCKS == FMM_BLOCK, "one block count per thread");
   int s, e;
   level_chunk(t.hdr, l, s, e);
   __shared__ int sc[FMM_BLOCK];
-  int run = t.hdr->lvl_start[l + 1] + t.scan_part[blockIdx.x];
+  __shared__ int part[FMM_BLOCK / 64];
+  const int cnt = t.scan_part[threadIdx.x];
+  const int before = block_sum((int)threadIdx.x < (int)blockIdx.x ? cnt : 0, part);
+  const int level_total = block_sum(cnt, part);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Header *h = t.hdr;
+    const int next = h->lvl_start[l + 1] + level_total;
+    for (int k = l + 2; k < FMM_NLEVELS + 2; ++k) h->lvl_start[k] = next;
+    if (next > t.cap_nodes) h->overflow |= OVF_NODES;
+  }
+  int run = t.hdr->lvl_start[l + 1] + before;
   for (int base = s; base < e; base += FMM_BLOCK) {
     int i = base + threadIdx.x;
     int nc = (i < e && i < t.cap_nodes) ? t.nnchild[i] : 0;
@@ -906,10 +931,12 @@ hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
       const int shift = by_req ? (pass - 8) * 8 : pass * 8;
       hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, sin, t.slot_req, n,
                          shift, by_req, t.sort_hist, nblk);
-      hipLaunchKernelGGL(k_sort_digit_scan, dim3(256), dim3(FMM_BLOCK), 0, s, t.sort_hist, nblk,
-                         t.sort_dtot);
+      const int raw = nblk <= SORT_RAW_TILES;
+      if (!raw)
+        hipLaunchKernelGGL(k_sort_digit_scan, dim3(256), dim3(FMM_BLOCK), 0, s, t.sort_hist, nblk,
+                           t.sort_dtot);
       hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, sin, kout, sout,
-                         t.slot_req, n, shift, by_req, t.sort_hist, nblk, t.sort_dtot);
+                         t.slot_req, n, shift, by_req, t.sort_hist, nblk, t.sort_dtot, raw);
       uint64_t *tk = kin; kin = kout; kout = tk;
       int32_t *ts = sin; sin = sout; sout = ts;
     }
@@ -929,7 +956,6 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, int max_level
     for (int l = 0; l < max_level && l < FMM_MAXLEVEL; ++l) {
       hipLaunchKernelGGL(k_tree_count, dim3(FMM_SCAN_BLOCKS), dim3(FMM_BLOCK), 0, s, t, l,
                          a.leaf_size);
-      hipLaunchKernelGGL(k_tree_scan, dim3(1), dim3(FMM_SCAN_BLOCKS), 0, s, t, l);
       hipLaunchKernelGGL(k_tree_emit, dim3(FMM_SCAN_BLOCKS), dim3(FMM_BLOCK), 0, s, t, l,
                          a.leaf_size);
     }
