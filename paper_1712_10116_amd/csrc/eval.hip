@@ -631,11 +631,17 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
   static_assert(SRC % (P2P_UNROLL * P2P_MAXPH) == 0, "window must hold its padding");
   __shared__ R4 src_all[P2P_WAVES][SRC];
   __shared__ int idx_all[P2P_WAVES][SRC];
+  __shared__ int3 leaf_all[P2P_WAVES][64];  // per list entry of a chunk: stream position, size, first particle
+  __shared__ R sink_all[P2P_WAVES][3][64];  // home sink position of each lane
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   R4 *src = src_all[w];
   int *idx = idx_all[w];
-  const int wave = xcd_block<32>(blockIdx.x, gridDim.x) * P2P_WAVES + w;
+  int3 *lf = leaf_all[w];
+  R(*sk)[64] = sink_all[w];
+  // the target leaf and all that is read from it are the same in every lane:
+  // kept in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(xcd_block<32>(blockIdx.x, gridDim.x) * P2P_WAVES + w);
   const int nwaves = gridDim.x * P2P_WAVES;
   const R eps2 = (R)(eps * eps);
   const R inv_eps = eps > 0 ? (R)(1.0 / eps) : R(0);
@@ -660,15 +666,15 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
       const int hs = passes > 1 ? ph * LP + ti : ti;
       const bool hv = hs < ns && (passes > 1 || ph == 0);
       const int gi = bA + tb + (hs < ns ? hs : 0);
-      R xh, yh, zh;
+      // home sink positions, kept in LDS across the windows
       if (MIXED) {
-        xh = (R)(t.sx[gi] - gA.x);
-        yh = (R)(t.sy[gi] - gA.y);
-        zh = (R)(t.sz[gi] - gA.z);
+        sk[0][lane] = (R)(t.sx[gi] - gA.x);
+        sk[1][lane] = (R)(t.sy[gi] - gA.y);
+        sk[2][lane] = (R)(t.sz[gi] - gA.z);
       } else {
-        xh = t.sx[gi];
-        yh = t.sy[gi];
-        zh = t.sz[gi];
+        sk[0][lane] = t.sx[gi];
+        sk[1][lane] = t.sy[gi];
+        sk[2][lane] = t.sz[gi];
       }
       double ax = 0, ay = 0, az = 0, pp = 0;
       for (int qb = 0; qb < cnt; qb += 64) {
@@ -679,17 +685,22 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
         const int nb = vq ? t.nend[B] - bB : 0;
         int total;
         const int pos = wave_excl_scan_int(nb, &total);  // lanes past cnt hold pos = total
+        total = __builtin_amdgcn_readfirstlane(total);
         const unsigned long long selfm = __ballot(vq && B == A);
         const int self_lane = selfm ? (int)__ffsll((long long)selfm) - 1 : 0;
-        const int self_start = selfm ? __shfl(pos, self_lane, 64) : -(1 << 30);
+        const int self_start =
+            __builtin_amdgcn_readfirstlane(selfm ? __shfl(pos, self_lane, 64) : -(1 << 30));
+        lf[lane] = make_int3(pos, nb, bB);  // kept in LDS across the windows
+        __builtin_amdgcn_wave_barrier();
         for (int w0 = 0; w0 < total; w0 += SRC) {
           const int W = min(SRC, total - w0);
           const int Wr = (W + blk - 1) / blk * blk;
           // particle index of every slot of the window, written by the lane
           // that holds its source leaf
           {
-            const int a0 = max(pos, w0), a1 = min(pos + nb, w0 + W);
-            for (int s = a0; s < a1; ++s) idx[s - w0] = bB + (s - pos);
+            const int3 e = lf[lane];
+            const int a0 = max(e.x, w0), a1 = min(e.x + e.y, w0 + W);
+            for (int s = a0; s < a1; ++s) idx[s - w0] = e.z + (s - e.x);
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -714,13 +725,13 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
           if (passes == 1) {
-            p2p_window_any<R, R4, KERNEL, SELF>(nph, src, ph, Wr, self_start + tb + ti - w0, xh,
-                                                yh, zh, eps2, inv_eps, inv_eps3, ax, ay, az, pp);
+            p2p_window_any<R, R4, KERNEL, SELF>(nph, src, ph, Wr, self_start + tb + ti - w0,
+                                                sk[0][lane], sk[1][lane], sk[2][lane], eps2,
+                                                inv_eps, inv_eps3, ax, ay, az, pp);
           } else {
             for (int p = 0; p < passes; ++p) {
               const int from = ti * nph + p;  // home lane of sink p * LP + ti
-              const R xi = __shfl(xh, from, 64), yi = __shfl(yh, from, 64),
-                      zi = __shfl(zh, from, 64);
+              const R xi = sk[0][from], yi = sk[1][from], zi = sk[2][from];
               double bx = 0, by = 0, bz = 0, bp = 0;
               p2p_window_any<R, R4, KERNEL, SELF>(nph, src, ph, Wr,
                                                   self_start + tb + p * LP + ti - w0, xi, yi, zi,
