@@ -142,7 +142,8 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
               hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->join, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&c->hdr_ev, hipEventDisableTiming) == hipSuccess;
+              hipEventCreateWithFlags(&c->hdr_ev, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->up_done, hipEventDisableTiming) == hipSuccess;
   for (int k = 0; pins && k < fmm_ctx::UP_SLOTS; ++k)
     pins = hipEventCreateWithFlags(&c->up_ev[k], hipEventDisableTiming) == hipSuccess;
   if (!pins) {
@@ -205,6 +206,7 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
   if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->join) (void)hipEventDestroy(c->join);
   if (c->hdr_ev) (void)hipEventDestroy(c->hdr_ev);
+  if (c->up_done) (void)hipEventDestroy(c->up_done);
   delete c;
   return FMM_OK;
 }
@@ -367,7 +369,7 @@ static void count_evaluation(fmm_ctx *c, int n_req, const fmm_request *reqs) {
 // overflowed, the build is redone the classic way and *evaluated stays false
 // (the caller evaluates again, overwriting whatever the queued kernels wrote).
 static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, double eps,
-                             double theta, int p_fused, bool *evaluated) {
+                             double theta, int p_fused, bool *evaluated, bool *upward) {
   int64_t n_all = 0;
   fmm_status st = check_requests(c, n_req, reqs, p_fused > 0, &n_all);
   if (st != FMM_OK) return st;
@@ -484,6 +486,22 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
   memcpy(lvl, c->hh.lvl_start, sizeof(lvl));
   a.lvl_host = lvl;
   a.depth = depth;
+  // with the masses known (fmm_forces), the mass gather, P2M and M2M need only
+  // the tree: they run on the second stream beside the walk, which leaves
+  // most of the chip idle
+  bool up = false;
+  if (p_fused > 0 && n_all > 0) {
+    EvalArgs u = {};
+    set_eval_args(c, u, n_all, p_fused, eps);
+    u.n_nodes = lvl[FMM_NLEVELS];
+    u.lvl_start_host = lvl;
+    u.depth = depth;
+    HIPCHK(c, hipEventRecord(c->fork, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->side, c->fork, 0));
+    HIPCHK(c, launch_upward(c->t, u, c->side));
+    HIPCHK(c, hipEventRecord(c->up_done, c->side));
+    up = true;
+  }
   // 2. symmetric walk; regrow a list buffer that turned out too small
   for (int attempt = 0; attempt < 10; ++attempt) {
     HIPCHK(c, launch_traverse(c->t, a, c->stream));
@@ -509,17 +527,29 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
       continue;
     }
     record_levels(c, max_level);
-    return finish(depth);
+    st = finish(depth);
+    if (st == FMM_OK && upward) *upward = up;
+    return st;
   }
   return fail(c, FMM_EOVERFLOW, "list workspace still too small after regrowth");
 }
 
 extern "C" fmm_status fmm_build_batched(fmm_ctx *c, int n_req, const fmm_request *reqs,
                                         double eps, double theta) {
-  return build_impl(c, n_req, reqs, eps, theta, 0, nullptr);
+  return build_impl(c, n_req, reqs, eps, theta, 0, nullptr, nullptr);
 }
 
+static fmm_status evaluate_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, int p,
+                                bool upward_done);
+
 extern "C" fmm_status fmm_evaluate_batched(fmm_ctx *c, int n_req, const fmm_request *reqs, int p) {
+  return evaluate_impl(c, n_req, reqs, p, false);
+}
+
+// upward_done: the build of these requests already queued the mass gather,
+// P2M and M2M (build_impl with p_fused = p)
+static fmm_status evaluate_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, int p,
+                                bool upward_done) {
   int64_t n_all = 0;
   fmm_status st = check_requests(c, n_req, reqs, true, &n_all);
   if (st != FMM_OK) return st;
@@ -539,6 +569,8 @@ extern "C" fmm_status fmm_evaluate_batched(fmm_ctx *c, int n_req, const fmm_requ
   e.n_nodes = c->n_nodes;
   e.lvl_start_host = c->hh.lvl_start;
   e.depth = c->depth;
+  e.upward_done = upward_done;
+  e.up_done = c->up_done;
   HIPCHK(c, launch_evaluate(c->t, e, c->stream));
   count_evaluation(c, n_req, reqs);
   return FMM_OK;
@@ -548,10 +580,10 @@ extern "C" fmm_status fmm_forces_batched(fmm_ctx *c, int n_req, const fmm_reques
                                          double eps, double theta, int p) {
   if (c && (p < 1 || p > c->prm.p_max || !eval_order_supported(p)))
     return fail(c, FMM_EINVAL, "order p=%d unsupported", p);
-  bool evaluated = false;
-  fmm_status st = build_impl(c, n_req, reqs, eps, theta, p, &evaluated);
+  bool evaluated = false, upward = false;
+  fmm_status st = build_impl(c, n_req, reqs, eps, theta, p, &evaluated, &upward);
   if (st != FMM_OK || evaluated) return st;
-  return fmm_evaluate_batched(c, n_req, reqs, p);
+  return evaluate_impl(c, n_req, reqs, p, upward);
 }
 
 static fmm_request one_request(const double *pos, const double *mass, int64_t n_total,

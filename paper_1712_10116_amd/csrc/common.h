@@ -267,8 +267,14 @@ struct EvalArgs {
   // depth are estimates (grid sizes, loop bounds) and the kernels take the
   // tree's sizes from the header
   bool dev;
+  // mass gather, P2M and M2M already queued by launch_upward (on the side
+  // stream, beside the walk); the main stream waits for up_done before M2L
+  bool upward_done;
+  hipEvent_t up_done;
 };
 hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s);
+// mass gather, P2M and M2M of an evaluation on stream s (exact tree sizes)
+hipError_t launch_upward(const DevTree &t, const EvalArgs &e, hipStream_t s);
 bool eval_order_supported(int p);
 // hhs.hip
 hipError_t launch_gather_mask_mass(const double *mass, const int32_t *sys, int n_sys,

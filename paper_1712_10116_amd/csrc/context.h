@@ -35,6 +35,7 @@ struct fmm_ctx {
   bool up_valid;
   Header *pin_hdr;                  // pinned destination of header readbacks
   hipEvent_t hdr_ev;                // recorded after a queued header readback
+  hipEvent_t up_done;               // upward pass queued beside the walk has finished
   int n_nodes, depth;
   int small_max;           // single-workgroup build and walk for batches of at most this many particles
   // split levels of recent multi-workgroup builds: the next build queues the

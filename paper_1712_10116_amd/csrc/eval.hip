@@ -333,9 +333,10 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2l(DevTree t, int s, int e) {
 // Small trees: all M2M levels (deepest first) or all L2L levels (root first)
 // in one workgroup, a barrier between levels.
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_m2m_small(DevTree t, int depth, bool harm) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_m2m_small(DevTree t, int depth, bool harm,
+                                                         bool dev) {
   const Header *h = t.hdr;
-  if (tree_incomplete(t)) return;
+  if (dev && tree_incomplete(t)) return;
   for (int l = depth - 1; l >= 0; --l) {
     for (int i = h->lvl_start[l] + (threadIdx.x >> 3); i < h->lvl_start[l + 1];
          i += blockDim.x >> 3)
@@ -345,9 +346,9 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2m_small(DevTree t, int depth, b
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_l2l_small(DevTree t, int depth) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_l2l_small(DevTree t, int depth, bool dev) {
   const Header *h = t.hdr;
-  if (tree_incomplete(t)) return;
+  if (dev && tree_incomplete(t)) return;
   for (int l = 1; l <= depth; ++l) {
     for (int c = h->lvl_start[l] + threadIdx.x; c < h->lvl_start[l + 1]; c += blockDim.x)
       l2l_cell<T, P>(t, c);
@@ -778,13 +779,50 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
 // Launch order: P2P goes to the side stream (after the mass gather, by an
 // event) and runs concurrently with P2M, M2M, M2L and L2L on the main stream,
 // which waits for it (second event) before L2P adds the near field.
+// Cells of level l for a launch with per_cell threads per cell: exact, or
+// (e.dev) an estimated grid and bounds read on the device.
+static void level_launch(const EvalArgs &e, int l, int per_cell, int &blocks, int &a0, int &a1) {
+  const int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
+  const int cnt = le - ls;
+  if (!e.dev) {
+    blocks = cnt > 0 ? (per_cell * cnt + FMM_BLOCK - 1) / FMM_BLOCK : 0;
+    a0 = ls;
+    a1 = le;
+  } else {
+    blocks = (per_cell * (cnt + cnt / 4 + 32) + FMM_BLOCK - 1) / FMM_BLOCK;
+    a0 = -1 - l;
+    a1 = 0;
+  }
+}
+
+// Upward pass: P2M and M2M (far-field cell kernels: 8 lanes per cell).
+template <typename T, int P, int KERNEL>
+static void run_upward(const DevTree &t, const EvalArgs &e, hipStream_t s) {
+  const int nn = e.n_nodes;
+  const int ga = e.dev ? nn + nn / 4 + 64 : nn;
+  const int narg = e.dev ? -1 : nn;
+  const bool harm = KERNEL == 0;  // folded moments feed the harmonic M2L
+  hipLaunchKernelGGL((k_p2m<T, P>), dim3((8 * ga + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
+                     s, t, narg, harm);
+  if (nn <= SMALL_NODES && e.depth > 0) {
+    hipLaunchKernelGGL((k_m2m_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth, harm,
+                       e.dev);
+  } else {
+    for (int l = e.depth - 1; l >= 0; --l) {
+      int blocks, a0, a1;
+      level_launch(e, l, 8, blocks, a0, a1);
+      if (blocks > 0)
+        hipLaunchKernelGGL((k_m2m<T, P>), dim3(blocks), dim3(FMM_BLOCK), 0, s, t, a0, a1, harm);
+    }
+  }
+}
+
 template <typename T, int P, int KERNEL>
 static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   const int nn = e.n_nodes;  // exact, or (e.dev) an estimate that sets grid sizes
   const int ga = e.dev ? nn + nn / 4 + 64 : nn;
   const int narg = e.dev ? -1 : nn;  // -1: node count read on the device
   PhaseTimer *tm = e.tm;
-  const bool harm = KERNEL == 0;  // folded moments feed the harmonic M2L
   hipEventRecord(e.fork, s);
   hipStreamWaitEvent(e.side, e.fork, 0);
   const int tp = tm ? tm->begin(PH_P2P, e.side) : -1;
@@ -798,35 +836,11 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
                        t, narg, e.eps);
   if (tm) tm->end(tp, e.side);
   hipEventRecord(e.join, e.side);
-  // far-field cell kernels: 8 lanes per cell
-  hipLaunchKernelGGL((k_p2m<T, P>), dim3((8 * ga + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
-                     s, t, narg, harm);
-  // cells of level l for a launch: exact, or (e.dev) an estimated grid and
-  // bounds read on the device
-  auto level = [&](int l, int per_cell, int &blocks, int &a0, int &a1) {
-    const int ls = e.lvl_start_host[l], le = e.lvl_start_host[l + 1];
-    const int cnt = le - ls;
-    if (!e.dev) {
-      blocks = cnt > 0 ? (per_cell * cnt + FMM_BLOCK - 1) / FMM_BLOCK : 0;
-      a0 = ls;
-      a1 = le;
-    } else {
-      blocks = (per_cell * (cnt + cnt / 4 + 32) + FMM_BLOCK - 1) / FMM_BLOCK;
-      a0 = -1 - l;
-      a1 = 0;
-    }
-  };
+  if (e.upward_done)
+    hipStreamWaitEvent(s, e.up_done, 0);  // P2M / M2M ran beside the walk
+  else
+    run_upward<T, P, KERNEL>(t, e, s);
   const bool small = nn <= SMALL_NODES;
-  if (small && e.depth > 0) {
-    hipLaunchKernelGGL((k_m2m_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth, harm);
-  } else {
-    for (int l = e.depth - 1; l >= 0; --l) {
-      int blocks, a0, a1;
-      level(l, 8, blocks, a0, a1);
-      if (blocks > 0)
-        hipLaunchKernelGGL((k_m2m<T, P>), dim3(blocks), dim3(FMM_BLOCK), 0, s, t, a0, a1, harm);
-    }
-  }
   const int wave_blocks = (ga + 3) / 4;
   if (tm) {
     tm->stop(s);
@@ -839,11 +853,11 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
     tm->start(PH_DOWN, s);
   }
   if (small && e.depth > 0) {
-    hipLaunchKernelGGL((k_l2l_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth);
+    hipLaunchKernelGGL((k_l2l_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth, e.dev);
   } else {
     for (int l = 1; l <= e.depth; ++l) {
       int blocks, a0, a1;
-      level(l, 1, blocks, a0, a1);
+      level_launch(e, l, 1, blocks, a0, a1);
       if (blocks > 0)
         hipLaunchKernelGGL((k_l2l<T, P>), dim3(blocks), dim3(FMM_BLOCK), 0, s, t, a0, a1);
     }
@@ -869,11 +883,38 @@ static bool dispatch_order(const DevTree &t, const EvalArgs &e, hipStream_t s) {
 
 bool eval_order_supported(int p) { return p >= 1 && p <= 6; }
 
+template <typename T, int KERNEL>
+static bool dispatch_upward(const DevTree &t, const EvalArgs &e, hipStream_t s) {
+  switch (e.p) {
+    case 1: run_upward<T, 1, KERNEL>(t, e, s); return true;
+    case 2: run_upward<T, 2, KERNEL>(t, e, s); return true;
+    case 3: run_upward<T, 3, KERNEL>(t, e, s); return true;
+    case 4: run_upward<T, 4, KERNEL>(t, e, s); return true;
+    case 5: run_upward<T, 5, KERNEL>(t, e, s); return true;
+    case 6: run_upward<T, 6, KERNEL>(t, e, s); return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_upward(const DevTree &t, const EvalArgs &e, hipStream_t s) {
+  if (e.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_mass, dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0, s,
+                     t, e.n);
+  bool ok;
+  if (e.mixed)
+    ok = e.kernel == 1 ? dispatch_upward<float, 1>(t, e, s) : dispatch_upward<float, 0>(t, e, s);
+  else
+    ok = e.kernel == 1 ? dispatch_upward<double, 1>(t, e, s) : dispatch_upward<double, 0>(t, e, s);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   if (e.n <= 0) return hipSuccess;
   if (e.tm) e.tm->start(PH_UP, s);
-  hipLaunchKernelGGL(k_gather_mass, dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0, s,
-                     t, e.n);
+  if (!e.upward_done)
+    hipLaunchKernelGGL(k_gather_mass, dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
+                       s, t, e.n);
   bool ok;
   if (e.mixed)
     ok = e.kernel == 1 ? dispatch_order<float, 1>(t, e, s) : dispatch_order<float, 0>(t, e, s);

@@ -323,3 +323,26 @@ def test_fused_forces_identical():
             assert torch.equal(a1, a2) and torch.equal(p1, p2), (precision, k)
             ref.close()
         fused.close()
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forces_equals_build_then_evaluate(kernel, precision):
+    """forces() runs the mass gather, P2M and M2M on the second stream beside
+    the walk; the result equals build() followed by evaluate() bit for bit,
+    on repeated calls and on a second system of another size."""
+    torch, F = _torch(), _F()
+    s1 = F.Solver(40000, p_max=5, leaf_size=24, kernel=kernel, precision=precision)
+    s2 = F.Solver(40000, p_max=5, leaf_size=24, kernel=kernel, precision=precision)
+    for k, (pos, _, m) in enumerate([W.plummer(40000, seed=61), W.plummer(40000, seed=61),
+                                     W.uniform_sphere(25000, seed=62)]):
+        tp = torch.from_numpy(np.ascontiguousarray(pos)).cuda()
+        tm = torch.from_numpy(np.ascontiguousarray(m)).cuda()
+        a1, p1 = s1.forces(tp, tm, eps=0.01, theta=0.45, p=5)
+        s2.build(tp, eps=0.01, theta=0.45)
+        a2, p2 = s2.evaluate(tp, tm, p=5)
+        torch.cuda.synchronize()
+        assert torch.equal(a1, a2) and torch.equal(p1, p2), k
+        assert s1.tree_info() == s2.tree_info(), k
+    s1.close()
+    s2.close()
