@@ -11,8 +11,8 @@
 //
 // Mixed form: cell-local FP32 offsets (x - z_leaf) and the FP64 difference of
 // the two leaf centres rounded once to FP32 give every particle separation;
-// each source leaf's FP32 partial sums are added into FP64 accumulators;
-// expansions are FP32 on size-scaled coefficients.
+// FP32 partial sums over blocks of 16 sources are added into FP64
+// accumulators; expansions are FP32 on size-scaled coefficients.
 #include "common.h"
 #include "expansion.h"
 
@@ -386,8 +386,8 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, bool dev) {
 }
 
 // ---------------------------------------------------------------------------
-// P2P: one wavefront per target leaf.  Lanes = (target particle, phase); a
-// lane takes every nph-th particle of each source leaf.
+// P2P: one wavefront per target leaf, lanes = (sink, phase) pairs in a layout
+// chosen per leaf (below).
 // ---------------------------------------------------------------------------
 template <typename R, int KERNEL>
 struct PairKernel {
@@ -776,9 +776,6 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
 }
 
 // ---------------------------------------------------------------------------
-// Launch order: P2P goes to the side stream (after the mass gather, by an
-// event) and runs concurrently with P2M, M2M, M2L and L2L on the main stream,
-// which waits for it (second event) before L2P adds the near field.
 // Cells of level l for a launch with per_cell threads per cell: exact, or
 // (e.dev) an estimated grid and bounds read on the device.
 static void level_launch(const EvalArgs &e, int l, int per_cell, int &blocks, int &a0, int &a1) {
@@ -817,6 +814,12 @@ static void run_upward(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   }
 }
 
+// Launch order: P2P goes to the side stream (after the walk and the mass
+// gather, by an event) and runs concurrently with M2L and L2L on the main
+// stream, which waits for it (second event) before L2P adds the near field.
+// P2M and M2M run on the main stream before M2L, unless launch_upward already
+// queued them on the side stream beside the walk (e.upward_done): then the
+// main stream waits for e.up_done instead.
 template <typename T, int P, int KERNEL>
 static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   const int nn = e.n_nodes;  // exact, or (e.dev) an estimate that sets grid sizes
