@@ -76,8 +76,9 @@ typedef struct fmm_ctx fmm_ctx;
 
 /* Create a solver context on the current HIP device for up to max_n active
  * particles per call.  stream: a hipStream_t (NULL = the null stream).
- * Allocates the whole workspace; later calls allocate only if an interaction
- * list outgrows its estimate (the list buffer is then regrown once). */
+ * Allocates the whole workspace; later calls allocate only if the cells or an
+ * interaction list outgrow their estimate (that buffer is then regrown, at
+ * least doubling, and the build repeated). */
 fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *stream, fmm_ctx **out);
 fmm_status fmm_destroy(fmm_ctx *ctx);
 const char *fmm_last_error(const fmm_ctx *ctx);
@@ -108,7 +109,9 @@ fmm_status fmm_evaluate(fmm_ctx *ctx, const double *pos, const double *mass, int
 
 /* fmm_build followed by fmm_evaluate: acceleration and potential of every
  * active particle due to all active masses (the Poisson solve called by each
- * kick of Algorithm 3). */
+ * kick of Algorithm 3).  The masses being known when the tree is built, the
+ * mass gather, P2M and M2M run on the context's second stream beside the
+ * walk; the results equal fmm_build + fmm_evaluate bit for bit. */
 fmm_status fmm_forces(fmm_ctx *ctx, const double *pos, const double *mass, int64_t n_total,
                       const int32_t *active, int64_t n_active, double eps, double theta,
                       int p, double *acc, double *pot);
