@@ -177,7 +177,7 @@ def ensemble_leg(args, F, torch, line):
         sv.close()
         return span
 
-    tl = autotune.fastest((8, 16, 32, 64), probe_run)
+    tl = autotune.fastest((16, 32, 64, 96, 128), probe_run)
     prm["leaf_size"] = tl["best"]
     s = F.Solver(args.ensemble_max_n, p_max=prm["p"], leaf_size=prm["leaf_size"],
                  kernel=prm["kernel"], precision=F.MIXED)
