@@ -2,7 +2,8 @@
 
 Wraps ``liboracle.so`` (plain C, built from ``fmm_oracle.c``) and adds the
 hierarchical Hamiltonian splitting (HHS) integrator of the paper (Sec. 2.2,
-Algorithms 1-3) in plain numpy on top of the oracle's force solve.
+Algorithms 1-3) and the paper's comparison integrator with individual
+timesteps (Sec. 2.3) in plain numpy on top of the oracle's force solve.
 
 Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
 may import this module.  It imports nothing from the GPU package, and the GPU
@@ -322,6 +323,65 @@ class HHSOracle:
         """Advance every particle by dt_top (one top-level EVOLVE_HOLD)."""
         sysall = np.arange(st.mass.shape[0], dtype=np.int32)
         self.evolve(st, 0, sysall, dt_top, True, dt_top)
+        st.t += dt_top
+
+
+# --------------------------------------------------------------------------
+# The comparison integrator of Sec. 2.3: individual (block) timesteps with the
+# same FMM, forces on the active particles from all the mass in the system
+# --------------------------------------------------------------------------
+class TradOracle:
+    """Individual-timestep KDK with FMM forces (Sec. 2.3), in plain numpy.
+
+    Readings where the paper is silent: the timestep of particle i is
+    sqrt(eta*eps/|a_i|) (the function of Sec. 2.2 with |a| the magnitude of
+    the particle's acceleration from an all-particle solve at the start of
+    the top step), rounded to a rung exactly as in HHSOracle.rungs; rungs are
+    fixed within a top step of length dt_top, which is split into 2^R ticks,
+    R the largest rung present.  At the start every particle takes the
+    opening half kick of its first step.  At the end of tick j the particles
+    whose step ends there (rung >= R - ctz(j+1)) drift over their own step,
+    are given the acceleration due to all the mass at the stored positions
+    (a particle that is not active sits where its last step ended: positions
+    are not synchronised), and take the closing half kick and, unless the top
+    step ends, the opening half kick of their next step, as two separate
+    additions.  a_cur holds |a| of each particle's latest force evaluation.
+    """
+
+    def __init__(self, *, p, theta, eps, leaf_size, kernel, eta, max_levels):
+        self.kw = dict(p=p, theta=theta, eps=eps, leaf_size=leaf_size, kernel=kernel)
+        self.H = HHSOracle(p=p, theta=theta, eps=eps, leaf_size=leaf_size, kernel=kernel,
+                           eta=eta, max_levels=max_levels)
+
+    def forces(self, st):
+        """Acceleration of every particle due to all the mass (one solve)."""
+        st.force_calls += 1
+        acc, _ = fmm(st.pos, st.mass, None, **self.kw)
+        return acc
+
+    def step(self, st, dt_top):
+        n = st.mass.shape[0]
+        everyone = np.arange(n, dtype=np.int32)
+        acc = self.forces(st)
+        st.force_particles += n
+        st.a_cur = np.sqrt((acc * acc).sum(axis=0))
+        st.a_old = np.zeros(n)
+        st.rung = self.H.rungs(st, everyone, dt_top)
+        R = int(st.rung.max())
+        half = np.ldexp(dt_top, -st.rung) * 0.5      # half step of each particle
+        st.vel += acc * half
+        for j in range(1 << R):
+            tz = ((j + 1) & -(j + 1)).bit_length() - 1  # trailing zeros of j + 1
+            ending = st.rung >= R - tz
+            full = np.ldexp(dt_top, -st.rung[ending])
+            st.pos[:, ending] += st.vel[:, ending] * full
+            acc = self.forces(st)
+            st.force_particles += int(ending.sum())
+            a = acc[:, ending]
+            st.vel[:, ending] += a * half[ending]
+            if j + 1 < (1 << R):
+                st.vel[:, ending] += a * half[ending]
+            st.a_cur[ending] = np.sqrt((a * a).sum(axis=0))
         st.t += dt_top
 
 
