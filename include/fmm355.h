@@ -245,6 +245,27 @@ fmm_status hhs_init(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp);
 fmm_status hhs_step(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp, double dt_top,
                     int64_t stats[3]);
 
+/* The paper's comparison integrator (Sec. 2.3): individual timesteps, each
+ * force evaluation giving the active particles the acceleration due to all
+ * the mass, with inactive particles where their last step left them (not
+ * synchronised).  One top step of length dt_top on the state of hhs_step
+ * (a_old is set to 0; a_cur holds |a| of each particle's latest evaluation):
+ * an all-particle solve at the start gives a_cur and, unless freeze_rungs,
+ * the rungs (the rule of hhs_step with |a| = a_cur); every particle takes the
+ * opening half kick of its step dt_top 2^-rung; the top step is split into
+ * 2^R ticks (R the deepest rung present); at the end of tick j the particles
+ * with rung >= R - ctz(j+1) drift over their step, get the acceleration of a
+ * solve over all particles at the stored positions, and take the closing half
+ * kick and, before the last tick, the opening half kick of their next step (two
+ * separate FP64 additions).  1 + 2^R force solves per call, each covering all
+ * particles.  stats (host, may be NULL): [0] solves, [1] sum over the solves
+ * of the particles kicked with their result (n for the first), [2] tree
+ * builds.  Synchronous: returns after the step has finished on the device.
+ * FMM_EINVAL for bad parameters, a rung outside 0..max_levels-1 (frozen
+ * rungs) or dt_top zero or not finite. */
+fmm_status trad_step(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp, double dt_top,
+                     int64_t stats[3]);
+
 /* Device scratch of one system's integration (rung split lists for every
  * rung, masked masses, accelerations): about hhs_run_bytes(n, max_levels)
  * bytes of device memory, owned by the run and freed by hhs_run_destroy

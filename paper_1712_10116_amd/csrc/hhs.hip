@@ -110,6 +110,64 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_amag(const double *__restrict__ a
   a_old[i] = 0.0;
 }
 
+// Individual-timestep integrator (Sec. 2.3): particle i steps with
+// dt_top 2^-rung[i]; the kick and drift kernels act on the particles with
+// rung >= rmin, the ones whose step ends at the current tick.  The histogram
+// counts rungs 0..30 and puts any other value in bucket 31.
+__global__ __launch_bounds__(FMM_BLOCK) void k_rung_hist(const int32_t *__restrict__ rung,
+                                                         int64_t n, int32_t *__restrict__ cnt) {
+  __shared__ int32_t h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int r = rung[i];
+    atomicAdd(&h[r >= 0 && r <= 30 ? r : 31], 1);  // 31: outside every valid rung range
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+}
+
+// v += a h (h = half of the particle's step), and again when twice is set
+// (the closing half kick of one step followed by the opening one of the
+// next); |a| into amag when given
+__global__ __launch_bounds__(FMM_BLOCK) void k_rung_kick(const double *__restrict__ acc,
+                                                         const int32_t *__restrict__ rung,
+                                                         int64_t n, double dt_top, int rmin,
+                                                         bool twice, double *__restrict__ vel,
+                                                         double *__restrict__ amag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = rung[i];
+  if (r < rmin) return;
+  const double h = ldexp(dt_top, -r) * 0.5;
+  const double ax = acc[i], ay = acc[n + i], az = acc[2 * n + i];
+  double vx = vel[i] + ax * h, vy = vel[n + i] + ay * h, vz = vel[2 * n + i] + az * h;
+  if (twice) {
+    vx += ax * h;
+    vy += ay * h;
+    vz += az * h;
+  }
+  vel[i] = vx;
+  vel[n + i] = vy;
+  vel[2 * n + i] = vz;
+  if (amag) amag[i] = sqrt(ax * ax + ay * ay + az * az);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_rung_drift(const double *__restrict__ vel,
+                                                          const int32_t *__restrict__ rung,
+                                                          int64_t n, double dt_top, int rmin,
+                                                          double *__restrict__ pos) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = rung[i];
+  if (r < rmin) return;
+  const double dt = ldexp(dt_top, -r);
+  pos[i] += vel[i] * dt;
+  pos[n + i] += vel[n + i] * dt;
+  pos[2 * n + i] += vel[2 * n + i] * dt;
+}
+
 // block minima of a[i] + b[i] (grid-stride), then one block reduces them
 __global__ __launch_bounds__(FMM_BLOCK) void k_min_sum_partial(const double *__restrict__ a,
                                                                const double *__restrict__ b,
@@ -238,6 +296,25 @@ void hhs_launch_iota(int32_t *v, int n, hipStream_t s) {
 
 void hhs_launch_amag(const double *acc, int64_t n, double *a_cur, double *a_old, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_amag, NB(n), dim3(FMM_BLOCK), 0, s, acc, n, a_cur, a_old);
+}
+
+void trad_launch_rung_hist(const int32_t *rung, int64_t n, int32_t *cnt, hipStream_t s) {
+  hipMemsetAsync(cnt, 0, 32 * sizeof(int32_t), s);
+  if (n > 0) hipLaunchKernelGGL(k_rung_hist, NB(n), dim3(FMM_BLOCK), 0, s, rung, n, cnt);
+}
+
+void trad_launch_kick(const double *acc, const int32_t *rung, int64_t n, double dt_top, int rmin,
+                      bool twice, double *vel, double *amag, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_rung_kick, NB(n), dim3(FMM_BLOCK), 0, s, acc, rung, n, dt_top, rmin,
+                       twice, vel, amag);
+}
+
+void trad_launch_drift(const double *vel, const int32_t *rung, int64_t n, double dt_top, int rmin,
+                       double *pos, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_rung_drift, NB(n), dim3(FMM_BLOCK), 0, s, vel, rung, n, dt_top, rmin,
+                       pos);
 }
 
 void hhs_launch_min_sum(const double *a, const double *b, int64_t n, double *part, double *out,

@@ -465,3 +465,73 @@ extern "C" fmm_status hhs_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp, 
   if (e != FMM_OK) return e;
   return hhs_step_batched(c, 1, &c->own_run, &st, hp, &dt_top, stats);
 }
+
+// The comparison integrator of Sec. 2.3: individual (block) timesteps, every
+// force evaluation giving the particles whose step ends the acceleration due
+// to all the mass, with the particles that are not active where their last
+// step left them.  Each tick's solve covers all particles (one tree over the
+// whole system); only the active ones are kicked with its result.
+extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp, double dt_top,
+                                int64_t stats[3]) {
+  fmm_status e = check_params(c, hp);
+  if (e != FMM_OK) return e;
+  if (!st) return FMM_EINVAL;
+  if (st->n < 1 || st->n > c->max_n) return fmm_fail(c, FMM_EINVAL, "state size outside [1, max_n]");
+  if (!st->pos || !st->vel || !st->mass || !st->a_old || !st->a_cur || !st->rung)
+    return fmm_fail(c, FMM_EINVAL, "NULL state array");
+  if (!std::isfinite(dt_top) || dt_top == 0.0) return fmm_fail(c, FMM_EINVAL, "dt_top");
+  e = own_run(c, st, hp);
+  if (e != FMM_OK) return e;
+  e = ensure_split_slots(c, 32);
+  if (e != FMM_OK) return e;
+  hhs_run *r = c->own_run;
+  const int64_t n = st->n;
+  hipStream_t s = c->stream;
+  int64_t calls = 0, parts = 0;
+  auto solve = [&]() {
+    ++calls;
+    return fmm_forces(c, st->pos, st->mass, n, nullptr, n, hp->eps, hp->theta, hp->p, r->acc,
+                      r->pot);
+  };
+  // rungs from |a| of an all-particle solve at the start of the top step
+  e = solve();
+  if (e != FMM_OK) return e;
+  parts += n;
+  hhs_launch_amag(r->acc, n, st->a_cur, st->a_old, s);
+  if (!hp->freeze_rungs)
+    hhs_launch_rungs(r->all_idx, (int)n, st->a_old, st->a_cur, st->rung, dt_top,
+                     hp->eta * hp->eps, hp->max_levels, s);
+  trad_launch_rung_hist(st->rung, n, c->split_cnt, s);
+  int32_t cnt[32];
+  if (hipMemcpyAsync(cnt, c->split_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fmm_fail(c, FMM_EDEVICE, "rung readback failed");
+  int R = 0;
+  for (int k = 0; k < 32; ++k) {
+    if (cnt[k] < 0 || (cnt[k] > 0 && k >= hp->max_levels))
+      return fmm_fail(c, FMM_EINVAL, "rung outside 0..max_levels-1");
+    if (cnt[k] > 0) R = k;
+  }
+  trad_launch_kick(r->acc, st->rung, n, dt_top, 0, false, st->vel, nullptr, s);  // opening
+  const int64_t ticks = (int64_t)1 << R;
+  for (int64_t j = 0; j < ticks; ++j) {
+    int tz = 0;
+    while (!(((j + 1) >> tz) & 1)) ++tz;  // trailing zeros of j + 1
+    const int rmin = std::max(0, R - tz);
+    trad_launch_drift(st->vel, st->rung, n, dt_top, rmin, st->pos, s);
+    e = solve();
+    if (e != FMM_OK) return e;
+    for (int k = rmin; k <= R; ++k) parts += cnt[k];
+    trad_launch_kick(r->acc, st->rung, n, dt_top, rmin, j + 1 < ticks, st->vel, st->a_cur, s);
+  }
+  if (hipStreamSynchronize(s) != hipSuccess)
+    return fmm_fail(c, FMM_EDEVICE, "trad_step synchronisation failed");
+  st->t += dt_top;
+  if (stats) {
+    stats[0] = calls;
+    stats[1] = parts;
+    stats[2] = calls;
+  }
+  c->tree_valid = false;
+  return FMM_OK;
+}

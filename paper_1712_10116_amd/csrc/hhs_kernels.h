@@ -19,6 +19,15 @@ void hhs_launch_drift(const int32_t *set, int n_set, const double *vel, double *
                       double dt, hipStream_t s);
 void hhs_launch_iota(int32_t *v, int n, hipStream_t s);
 void hhs_launch_amag(const double *acc, int64_t n, double *a_cur, double *a_old, hipStream_t s);
+// Individual-timestep integrator: cnt[k] = particles on rung k (32 ints,
+// cleared first); kick (v += a h, twice when asked, h half the particle's
+// step, |a| into amag if not NULL) and drift (x += v dt) of the particles with
+// rung >= rmin.
+void trad_launch_rung_hist(const int32_t *rung, int64_t n, int32_t *cnt, hipStream_t s);
+void trad_launch_kick(const double *acc, const int32_t *rung, int64_t n, double dt_top, int rmin,
+                      bool twice, double *vel, double *amag, hipStream_t s);
+void trad_launch_drift(const double *vel, const int32_t *rung, int64_t n, double dt_top, int rmin,
+                       double *pos, hipStream_t s);
 // out[0] = min_i (a[i] + b[i]) over n >= 1 values; part holds
 // min(1024, ceil(n / 256)) doubles of scratch
 void hhs_launch_min_sum(const double *a, const double *b, int64_t n, double *part, double *out,

@@ -25,7 +25,7 @@ EXPORTED = (
     "fmm_forces_batched", "hhs_run_bytes", "hhs_run_create", "hhs_run_destroy",
     "hhs_init_batched", "hhs_step_batched", "serve_footprint", "serve_create", "serve_destroy",
     "serve_submit", "serve_step", "serve_poll", "serve_cancel", "serve_info",
-    "fmm_set_small_path", "fmm_set_level_prediction",
+    "fmm_set_small_path", "fmm_set_level_prediction", "trad_step",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -102,6 +102,7 @@ def lib():
         L.fmm_invariants.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
         L.hhs_init.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams)]
         L.hhs_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
+        L.trad_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
         L.fmm_build_batched.argtypes = [vp, ci, ctypes.POINTER(Request), dbl, dbl]
         L.fmm_evaluate_batched.argtypes = [vp, ci, ctypes.POINTER(Request), ci]
         L.fmm_forces_batched.argtypes = [vp, ci, ctypes.POINTER(Request), dbl, dbl, ci]
@@ -398,6 +399,16 @@ class HHS:
         stats = np.zeros(3, dtype=np.int64)
         self.solver._raise(lib().hhs_step(self.solver._h, ctypes.byref(self.state),
                                           ctypes.byref(self.params), float(dt_top), _hptr(stats)))
+        return dict(force_calls=int(stats[0]), force_particles=int(stats[1]), builds=int(stats[2]))
+
+    def trad_step(self, dt_top):
+        """One top step of the individual-timestep comparison integrator
+        (trad_step) on this state; needs no init()."""
+        import numpy as np
+        stats = np.zeros(3, dtype=np.int64)
+        self.solver._raise(lib().trad_step(self.solver._h, ctypes.byref(self.state),
+                                           ctypes.byref(self.params), float(dt_top),
+                                           _hptr(stats)))
         return dict(force_calls=int(stats[0]), force_particles=int(stats[1]), builds=int(stats[2]))
 
 

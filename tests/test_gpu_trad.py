@@ -1,0 +1,102 @@
+"""The individual-timestep comparison integrator (Sec. 2.3) on the GPU
+(trad_step) against the oracle's: same rungs, solver calls, positions,
+velocities and |a| after whole top steps (FP64); the momentum contrast with
+HHS on the GPU in both precisions; argument errors."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+from paper_1712_10116_amd import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+PRM0 = dict(W.PARAMS[0])
+
+
+def _system(solver, pos, vel, m, prm, **kw):
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    tp = torch.from_numpy(pos.copy()).cuda()
+    tv = torch.from_numpy(vel.copy()).cuda()
+    tm = torch.from_numpy(m).cuda()
+    h = F.HHS(solver, tp, tv, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
+              max_levels=prm["max_levels"], **kw)
+    return h, tp, tv, tm
+
+
+def _solver(n, prm, precision=0):
+    from paper_1712_10116_amd import fmm as F
+    return F.Solver(n, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
+                    precision=precision)
+
+
+@pytest.mark.parametrize("n,steps", [(1024, 2), (4096, 1)])
+def test_trad_matches_oracle(oracle, n, steps):
+    pos, vel, m = W.plummer(n, seed=1000)
+    prm = dict(PRM0)
+    dt = 1.0 / 16
+    T = oracle.TradOracle(p=prm["p"], theta=prm["theta"], eps=prm["eps"],
+                          leaf_size=prm["leaf_size"], kernel=prm["kernel"], eta=prm["eta"],
+                          max_levels=prm["max_levels"])
+    st = oracle.HHSState(pos, vel, m)
+    calls = []
+    for _ in range(steps):
+        c0 = st.force_calls
+        T.step(st, dt)
+        calls.append(st.force_calls - c0)
+    s = _solver(n, prm)
+    h, tp, tv, _ = _system(s, pos, vel, m, prm)
+    stats = [h.trad_step(dt) for _ in range(steps)]
+    gp, gv = tp.cpu().numpy(), tv.cpu().numpy()
+    grung, gac, gao = h.rung.cpu().numpy(), h.a_cur.cpu().numpy(), h.a_old.cpu().numpy()
+    s.close()
+    assert [x["force_calls"] for x in stats] == calls
+    np.testing.assert_array_equal(grung, st.rung)
+    assert len(np.unique(grung)) >= 3
+    assert np.abs(gp - st.pos).max() / np.abs(pos).max() < 1e-10
+    assert np.abs(gv - st.vel).max() / np.abs(vel).max() < 1e-10
+    np.testing.assert_allclose(gac, st.a_cur, rtol=1e-10)
+    assert (gao == 0).all()
+    assert sum(x["force_particles"] for x in stats) == st.force_particles
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_trad_breaks_momentum_hhs_keeps_it(precision):
+    pos, vel, m = W.plummer(8192, seed=1000)
+    prm = dict(PRM0)
+    dt = 1.0 / 16
+    P0 = (m * vel).sum(axis=1)
+    scale = (m * np.sqrt((vel * vel).sum(axis=0))).sum()
+    s = _solver(8192, prm, precision)
+    h, tp, tv, tm = _system(s, pos, vel, m, prm)
+    st = h.trad_step(dt)
+    assert st["force_calls"] >= 9
+    dp_trad = np.abs(s.invariants(pos=tp, vel=tv, mass=tm)["P"] - P0).max() / scale
+    g, tp2, tv2, tm2 = _system(s, pos, vel, m, prm)
+    g.init()
+    g.step(dt)
+    dp_hhs = np.abs(s.invariants(pos=tp2, vel=tv2, mass=tm2)["P"] - P0).max() / scale
+    s.close()
+    assert dp_hhs < (1e-13 if precision == 0 else 1e-6)
+    assert dp_trad > 1e-7
+    assert dp_trad > 100 * dp_hhs
+
+
+def test_trad_argument_errors():
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    pos, vel, m = W.plummer(512, seed=1000)
+    prm = dict(PRM0)
+    s = _solver(512, prm)
+    h, _, _, _ = _system(s, pos, vel, m, prm, freeze_rungs=True)
+    with pytest.raises(F.FMMError):
+        h.trad_step(0.0)
+    h.rung.fill_(prm["max_levels"])  # frozen rungs outside 0..max_levels-1
+    with pytest.raises(F.FMMError):
+        h.trad_step(1.0 / 16)
+    h.rung.fill_(1)                  # frozen at rung 1: two ticks
+    st = h.trad_step(1.0 / 16)
+    assert st["force_calls"] == 3 and st["force_particles"] == 3 * 512
+    torch.cuda.synchronize()
+    s.close()
+    del F
