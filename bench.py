@@ -602,9 +602,34 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         rungs = torch.bincount(h.rung.long()).cpu().numpy().tolist()
+        # momentum change over the step, against sum m |a| dt_top (FP64 acc of the timed solves)
+        a64 = res["fp64"]["acc"]
+        p_scale = float((mass * np.sqrt((a64 * a64).sum(axis=0))).sum()) * dt_top
+        P0 = (mass * vel).sum(axis=1)
+
+        def dp(pp, vv):
+            return float(np.abs(s.invariants(pos=pp, vel=vv, mass=tm)["P"] - P0).max() / p_scale)
+
         line["hhs"] = {"dt_top": dt_top, "seconds": round(t1 - t0, 4), **st,
                        "particles_per_s": round(st["force_particles"] / (t1 - t0), 1),
-                       "rung_histogram": rungs}
+                       "rung_histogram": rungs, "momentum_change": dp(tpp, tv)}
+        # the paper's comparison integrator (individual timesteps, Sec. 2.3) on
+        # the same particles and top step: 1 + 2^R all-particle solves
+        progress("individual-timestep step")
+        tpp = tp.clone()
+        tv = torch.from_numpy(vel).to(dev)
+        g = F.HHS(s, tpp, tv, tm, eps=eps, theta=prm["theta"], p=prm["p"], eta=0.0025,
+                  max_levels=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = g.trad_step(dt_top)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        line["trad"] = {"dt_top": dt_top, "seconds": round(t1 - t0, 4), **st,
+                        "particles_per_s": round(st["force_particles"] / (t1 - t0), 1),
+                        "solves_per_s": round(st["force_calls"] / (t1 - t0), 1),
+                        "rung_histogram": torch.bincount(g.rung.long()).cpu().numpy().tolist(),
+                        "momentum_change": dp(tpp, tv)}
         s.close()
 
     if "mixed_named" in res:
