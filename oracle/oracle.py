@@ -230,6 +230,7 @@ class HHSState:
         n = self.mass.shape[0]
         self.a_old = np.zeros(n)   # |a| from the latest second kickS2F
         self.a_cur = np.zeros(n)   # |a| from the latest second kickFS2S
+        self.a_tot = np.zeros(n)   # |a| of the latest all-particle kickFS2S (Eq. 9)
         self.rung = np.zeros(n, dtype=np.int32)
         self.t = 0.0
         self.force_calls = 0
@@ -246,12 +247,22 @@ class HHSOracle:
     at rung k the slow set is {rung <= k}, the fast set {rung > k}; rungs of the
     system are recomputed on entry when calc_timestep is set; a_old is refreshed
     at second kickS2F kicks and a_cur at second kickFS2S kicks (Algorithm 3).
+
+    With eta1 > 0 the timestep is also bounded by sqrt(eta1*eps/|a|_tot)
+    (Eq. 9, Sec. 3.4): a rung must satisfy both (dt_r*dt_r)*(|a_old|+|a_cur|)
+    <= eta*eps and (dt_r*dt_r)*|a|_tot <= eta1*eps.  |a|_tot is the magnitude
+    of the acceleration due to all the mass, taken where the solver sees every
+    particle: the full solve of init_forces, then the second kickFS2S of each
+    top-level (rung 0) KDK, whose joint set is the whole system; a top-level
+    KDK with no slow particle skips that kick and leaves |a|_tot as it was.
     """
 
-    def __init__(self, *, p, theta, eps, leaf_size, kernel, eta, max_levels, freeze_rungs=False):
+    def __init__(self, *, p, theta, eps, leaf_size, kernel, eta, max_levels, freeze_rungs=False,
+                 eta1=0.0):
         self.kw = dict(p=p, theta=theta, eps=eps, leaf_size=leaf_size, kernel=kernel)
         self.eps = float(eps)
         self.eta = float(eta)
+        self.eta1 = float(eta1)
         self.max_levels = int(max_levels)
         self.freeze_rungs = bool(freeze_rungs)
 
@@ -265,6 +276,7 @@ class HHSOracle:
         acc, pot = self.forces(st, idx, st.mass)
         st.a_cur = np.sqrt((acc * acc).sum(axis=0))
         st.a_old = np.zeros_like(st.a_cur)
+        st.a_tot = st.a_cur.copy()
         return acc, pot
 
     def rungs(self, st, idx, dt_top):
@@ -274,14 +286,18 @@ class HHSOracle:
         for k in range(self.max_levels - 1, -1, -1):
             dtk = np.ldexp(dt_top, -k)
             ok = (dtk * dtk) * a <= rhs
+            if self.eta1 > 0:
+                ok &= (dtk * dtk) * st.a_tot[idx] <= self.eta1 * self.eps
             r = np.where(ok, k, r)
         return r
 
-    def kick(self, st, sys1, joint, dt, kick_s2f, second):
+    def kick(self, st, sys1, joint, dt, kick_s2f, second, top=False):
         mass = st.mass.copy()
         if kick_s2f:
             mass[sys1] = 0.0
         acc, _ = self.forces(st, joint, mass)
+        if top and second and not kick_s2f:   # every particle is a sink here (Eq. 9)
+            st.a_tot[joint] = np.sqrt((acc * acc).sum(axis=0))
         pos_in_joint = np.searchsorted(joint, sys1)
         a1 = acc[:, pos_in_joint]
         st.vel[:, sys1] += a1 * dt
@@ -292,7 +308,7 @@ class HHSOracle:
             else:
                 st.a_cur[sys1] = mag
 
-    def kdk(self, st, slow, fast, sysall, dt):
+    def kdk(self, st, slow, fast, sysall, dt, k=1):
         # Algorithm 2.  A kick whose sink set is empty, or a kickS2F whose source
         # set S is empty (every force would be zero), is skipped; this is what
         # makes a two-rung system cost 2 + 2 + 2^(k+1) solver calls (Sec. 2.2).
@@ -303,7 +319,7 @@ class HHSOracle:
             self.kick(st, slow, sysall, dt / 2, False, False)
         st.pos[:, slow] += st.vel[:, slow] * dt
         if len(slow):
-            self.kick(st, slow, sysall, dt / 2, False, True)
+            self.kick(st, slow, sysall, dt / 2, False, True, top=(k == 0))
         if s2f:
             self.kick(st, fast, sysall, dt / 2, True, True)
 
@@ -315,7 +331,7 @@ class HHSOracle:
         fast = sysall[r > k]
         if len(fast):
             self.evolve(st, k + 1, fast, dt / 2, False, dt_top)
-        self.kdk(st, slow, fast, sysall, dt)
+        self.kdk(st, slow, fast, sysall, dt, k)
         if len(fast):
             self.evolve(st, k + 1, fast, dt / 2, True, dt_top)
 
