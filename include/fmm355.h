@@ -220,6 +220,9 @@ typedef struct {
     int32_t *rung;    /* device, n: timestep rung (0 = dt_top)                  */
     int64_t n;
     double t;         /* host-side time, advanced by hhs_step                    */
+    double *a_tot;    /* device, n, or NULL: |a| due to all the mass, from the
+                         full solve of hhs_init and then the second kickFS2S of
+                         each top-level KDK (Eq. 9); needed when eta1 > 0      */
 } hhs_state;
 
 typedef struct {
@@ -228,15 +231,22 @@ typedef struct {
     double eta;        /* timestep dt_i = sqrt(eta * eps / (|a_old| + |a_cur|))  */
     int max_levels;    /* rungs 0 .. max_levels-1 (>= 1)                         */
     int freeze_rungs;  /* nonzero: keep the rungs in state->rung                 */
+    double eta1;       /* > 0: also dt_i <= sqrt(eta1 * eps / |a|_tot) (Eq. 9,
+                          Sec. 3.4); 0: off                                     */
 } hhs_params;
 
-/* Full force solve on all n particles, then a_cur = |a|, a_old = 0. */
+/* Full force solve on all n particles, then a_cur = |a|, a_old = 0 (and
+ * a_tot = |a| when the state has that array). */
 fmm_status hhs_init(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp);
 
 /* One top-level step of length dt_top (EVOLVE_HOLD at rung 0).  Rung of a
  * particle: the smallest r >= 0 with dt_top 2^-r <= dt_i (clamped to
  * max_levels-1), recomputed for a subsystem on entry when Algorithm 1 asks
- * for it.  At rung k the slow set is {rung <= k}, the fast set {rung > k}.
+ * for it; with eta1 > 0 the rung must also give dt_top 2^-r <= sqrt(eta1 eps /
+ * |a|_tot), and the second kickFS2S of every top-level KDK, whose solve covers
+ * the whole system, refreshes a_tot (a top-level KDK with no slow particle
+ * skips that kick and leaves a_tot as it was).  FMM_EINVAL when eta1 > 0 and
+ * a_tot is NULL, or eta1 < 0.  At rung k the slow set is {rung <= k}, the fast set {rung > k}.
  * Each KDK (Algorithm 2) evaluates kickS2F (fast sinks, masses of the fast set
  * zeroed) and kickFS2S (slow sinks, all masses) on one tree built over the
  * joint set; a kick with no sinks, or a kickS2F with an empty slow set, is

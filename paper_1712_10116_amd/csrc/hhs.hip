@@ -8,22 +8,38 @@
 #include "hhs_kernels.h"
 
 // rung = smallest k with dt_top 2^-k <= sqrt(eta eps / a), a = |a_old| + |a_cur|,
-// decided as (dt_k dt_k) a <= eta eps (no square root), clamped to L-1
+// decided as (dt_k dt_k) a <= eta eps (no square root), clamped to L-1; with
+// a_tot (Eq. 9) the rung must also satisfy (dt_k dt_k) |a|_tot <= eta1 eps
 __global__ __launch_bounds__(FMM_BLOCK) void k_rungs(const int32_t *__restrict__ sys, int n_sys,
                                                      const double *__restrict__ a_old,
                                                      const double *__restrict__ a_cur,
+                                                     const double *__restrict__ a_tot,
                                                      int32_t *__restrict__ rung, double dt_top,
-                                                     double eta_eps, int max_levels) {
+                                                     double eta_eps, double eta1_eps,
+                                                     int max_levels) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_sys) return;
   int p = sys[i];
   double a = a_old[p] + a_cur[p];
+  const double at = a_tot ? a_tot[p] : 0.0;
   int r = max_levels - 1;
   for (int k = max_levels - 1; k >= 0; --k) {
     double dtk = ldexp(dt_top, -k);
-    if ((dtk * dtk) * a <= eta_eps) r = k;
+    bool ok = (dtk * dtk) * a <= eta_eps;
+    if (a_tot) ok = ok && (dtk * dtk) * at <= eta1_eps;
+    if (ok) r = k;
   }
   rung[p] = r;
+}
+
+// out[sys[q]] = |a| of row q of a joint-set acceleration (SoA, n_sys rows)
+__global__ __launch_bounds__(FMM_BLOCK) void k_norm_at(const int32_t *__restrict__ sys,
+                                                       int n_sys, const double *__restrict__ acc,
+                                                       double *__restrict__ out) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_sys) return;
+  const double ax = acc[q], ay = acc[n_sys + q], az = acc[2 * n_sys + q];
+  out[sys[q]] = sqrt(ax * ax + ay * ay + az * az);
 }
 
 // flag[i] = 1 if sys[i] is fast at rung k (rung > k)
@@ -253,10 +269,17 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_invariants(const double *__restri
 #define NB(n) dim3((unsigned)(((n) + FMM_BLOCK - 1) / FMM_BLOCK))
 
 void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const double *a_cur,
-                      int32_t *rung, double dt_top, double eta_eps, int max_levels, hipStream_t s) {
+                      const double *a_tot, int32_t *rung, double dt_top, double eta_eps,
+                      double eta1_eps, int max_levels, hipStream_t s) {
   if (n_sys > 0)
-    hipLaunchKernelGGL(k_rungs, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, a_old, a_cur, rung,
-                       dt_top, eta_eps, max_levels);
+    hipLaunchKernelGGL(k_rungs, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, a_old, a_cur, a_tot,
+                       rung, dt_top, eta_eps, eta1_eps, max_levels);
+}
+
+void hhs_launch_norm_at(const int32_t *sys, int n_sys, const double *acc, double *out,
+                        hipStream_t s) {
+  if (n_sys > 0)
+    hipLaunchKernelGGL(k_norm_at, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, acc, out);
 }
 
 void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,

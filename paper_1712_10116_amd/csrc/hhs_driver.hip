@@ -167,8 +167,9 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
     switch (f.pc) {
       case 0:  // (re)assign rungs, split into slow {rung <= k} and fast {rung > k}
         if (f.calc && !hp->freeze_rungs)
-          hhs_launch_rungs(f.sys, f.n_sys, st->a_old, st->a_cur, st->rung, S.dt_top,
-                           hp->eta * hp->eps, hp->max_levels, c->stream);
+          hhs_launch_rungs(f.sys, f.n_sys, st->a_old, st->a_cur,
+                           hp->eta1 > 0 ? st->a_tot : nullptr, st->rung, S.dt_top,
+                           hp->eta * hp->eps, hp->eta1 * hp->eps, hp->max_levels, c->stream);
         hhs_launch_split(f.sys, f.n_sys, st->rung, k, r->flag, r->scan_part, r->slow[k],
                          r->slow_pos[k], r->fast[k], r->fast_pos[k], c->split_cnt + slot,
                          c->stream);
@@ -267,6 +268,10 @@ static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const 
         hhs_launch_kick(S.run->slow[k], S.run->slow_pos[k], f.n_slow, S.run->acc, f.n_sys,
                         S.st->vel, S.st->n, 0.5 * f.dt, K.second ? S.st->a_cur : nullptr,
                         c->stream);
+      // Eq. 9: the second kickFS2S of a top-level KDK sees every particle as a
+      // sink, so its solve gives |a|_tot for the whole system
+      if (!K.s2f && K.second && k == 0 && S.st->a_tot)
+        hhs_launch_norm_at(f.sys, f.n_sys, S.run->acc, S.st->a_tot, c->stream);
       ++*kicks;
       ++S.kicks;
       S.parts += f.n_sys;
@@ -291,6 +296,8 @@ static fmm_status check_system(fmm_ctx *c, hhs_run *r, hhs_state *st, const hhs_
   if (!st->pos || !st->vel || !st->mass || !st->a_old || !st->a_cur || !st->rung)
     return fmm_fail(c, FMM_EINVAL, "NULL state array");
   if (hp->max_levels + 1 > r->levels) return fmm_fail(c, FMM_EINVAL, "scratch has too few rungs");
+  if (hp->eta1 > 0 && !st->a_tot)
+    return fmm_fail(c, FMM_EINVAL, "eta1 > 0 needs the a_tot array");
   return FMM_OK;
 }
 
@@ -310,7 +317,7 @@ static fmm_status check_distinct(fmm_ctx *c, int n_sys, hhs_run *const *runs,
 static fmm_status check_params(fmm_ctx *c, const hhs_params *hp) {
   if (!c || !hp) return FMM_EINVAL;
   if (hp->max_levels < 1 || hp->max_levels > 30 || !(hp->eta > 0) || hp->p < 1 ||
-      hp->p > c->prm.p_max)
+      hp->p > c->prm.p_max || !(hp->eta1 >= 0))
     return fmm_fail(c, FMM_EINVAL, "bad HHS parameters");
   return FMM_OK;
 }
@@ -337,8 +344,12 @@ extern "C" fmm_status hhs_init_batched(fmm_ctx *c, int n_sys, hhs_run *const *ru
     if (e != FMM_OK) return e;
     g0 = g1;
   }
-  for (int i = 0; i < n_sys; ++i)
+  for (int i = 0; i < n_sys; ++i) {
     hhs_launch_amag(runs[i]->acc, states[i]->n, states[i]->a_cur, states[i]->a_old, c->stream);
+    if (states[i]->a_tot)
+      hhs_launch_norm_at(runs[i]->all_idx, (int)states[i]->n, runs[i]->acc, states[i]->a_tot,
+                         c->stream);
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess)
     return fmm_fail(c, FMM_EDEVICE, "hhs_init synchronisation failed");
   return FMM_OK;
@@ -499,8 +510,8 @@ extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp,
   parts += n;
   hhs_launch_amag(r->acc, n, st->a_cur, st->a_old, s);
   if (!hp->freeze_rungs)
-    hhs_launch_rungs(r->all_idx, (int)n, st->a_old, st->a_cur, st->rung, dt_top,
-                     hp->eta * hp->eps, hp->max_levels, s);
+    hhs_launch_rungs(r->all_idx, (int)n, st->a_old, st->a_cur, nullptr, st->rung, dt_top,
+                     hp->eta * hp->eps, 0.0, hp->max_levels, s);
   trad_launch_rung_hist(st->rung, n, c->split_cnt, s);
   int32_t cnt[32];
   if (hipMemcpyAsync(cnt, c->split_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||

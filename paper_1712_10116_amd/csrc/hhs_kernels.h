@@ -5,8 +5,13 @@
 #include <stdint.h>
 
 void hhs_launch_scan_u32(uint32_t *v, int m, uint32_t *part, hipStream_t s);
+// a_tot NULL: the bound of Eq. 9 is off
 void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const double *a_cur,
-                      int32_t *rung, double dt_top, double eta_eps, int max_levels, hipStream_t s);
+                      const double *a_tot, int32_t *rung, double dt_top, double eta_eps,
+                      double eta1_eps, int max_levels, hipStream_t s);
+// out[sys[q]] = |a| of row q of acc (SoA, n_sys rows)
+void hhs_launch_norm_at(const int32_t *sys, int n_sys, const double *acc, double *out,
+                        hipStream_t s);
 void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
                       uint32_t *scan_part, int32_t *slow, int32_t *slow_pos, int32_t *fast,
                       int32_t *fast_pos, int32_t *count, hipStream_t s);

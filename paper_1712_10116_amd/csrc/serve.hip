@@ -95,6 +95,7 @@ int64_t state_layout(hhs_state *st, char *base, int64_t n) {
   take(&mass, n);
   take(&q->a_old, n);
   take(&q->a_cur, n);
+  take(&q->a_tot, n);
   take(&q->rung, n);
   if (base) q->mass = mass;
   return align_up(off);
@@ -142,7 +143,7 @@ extern "C" fmm_status serve_create(fmm_ctx *c, const hhs_params *hp, const serve
                                    fmm_server **out) {
   if (!c || !hp || !sp || !out) return FMM_EINVAL;
   if (hp->max_levels < 1 || hp->max_levels > 30 || !(hp->eta > 0) || hp->p < 1 ||
-      hp->p > c->prm.p_max)
+      hp->p > c->prm.p_max || !(hp->eta1 >= 0))
     return fmm_fail(c, FMM_EINVAL, "bad HHS parameters");
   if (sp->arena_bytes < kAlign || sp->max_slots < 1 || !(sp->dt_max > 0))
     return fmm_fail(c, FMM_EINVAL, "bad server parameters");

@@ -70,13 +70,13 @@ class Request(ctypes.Structure):
 class HHSState(ctypes.Structure):
     _fields_ = [("pos", ctypes.c_void_p), ("vel", ctypes.c_void_p), ("mass", ctypes.c_void_p),
                 ("a_old", ctypes.c_void_p), ("a_cur", ctypes.c_void_p), ("rung", ctypes.c_void_p),
-                ("n", ctypes.c_int64), ("t", ctypes.c_double)]
+                ("n", ctypes.c_int64), ("t", ctypes.c_double), ("a_tot", ctypes.c_void_p)]
 
 
 class HHSParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("theta", ctypes.c_double), ("p", ctypes.c_int),
                 ("eta", ctypes.c_double), ("max_levels", ctypes.c_int),
-                ("freeze_rungs", ctypes.c_int)]
+                ("freeze_rungs", ctypes.c_int), ("eta1", ctypes.c_double)]
 
 
 _lib = None
@@ -370,7 +370,7 @@ class HHS:
     in hhs_init_batched / hhs_step_batched with other systems."""
 
     def __init__(self, solver, pos, vel, mass, *, eps, theta, p, eta, max_levels,
-                 freeze_rungs=False, run=None):
+                 freeze_rungs=False, run=None, eta1=0.0):
         self.solver = solver
         self.run = run
         n = pos.shape[1]
@@ -381,10 +381,12 @@ class HHS:
         self.a_old = torch.zeros(n, dtype=torch.float64, device=dev)
         self.a_cur = torch.zeros(n, dtype=torch.float64, device=dev)
         self.rung = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.a_tot = torch.zeros(n, dtype=torch.float64, device=dev)
         self.state = HHSState(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), self.a_old.data_ptr(),
-                              self.a_cur.data_ptr(), self.rung.data_ptr(), n, 0.0)
+                              self.a_cur.data_ptr(), self.rung.data_ptr(), n, 0.0,
+                              self.a_tot.data_ptr())
         self.params = HHSParams(float(eps), float(theta), int(p), float(eta), int(max_levels),
-                                int(bool(freeze_rungs)))
+                                int(bool(freeze_rungs)), float(eta1))
 
     @property
     def t(self):
@@ -444,9 +446,10 @@ class Server:
     them, with the output arrays, alive until the request's result is polled."""
 
     def __init__(self, solver, *, eps, theta, p, eta, max_levels, arena_bytes, max_slots,
-                 dt_max=1.0 / 16):
+                 dt_max=1.0 / 16, eta1=0.0):
         self.solver = solver
-        self.params = HHSParams(float(eps), float(theta), int(p), float(eta), int(max_levels), 0)
+        self.params = HHSParams(float(eps), float(theta), int(p), float(eta), int(max_levels), 0,
+                                float(eta1))
         sp = ServeParams(int(arena_bytes), int(max_slots), float(dt_max))
         h = ctypes.c_void_p()
         solver._raise(lib().serve_create(solver._h, ctypes.byref(self.params), ctypes.byref(sp),

@@ -11,7 +11,7 @@ from paper_1712_10116_amd import workloads as W
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 
-def _gpu_hhs(pos, vel, m, prm, steps, dt_top, precision=0, freeze=None):
+def _gpu_hhs(pos, vel, m, prm, steps, dt_top, precision=0, freeze=None, eta1=0.0, a_tot=None):
     import torch
     from paper_1712_10116_amd import fmm as F
     n = m.size
@@ -21,12 +21,14 @@ def _gpu_hhs(pos, vel, m, prm, steps, dt_top, precision=0, freeze=None):
     tv = torch.from_numpy(vel.copy()).cuda()
     tm = torch.from_numpy(m).cuda()
     h = F.HHS(s, tp, tv, tm, eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
-              max_levels=prm["max_levels"], freeze_rungs=freeze is not None)
+              max_levels=prm["max_levels"], freeze_rungs=freeze is not None, eta1=eta1)
     h.init()
     if freeze is not None:
         h.rung.copy_(torch.from_numpy(freeze.astype(np.int32)).cuda())
     stats = [h.step(dt_top) for _ in range(steps)]
     inv = s.invariants(pos=tp, vel=tv, mass=tm)
+    if a_tot is not None:
+        a_tot.append(h.a_tot.cpu().numpy())
     out = (tp.cpu().numpy(), tv.cpu().numpy(), h.rung.cpu().numpy(), h.a_old.cpu().numpy(),
            h.a_cur.cpu().numpy(), stats, inv)
     s.close()
@@ -36,10 +38,10 @@ def _gpu_hhs(pos, vel, m, prm, steps, dt_top, precision=0, freeze=None):
 PRM0 = dict(W.PARAMS[0])
 
 
-def _oracle_hhs(oracle, pos, vel, m, prm, steps, dt_top):
+def _oracle_hhs(oracle, pos, vel, m, prm, steps, dt_top, eta1=0.0):
     H = oracle.HHSOracle(p=prm["p"], theta=prm["theta"], eps=prm["eps"],
                          leaf_size=prm["leaf_size"], kernel=prm["kernel"], eta=prm["eta"],
-                         max_levels=prm["max_levels"])
+                         max_levels=prm["max_levels"], eta1=eta1)
     st = oracle.HHSState(pos, vel, m)
     H.init_forces(st)
     calls = []
@@ -133,3 +135,33 @@ def test_hhs_batched_equals_solo(precision, max_n):
     for h in hs:
         h.run.close()
     s.close()
+
+
+def test_hhs_eq9_matches_oracle(oracle):
+    """The total-acceleration bound of Eq. (9) binding on part of the system."""
+    pos, vel, m = W.plummer(1024, seed=1000)
+    prm = dict(PRM0)
+    dt_top, eta1 = 1.0 / 16, 0.0005
+    st, calls = _oracle_hhs(oracle, pos, vel, m, prm, 2, dt_top, eta1=eta1)
+    st0, _ = _oracle_hhs(oracle, pos, vel, m, prm, 2, dt_top)
+    assert (st.rung != st0.rung).any()
+    got = []
+    gp, gv, grung, gao, gac, stats, inv = _gpu_hhs(pos, vel, m, prm, 2, dt_top, eta1=eta1,
+                                                  a_tot=got)
+    np.testing.assert_array_equal(grung, st.rung)
+    assert [s["force_calls"] for s in stats] == calls
+    assert np.abs(gp - st.pos).max() / np.abs(pos).max() < 1e-10
+    assert np.abs(gv - st.vel).max() / np.abs(vel).max() < 1e-10
+    np.testing.assert_allclose(got[0], st.a_tot, rtol=1e-10)
+    np.testing.assert_allclose(gac, st.a_cur, rtol=1e-10)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_hhs_eq9_loose_bound_changes_nothing(precision):
+    pos, vel, m = W.plummer(4096, seed=1000)
+    prm = dict(PRM0)
+    a = _gpu_hhs(pos, vel, m, prm, 2, 1.0 / 16, precision)
+    b = _gpu_hhs(pos, vel, m, prm, 2, 1.0 / 16, precision, eta1=1e30)
+    for x, y in zip(a[:5], b[:5]):
+        np.testing.assert_array_equal(x, y)
+    assert [s["force_calls"] for s in a[5]] == [s["force_calls"] for s in b[5]]
