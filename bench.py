@@ -613,6 +613,22 @@ def main():
         line["hhs"] = {"dt_top": dt_top, "seconds": round(t1 - t0, 4), **st,
                        "particles_per_s": round(st["force_particles"] / (t1 - t0), 1),
                        "rung_histogram": rungs, "momentum_change": dp(tpp, tv)}
+        # the same step with the total-acceleration bound of Eq. 9 (eta1 = eta)
+        progress("HHS step with the Eq. 9 bound")
+        tpp = tp.clone()
+        tv = torch.from_numpy(vel).to(dev)
+        h = F.HHS(s, tpp, tv, tm, eps=eps, theta=prm["theta"], p=prm["p"], eta=0.0025,
+                  max_levels=10, eta1=0.0025)
+        h.init()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = h.step(dt_top)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        line["hhs_eq9"] = {"dt_top": dt_top, "eta1": 0.0025, "seconds": round(t1 - t0, 4), **st,
+                           "particles_per_s": round(st["force_particles"] / (t1 - t0), 1),
+                           "rung_histogram": torch.bincount(h.rung.long()).cpu().numpy().tolist(),
+                           "momentum_change": dp(tpp, tv)}
         # the paper's comparison integrator (individual timesteps, Sec. 2.3) on
         # the same particles and top step: 1 + 2^R all-particle solves
         progress("individual-timestep step")
