@@ -135,6 +135,14 @@ typedef struct {
                                the system is skipped, acc/pot left untouched   */
     double *acc;            /* device, 3 x n_active doubles (out)              */
     double *pot;            /* device, n_active doubles (out)                  */
+    const uint8_t *sinks;   /* device uint8[n_active], or NULL = every active
+                               particle is a sink.  With flags, acc/pot are
+                               written only for flagged particles (the others
+                               are left untouched) and P2P is skipped for
+                               leaves without a flagged particle; the flagged
+                               results equal those without flags bit for bit.
+                               Every active particle is still a source.  Read
+                               by evaluations only.                          */
 } fmm_request;
 
 /* Build the trees and lists of n_req systems at once (sum of n_active <=
@@ -267,8 +275,8 @@ fmm_status hhs_step(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp, double dt
  * with rung >= R - ctz(j+1) drift over their step, get the acceleration of a
  * solve over all particles at the stored positions, and take the closing half
  * kick and, before the last tick, the opening half kick of their next step (two
- * separate FP64 additions).  1 + 2^R force solves per call, each covering all
- * particles.  stats (host, may be NULL): [0] solves, [1] sum over the solves
+ * separate FP64 additions).  1 + 2^R force solves per call, each with a tree
+ * over all particles and the particles of the tick as its only sinks.  stats (host, may be NULL): [0] solves, [1] sum over the solves
  * of the particles kicked with their result (n for the first), [2] tree
  * builds.  Synchronous: returns after the step has finished on the device.
  * FMM_EINVAL for bad parameters, a rung outside 0..max_levels-1 (frozen

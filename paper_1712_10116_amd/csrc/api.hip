@@ -284,6 +284,7 @@ static fmm_status upload_requests(fmm_ctx *c, int n_req, const fmm_request *reqs
     hr[r].mass = q.mass;
     hr[r].acc = q.acc;
     hr[r].pot = q.pot;
+    hr[r].sinks = q.sinks;
     hr[r].n_total = q.n_total;
     hr[r].off = off;
     hr[r].n = (int32_t)q.n_active;
@@ -588,7 +589,7 @@ extern "C" fmm_status fmm_forces_batched(fmm_ctx *c, int n_req, const fmm_reques
 
 static fmm_request one_request(const double *pos, const double *mass, int64_t n_total,
                                const int32_t *active, int64_t n_active, double *acc, double *pot) {
-  fmm_request q;
+  fmm_request q = {};
   q.pos = pos;
   q.n_total = n_total;
   q.active = active;

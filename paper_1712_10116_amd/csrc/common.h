@@ -67,6 +67,7 @@ struct DevReq {
   const double *mass;     // n_total
   double *acc;            // 3 x n SoA
   double *pot;            // n
+  const uint8_t *sinks;   // n flags, or NULL: every particle is a sink
   int64_t n_total;
   int32_t off;
   int32_t n;

@@ -61,6 +61,18 @@ __device__ __forceinline__ bool skipped(const DevTree &t, int node) {
   return t.reqs[t.nreq[node]].mass == nullptr;
 }
 
+// Whether leaf A (sorted particles bA .. bA+nA-1) holds a sink of its
+// system's evaluation; every one does when the system has no sink flags.
+// Called by a whole wavefront with A the same in every lane.
+__device__ __forceinline__ bool has_sink(const DevTree &t, int A, int bA, int nA) {
+  const DevReq &q = t.reqs[t.nreq[A]];
+  if (!q.sinks) return true;
+  bool any = false;
+  for (int j = bA + (int)(threadIdx.x & 63); j < bA + nA; j += 64)
+    any = any || q.sinks[t.slot[j] - q.off] != 0;
+  return __ballot(any) != 0ull;
+}
+
 // Node range of an evaluation.  n >= 0: the host's count.  n < 0: queued
 // before the host read the tree header (the tree is checked afterwards and
 // the evaluation redone if it fails): the count comes from the header, and
@@ -367,6 +379,9 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, bool dev) {
   // the system first: leaf_of is written only for systems this evaluation covers
   const DevReq q = t.reqs[upper_index(t.req_off, t.n_req, j)];
   if (!q.mass) return;
+  const int s = t.slot[j];
+  const int64_t i = s - q.off, nq = q.n;
+  if (q.sinks && !q.sinks[i]) return;  // not a sink of this evaluation
   const int leaf = t.leaf_of[j];
   const double4 g = t.ngeo[leaf];
   const double ih = 1.0 / g.w;
@@ -376,8 +391,6 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, bool dev) {
   load_row<T, P>(L, t.kmax, leaf, Lt);
   T phi, gx, gy, gz;
   l2p_eval<T, P>(Lt, mono, phi, gx, gy, gz);
-  const int s = t.slot[j];
-  const int64_t i = s - q.off, nq = q.n;
   const int64_t cap = t.cap_n;
   q.acc[i] = t.near[j] - (double)gx * ih;
   q.acc[nq + i] = t.near[cap + j] - (double)gy * ih;
@@ -652,6 +665,7 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (t.nnchild[A] != 0 || skipped(t, A)) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
+    if (!has_sink(t, A, bA, nA)) continue;
     const double4 gA = t.ngeo[A];
     const int off = t.p2p_off[A], cnt = t.p2p_cnt[A];
     for (int tb = 0; tb < nA; tb += 64) {

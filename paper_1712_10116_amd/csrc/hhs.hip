@@ -170,6 +170,14 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_rung_kick(const double *__restric
   if (amag) amag[i] = sqrt(ax * ax + ay * ay + az * az);
 }
 
+// flag[i] = 1 for the particles whose step ends at the tick (rung >= rmin)
+__global__ __launch_bounds__(FMM_BLOCK) void k_rung_flags(const int32_t *__restrict__ rung,
+                                                          int64_t n, int rmin,
+                                                          uint8_t *__restrict__ flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = rung[i] >= rmin ? 1 : 0;
+}
+
 __global__ __launch_bounds__(FMM_BLOCK) void k_rung_drift(const double *__restrict__ vel,
                                                           const int32_t *__restrict__ rung,
                                                           int64_t n, double dt_top, int rmin,
@@ -331,6 +339,10 @@ void trad_launch_kick(const double *acc, const int32_t *rung, int64_t n, double 
   if (n > 0)
     hipLaunchKernelGGL(k_rung_kick, NB(n), dim3(FMM_BLOCK), 0, s, acc, rung, n, dt_top, rmin,
                        twice, vel, amag);
+}
+
+void trad_launch_flags(const int32_t *rung, int64_t n, int rmin, uint8_t *flag, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_rung_flags, NB(n), dim3(FMM_BLOCK), 0, s, rung, n, rmin, flag);
 }
 
 void trad_launch_drift(const double *vel, const int32_t *rung, int64_t n, double dt_top, int rmin,

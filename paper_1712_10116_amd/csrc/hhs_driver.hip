@@ -480,8 +480,9 @@ extern "C" fmm_status hhs_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp, 
 // The comparison integrator of Sec. 2.3: individual (block) timesteps, every
 // force evaluation giving the particles whose step ends the acceleration due
 // to all the mass, with the particles that are not active where their last
-// step left them.  Each tick's solve covers all particles (one tree over the
-// whole system); only the active ones are kicked with its result.
+// step left them.  Each tick's solve builds one tree over the whole system
+// and evaluates only the active particles as sinks (sink flags: P2P skips
+// leaves without one, L2P writes only theirs).
 extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp, double dt_top,
                                 int64_t stats[3]) {
   fmm_status e = check_params(c, hp);
@@ -499,13 +500,14 @@ extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp,
   const int64_t n = st->n;
   hipStream_t s = c->stream;
   int64_t calls = 0, parts = 0;
-  auto solve = [&]() {
+  uint8_t *sinks = (uint8_t *)r->flag;  // n bytes of the run's flag scratch
+  auto solve = [&](const uint8_t *flags) {
     ++calls;
-    return fmm_forces(c, st->pos, st->mass, n, nullptr, n, hp->eps, hp->theta, hp->p, r->acc,
-                      r->pot);
+    fmm_request q = {st->pos, n, nullptr, n, st->mass, r->acc, r->pot, flags};
+    return fmm_forces_batched(c, 1, &q, hp->eps, hp->theta, hp->p);
   };
   // rungs from |a| of an all-particle solve at the start of the top step
-  e = solve();
+  e = solve(nullptr);
   if (e != FMM_OK) return e;
   parts += n;
   hhs_launch_amag(r->acc, n, st->a_cur, st->a_old, s);
@@ -530,7 +532,8 @@ extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp,
     while (!(((j + 1) >> tz) & 1)) ++tz;  // trailing zeros of j + 1
     const int rmin = std::max(0, R - tz);
     trad_launch_drift(st->vel, st->rung, n, dt_top, rmin, st->pos, s);
-    e = solve();
+    trad_launch_flags(st->rung, n, rmin, sinks, s);
+    e = solve(rmin > 0 ? sinks : nullptr);
     if (e != FMM_OK) return e;
     for (int k = rmin; k <= R; ++k) parts += cnt[k];
     trad_launch_kick(r->acc, st->rung, n, dt_top, rmin, j + 1 < ticks, st->vel, st->a_cur, s);

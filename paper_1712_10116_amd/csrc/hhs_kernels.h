@@ -33,6 +33,8 @@ void trad_launch_kick(const double *acc, const int32_t *rung, int64_t n, double 
                       bool twice, double *vel, double *amag, hipStream_t s);
 void trad_launch_drift(const double *vel, const int32_t *rung, int64_t n, double dt_top, int rmin,
                        double *pos, hipStream_t s);
+// flag[i] = rung[i] >= rmin (the sinks of a tick)
+void trad_launch_flags(const int32_t *rung, int64_t n, int rmin, uint8_t *flag, hipStream_t s);
 // out[0] = min_i (a[i] + b[i]) over n >= 1 values; part holds
 // min(1024, ceil(n / 256)) doubles of scratch
 void hhs_launch_min_sum(const double *a, const double *b, int64_t n, double *part, double *out,

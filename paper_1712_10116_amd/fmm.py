@@ -64,7 +64,7 @@ class Request(ctypes.Structure):
     """One independent system of a batched solve (fmm_request)."""
     _fields_ = [("pos", ctypes.c_void_p), ("n_total", ctypes.c_int64), ("active", ctypes.c_void_p),
                 ("n_active", ctypes.c_int64), ("mass", ctypes.c_void_p), ("acc", ctypes.c_void_p),
-                ("pot", ctypes.c_void_p)]
+                ("pot", ctypes.c_void_p), ("sinks", ctypes.c_void_p)]
 
 
 class HHSState(ctypes.Structure):
@@ -212,8 +212,17 @@ class Solver:
                                        int(p), _ptr(acc), _ptr(pot)))
         return acc, pot
 
-    def forces(self, pos, mass, active=None, *, eps, theta, p, acc=None, pot=None):
-        """Build and evaluate in one call (fmm_forces)."""
+    def forces(self, pos, mass, active=None, *, eps, theta, p, acc=None, pot=None, sinks=None):
+        """Build and evaluate in one call (fmm_forces).  sinks: optional uint8
+        flags over the active set; then only flagged particles get acc/pot."""
+        if sinks is not None:
+            d = dict(pos=pos, mass=mass, sinks=sinks, acc=acc, pot=pot)
+            if active is not None:
+                d["active"] = active
+            arr, outs = self._requests([d], True)
+            self._raise(lib().fmm_forces_batched(self._h, 1, arr, float(eps), float(theta),
+                                                 int(p)))
+            return outs[0]
         n_total = pos.shape[1]
         _check_dev(pos, torch.float64, (3, n_total), "pos")
         n = n_total if active is None else active.shape[0]
@@ -251,7 +260,13 @@ class Solver:
                     acc = torch.empty((3, n), dtype=torch.float64, device=pos.device)
                 if pot is None:
                     pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+                _check_dev(acc, torch.float64, (3, n), "acc")
+                _check_dev(pot, torch.float64, (n,), "pot")
                 q.mass, q.acc, q.pot = mass.data_ptr(), acc.data_ptr(), pot.data_ptr()
+                sinks = sysd.get("sinks")
+                if sinks is not None:
+                    _check_dev(sinks, torch.uint8, (n,), "sinks")
+                    q.sinks = sinks.data_ptr()
                 outs.append((acc, pot))
         return arr, outs
 

@@ -100,3 +100,34 @@ def test_trad_argument_errors():
     torch.cuda.synchronize()
     s.close()
     del F
+
+
+@pytest.mark.parametrize("precision,kernel", [(0, 0), (1, 0), (1, 1)])
+def test_sink_flags_equal_full_solve(precision, kernel):
+    """Sink flags (the solves of trad_step): flagged particles get exactly the
+    results of the solve without flags, the others keep their outputs, with
+    and without an active subset; random and spatially clustered flags."""
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    pos, vel, m = W.plummer(20000, seed=1000)
+    rng = np.random.default_rng(7)
+    s = F.Solver(20000, p_max=4, leaf_size=32, kernel=kernel, precision=precision)
+    tp = torch.from_numpy(pos).cuda()
+    tm = torch.from_numpy(m).cuda()
+    kw = dict(eps=0.01, theta=0.5, p=4)
+    for active in (None, np.sort(rng.choice(20000, 12000, replace=False)).astype(np.int32)):
+        ta = None if active is None else torch.from_numpy(active).cuda()
+        n = 20000 if active is None else active.size
+        a_full, p_full = s.forces(tp, tm, ta, **kw)
+        ref_a, ref_p = a_full.cpu().numpy(), p_full.cpu().numpy()
+        sub = pos if active is None else pos[:, active]
+        for flags in (rng.random(n) < 0.1, sub[0] > 0.5, np.zeros(n, dtype=bool)):
+            tf = torch.from_numpy(flags.astype(np.uint8)).cuda()
+            acc = torch.full((3, n), 7.0, dtype=torch.float64, device="cuda")
+            pot = torch.full((n,), 7.0, dtype=torch.float64, device="cuda")
+            s.forces(tp, tm, ta, acc=acc, pot=pot, sinks=tf, **kw)
+            ga, gp = acc.cpu().numpy(), pot.cpu().numpy()
+            np.testing.assert_array_equal(ga[:, flags], ref_a[:, flags])
+            np.testing.assert_array_equal(gp[flags], ref_p[flags])
+            assert (ga[:, ~flags] == 7.0).all() and (gp[~flags] == 7.0).all()
+    s.close()
