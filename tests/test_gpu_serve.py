@@ -36,10 +36,10 @@ def _solver(max_n, precision):
                     precision=precision)
 
 
-def _server(s, arena, slots):
+def _server(s, arena, slots, eta1=0.0):
     from paper_1712_10116_amd import fmm as F
     return F.Server(s, eps=PRM["eps"], theta=PRM["theta"], p=PRM["p"], eta=PRM["eta"],
-                    max_levels=PRM["max_levels"], arena_bytes=arena, max_slots=slots)
+                    max_levels=PRM["max_levels"], arena_bytes=arena, max_slots=slots, eta1=eta1)
 
 
 def _drain(srv, got, limit=10000):
@@ -98,19 +98,21 @@ def test_alone_equals_mix(precision):
     s.close()
 
 
-def test_server_equals_hhs_step():
+@pytest.mark.parametrize("eta1", [0.0, 0.0005])
+def test_server_equals_hhs_step(eta1):
+    """Also with the total-acceleration bound of Eq. (9) (eta1 > 0)."""
     import torch
     from paper_1712_10116_amd import fmm as F
     pos, vel, m = _requests()[1]
     s = _solver(4096, 0)
-    srv = _server(s, F.Server.footprint(m.size, PRM["max_levels"]), 1)
+    srv = _server(s, F.Server.footprint(m.size, PRM["max_levels"]), 1, eta1)
     got = {}
     rid = srv.submit(pos, vel, m, T_END)
     _drain(srv, got)
     r = got[rid]
     srv.close()
     kw = dict(eps=PRM["eps"], theta=PRM["theta"], p=PRM["p"], eta=PRM["eta"],
-              max_levels=PRM["max_levels"])
+              max_levels=PRM["max_levels"], eta1=eta1)
     h = F.HHS(s, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda(),
               torch.from_numpy(m).cuda(), **kw)
     h.init()
