@@ -250,15 +250,16 @@ fmm_status hhs_init(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp);
 /* One top-level step of length dt_top (EVOLVE_HOLD at rung 0).  Rung of a
  * particle: the smallest r >= 0 with dt_top 2^-r <= dt_i (clamped to
  * max_levels-1), recomputed for a subsystem on entry when Algorithm 1 asks
- * for it; with eta1 > 0 the rung must also give dt_top 2^-r <= sqrt(eta1 eps /
- * |a|_tot), and the second kickFS2S of every top-level KDK, whose solve covers
- * the whole system, refreshes a_tot (a top-level KDK with no slow particle
- * skips that kick and leaves a_tot as it was).  FMM_EINVAL when eta1 > 0 and
- * a_tot is NULL, or eta1 < 0.  At rung k the slow set is {rung <= k}, the fast set {rung > k}.
+ * for it.  At rung k the slow set is {rung <= k}, the fast set {rung > k}.
  * Each KDK (Algorithm 2) evaluates kickS2F (fast sinks, masses of the fast set
  * zeroed) and kickFS2S (slow sinks, all masses) on one tree built over the
- * joint set; a kick with no sinks, or a kickS2F with an empty slow set, is
- * skipped.  Kicks and drifts are FP64.  stats (host, may be NULL):
+ * joint set, each evaluation with the kicked set as its only sinks; a kick
+ * with no sinks, or a kickS2F with an empty slow set, is skipped.  With
+ * eta1 > 0 the rung must also give dt_top 2^-r <= sqrt(eta1 eps / |a|_tot):
+ * the second kickFS2S of each top-level KDK is then evaluated at every
+ * particle and refreshes a_tot (a top-level KDK with no slow particle skips
+ * that kick and leaves a_tot as it was); FMM_EINVAL when eta1 > 0 and a_tot is
+ * NULL, or eta1 < 0.  Kicks and drifts are FP64.  stats (host, may be NULL):
  * [0] force calls, [1] sum of active particles over the calls, [2] tree builds. */
 fmm_status hhs_step(fmm_ctx *ctx, hhs_state *st, const hhs_params *hp, double dt_top,
                     int64_t stats[3]);

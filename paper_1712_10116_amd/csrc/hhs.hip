@@ -170,6 +170,13 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_rung_kick(const double *__restric
   if (amag) amag[i] = sqrt(ax * ax + ay * ay + az * az);
 }
 
+// flag[setpos[i]] = 1 (the flags were cleared first)
+__global__ __launch_bounds__(FMM_BLOCK) void k_set_flags(const int32_t *__restrict__ setpos,
+                                                         int n_set, uint8_t *__restrict__ flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_set) flag[setpos[i]] = 1;
+}
+
 // flag[i] = 1 for the particles whose step ends at the tick (rung >= rmin)
 __global__ __launch_bounds__(FMM_BLOCK) void k_rung_flags(const int32_t *__restrict__ rung,
                                                           int64_t n, int rmin,
@@ -339,6 +346,14 @@ void trad_launch_kick(const double *acc, const int32_t *rung, int64_t n, double 
   if (n > 0)
     hipLaunchKernelGGL(k_rung_kick, NB(n), dim3(FMM_BLOCK), 0, s, acc, rung, n, dt_top, rmin,
                        twice, vel, amag);
+}
+
+void hhs_launch_sink_flags(const int32_t *setpos, int n_set, int n_sys, uint8_t *flag,
+                           hipStream_t s) {
+  if (n_sys <= 0) return;
+  hipMemsetAsync(flag, 0, (size_t)n_sys, s);
+  if (n_set > 0)
+    hipLaunchKernelGGL(k_set_flags, NB(n_set), dim3(FMM_BLOCK), 0, s, setpos, n_set, flag);
 }
 
 void trad_launch_flags(const int32_t *rung, int64_t n, int rmin, uint8_t *flag, hipStream_t s) {

@@ -31,6 +31,7 @@ struct hhs_run {
   void *owned;  // device block of the run, or NULL when carved from caller memory
   int32_t *all_idx;
   uint32_t *flag, *scan_part;
+  uint8_t *sinks;  // sink flags of one evaluation over the joint set
   std::vector<int32_t *> slow, slow_pos, fast, fast_pos;  // per rung
   double *mmask, *acc, *pot;
 };
@@ -53,6 +54,7 @@ static int64_t run_layout(hhs_run *r, char *base, int64_t n, int levels) {
   q->fast_pos.resize(levels);
   take(&q->all_idx, n);
   take(&q->flag, n);
+  take(&q->sinks, n);
   take(&q->scan_part, n / 1024 + 64);
   take(&q->mmask, n);
   take(&q->acc, 3 * n);
@@ -221,7 +223,10 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
 
 // The KDK halves of W waiting systems: their trees in one batched build, then
 // the kicks of the half in two batched evaluation slots (a system with no kick
-// in a slot is skipped there), each followed by its systems' kicks.
+// in a slot is skipped there), each followed by its systems' kicks.  Each
+// evaluation takes the kicked set as its sinks (P2P skips leaves without one);
+// the second kickFS2S of a top-level KDK evaluates the whole system when the
+// bound of Eq. 9 needs |a|_tot.
 static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const hhs_params *hp,
                              int64_t *kicks) {
   std::vector<fmm_request> q(W);
@@ -243,12 +248,22 @@ static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const 
       q[w].mass = nullptr;
       if (slot >= nk[w]) continue;
       any = true;
-      if (kk[2 * w + slot].s2f) {
+      const Kick &K = kk[2 * w + slot];
+      if (K.s2f) {
         hhs_launch_masked_mass(S.st->mass, S.st->n, S.run->fast[f.k], f.n_fast, S.run->mmask,
                                c->stream);
         q[w].mass = S.run->mmask;
       } else {
         q[w].mass = S.st->mass;
+      }
+      const int n_set = K.s2f ? f.n_fast : f.n_slow;
+      const bool all = n_set == f.n_sys ||
+                       (!K.s2f && K.second && f.k == 0 && hp->eta1 > 0 && S.st->a_tot);
+      q[w].sinks = nullptr;
+      if (!all) {
+        hhs_launch_sink_flags(K.s2f ? S.run->fast_pos[f.k] : S.run->slow_pos[f.k], n_set,
+                              f.n_sys, S.run->sinks, c->stream);
+        q[w].sinks = S.run->sinks;
       }
     }
     if (!any) continue;
@@ -270,7 +285,7 @@ static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const 
                         c->stream);
       // Eq. 9: the second kickFS2S of a top-level KDK sees every particle as a
       // sink, so its solve gives |a|_tot for the whole system
-      if (!K.s2f && K.second && k == 0 && S.st->a_tot)
+      if (!K.s2f && K.second && k == 0 && hp->eta1 > 0 && S.st->a_tot)
         hhs_launch_norm_at(f.sys, f.n_sys, S.run->acc, S.st->a_tot, c->stream);
       ++*kicks;
       ++S.kicks;

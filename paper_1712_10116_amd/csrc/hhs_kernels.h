@@ -33,6 +33,9 @@ void trad_launch_kick(const double *acc, const int32_t *rung, int64_t n, double 
                       bool twice, double *vel, double *amag, hipStream_t s);
 void trad_launch_drift(const double *vel, const int32_t *rung, int64_t n, double dt_top, int rmin,
                        double *pos, hipStream_t s);
+// flags over a joint set of n_sys particles: 1 at positions setpos[0..n_set)
+void hhs_launch_sink_flags(const int32_t *setpos, int n_set, int n_sys, uint8_t *flag,
+                           hipStream_t s);
 // flag[i] = rung[i] >= rmin (the sinks of a tick)
 void trad_launch_flags(const int32_t *rung, int64_t n, int rmin, uint8_t *flag, hipStream_t s);
 // out[0] = min_i (a[i] + b[i]) over n >= 1 values; part holds
