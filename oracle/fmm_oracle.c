@@ -175,6 +175,22 @@ double orc_plummer_g(double r, double eps)
     return 1.0 / (s * sqrt(s));
 }
 
+/* (dg/dr)/r, for the force gradient (Sec. 4.1): -3/r^5 outside the Wendland
+ * radius; inside, differentiating g's polynomial term by term and dividing by
+ * r = u eps gives (105u^3 - 360u^2 + 420u - 168) / eps^5; Plummer:
+ * -3 (r^2 + eps^2)^(-5/2). */
+static double pair_dg_over_r(int kernel, double eps, double r)
+{
+    if (kernel == ORC_PLUMMER) {
+        double s = r * r + eps * eps;
+        return -3.0 / (s * s * sqrt(s));
+    }
+    if (r >= eps) return -3.0 / (r * r * r * r * r);
+    double u = r / eps;
+    double e5 = eps * eps * eps * eps * eps;
+    return (105.0 * ipow(u, 3) - 360.0 * u * u + 420.0 * u - 168.0) / e5;
+}
+
 static void pair_kernel(int kernel, double eps, double r, double *phi, double *g)
 {
     if (kernel == ORC_PLUMMER) {
@@ -581,8 +597,14 @@ void orc_tree_export(const orc_tree *t, int64_t *perm, int32_t *level, uint64_t 
 
 /* Multipoles and locals of every node are written to Mout/Lout (n_nodes x K,
  * row-major) when non-NULL, for the test-suite. */
-int orc_tree_eval_ex(const orc_tree *t, const double *mass_total, int64_t n_total,
-                     const int32_t *active, double *acc, double *pot, double *Mout, double *Lout)
+/* grad (optional, SoA 6 x n: xx, yy, zz, xy, xz, yz): the force gradient
+ * d a_i / d x_i of every sink (the tidal tensor, Sec. 4.1), from the same
+ * expansions: minus the Hessian of the local expansion at L2P, and for every
+ * P2P pair the derivative of m g(r) d with respect to the sink's position,
+ * -m (g I + (dg/dr)/r d d^T), d = x_j - x_i, applied to both sides. */
+static int tree_eval(const orc_tree *t, const double *mass_total, int64_t n_total,
+                     const int32_t *active, double *acc, double *pot, double *grad, double *Mout,
+                     double *Lout)
 {
     const int64_t n = t->n;
     if (n == 0) return ORC_OK;
@@ -602,11 +624,15 @@ int orc_tree_eval_ex(const orc_tree *t, const double *mass_total, int64_t n_tota
     double *az = (double *)calloc((size_t)n, sizeof(double));
     double *ph = (double *)calloc((size_t)n, sizeof(double));
     double *D = (double *)malloc(sizeof(double) * K);
-    if (!M || !Lc || !m || !sx[0] || !sx[1] || !sx[2] || !ax || !ay || !az || !ph || !D) {
+    double *G = grad ? (double *)calloc((size_t)(6 * n), sizeof(double)) : NULL;
+    if (!M || !Lc || !m || !sx[0] || !sx[1] || !sx[2] || !ax || !ay || !az || !ph || !D ||
+        (grad && !G)) {
         free(mi); free(M); free(Lc); free(m); free(sx[0]); free(sx[1]); free(sx[2]);
-        free(ax); free(ay); free(az); free(ph); free(D);
+        free(ax); free(ay); free(az); free(ph); free(D); free(G);
         return ORC_ENOMEM;
     }
+    /* tensor component c = (a, b): xx, yy, zz, xy, xz, yz */
+    static const int ca[6] = {0, 1, 2, 0, 0, 1}, cb[6] = {0, 1, 2, 1, 2, 2};
     for (int64_t i = 0; i < n; ++i) {
         int64_t slot = t->perm[i];
         int64_t g = active ? active[slot] : slot;
@@ -705,6 +731,19 @@ int orc_tree_eval_ex(const orc_tree *t, const double *mass_total, int64_t n_tota
             ax[i] -= g[0];
             ay[i] -= g[1];
             az[i] -= g[2];
+            if (G) { /* minus the Hessian: L[k + e_a + e_b] for |k| <= p - 2 */
+                for (int k = 0; k < K; ++k) {
+                    const int *kk = mi->k[k];
+                    if (kk[0] + kk[1] + kk[2] > p - 2) continue;
+                    double mono = mono_over_fact(mi, u, k);
+                    for (int c6 = 0; c6 < 6; ++c6) {
+                        int e[3] = {kk[0], kk[1], kk[2]};
+                        e[ca[c6]] += 1;
+                        e[cb[c6]] += 1;
+                        G[c6 * n + i] -= mono * Lc[c * K + mi->idx[e[0]][e[1]][e[2]]];
+                    }
+                }
+            }
         }
     }
     /* P2P, mutual: each unordered particle pair evaluated once */
@@ -726,6 +765,15 @@ int orc_tree_eval_ex(const orc_tree *t, const double *mass_total, int64_t n_tota
                 ay[j] -= m[i] * g * dy;
                 az[j] -= m[i] * g * dz;
                 ph[j] += m[i] * phi;
+                if (G) {
+                    double h = pair_dg_over_r(t->prm.kernel, t->prm.eps, r);
+                    double dv[3] = {dx, dy, dz};
+                    for (int c6 = 0; c6 < 6; ++c6) {
+                        double T = -h * dv[ca[c6]] * dv[cb[c6]] - (ca[c6] == cb[c6] ? g : 0.0);
+                        G[c6 * n + i] += m[j] * T;
+                        G[c6 * n + j] += m[i] * T;
+                    }
+                }
             }
         }
     }
@@ -736,12 +784,27 @@ int orc_tree_eval_ex(const orc_tree *t, const double *mass_total, int64_t n_tota
         acc[n + slot] = ay[i];
         acc[2 * n + slot] = az[i];
         pot[slot] = ph[i];
+        if (G)
+            for (int c6 = 0; c6 < 6; ++c6) grad[c6 * n + slot] = G[c6 * n + i];
     }
     if (Mout) memcpy(Mout, M, sizeof(double) * NN * K);
     if (Lout) memcpy(Lout, Lc, sizeof(double) * NN * K);
     free(mi); free(M); free(Lc); free(m); free(sx[0]); free(sx[1]); free(sx[2]);
-    free(ax); free(ay); free(az); free(ph); free(D);
+    free(ax); free(ay); free(az); free(ph); free(D); free(G);
     return ORC_OK;
+}
+
+int orc_tree_eval_ex(const orc_tree *t, const double *mass_total, int64_t n_total,
+                     const int32_t *active, double *acc, double *pot, double *Mout, double *Lout)
+{
+    return tree_eval(t, mass_total, n_total, active, acc, pot, NULL, Mout, Lout);
+}
+
+int orc_tree_eval_grad(const orc_tree *t, const double *mass_total, int64_t n_total,
+                       const int32_t *active, double *acc, double *pot, double *grad)
+{
+    if (!grad) return ORC_EINVAL;
+    return tree_eval(t, mass_total, n_total, active, acc, pot, grad, NULL, NULL);
 }
 
 int orc_tree_eval(const orc_tree *t, const double *mass_total, int64_t n_total,

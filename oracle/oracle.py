@@ -57,6 +57,7 @@ def lib():
         L.orc_tree_export.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 11
         L.orc_tree_eval_ex.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp,
                                        ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_tree_eval_grad.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp, dp]
         L.orc_tree_eval_sinks.argtypes = [ctypes.c_void_p, dp, ctypes.c_void_p, ctypes.c_void_p,
                                           i64, dp, dp]
         L.orc_direct.argtypes = [dp, dp, i64, ctypes.c_void_p, i64, ctypes.c_int,
@@ -198,6 +199,18 @@ class Tree:
             return acc, pot, M, L
         return acc, pot
 
+
+    def evaluate_grad(self, mass):
+        """acc (3,n), pot (n) and the force gradient d a_i / d x_i of every
+        sink, SoA (6,n) in the order xx, yy, zz, xy, xz, yz (Sec. 4.1)."""
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        acc = np.zeros((3, self.n))
+        pot = np.zeros(self.n)
+        grad = np.zeros((6, self.n))
+        rc = lib().orc_tree_eval_grad(self._h, _dp(mass), self.n_total, _vp(self.active),
+                                      _dp(acc), _dp(pot), _dp(grad))
+        assert rc == 0
+        return acc, pot, grad
 
     def evaluate_sinks(self, mass, sinks):
         """FMM acceleration/potential of the given active slots only."""
