@@ -116,6 +116,19 @@ fmm_status fmm_forces(fmm_ctx *ctx, const double *pos, const double *mass, int64
                       const int32_t *active, int64_t n_active, double eps, double theta,
                       int p, double *acc, double *pot);
 
+/* fmm_forces plus the force gradient d a_i / d x_i of every active particle
+ * (the tidal tensor that the fourth-order integrator of Sec. 4.1 needs from
+ * the FMM), from the same tree, lists and local expansions: minus the Hessian
+ * of the leaf's local expansion (exact derivative of the truncated expansion;
+ * zero for p = 1), plus for every particle j of the P2P partners the
+ * derivative of m_j g(r) d, d = x_j - x_i, with respect to x_i,
+ * -m_j (g I + (dg/dr)/r d d^T) (near part in FP64 in both precisions).
+ * grad: device, 6 x n_active doubles (SoA rows xx, yy, zz, xy, xz, yz), in
+ * active order.  Errors as fmm_forces, and FMM_EINVAL for a NULL grad. */
+fmm_status fmm_forces_grad(fmm_ctx *ctx, const double *pos, const double *mass, int64_t n_total,
+                           const int32_t *active, int64_t n_active, double eps, double theta,
+                           int p, double *acc, double *pot, double *grad);
+
 /* ---------------------------------------------------------------------------
  * Batched solves: several independent particle systems in one set of launches
  * ------------------------------------------------------------------------- */

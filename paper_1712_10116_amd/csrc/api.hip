@@ -621,6 +621,19 @@ extern "C" fmm_status fmm_forces(fmm_ctx *c, const double *pos, const double *ma
   return fmm_forces_batched(c, 1, &q, eps, theta, p);
 }
 
+extern "C" fmm_status fmm_forces_grad(fmm_ctx *c, const double *pos, const double *mass,
+                                      int64_t n_total, const int32_t *active, int64_t n_active,
+                                      double eps, double theta, int p, double *acc, double *pot,
+                                      double *grad) {
+  if (!c) return FMM_EINVAL;
+  if (n_active > 0 && !grad) return fail(c, FMM_EINVAL, "grad is NULL");
+  fmm_status st = fmm_forces(c, pos, mass, n_total, active, n_active, eps, theta, p, acc, pot);
+  if (st != FMM_OK || n_active == 0) return st;
+  HIPCHK(c, launch_force_gradient(c->t, c->n_nodes, (int)n_active, p, c->prm.kernel,
+                                  c->prm.precision == FMM_PREC_MIXED, eps, grad, c->stream));
+  return FMM_OK;
+}
+
 extern "C" fmm_status fmm_tree_info(fmm_ctx *c, int64_t info[9]) {
   if (!c || !info) return FMM_EINVAL;
   if (!c->tree_valid) return fail(c, FMM_ESTALE, "no tree");

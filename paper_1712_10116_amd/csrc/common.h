@@ -277,6 +277,10 @@ hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s);
 // mass gather, P2M and M2M of an evaluation on stream s (exact tree sizes)
 hipError_t launch_upward(const DevTree &t, const EvalArgs &e, hipStream_t s);
 bool eval_order_supported(int p);
+// grad.hip: force gradient of one system's n active particles (SoA 6 x n) on
+// the tree and local expansions of the evaluation just queued on stream s
+hipError_t launch_force_gradient(const DevTree &t, int n_nodes, int n, int p, int kernel,
+                                 bool mixed, double eps, double *grad, hipStream_t s);
 // hhs.hip
 hipError_t launch_gather_mask_mass(const double *mass, const int32_t *sys, int n_sys,
                                    const int32_t *flag_fast, int mask_fast, double *out,

@@ -25,7 +25,7 @@ EXPORTED = (
     "fmm_forces_batched", "hhs_run_bytes", "hhs_run_create", "hhs_run_destroy",
     "hhs_init_batched", "hhs_step_batched", "serve_footprint", "serve_create", "serve_destroy",
     "serve_submit", "serve_step", "serve_poll", "serve_cancel", "serve_info",
-    "fmm_set_small_path", "fmm_set_level_prediction", "trad_step",
+    "fmm_set_small_path", "fmm_set_level_prediction", "trad_step", "fmm_forces_grad",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -97,6 +97,7 @@ def lib():
         L.fmm_build.argtypes = [vp, vp, i64, vp, i64, dbl, dbl]
         L.fmm_evaluate.argtypes = [vp, vp, vp, i64, vp, i64, ci, vp, vp]
         L.fmm_forces.argtypes = [vp, vp, vp, i64, vp, i64, dbl, dbl, ci, vp, vp]
+        L.fmm_forces_grad.argtypes = [vp, vp, vp, i64, vp, i64, dbl, dbl, ci, vp, vp, vp]
         L.fmm_tree_info.argtypes = [vp, vp]
         L.fmm_export_tree.argtypes = [vp] + [vp] * 11
         L.fmm_invariants.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
@@ -238,6 +239,23 @@ class Solver:
         self._raise(lib().fmm_forces(self._h, _ptr(pos), _ptr(mass), n_total, _ptr(active), n,
                                      float(eps), float(theta), int(p), _ptr(acc), _ptr(pot)))
         return acc, pot
+
+    def forces_grad(self, pos, mass, active=None, *, eps, theta, p):
+        """forces() plus the force gradient d a_i/d x_i (fmm_forces_grad):
+        (acc (3,n), pot (n), grad (6,n): xx, yy, zz, xy, xz, yz)."""
+        n_total = pos.shape[1]
+        _check_dev(pos, torch.float64, (3, n_total), "pos")
+        n = n_total if active is None else active.shape[0]
+        if active is not None:
+            _check_dev(active, torch.int32, None, "active")
+        _check_dev(mass, torch.float64, (n_total,), "mass")
+        acc = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        pot = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        grad = torch.empty((6, n), dtype=torch.float64, device=pos.device)
+        self._raise(lib().fmm_forces_grad(self._h, _ptr(pos), _ptr(mass), n_total, _ptr(active),
+                                          n, float(eps), float(theta), int(p), _ptr(acc),
+                                          _ptr(pot), _ptr(grad)))
+        return acc, pot, grad
 
     def _requests(self, systems, with_outputs):
         arr = (Request * len(systems))()
