@@ -584,6 +584,28 @@ def main():
     if line_tune:
         line["autotune"] = line_tune
 
+    # force gradient d a_i/d x_i beside the forces (the input of the fourth-order
+    # integrator the paper proposes in Sec. 4.1), same particles and parameters
+    progress("force gradient")
+    s = F.Solver(n, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=F.WENDLAND,
+                 precision=F.MIXED)
+    kw = dict(eps=eps, theta=prm["theta"], p=prm["p"])
+    s.forces_grad(tp, tm, **kw)
+    reps = 5
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.forces_grad(tp, tm, **kw)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        s.forces(tp, tm, **kw)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    line["force_gradient"] = {"ms_forces_and_gradient": round((t1 - t0) / reps * 1e3, 3),
+                              "ms_forces": round((t2 - t1) / reps * 1e3, 3), "precision": "mixed"}
+    s.close()
+
     if not args.no_hhs:
         progress("HHS step")
         # one HHS top-level step of the same particles (mixed precision)
