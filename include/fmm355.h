@@ -122,7 +122,8 @@ fmm_status fmm_forces(fmm_ctx *ctx, const double *pos, const double *mass, int64
  * of the leaf's local expansion (exact derivative of the truncated expansion;
  * zero for p = 1), plus for every particle j of the P2P partners the
  * derivative of m_j g(r) d, d = x_j - x_i, with respect to x_i,
- * -m_j (g I + (dg/dr)/r d d^T) (near part in FP64 in both precisions).
+ * -m_j (g I + (dg/dr)/r d d^T), in the context's precision (pair terms on
+ * FP64 differences, summed into FP64 per source leaf).
  * grad: device, 6 x n_active doubles (SoA rows xx, yy, zz, xy, xz, yz), in
  * active order.  Errors as fmm_forces, and FMM_EINVAL for a NULL grad. */
 fmm_status fmm_forces_grad(fmm_ctx *ctx, const double *pos, const double *mass, int64_t n_total,

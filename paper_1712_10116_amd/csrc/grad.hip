@@ -6,9 +6,8 @@
 // m g(r) d (d = x_j - x_i) with respect to x_i, -m (g I + (dg/dr)/r d d^T).
 // Output SoA, 6 rows of n: xx, yy, zz, xy, xz, yz, in active order.
 //
-// The near part runs in FP64 in both precisions (one wavefront per sink
-// leaf, lanes over its sinks, the sources read in the same order by every
-// lane); the far part in the evaluation's precision.
+// Both parts run in the evaluation's precision (the near part's pair terms
+// on FP64 differences, summed into FP64 per source leaf).
 #include "common.h"
 #include "expansion.h"
 
@@ -20,34 +19,41 @@ constexpr int CA[6] = {0, 1, 2, 0, 0, 1}, CB[6] = {0, 1, 2, 1, 2, 2};
 // inside the radius g = (21u^5 - 90u^4 + 140u^3 - 84u^2 + 14)/eps^3 and h =
 // (105u^3 - 360u^2 + 420u - 168)/eps^5 (u = r/eps), outside 1/r^3 and
 // -3/r^5; Plummer: s^(-3/2) and -3 s^(-5/2), s = r^2 + eps^2.
-template <int KERNEL>
-__device__ __forceinline__ void pair_gh(double r2, double eps, double &g, double &h) {
+template <typename R, int KERNEL>
+__device__ __forceinline__ void pair_gh(R r2, R eps, R ie, R &g, R &h) {
   if (KERNEL == 1) {
-    const double s = r2 + eps * eps;
-    const double is = 1.0 / s, rs = 1.0 / sqrt(s);
+    const R rs = fast_rsqrt<R>(r2 + eps * eps), is = rs * rs;
     g = is * rs;
-    h = -3.0 * g * is;
+    h = R(-3) * g * is;
   } else {
-    const double r = sqrt(r2);
+    const R ir = fast_rsqrt<R>(r2);
+    const R r = r2 * ir;
     if (r >= eps) {
-      const double ir = 1.0 / r, ir2 = ir * ir;
+      const R ir2 = ir * ir;
       g = ir2 * ir;
-      h = -3.0 * g * ir2;
+      h = R(-3) * g * ir2;
     } else {
-      const double u = r / eps, ie = 1.0 / eps, ie3 = ie * ie * ie;
-      g = ((((21.0 * u - 90.0) * u + 140.0) * u - 84.0) * u * u + 14.0) * ie3;
-      h = (((105.0 * u - 360.0) * u + 420.0) * u - 168.0) * ie3 * ie * ie;
+      const R u = r2 > R(0) ? r * ie : R(0), ie3 = ie * ie * ie;
+      g = ((((R(21) * u - R(90)) * u + R(140)) * u - R(84)) * u * u + R(14)) * ie3;
+      h = (((R(105) * u - R(360)) * u + R(420)) * u - R(168)) * ie3 * ie * ie;
     }
   }
 }
 
-template <int KERNEL>
+// near part: one wavefront per sink leaf, lanes over its sinks, each source
+// leaf staged through LDS 64 particles at a time; pair terms in R (FP32 in the
+// mixed form, on FP64 differences), summed in R over one source leaf and then
+// into FP64
+template <typename R, int KERNEL>
 __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, double eps,
                                                         double *__restrict__ grad, int64_t nq,
                                                         int32_t off) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const R reps = (R)eps, ie = eps > 0 ? (R)(1.0 / eps) : R(0);
+  __shared__ double4 stage[FMM_BLOCK / 64][64];
+  double4 *st = stage[threadIdx.x >> 6];
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (t.nnchild[A] != 0) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
@@ -59,17 +65,31 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, 
       double G[6] = {0, 0, 0, 0, 0, 0};
       for (int q = 0; q < cnt; ++q) {
         const int B = t.p2p_src[loff + q];
-        for (int j = t.nbeg[B]; j < t.nend[B]; ++j) {
-          if (j == i) continue;
-          const double d[3] = {t.sx[j] - xi, t.sy[j] - yi, t.sz[j] - zi};
-          const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-          double g, h;
-          pair_gh<KERNEL>(r2, eps, g, h);
-          const double m = t.sm[j];
+        const int eB = t.nend[B];
+        R Gs[6] = {0, 0, 0, 0, 0, 0};
+        for (int jb = t.nbeg[B]; jb < eB; jb += 64) {
+          // up to 64 sources of leaf B staged in LDS by the wave's lanes
+          const int nj = min(64, eB - jb);
+          if (lane < nj)
+            st[lane] = make_double4(t.sx[jb + lane], t.sy[jb + lane], t.sz[jb + lane],
+                                    t.sm[jb + lane]);
+          __builtin_amdgcn_wave_barrier();
+          for (int u = 0; u < nj; ++u) {
+            if (jb + u == i) continue;
+            const double4 sv = st[u];
+            const R d[3] = {(R)(sv.x - xi), (R)(sv.y - yi), (R)(sv.z - zi)};
+            const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            R g, h;
+            pair_gh<R, KERNEL>(r2, reps, ie, g, h);
+            const R m = (R)sv.w;
 #pragma unroll
-          for (int c = 0; c < 6; ++c)
-            G[c] += m * (-h * d[CA[c]] * d[CB[c]] - (CA[c] == CB[c] ? g : 0.0));
+            for (int c = 0; c < 6; ++c)
+              Gs[c] += m * (-h * d[CA[c]] * d[CB[c]] - (CA[c] == CB[c] ? g : R(0)));
+          }
+          __builtin_amdgcn_wave_barrier();
         }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) G[c] += (double)Gs[c];
       }
       if (valid) {
         const int64_t k = t.slot[i] - off;
@@ -121,7 +141,7 @@ template <typename T, int KERNEL>
 bool dispatch_grad(const DevTree &t, int n_nodes, int n, int p, double eps, double *grad,
                    hipStream_t s) {
   const int nb = (n + FMM_BLOCK - 1) / FMM_BLOCK;
-  hipLaunchKernelGGL(k_p2p_grad<KERNEL>, dim3((n_nodes + 3) / 4), dim3(FMM_BLOCK), 0, s, t,
+  hipLaunchKernelGGL((k_p2p_grad<T, KERNEL>), dim3((n_nodes + 3) / 4), dim3(FMM_BLOCK), 0, s, t,
                      n_nodes, eps, grad, (int64_t)n, 0);
   switch (p) {
     case 1: return true;  // the Hessian of a degree-1 local expansion is zero
