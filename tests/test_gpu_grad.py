@@ -41,3 +41,23 @@ def test_grad_matches_oracle(oracle, kernel, p):
         assert check(e), (prec, e.max(), np.sqrt((e ** 2).mean()))
         assert torch.equal(a, a2) and torch.equal(pt, pt2)
         s.close()
+
+
+@pytest.mark.parametrize("n,subset", [(600, False), (5000, True)])
+def test_grad_small_path_and_active_subset(oracle, n, subset):
+    """The single-workgroup build (600 particles) and an active subset."""
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    pos, _, m = W.plummer(n, seed=1002)
+    active = None
+    if subset:
+        active = np.sort(np.random.default_rng(5).choice(n, 3000, replace=False)).astype(np.int32)
+    kw = dict(p=5, theta=0.5, eps=0.01, leaf_size=16, kernel=1)
+    _, _, ref = oracle.Tree(pos, active, **kw).evaluate_grad(m)
+    s = F.Solver(n, p_max=6, leaf_size=16, kernel=1, precision=F.FP64)
+    ta = None if active is None else torch.from_numpy(active).cuda()
+    _, _, g = s.forces_grad(torch.from_numpy(pos).cuda(), torch.from_numpy(m).cuda(), ta,
+                            eps=0.01, theta=0.5, p=5)
+    torch.cuda.synchronize()
+    assert _rel(g.cpu().numpy(), ref).max() < 1e-10
+    s.close()
