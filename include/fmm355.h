@@ -131,6 +131,35 @@ fmm_status fmm_forces_grad(fmm_ctx *ctx, const double *pos, const double *mass, 
                            int p, double *acc, double *pot, double *grad);
 
 /* ---------------------------------------------------------------------------
+ * Comoving integration factors (Sec. 3.5, Eqs. 10-11): the drift operator
+ * moves comoving positions by p/m times the integral of dt/a^2 over the step,
+ * the kick operator changes the canonical momenta by the force times the
+ * integral of dt/a; both are kept in a lookup table over the scale factor a.
+ * Host-side only (no device memory, no GPU work).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double omega_m;  /* matter density parameter (>= 0)                        */
+    double omega_l;  /* cosmological constant; curvature 1 - omega_m - omega_l */
+    double h0;       /* Hubble constant in the integrator's time unit (> 0)     */
+    double a_min, a_max; /* table range of the scale factor, 0 < a_min < a_max */
+    int n;           /* grid points, uniform in ln a (2 .. 2^24)                */
+} fmm_cosmo_params;
+typedef struct fmm_cosmo fmm_cosmo;
+
+/* Builds the table: integrals of dt/a^2 and dt/a over each grid interval,
+ * with dt = d(ln a) / H(a), H = h0 sqrt(omega_m a^-3 + (1 - omega_m - omega_l) a^-2
+ * + omega_l), each grid interval by 8-point Gauss-Legendre.  FMM_EINVAL for
+ * bad parameters or H^2 <= 0 inside the range; FMM_ENOMEM. */
+fmm_status fmm_cosmo_create(const fmm_cosmo_params *prm, fmm_cosmo **out);
+/* drift = integral of dt/a^2 and kick = integral of dt/a from a0 to a1 (both
+ * inside the table's range; a1 < a0 gives negative factors): the intervals
+ * between them from the table plus the two partial intervals by the same
+ * rule.  FMM_EINVAL for a NULL argument or a scale factor outside the range. */
+fmm_status fmm_cosmo_factors(const fmm_cosmo *tab, double a0, double a1, double *drift,
+                             double *kick);
+fmm_status fmm_cosmo_destroy(fmm_cosmo *tab);
+
+/* ---------------------------------------------------------------------------
  * Batched solves: several independent particle systems in one set of launches
  * ------------------------------------------------------------------------- */
 

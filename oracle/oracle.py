@@ -3,7 +3,8 @@
 Wraps ``liboracle.so`` (plain C, built from ``fmm_oracle.c``) and adds the
 hierarchical Hamiltonian splitting (HHS) integrator of the paper (Sec. 2.2,
 Algorithms 1-3) and the paper's comparison integrator with individual
-timesteps (Sec. 2.3) in plain numpy on top of the oracle's force solve.
+timesteps (Sec. 2.3) in plain numpy on top of the oracle's force solve, and
+the comoving drift and kick factors of Sec. 3.5 by adaptive quadrature.
 
 Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
 may import this module.  It imports nothing from the GPU package, and the GPU
@@ -412,6 +413,25 @@ class TradOracle:
                 st.vel[:, ending] += a * half[ending]
             st.a_cur[ending] = np.sqrt((a * a).sum(axis=0))
         st.t += dt_top
+
+
+# --------------------------------------------------------------------------
+# Comoving integration factors of Sec. 3.5 (Eqs. 10-11)
+# --------------------------------------------------------------------------
+def cosmo_factors(a0, a1, *, omega_m, omega_l, h0):
+    """(integral of dt/a^2, integral of dt/a) from scale factor a0 to a1, by
+    adaptive quadrature over a with dt = da / (a H(a)),
+    H = h0 sqrt(omega_m a^-3 + (1 - omega_m - omega_l) a^-2 + omega_l)."""
+    from scipy.integrate import quad
+    ok = 1.0 - omega_m - omega_l
+
+    def hub(a):
+        return h0 * np.sqrt(omega_m / a**3 + ok / a**2 + omega_l)
+
+    kw = dict(epsabs=0.0, epsrel=1e-13, limit=200)
+    drift = quad(lambda a: 1.0 / (a**3 * hub(a)), a0, a1, **kw)[0]
+    kick = quad(lambda a: 1.0 / (a**2 * hub(a)), a0, a1, **kw)[0]
+    return drift, kick
 
 
 def invariants(pos, vel, mass, acc=None, pot=None):

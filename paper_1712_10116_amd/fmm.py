@@ -26,6 +26,7 @@ EXPORTED = (
     "hhs_init_batched", "hhs_step_batched", "serve_footprint", "serve_create", "serve_destroy",
     "serve_submit", "serve_step", "serve_poll", "serve_cancel", "serve_info",
     "fmm_set_small_path", "fmm_set_level_prediction", "trad_step", "fmm_forces_grad",
+    "fmm_cosmo_create", "fmm_cosmo_factors", "fmm_cosmo_destroy",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -73,6 +74,45 @@ class HHSState(ctypes.Structure):
                 ("n", ctypes.c_int64), ("t", ctypes.c_double), ("a_tot", ctypes.c_void_p)]
 
 
+class CosmoParams(ctypes.Structure):
+    _fields_ = [("omega_m", ctypes.c_double), ("omega_l", ctypes.c_double),
+                ("h0", ctypes.c_double), ("a_min", ctypes.c_double), ("a_max", ctypes.c_double),
+                ("n", ctypes.c_int)]
+
+
+class Cosmology:
+    """Lookup table of the comoving drift and kick factors (fmm_cosmo_*)."""
+
+    def __init__(self, *, omega_m, omega_l, h0, a_min, a_max, n=1024):
+        self.params = CosmoParams(float(omega_m), float(omega_l), float(h0), float(a_min),
+                                  float(a_max), int(n))
+        h = ctypes.c_void_p()
+        st = lib().fmm_cosmo_create(ctypes.byref(self.params), ctypes.byref(h))
+        if st != FMM_OK:
+            raise FMMError(st, "cosmology table rejected its parameters")
+        self._h = h
+
+    def factors(self, a0, a1):
+        """(integral of dt/a^2, integral of dt/a) from a0 to a1."""
+        d, k = ctypes.c_double(), ctypes.c_double()
+        st = lib().fmm_cosmo_factors(self._h, float(a0), float(a1), ctypes.byref(d),
+                                     ctypes.byref(k))
+        if st != FMM_OK:
+            raise FMMError(st, "scale factor outside the table")
+        return d.value, k.value
+
+    def close(self):
+        if self._h:
+            lib().fmm_cosmo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class HHSParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("theta", ctypes.c_double), ("p", ctypes.c_int),
                 ("eta", ctypes.c_double), ("max_levels", ctypes.c_int),
@@ -98,6 +138,9 @@ def lib():
         L.fmm_evaluate.argtypes = [vp, vp, vp, i64, vp, i64, ci, vp, vp]
         L.fmm_forces.argtypes = [vp, vp, vp, i64, vp, i64, dbl, dbl, ci, vp, vp]
         L.fmm_forces_grad.argtypes = [vp, vp, vp, i64, vp, i64, dbl, dbl, ci, vp, vp, vp]
+        L.fmm_cosmo_create.argtypes = [ctypes.POINTER(CosmoParams), ctypes.POINTER(vp)]
+        L.fmm_cosmo_factors.argtypes = [vp, dbl, dbl, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+        L.fmm_cosmo_destroy.argtypes = [vp]
         L.fmm_tree_info.argtypes = [vp, vp]
         L.fmm_export_tree.argtypes = [vp] + [vp] * 11
         L.fmm_invariants.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
