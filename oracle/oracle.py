@@ -272,11 +272,18 @@ class HHSOracle:
     """
 
     def __init__(self, *, p, theta, eps, leaf_size, kernel, eta, max_levels, freeze_rungs=False,
-                 eta1=0.0):
+                 eta1=0.0, cosmo=None):
         self.kw = dict(p=p, theta=theta, eps=eps, leaf_size=leaf_size, kernel=kernel)
         self.eps = float(eps)
         self.eta = float(eta)
         self.eta1 = float(eta1)
+        # comoving form (Sec. 3.5): cosmo = dict(omega_m, omega_l, h0); the time
+        # variable is then ln a, velocities are canonical momenta per unit
+        # mass, a kick over [x0, x1] uses the integral of dt/a and a drift the
+        # integral of dt/a^2 between a = e^x0 and e^x1 (Eqs. 10-11), and a
+        # rung's step is compared in physical time, d(ln a) / H(a) at the start
+        # of the subsystem's step
+        self.cosmo = cosmo
         self.max_levels = int(max_levels)
         self.freeze_rungs = bool(freeze_rungs)
 
@@ -293,9 +300,23 @@ class HHSOracle:
         st.a_tot = st.a_cur.copy()
         return acc, pot
 
-    def rungs(self, st, idx, dt_top):
+    def hubble(self, a):
+        c = self.cosmo
+        ok = 1.0 - c["omega_m"] - c["omega_l"]
+        return c["h0"] * np.sqrt(c["omega_m"] / (a * a * a) + ok / (a * a) + c["omega_l"])
+
+    def factors(self, x0, x1):
+        """(drift, kick) factors of a step from ln a = x0 to x1."""
+        c = self.cosmo
+        return cosmo_factors(np.exp(x0), np.exp(x1), omega_m=c["omega_m"],
+                             omega_l=c["omega_l"], h0=c["h0"])
+
+    def rungs(self, st, idx, dt_top, t0=0.0):
         a = st.a_old[idx] + st.a_cur[idx]
         rhs = self.eta * self.eps
+        if self.cosmo is not None:
+            H = self.hubble(np.exp(t0))
+            rhs = rhs * (H * H)
         r = np.full(len(idx), self.max_levels - 1, dtype=np.int32)
         for k in range(self.max_levels - 1, -1, -1):
             dtk = np.ldexp(dt_top, -k)
@@ -305,7 +326,7 @@ class HHSOracle:
             r = np.where(ok, k, r)
         return r
 
-    def kick(self, st, sys1, joint, dt, kick_s2f, second, top=False):
+    def kick(self, st, sys1, joint, dt, kick_s2f, second, top=False, t0=0.0):
         mass = st.mass.copy()
         if kick_s2f:
             mass[sys1] = 0.0
@@ -314,6 +335,8 @@ class HHSOracle:
             st.a_tot[joint] = np.sqrt((acc * acc).sum(axis=0))
         pos_in_joint = np.searchsorted(joint, sys1)
         a1 = acc[:, pos_in_joint]
+        if self.cosmo is not None:
+            dt = self.factors(t0, t0 + dt)[1]
         st.vel[:, sys1] += a1 * dt
         if second:
             mag = np.sqrt((a1 * a1).sum(axis=0))
@@ -322,37 +345,42 @@ class HHSOracle:
             else:
                 st.a_cur[sys1] = mag
 
-    def kdk(self, st, slow, fast, sysall, dt, k=1):
+    def kdk(self, st, slow, fast, sysall, dt, k=1, t0=0.0):
         # Algorithm 2.  A kick whose sink set is empty, or a kickS2F whose source
         # set S is empty (every force would be zero), is skipped; this is what
         # makes a two-rung system cost 2 + 2 + 2^(k+1) solver calls (Sec. 2.2).
+        # The first kicks cover [t0, t0 + dt/2], the drift [t0, t0 + dt], the
+        # second kicks [t0 + dt/2, t0 + dt].
         s2f = len(fast) > 0 and len(slow) > 0
+        h = dt / 2
         if s2f:
-            self.kick(st, fast, sysall, dt / 2, True, False)
+            self.kick(st, fast, sysall, h, True, False, t0=t0)
         if len(slow):
-            self.kick(st, slow, sysall, dt / 2, False, False)
-        st.pos[:, slow] += st.vel[:, slow] * dt
+            self.kick(st, slow, sysall, h, False, False, t0=t0)
+        drift = dt if self.cosmo is None else self.factors(t0, t0 + dt)[0]
+        st.pos[:, slow] += st.vel[:, slow] * drift
         if len(slow):
-            self.kick(st, slow, sysall, dt / 2, False, True, top=(k == 0))
+            self.kick(st, slow, sysall, h, False, True, top=(k == 0), t0=t0 + h)
         if s2f:
-            self.kick(st, fast, sysall, dt / 2, True, True)
+            self.kick(st, fast, sysall, h, True, True, t0=t0 + h)
 
-    def evolve(self, st, k, sysall, dt, calc, dt_top):
+    def evolve(self, st, k, sysall, dt, calc, dt_top, t0=0.0):
         if calc and not self.freeze_rungs:
-            st.rung[sysall] = self.rungs(st, sysall, dt_top)
+            st.rung[sysall] = self.rungs(st, sysall, dt_top, t0)
         r = st.rung[sysall]
         slow = sysall[r <= k]
         fast = sysall[r > k]
         if len(fast):
-            self.evolve(st, k + 1, fast, dt / 2, False, dt_top)
-        self.kdk(st, slow, fast, sysall, dt, k)
+            self.evolve(st, k + 1, fast, dt / 2, False, dt_top, t0)
+        self.kdk(st, slow, fast, sysall, dt, k, t0)
         if len(fast):
-            self.evolve(st, k + 1, fast, dt / 2, True, dt_top)
+            self.evolve(st, k + 1, fast, dt / 2, True, dt_top, t0 + dt / 2)
 
     def step(self, st, dt_top):
-        """Advance every particle by dt_top (one top-level EVOLVE_HOLD)."""
+        """Advance every particle by dt_top (one top-level EVOLVE_HOLD); in the
+        comoving form st.t is ln a and dt_top a step in ln a."""
         sysall = np.arange(st.mass.shape[0], dtype=np.int32)
-        self.evolve(st, 0, sysall, dt_top, True, dt_top)
+        self.evolve(st, 0, sysall, dt_top, True, dt_top, st.t)
         st.t += dt_top
 
 
