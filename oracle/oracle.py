@@ -314,6 +314,7 @@ class HHSOracle:
     def rungs(self, st, idx, dt_top, t0=0.0):
         a = st.a_old[idx] + st.a_cur[idx]
         rhs = self.eta * self.eps
+        H = None
         if self.cosmo is not None:
             H = self.hubble(np.exp(t0))
             rhs = rhs * (H * H)
@@ -322,7 +323,10 @@ class HHSOracle:
             dtk = np.ldexp(dt_top, -k)
             ok = (dtk * dtk) * a <= rhs
             if self.eta1 > 0:
-                ok &= (dtk * dtk) * st.a_tot[idx] <= self.eta1 * self.eps
+                rhs1 = self.eta1 * self.eps
+                if self.cosmo is not None:
+                    rhs1 = rhs1 * (H * H)
+                ok &= (dtk * dtk) * st.a_tot[idx] <= rhs1
             r = np.where(ok, k, r)
         return r
 
