@@ -284,6 +284,15 @@ typedef struct {
     int freeze_rungs;  /* nonzero: keep the rungs in state->rung                 */
     double eta1;       /* > 0: also dt_i <= sqrt(eta1 * eps / |a|_tot) (Eq. 9,
                           Sec. 3.4); 0: off                                     */
+    const struct fmm_cosmo *cosmo; /* NULL, or the comoving form (Sec. 3.5):
+                          state->t and dt_top are in ln a, velocities are
+                          canonical momenta per unit mass, every kick and drift
+                          is scaled by this table's factors (Eqs. 10-11) over
+                          its own sub-interval instead of its length, and a
+                          rung's step is compared in physical time, d(ln a)/H
+                          at the start of the subsystem's step.  hhs_step and
+                          hhs_step_batched only (trad_step and the server
+                          reject it)                                           */
 } hhs_params;
 
 /* Full force solve on all n particles, then a_cur = |a|, a_old = 0 (and

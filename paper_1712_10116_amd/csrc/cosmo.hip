@@ -116,6 +116,8 @@ extern "C" fmm_status fmm_cosmo_factors(const fmm_cosmo *c, double a0, double a1
   return FMM_OK;
 }
 
+double cosmo_hubble(const fmm_cosmo *c, double a) { return hubble(c->prm, a); }
+
 extern "C" fmm_status fmm_cosmo_destroy(fmm_cosmo *c) {
   if (!c) return FMM_EINVAL;
   delete c;

@@ -24,6 +24,9 @@
 #include "hhs_driver.h"
 #include "hhs_kernels.h"
 
+// cosmo.hip: H(a) of a comoving-factor table's cosmology
+double cosmo_hubble(const fmm_cosmo *c, double a);
+
 struct hhs_run {
   fmm_ctx *ctx;
   int64_t n;
@@ -119,7 +122,22 @@ struct Frame {
   bool calc;
   int pc;
   int n_fast, n_slow;
+  double t0;  // start of the frame's step (ln a in the comoving form)
 };
+
+// Comoving form (Sec. 3.5): the factor that replaces the length of a kick
+// (integral of dt/a) or a drift (integral of dt/a^2) over [x0, x0 + dx] in
+// ln a; the plain length dx otherwise.
+bool step_factor(const hhs_params *hp, double x0, double dx, bool kick, double *out) {
+  if (!hp->cosmo) {
+    *out = dx;
+    return true;
+  }
+  double d, k;
+  if (fmm_cosmo_factors(hp->cosmo, exp(x0), exp(x0 + dx), &d, &k) != FMM_OK) return false;
+  *out = kick ? k : d;
+  return true;
+}
 
 enum SysState { S_RUN, S_WAIT_SPLIT, S_WAIT_HALF, S_DONE };
 
@@ -131,6 +149,7 @@ struct Sys {
   SysState state;
   int half;
   int64_t kicks, parts;  // force evaluations of this system, and their active particles
+  bool range_err;        // a comoving factor fell outside the cosmology table
 };
 
 // One kick of Algorithm 3 inside a KDK half: which set is kicked, with which
@@ -168,10 +187,19 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
     if (k >= r->levels) return false;
     switch (f.pc) {
       case 0:  // (re)assign rungs, split into slow {rung <= k} and fast {rung > k}
-        if (f.calc && !hp->freeze_rungs)
+        if (f.calc && !hp->freeze_rungs) {
+          // comoving form: a rung's step in ln a is compared in physical
+          // time, d(ln a) / H at the start of the subsystem's step
+          double h2 = 1.0;
+          if (hp->cosmo) {
+            const double H = cosmo_hubble(hp->cosmo, exp(f.t0));
+            h2 = H * H;
+          }
           hhs_launch_rungs(f.sys, f.n_sys, st->a_old, st->a_cur,
                            hp->eta1 > 0 ? st->a_tot : nullptr, st->rung, S.dt_top,
-                           hp->eta * hp->eps, hp->eta1 * hp->eps, hp->max_levels, c->stream);
+                           (hp->eta * hp->eps) * h2, (hp->eta1 * hp->eps) * h2, hp->max_levels,
+                           c->stream);
+        }
         hhs_launch_split(f.sys, f.n_sys, st->rung, k, r->flag, r->scan_part, r->slow[k],
                          r->slow_pos[k], r->fast[k], r->fast_pos[k], c->split_cnt + slot,
                          c->stream);
@@ -181,7 +209,7 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
       case 1: {  // first half of the fast system's evolution
         f.pc = 2;
         if (f.n_fast > 0) {
-          Frame ch{k + 1, r->fast[k], f.n_fast, 0.5 * f.dt, false, 0, 0, 0};
+          Frame ch{k + 1, r->fast[k], f.n_fast, 0.5 * f.dt, false, 0, 0, 0, f.t0};
           S.stack.push_back(ch);
         }
         break;
@@ -194,8 +222,13 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
           return true;
         }
         break;
-      case 3:  // drift the slow system, second half of the KDK
-        hhs_launch_drift(r->slow[k], f.n_slow, st->vel, st->pos, st->n, f.dt, c->stream);
+      case 3: {  // drift the slow system, second half of the KDK
+        double fd;
+        if (!step_factor(hp, f.t0, f.dt, false, &fd)) {
+          S.range_err = true;
+          return false;
+        }
+        hhs_launch_drift(r->slow[k], f.n_slow, st->vel, st->pos, st->n, fd, c->stream);
         f.pc = 4;
         if ((f.n_fast > 0 && f.n_slow > 0) || f.n_slow > 0) {
           S.half = 1;
@@ -203,10 +236,11 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
           return true;
         }
         break;
+      }
       case 4: {  // second half of the fast system's evolution, rungs recomputed
         f.pc = 5;
         if (f.n_fast > 0) {
-          Frame ch{k + 1, r->fast[k], f.n_fast, 0.5 * f.dt, true, 0, 0, 0};
+          Frame ch{k + 1, r->fast[k], f.n_fast, 0.5 * f.dt, true, 0, 0, 0, f.t0 + 0.5 * f.dt};
           S.stack.push_back(ch);
         }
         break;
@@ -275,14 +309,16 @@ static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const 
       const Frame &f = S.stack.back();
       const Kick &K = kk[2 * w + slot];
       const int k = f.k;
+      // first kicks cover [t0, t0 + dt/2], second ones [t0 + dt/2, t0 + dt]
+      double fk;
+      if (!step_factor(hp, S.half ? f.t0 + 0.5 * f.dt : f.t0, 0.5 * f.dt, true, &fk))
+        return fmm_fail(c, FMM_EINVAL, "scale factor outside the cosmology table");
       if (K.s2f)
         hhs_launch_kick(S.run->fast[k], S.run->fast_pos[k], f.n_fast, S.run->acc, f.n_sys,
-                        S.st->vel, S.st->n, 0.5 * f.dt, K.second ? S.st->a_old : nullptr,
-                        c->stream);
+                        S.st->vel, S.st->n, fk, K.second ? S.st->a_old : nullptr, c->stream);
       else
         hhs_launch_kick(S.run->slow[k], S.run->slow_pos[k], f.n_slow, S.run->acc, f.n_sys,
-                        S.st->vel, S.st->n, 0.5 * f.dt, K.second ? S.st->a_cur : nullptr,
-                        c->stream);
+                        S.st->vel, S.st->n, fk, K.second ? S.st->a_cur : nullptr, c->stream);
       // Eq. 9: the second kickFS2S of a top-level KDK sees every particle as a
       // sink, so its solve gives |a|_tot for the whole system
       if (!K.s2f && K.second && k == 0 && hp->eta1 > 0 && S.st->a_tot)
@@ -393,7 +429,9 @@ fmm_status hhs_step_batched_ex(fmm_ctx *c, int n_sys, hhs_run *const *runs,
     S.state = S_RUN;
     S.half = 0;
     S.kicks = S.parts = 0;
-    S.stack.push_back(Frame{0, runs[i]->all_idx, (int)states[i]->n, dt_top[i], true, 0, 0, 0});
+    S.range_err = false;
+    S.stack.push_back(
+        Frame{0, runs[i]->all_idx, (int)states[i]->n, dt_top[i], true, 0, 0, 0, states[i]->t});
   }
   const int64_t c0 = c->stat_parts, b0 = c->stat_builds;
   int64_t kicks = 0;
@@ -402,7 +440,10 @@ fmm_status hhs_step_batched_ex(fmm_ctx *c, int n_sys, hhs_run *const *runs,
   for (;;) {
     for (int i = 0; i < n_sys; ++i)
       if (sys[i].state == S_RUN && !advance(c, sys[i], hp, i))
-        return fmm_fail(c, FMM_EINVAL, "system %d: rung recursion deeper than max_levels", i);
+        return fmm_fail(c, FMM_EINVAL,
+                        sys[i].range_err ? "system %d: scale factor outside the cosmology table"
+                                         : "system %d: rung recursion deeper than max_levels",
+                        i);
     wait.clear();
     for (int i = 0; i < n_sys; ++i)
       if (sys[i].state == S_WAIT_SPLIT) wait.push_back(i);
@@ -507,6 +548,7 @@ extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp,
   if (!st->pos || !st->vel || !st->mass || !st->a_old || !st->a_cur || !st->rung)
     return fmm_fail(c, FMM_EINVAL, "NULL state array");
   if (!std::isfinite(dt_top) || dt_top == 0.0) return fmm_fail(c, FMM_EINVAL, "dt_top");
+  if (hp->cosmo) return fmm_fail(c, FMM_EINVAL, "trad_step has no comoving form");
   e = own_run(c, st, hp);
   if (e != FMM_OK) return e;
   e = ensure_split_slots(c, 32);

@@ -145,6 +145,7 @@ extern "C" fmm_status serve_create(fmm_ctx *c, const hhs_params *hp, const serve
   if (hp->max_levels < 1 || hp->max_levels > 30 || !(hp->eta > 0) || hp->p < 1 ||
       hp->p > c->prm.p_max || !(hp->eta1 >= 0))
     return fmm_fail(c, FMM_EINVAL, "bad HHS parameters");
+  if (hp->cosmo) return fmm_fail(c, FMM_EINVAL, "the server has no comoving form");
   if (sp->arena_bytes < kAlign || sp->max_slots < 1 || !(sp->dt_max > 0))
     return fmm_fail(c, FMM_EINVAL, "bad server parameters");
   fmm_server *s = new (std::nothrow) fmm_server();

@@ -116,7 +116,8 @@ class Cosmology:
 class HHSParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("theta", ctypes.c_double), ("p", ctypes.c_int),
                 ("eta", ctypes.c_double), ("max_levels", ctypes.c_int),
-                ("freeze_rungs", ctypes.c_int), ("eta1", ctypes.c_double)]
+                ("freeze_rungs", ctypes.c_int), ("eta1", ctypes.c_double),
+                ("cosmo", ctypes.c_void_p)]
 
 
 _lib = None
@@ -446,12 +447,12 @@ class HHS:
     in hhs_init_batched / hhs_step_batched with other systems."""
 
     def __init__(self, solver, pos, vel, mass, *, eps, theta, p, eta, max_levels,
-                 freeze_rungs=False, run=None, eta1=0.0):
+                 freeze_rungs=False, run=None, eta1=0.0, cosmo=None, t=0.0):
         self.solver = solver
         self.run = run
         n = pos.shape[1]
-        for t, nm, shp in ((pos, "pos", (3, n)), (vel, "vel", (3, n)), (mass, "mass", (n,))):
-            _check_dev(t, torch.float64, shp, nm)
+        for arr, nm, shp in ((pos, "pos", (3, n)), (vel, "vel", (3, n)), (mass, "mass", (n,))):
+            _check_dev(arr, torch.float64, shp, nm)
         self.pos, self.vel, self.mass = pos, vel, mass
         dev = pos.device
         self.a_old = torch.zeros(n, dtype=torch.float64, device=dev)
@@ -459,10 +460,13 @@ class HHS:
         self.rung = torch.zeros(n, dtype=torch.int32, device=dev)
         self.a_tot = torch.zeros(n, dtype=torch.float64, device=dev)
         self.state = HHSState(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), self.a_old.data_ptr(),
-                              self.a_cur.data_ptr(), self.rung.data_ptr(), n, 0.0,
+                              self.a_cur.data_ptr(), self.rung.data_ptr(), n, float(t),
                               self.a_tot.data_ptr())
+        # cosmo: a Cosmology table for the comoving form (t and dt_top in ln a)
+        self.cosmo = cosmo
         self.params = HHSParams(float(eps), float(theta), int(p), float(eta), int(max_levels),
-                                int(bool(freeze_rungs)), float(eta1))
+                                int(bool(freeze_rungs)), float(eta1),
+                                None if cosmo is None else cosmo._h.value)
 
     @property
     def t(self):
