@@ -557,7 +557,7 @@ extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp,
   const int64_t n = st->n;
   hipStream_t s = c->stream;
   int64_t calls = 0, parts = 0;
-  uint8_t *sinks = (uint8_t *)r->flag;  // n bytes of the run's flag scratch
+  uint8_t *sinks = r->sinks;  // the run's sink-flag scratch (n bytes)
   auto solve = [&](const uint8_t *flags) {
     ++calls;
     fmm_request q = {st->pos, n, nullptr, n, st->mass, r->acc, r->pot, flags};
