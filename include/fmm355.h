@@ -11,7 +11,12 @@
  *     Sec. 2.3, Algorithm 4);
  *   - the HOLD/HHS integrator that splits particles into slow and fast systems
  *     on power-of-two timestep rungs, with kickS2F forces computed by masking
- *     the masses of the fast system (Sec. 2.2, Algorithms 1-3; Sec. 2.3).
+ *     the masses of the fast system (Sec. 2.2, Algorithms 1-3; Sec. 2.3);
+ *   - around them: the individual-timestep integrator the paper compares
+ *     against (Sec. 2.3), the total-acceleration timestep bound (Eq. (9)),
+ *     the comoving drift and kick factors and the HHS in comoving form
+ *     (Sec. 3.5, Eqs. (10)-(11)), and the force gradient that a fourth-order
+ *     integrator needs (Sec. 4.1).
  *
  * Conventions for every call
  *   - Units: G = 1.  Outputs are accelerations per unit mass,
