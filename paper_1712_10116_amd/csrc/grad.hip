@@ -40,8 +40,9 @@ __device__ __forceinline__ void pair_gh(R r2, R eps, R ie, R &g, R &h) {
   }
 }
 
-// near part: one wavefront per sink leaf, lanes over its sinks, each source
-// leaf staged through LDS 64 particles at a time; pair terms in R (FP32 in the
+// near part: one wavefront per sink leaf, lanes over its sinks (and, for
+// leaves of at most 32, over 2-16 phases of the sources), each source leaf
+// staged through LDS 64 particles at a time; pair terms in R (FP32 in the
 // mixed form, on FP64 differences), summed in R over one source leaf and then
 // into FP64
 template <typename R, int KERNEL>
@@ -59,8 +60,13 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, 
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
     const int loff = t.p2p_off[A], cnt = t.p2p_cnt[A];
     for (int tb = 0; tb < nA; tb += 64) {
-      const bool valid = tb + lane < nA;
-      const int i = bA + tb + (valid ? lane : 0);
+      // lanes = (sink, phase): nph phases share each sink and take every
+      // nph-th source, so a leaf of fewer than 64 sinks still fills the wave
+      const int ns = min(64, nA - tb);
+      const int nph = ns <= 4 ? 16 : ns <= 8 ? 8 : ns <= 16 ? 4 : ns <= 32 ? 2 : 1;
+      const int ti = lane / nph, ph = lane % nph;
+      const bool valid = ti < ns;
+      const int i = bA + tb + (valid ? ti : 0);
       const double xi = t.sx[i], yi = t.sy[i], zi = t.sz[i];
       double G[6] = {0, 0, 0, 0, 0, 0};
       for (int q = 0; q < cnt; ++q) {
@@ -74,7 +80,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, 
             st[lane] = make_double4(t.sx[jb + lane], t.sy[jb + lane], t.sz[jb + lane],
                                     t.sm[jb + lane]);
           __builtin_amdgcn_wave_barrier();
-          for (int u = 0; u < nj; ++u) {
+          for (int u = ph; u < nj; u += nph) {
             if (jb + u == i) continue;
             const double4 sv = st[u];
             const R d[3] = {(R)(sv.x - xi), (R)(sv.y - yi), (R)(sv.z - zi)};
@@ -91,7 +97,11 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, 
 #pragma unroll
         for (int c = 0; c < 6; ++c) G[c] += (double)Gs[c];
       }
-      if (valid) {
+      // the phases of a sink are consecutive lanes: fold them onto phase 0
+      for (int o = nph >> 1; o > 0; o >>= 1)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) G[c] += __shfl_xor(G[c], o, 64);
+      if (valid && ph == 0) {
         const int64_t k = t.slot[i] - off;
 #pragma unroll
         for (int c = 0; c < 6; ++c) grad[c * nq + k] = G[c];
