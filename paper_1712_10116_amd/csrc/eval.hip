@@ -375,7 +375,7 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, bool dev) {
   const T *L = (const T *)t.L;
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  if (dev && tree_incomplete(t)) return;  // leaf_of not written by this build
+  if (dev && tree_incomplete(t)) return;  // leaf_of not written for this tree
   // the system first: leaf_of is written only for systems this evaluation covers
   const DevReq q = t.reqs[upper_index(t.req_off, t.n_req, j)];
   if (!q.mass) return;
