@@ -63,3 +63,34 @@ def test_footprints_without_a_gpu():
     assert lib.serve_footprint(10, 31) == -1
     h = ctypes.c_void_p()
     assert lib.serve_create(None, None, None, ctypes.byref(h)) == F.FMM_EINVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror of a header struct has the C layout: size and the
+    offset of each field, from a small C program compiled against the header."""
+    import shutil
+    import subprocess
+    from paper_1712_10116_amd import fmm as F
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"fmm_params": F._Params, "fmm_request": F.Request, "hhs_state": F.HHSState,
+               "hhs_params": F.HHSParams, "fmm_cosmo_params": F.CosmoParams,
+               "serve_params": F.ServeParams, "serve_request": F.ServeRequest,
+               "serve_result": F.ServeResult}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
