@@ -467,7 +467,10 @@ def cosmo_factors(a0, a1, *, omega_m, omega_l, h0):
 
 
 def invariants(pos, vel, mass, acc=None, pot=None):
-    """Total momentum, angular momentum, kinetic energy, (potential energy, sum m a)."""
+    """Sec. 3.2's accuracy monitors as plain numpy sums: total momentum P,
+    angular momentum L = sum m x cross v, kinetic energy T, and, when given,
+    the potential energy W = 1/2 sum m Phi, the total force sum m a and the
+    scale sum m |a|."""
     P = (mass * vel).sum(axis=1)
     Lm = (mass * np.cross(pos.T, vel.T).T).sum(axis=1)
     T = 0.5 * (mass * (vel * vel).sum(axis=0)).sum()
@@ -476,4 +479,5 @@ def invariants(pos, vel, mass, acc=None, pot=None):
         out["W"] = 0.5 * (mass * pot).sum()
     if acc is not None:
         out["F"] = (mass * acc).sum(axis=1)
+        out["Fabs"] = (mass * np.sqrt((acc * acc).sum(axis=0))).sum()
     return out

@@ -70,15 +70,111 @@ def test_hhs_matches_oracle(oracle, n, steps):
     assert len(np.unique(grung)) >= 3
 
 
+def _boosted(n, seed=1000):
+    """Plummer sphere moving as a whole and spinning about z: non-zero total
+    momentum and angular momentum."""
+    pos, vel, m = W.plummer(n, seed=seed)
+    pos = pos + np.array([[0.5], [-1.0], [0.25]])
+    vel = vel + np.array([[0.3], [-0.2], [0.1]])
+    vel[0] += -0.4 * (pos[1] + 1.0)
+    vel[1] += 0.4 * (pos[0] - 0.5)
+    return pos, vel, m
+
+
 @pytest.mark.parametrize("precision,tol", [(0, 1e-13), (1, 1e-6)])
 def test_hhs_momentum_conserved(precision, tol):
-    pos, vel, m = W.plummer(8192, seed=1000)
+    pos, vel, m = _boosted(8192)
     prm = dict(PRM0)
     P0 = (m * vel).sum(axis=1)
+    assert np.abs(P0).max() > 0.1
     gp, gv, grung, _, _, stats, inv = _gpu_hhs(pos, vel, m, prm, 2, 1.0 / 16, precision)
     scale = (m * np.sqrt((vel * vel).sum(axis=0))).sum()
+    # the library's reduction against a plain sum over the downloaded state
+    np.testing.assert_allclose(inv["P"], (m * gv).sum(axis=1), rtol=1e-13, atol=1e-16 * scale)
     assert np.abs(inv["P"] - P0).max() / scale < tol
+    assert np.abs((m * gv).sum(axis=1) - P0).max() / scale < tol
     assert sum(s["force_calls"] for s in stats) > 8
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_invariants_match_oracle(oracle, kernel):
+    """fmm_invariants (the FP64 reductions behind every momentum figure)
+    against the oracle's numpy sums on a moving, rotating system with the
+    accelerations and potentials of a real solve: all twelve outputs."""
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    pos, vel, m = _boosted(20011, seed=1007)
+    m = m * np.random.default_rng(5).uniform(0.5, 1.5, m.size)
+    s = F.Solver(m.size, p_max=4, leaf_size=16, kernel=kernel, precision=F.FP64)
+    tp, tv, tm = (torch.from_numpy(x.copy()).cuda() for x in (pos, vel, m))
+    a, pt = s.forces(tp, tm, eps=0.01, theta=0.5, p=4)
+    # the solve's own sum m a is zero to round-off (momentum balance); a uniform
+    # field added to its accelerations makes every output non-zero
+    a_np = a.cpu().numpy() + np.array([[0.1], [0.2], [-0.3]])
+    ta = torch.from_numpy(a_np).cuda()
+    bal = s.invariants(mass=tm, acc=a)
+    assert np.abs(bal["F"]).max() <= 1e-13 * bal["Fabs"]
+    got = s.invariants(pos=tp, vel=tv, mass=tm, acc=ta, pot=pt)
+    ref = oracle.invariants(pos, vel, m, acc=a_np, pot=pt.cpu().numpy())
+    mv = m * np.sqrt((vel * vel).sum(axis=0))
+    scales = dict(P=mv.sum(), L=(mv * np.sqrt((pos * pos).sum(axis=0))).sum(), T=abs(ref["T"]),
+                  W=abs(ref["W"]), F=ref["Fabs"], Fabs=ref["Fabs"])
+    for k, sc in scales.items():
+        assert np.all(np.abs(np.atleast_1d(ref[k])) > 1e-3 * sc), k   # not a zero case
+        assert np.abs(np.atleast_1d(got[k] - ref[k])).max() <= 1e-13 * sc, (k, got[k], ref[k])
+    # momentum only (NULL arrays elsewhere), and no mass (unit masses)
+    only = s.invariants(vel=tv, mass=tm)
+    assert np.abs(only["P"] - ref["P"]).max() <= 1e-13 * scales["P"]
+    assert np.all(only["F"] == 0) and only["W"] == 0 and np.all(only["L"] == 0)
+    unit = s.invariants(vel=tv)
+    assert np.abs(unit["P"] - vel.sum(axis=1)).max() <= 1e-13 * np.abs(vel).sum()
+    s.close()
+
+
+def test_hhs_mixed_wendland_matches_oracle(oracle):
+    """Mixed precision with the Wendland kernel (the ensemble's kernel,
+    softening, order and rung ladder) stepped in lock-step with the FP64
+    oracle HHS: rungs frozen at the oracle's initial assignment (a
+    mixed-precision |a| may land on the other side of a rung boundary), two
+    top-level steps.  theta is tiny so that every pair is summed directly:
+    mixed and FP64 positions part at the 1e-10 level after the first drift,
+    which moves the root box and with it the rounding of every cell centre,
+    and at theta 0.5 that can flip an acceptance test that sits exactly on
+    its threshold and change those forces by the truncation error.  The mixed
+    pair sums are within about 1e-6 of the FP64 ones, so the velocities may
+    part by at most 1e-5 of the largest |a| times the time stepped, and the
+    positions by that times dt_top."""
+    from paper_1712_10116_amd import fmm as F
+    pos, vel, m = W.plummer(2000, seed=1010, a=3.0 * np.pi / 16.0)
+    prm = dict(W.PARAMS[4], theta=1e-6)
+    dt_top, steps = 1.0 / 16, 2
+    H = oracle.HHSOracle(p=prm["p"], theta=prm["theta"], eps=prm["eps"],
+                         leaf_size=prm["leaf_size"], kernel=prm["kernel"], eta=prm["eta"],
+                         max_levels=prm["max_levels"], freeze_rungs=True)
+    st = oracle.HHSState(pos, vel, m)
+    acc0, _ = H.init_forces(st)
+    frozen = H.rungs(st, np.arange(m.size, dtype=np.int32), dt_top)
+    assert len(np.unique(frozen)) >= 3
+    st.rung = frozen.copy()
+    calls = []
+    for _ in range(steps):
+        c0 = st.force_calls
+        H.step(st, dt_top)
+        calls.append(st.force_calls - c0)
+    gp, gv, grung, gao, gac, stats, inv = _gpu_hhs(pos, vel, m, prm, steps, dt_top,
+                                                  precision=F.MIXED, freeze=frozen)
+    np.testing.assert_array_equal(grung, frozen)
+    assert [x["force_calls"] for x in stats] == calls
+    amax = np.sqrt((acc0 * acc0).sum(axis=0)).max()
+    dv = np.sqrt(((gv - st.vel) ** 2).sum(axis=0))
+    dx = np.sqrt(((gp - st.pos) ** 2).sum(axis=0))
+    assert dv.max() < 1e-5 * amax * dt_top * steps, dv.max() / (amax * dt_top * steps)
+    assert dx.max() < 1e-5 * amax * dt_top * dt_top * steps, dx.max()
+    np.testing.assert_allclose(gac, st.a_cur, rtol=2e-4)
+    # momentum of the mixed run still conserved to its bound
+    P0 = (m * vel).sum(axis=1)
+    scale = (m * np.sqrt((vel * vel).sum(axis=0))).sum()
+    assert np.abs(inv["P"] - P0).max() / scale < 1e-6
 
 
 def _hhs_systems():
