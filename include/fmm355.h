@@ -252,6 +252,22 @@ fmm_status fmm_export_tree(fmm_ctx *ctx, int64_t *perm, int32_t *level, uint64_t
 fmm_status fmm_invariants(fmm_ctx *ctx, const double *pos, const double *vel, const double *mass,
                           const double *acc, const double *pot, int64_t n, double out[12]);
 
+/* fmm_invariants for callers that cannot allocate device memory or wait for
+ * the device: code under HIP graph capture, tight serving loops.  The same
+ * twelve sums in the same order, bit for bit, but written to DEVICE memory
+ * out[0..11] (caller-owned) on `stream` (a hipStream_t, NULL = the null
+ * stream), without a context, an allocation, a copy or a synchronisation.
+ * Inputs as for fmm_invariants (device SoA over n particles, any may be
+ * NULL).  Its scratch is a library-owned device array of 512 x 12 doubles
+ * (48 KiB on each device it runs on, kept until the process ends) whatever n
+ * is, so no n is too large for it; every call on one device shares that
+ * array, so calls that overlap on one device (different streams) race and
+ * must be ordered by the caller.  FMM_EINVAL: out NULL or n < 0;
+ * FMM_EDEVICE: the scratch could not be looked up or a launch failed. */
+fmm_status fmm_invariants_noalloc(void *stream, const double *pos, const double *vel,
+                                  const double *mass, const double *acc, const double *pot,
+                                  int64_t n, double *out);
+
 /* Per-phase timing with HIP events recorded on the context's stream between
  * launch groups (nothing else changes).  enable = 1 starts recording every
  * phase, enable = 2 only the M2L and P2P kernels (one event pair each per

@@ -170,7 +170,7 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
     ok = dalloc(c, &t.m2l_src, t.cap_m2l) && dalloc(c, &t.p2p_src, t.cap_p2p) &&
          dalloc(c, &t.open_buf0, t.cap_open) && dalloc(c, &t.open_buf1, t.cap_open);
   }
-  ok = ok && dalloc(c, &c->inv_part, 512 * 12);
+  ok = ok && dalloc(c, &c->inv_part, FMM_INV_BLOCKS * 12);
   if (!ok) {
     fmm_destroy(c);
     return FMM_ENOMEM;
@@ -743,7 +743,7 @@ extern "C" fmm_status fmm_invariants(fmm_ctx *c, const double *pos, const double
                                      const double *mass, const double *acc, const double *pot,
                                      int64_t n, double out[12]) {
   if (!c || !out || n < 0) return FMM_EINVAL;
-  const int nblk = 512;
+  const int nblk = FMM_INV_BLOCKS;
   launch_invariants(pos, vel, mass, acc, pot, n, c->inv_part, nblk, c->stream);
   std::vector<double> part(nblk * 12);
   HIPCHK(c, hipMemcpyAsync(part.data(), c->inv_part, sizeof(double) * nblk * 12,

@@ -42,6 +42,9 @@ void trad_launch_flags(const int32_t *rung, int64_t n, int rmin, uint8_t *flag, 
 // min(1024, ceil(n / 256)) doubles of scratch
 void hhs_launch_min_sum(const double *a, const double *b, int64_t n, double *part, double *out,
                         hipStream_t s);
+// Blocks of the invariant reduction: each writes 12 FP64 partial sums to
+// part[block * 12 + k], which are then added in block order.
+#define FMM_INV_BLOCKS 512
 void launch_invariants(const double *pos, const double *vel, const double *mass,
                        const double *acc, const double *pot, int64_t n, double *part, int nblk,
                        hipStream_t s);

@@ -26,7 +26,7 @@ EXPORTED = (
     "hhs_init_batched", "hhs_step_batched", "serve_footprint", "serve_create", "serve_destroy",
     "serve_submit", "serve_step", "serve_poll", "serve_cancel", "serve_info",
     "fmm_set_small_path", "fmm_set_level_prediction", "trad_step", "fmm_forces_grad",
-    "fmm_cosmo_create", "fmm_cosmo_factors", "fmm_cosmo_destroy",
+    "fmm_cosmo_create", "fmm_cosmo_factors", "fmm_cosmo_destroy", "fmm_invariants_noalloc",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -145,6 +145,7 @@ def lib():
         L.fmm_tree_info.argtypes = [vp, vp]
         L.fmm_export_tree.argtypes = [vp] + [vp] * 11
         L.fmm_invariants.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
+        L.fmm_invariants_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
         L.hhs_init.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams)]
         L.hhs_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
         L.trad_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
@@ -413,6 +414,25 @@ class Solver:
         res = {k: out[3 * i:3 * i + 3].copy() for i, k in enumerate(keys)}
         res.update(T=out[9], W=out[10], Fabs=out[11])
         return res
+
+
+def invariants_noalloc(out, pos=None, vel=None, mass=None, acc=None, pot=None, n=None,
+                       stream=None):
+    """fmm_invariants_noalloc: the twelve sums of Solver.invariants written to
+    the device tensor ``out`` (12 float64) on ``stream`` (default: torch's
+    current stream), with no allocation and no synchronisation."""
+    if n is None:
+        for t in (pos, vel, acc, pot, mass):
+            if t is not None:
+                n = t.shape[-1]
+                break
+    _check_dev(out, torch.float64, (12,), "out")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = lib().fmm_invariants_noalloc(ctypes.c_void_p(s.cuda_stream), _ptr(pos), _ptr(vel),
+                                      _ptr(mass), _ptr(acc), _ptr(pot), int(n), _ptr(out))
+    if st != FMM_OK:
+        raise FMMError(st, "fmm_invariants_noalloc failed")
+    return out
 
 
 class HHSRun:
