@@ -602,9 +602,19 @@ void orc_tree_export(const orc_tree *t, int64_t *perm, int32_t *level, uint64_t 
  * expansions: minus the Hessian of the local expansion at L2P, and for every
  * P2P pair the derivative of m g(r) d with respect to the sink's position,
  * -m (g I + (dg/dr)/r d d^T), d = x_j - x_i, applied to both sides. */
+/* dvec (optional, SoA 3 x n in active order): instead of point masses the
+ * sources are vectors m_j v_j, and the outputs become the field
+ * u_i = sum_j m_j H(x_i - x_j) v_j, H = grad grad psi (the pair Hessian,
+ * g I + (dg/dr)/r d d^T), written to acc, and Phi_i = sum_j m_j v_j . grad psi
+ * (x_i - x_j), written to pot.  This is the derivative of the accelerations
+ * along a displacement of every particle j by v_j: sum_{j != i} (d a_i /
+ * d x_j) v_j.  Through the same expansions: a source's "dipole moments"
+ * M[m] = -m_j sum_a v_a (x_j - z)^(m - e_a) / (m - e_a)! (the derivative of its
+ * mass moments along v), the same M2M, M2L and L2L, and u = +grad of the
+ * local expansion; the near part sums m_j H v_j over the P2P partners. */
 static int tree_eval(const orc_tree *t, const double *mass_total, int64_t n_total,
-                     const int32_t *active, double *acc, double *pot, double *grad, double *Mout,
-                     double *Lout)
+                     const int32_t *active, const double *dvec, double *acc, double *pot,
+                     double *grad, double *Mout, double *Lout)
 {
     const int64_t n = t->n;
     if (n == 0) return ORC_OK;
@@ -625,10 +635,11 @@ static int tree_eval(const orc_tree *t, const double *mass_total, int64_t n_tota
     double *ph = (double *)calloc((size_t)n, sizeof(double));
     double *D = (double *)malloc(sizeof(double) * K);
     double *G = grad ? (double *)calloc((size_t)(6 * n), sizeof(double)) : NULL;
+    double *V = dvec ? (double *)malloc(sizeof(double) * 3 * n) : NULL; /* sorted order */
     if (!M || !Lc || !m || !sx[0] || !sx[1] || !sx[2] || !ax || !ay || !az || !ph || !D ||
-        (grad && !G)) {
+        (grad && !G) || (dvec && !V)) {
         free(mi); free(M); free(Lc); free(m); free(sx[0]); free(sx[1]); free(sx[2]);
-        free(ax); free(ay); free(az); free(ph); free(D); free(G);
+        free(ax); free(ay); free(az); free(ph); free(D); free(G); free(V);
         return ORC_ENOMEM;
     }
     /* tensor component c = (a, b): xx, yy, zz, xy, xz, yz */
@@ -638,6 +649,8 @@ static int tree_eval(const orc_tree *t, const double *mass_total, int64_t n_tota
         int64_t g = active ? active[slot] : slot;
         m[i] = mass_total[g];
         for (int d = 0; d < 3; ++d) sx[d][i] = t->x[d][slot];
+        if (V)
+            for (int d = 0; d < 3; ++d) V[d * n + i] = dvec[d * n + slot];
     }
     (void)n_total;
     const double e2 = t->prm.kernel == ORC_PLUMMER ? t->prm.eps * t->prm.eps : 0.0;
@@ -648,7 +661,22 @@ static int tree_eval(const orc_tree *t, const double *mass_total, int64_t n_tota
         if (nd->nchild) continue;
         for (int64_t i = nd->begin; i < nd->end; ++i) {
             double u[3] = {sx[0][i] - nd->z[0], sx[1][i] - nd->z[1], sx[2][i] - nd->z[2]};
-            for (int k = 0; k < K; ++k) M[c * K + k] += m[i] * mono_over_fact(mi, u, k);
+            if (!V) {
+                for (int k = 0; k < K; ++k) M[c * K + k] += m[i] * mono_over_fact(mi, u, k);
+                continue;
+            }
+            /* dipole moments: -m v . grad_x of (x - z)^k / k! */
+            for (int k = 0; k < K; ++k) {
+                const int *kk = mi->k[k];
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    if (kk[a] == 0) continue;
+                    int e[3] = {kk[0], kk[1], kk[2]};
+                    e[a] -= 1;
+                    s += V[a * n + i] * mono_over_fact(mi, u, mi->idx[e[0]][e[1]][e[2]]);
+                }
+                M[c * K + k] -= m[i] * s;
+            }
         }
     }
     /* M2M: children have larger pre-order ids than their parent */
@@ -757,6 +785,24 @@ static int tree_eval(const orc_tree *t, const double *mass_total, int64_t n_tota
                 double r = sqrt(dx * dx + dy * dy + dz * dz);
                 double phi, g;
                 pair_kernel(t->prm.kernel, t->prm.eps, r, &phi, &g);
+                if (V) {
+                    /* H v = g v + h (d . v) d with d = +-(x_j - x_i) (H is even);
+                     * acc holds minus the field, as for masses */
+                    const double h = pair_dg_over_r(t->prm.kernel, t->prm.eps, r);
+                    const double vj[3] = {V[j], V[n + j], V[2 * n + j]};
+                    const double vi[3] = {V[i], V[n + i], V[2 * n + i]};
+                    const double dvj = dx * vj[0] + dy * vj[1] + dz * vj[2];
+                    const double dvi = dx * vi[0] + dy * vi[1] + dz * vi[2];
+                    ax[i] -= m[j] * (g * vj[0] + h * dvj * dx);
+                    ay[i] -= m[j] * (g * vj[1] + h * dvj * dy);
+                    az[i] -= m[j] * (g * vj[2] + h * dvj * dz);
+                    ph[i] -= m[j] * g * dvj;  /* v_j . grad psi(x_i - x_j), x_i - x_j = -d */
+                    ax[j] -= m[i] * (g * vi[0] + h * dvi * dx);
+                    ay[j] -= m[i] * (g * vi[1] + h * dvi * dy);
+                    az[j] -= m[i] * (g * vi[2] + h * dvi * dz);
+                    ph[j] += m[i] * g * dvi;
+                    continue;
+                }
                 ax[i] += m[j] * g * dx;
                 ay[i] += m[j] * g * dy;
                 az[i] += m[j] * g * dz;
@@ -778,11 +824,12 @@ static int tree_eval(const orc_tree *t, const double *mass_total, int64_t n_tota
         }
     }
     /* outputs in active order */
+    const double sgn = V ? -1.0 : 1.0;  /* the vector field is +grad, acc is -grad */
     for (int64_t i = 0; i < n; ++i) {
         int64_t slot = t->perm[i];
-        acc[slot] = ax[i];
-        acc[n + slot] = ay[i];
-        acc[2 * n + slot] = az[i];
+        acc[slot] = sgn * ax[i];
+        acc[n + slot] = sgn * ay[i];
+        acc[2 * n + slot] = sgn * az[i];
         pot[slot] = ph[i];
         if (G)
             for (int c6 = 0; c6 < 6; ++c6) grad[c6 * n + slot] = G[c6 * n + i];
@@ -790,21 +837,30 @@ static int tree_eval(const orc_tree *t, const double *mass_total, int64_t n_tota
     if (Mout) memcpy(Mout, M, sizeof(double) * NN * K);
     if (Lout) memcpy(Lout, Lc, sizeof(double) * NN * K);
     free(mi); free(M); free(Lc); free(m); free(sx[0]); free(sx[1]); free(sx[2]);
-    free(ax); free(ay); free(az); free(ph); free(D); free(G);
+    free(ax); free(ay); free(az); free(ph); free(D); free(G); free(V);
     return ORC_OK;
 }
 
 int orc_tree_eval_ex(const orc_tree *t, const double *mass_total, int64_t n_total,
                      const int32_t *active, double *acc, double *pot, double *Mout, double *Lout)
 {
-    return tree_eval(t, mass_total, n_total, active, acc, pot, NULL, Mout, Lout);
+    return tree_eval(t, mass_total, n_total, active, NULL, acc, pot, NULL, Mout, Lout);
 }
 
 int orc_tree_eval_grad(const orc_tree *t, const double *mass_total, int64_t n_total,
                        const int32_t *active, double *acc, double *pot, double *grad)
 {
     if (!grad) return ORC_EINVAL;
-    return tree_eval(t, mass_total, n_total, active, acc, pot, grad, NULL, NULL);
+    return tree_eval(t, mass_total, n_total, active, NULL, acc, pot, grad, NULL, NULL);
+}
+
+/* The field of vector sources m_j v_j (see tree_eval): u (SoA 3 x n) and
+ * phi (n), active order; vec SoA 3 x n in active order. */
+int orc_tree_eval_dipole(const orc_tree *t, const double *mass_total, int64_t n_total,
+                         const int32_t *active, const double *vec, double *u, double *phi)
+{
+    if (!vec) return ORC_EINVAL;
+    return tree_eval(t, mass_total, n_total, active, vec, u, phi, NULL, NULL, NULL);
 }
 
 int orc_tree_eval(const orc_tree *t, const double *mass_total, int64_t n_total,

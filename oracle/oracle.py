@@ -2,9 +2,10 @@
 
 Wraps ``liboracle.so`` (plain C, built from ``fmm_oracle.c``) and adds the
 hierarchical Hamiltonian splitting (HHS) integrator of the paper (Sec. 2.2,
-Algorithms 1-3) and the paper's comparison integrator with individual
-timesteps (Sec. 2.3) in plain numpy on top of the oracle's force solve, and
-the comoving drift and kick factors of Sec. 3.5 by adaptive quadrature.
+Algorithms 1-3), the paper's comparison integrator with individual
+timesteps (Sec. 2.3) and the fourth-order integrator it proposes (Sec. 4.1)
+in plain numpy on top of the oracle's force solve, and the comoving drift and
+kick factors of Sec. 3.5 by adaptive quadrature.
 
 Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
 may import this module.  It imports nothing from the GPU package, and the GPU
@@ -59,6 +60,8 @@ def lib():
         L.orc_tree_eval_ex.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp,
                                        ctypes.c_void_p, ctypes.c_void_p]
         L.orc_tree_eval_grad.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp, dp]
+        L.orc_tree_eval_dipole.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp,
+                                           dp]
         L.orc_tree_eval_sinks.argtypes = [ctypes.c_void_p, dp, ctypes.c_void_p, ctypes.c_void_p,
                                           i64, dp, dp]
         L.orc_direct.argtypes = [dp, dp, i64, ctypes.c_void_p, i64, ctypes.c_int,
@@ -212,6 +215,23 @@ class Tree:
                                       _dp(acc), _dp(pot), _dp(grad))
         assert rc == 0
         return acc, pot, grad
+
+    def evaluate_dipole(self, mass, vec):
+        """Field of the vector sources m_j v_j on this tree: u (3,n) with
+        u_i = sum_j m_j H(x_i - x_j) v_j (H the pair Hessian of psi), i.e. the
+        derivative of a_i along a displacement of every particle j by v_j, and
+        phi (n) = sum_j m_j v_j . grad psi(x_i - x_j).  vec: (3,n) in active
+        order.  With vec = the accelerations this is the cross term of the
+        force-gradient kick of Chin's fourth-order integrator (Sec. 4.1)."""
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        vec = np.ascontiguousarray(vec, dtype=np.float64)
+        assert vec.shape == (3, self.n)
+        u = np.zeros((3, self.n))
+        phi = np.zeros(self.n)
+        rc = lib().orc_tree_eval_dipole(self._h, _dp(mass), self.n_total, _vp(self.active),
+                                        _dp(vec), _dp(u), _dp(phi))
+        assert rc == 0
+        return u, phi
 
     def evaluate_sinks(self, mass, sinks):
         """FMM acceleration/potential of the given active slots only."""
@@ -445,6 +465,79 @@ class TradOracle:
                 st.vel[:, ending] += a * half[ending]
             st.a_cur[ending] = np.sqrt((a * a).sum(axis=0))
         st.t += dt_top
+
+
+# --------------------------------------------------------------------------
+# The fourth-order integrator proposed in Sec. 4.1 (Chin & Chen 2005)
+# --------------------------------------------------------------------------
+class ChinState:
+    """Particle state of the fourth-order integrator (float64, SoA); acc is
+    the acceleration at pos."""
+
+    def __init__(self, pos, vel, mass):
+        self.pos = np.array(pos, dtype=np.float64, copy=True)
+        self.vel = np.array(vel, dtype=np.float64, copy=True)
+        self.mass = np.array(mass, dtype=np.float64, copy=True)
+        self.acc = np.zeros_like(self.pos)
+        self.t = 0.0
+        self.evaluations = 0
+
+
+def tensor_apply(grad, v):
+    """T v for the symmetric tensors of Tree.evaluate_grad (rows xx, yy, zz,
+    xy, xz, yz) and vectors v (3, n)."""
+    xx, yy, zz, xy, xz, yz = grad
+    return np.stack([xx * v[0] + xy * v[1] + xz * v[2],
+                     xy * v[0] + yy * v[1] + yz * v[2],
+                     xz * v[0] + yz * v[1] + zz * v[2]])
+
+
+class ChinOracle:
+    """Forward fourth-order symplectic integrator of Chin & Chen (2005),
+    their algorithm 4A, with one shared timestep h and the oracle FMM.
+
+    The flow exp(h (T + V)) is approximated by kicks and drifts with positive
+    coefficients only: kick h/6 with the acceleration, drift h/2, kick 2h/3
+    with the acceleration of the modified potential V + (h^2/48)[V,[T,V]],
+    drift h/2, kick h/6.  For gravity that modified acceleration is
+        a~_i = a_i + (h^2/24) sum_j (d a_i / d x_j) a_j,
+    the sum being the derivative of a_i along a displacement of every
+    particle by its own acceleration.  It splits into the force gradient of
+    particle i applied to a_i (Tree.evaluate_grad) and the field of the
+    vector sources m_j a_j (Tree.evaluate_dipole), both on the tree of the
+    middle positions.  The paper names the scheme (Sec. 4.1) without its
+    details: the coefficients and the form of the modified force are the
+    published algorithm's, the sign of the correction pinned by its order.
+    """
+
+    def __init__(self, *, p, theta, eps, leaf_size, kernel):
+        self.kw = dict(p=p, theta=theta, eps=eps, leaf_size=leaf_size, kernel=kernel)
+
+    def accelerations(self, st):
+        st.evaluations += 1
+        acc, _ = fmm(st.pos, st.mass, None, **self.kw)
+        return acc
+
+    def init(self, st):
+        st.acc = self.accelerations(st)
+
+    def modified_acceleration(self, st, h):
+        """a~ at the current positions, and the plain acceleration there."""
+        t = Tree(st.pos, None, **self.kw)
+        acc, _, grad = t.evaluate_grad(st.mass)
+        u, _ = t.evaluate_dipole(st.mass, acc)
+        st.evaluations += 2
+        return acc + h * h / 24 * (tensor_apply(grad, acc) + u), acc
+
+    def step(self, st, h):
+        st.vel += h / 6 * st.acc
+        st.pos += h / 2 * st.vel
+        amod, _ = self.modified_acceleration(st, h)
+        st.vel += 2 * h / 3 * amod
+        st.pos += h / 2 * st.vel
+        st.acc = self.accelerations(st)
+        st.vel += h / 6 * st.acc
+        st.t += h
 
 
 # --------------------------------------------------------------------------
