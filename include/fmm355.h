@@ -135,6 +135,62 @@ fmm_status fmm_forces_grad(fmm_ctx *ctx, const double *pos, const double *mass, 
                            const int32_t *active, int64_t n_active, double eps, double theta,
                            int p, double *acc, double *pot, double *grad);
 
+/* The field of vector sources on the tree of the last fmm_build /
+ * fmm_forces / fmm_forces_grad (one system; same pos, active, n_total and
+ * n_active, else FMM_ESTALE): every active particle j carries the vector
+ * m_j v_j, and
+ *   u_i   = sum_{j != i} m_j H(x_i - x_j) v_j,   H = grad grad psi
+ *           (the pair Hessian g I + (dg/dr)/r d d^T of the softened kernel),
+ *   phi_i = sum_{j != i} m_j v_j . grad psi(x_i - x_j).
+ * u_i is the derivative of a_i along a displacement of every other particle j
+ * by v_j, sum_j (d a_i / d x_j) v_j; with v = a it is the cross term of the
+ * force-gradient kick of the fourth-order integrator of Sec. 4.1.  Computed
+ * through the same expansions as the forces: each source's moments are the
+ * derivative of its mass moments along v_j (total degree <= p), the same
+ * M2M, M2L and L2L, u = +grad of the local expansion at L2P, and the P2P
+ * partners summed directly (context precision, as fmm_forces_grad).
+ * vec, u: device SoA 3 x n_active; phi: device n_active; all in active
+ * order.  The first call allocates 3 x max_n doubles of scratch in the
+ * context.  FMM_EINVAL for NULL arrays, a batched tree or p outside 1..p_max;
+ * asynchronous on the context's stream. */
+fmm_status fmm_evaluate_dipole(fmm_ctx *ctx, const double *pos, const double *mass,
+                               int64_t n_total, const int32_t *active, int64_t n_active, int p,
+                               const double *vec, double *u, double *phi);
+
+/* ---------------------------------------------------------------------------
+ * Forward fourth-order integrator (Sec. 4.1: Chin & Chen 2005, algorithm 4A)
+ * with one shared timestep h:  v += h/6 a;  x += h/2 v;  v += 2h/3 a~;
+ * x += h/2 v;  v += h/6 a, where the middle kick uses the modified
+ * acceleration a~_i = a_i + (h^2/24) sum_j (d a_i / d x_j) a_j
+ * = a_i + (h^2/24) (T_i a_i + u_i), T_i the force gradient of fmm_forces_grad
+ * and u_i the field of the vector sources m_j a_j (fmm_evaluate_dipole).
+ * Per step: two trees, three evaluations (forces with the gradient, the
+ * vector-source pass, forces at the end, whose acceleration opens the next
+ * step).  Kicks and drifts FP64.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    double *pos;        /* device, 3 x n SoA (updated in place)                */
+    double *vel;        /* device, 3 x n SoA (updated in place)                */
+    const double *mass; /* device, n                                           */
+    double *acc;        /* device, 3 x n: acceleration at pos (set by chin_init
+                           and by every step)                                  */
+    double *work;       /* device scratch of chin_work_bytes(n) bytes, owned by
+                           the caller, not read between calls                  */
+    int64_t n;          /* 1 .. max_n of the context                           */
+    double t;           /* advanced by h per step                              */
+} chin_state;
+
+/* Bytes of the work array for n particles (13 n doubles); -1 for n < 1. */
+int64_t chin_work_bytes(int64_t n);
+/* acc = acceleration at pos (one fmm_forces); needed once before chin_step. */
+fmm_status chin_init(fmm_ctx *ctx, chin_state *st, double eps, double theta, int p);
+/* One step of length h (h != 0 and finite: a negative h steps backwards, the
+ * scheme being time symmetric).  stats (host, may be NULL): [0] evaluations
+ * (3), [1] particles summed over them, [2] tree builds (2).  FMM_EINVAL for a
+ * bad state or h; errors of the solves are passed on. */
+fmm_status chin_step(fmm_ctx *ctx, chin_state *st, double eps, double theta, int p, double h,
+                     int64_t stats[3]);
+
 /* ---------------------------------------------------------------------------
  * Comoving integration factors (Sec. 3.5, Eqs. 10-11): the drift operator
  * moves comoving positions by p/m times the integral of dt/a^2 over the step,

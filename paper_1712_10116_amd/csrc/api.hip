@@ -634,6 +634,39 @@ extern "C" fmm_status fmm_forces_grad(fmm_ctx *c, const double *pos, const doubl
   return FMM_OK;
 }
 
+extern "C" fmm_status fmm_evaluate_dipole(fmm_ctx *c, const double *pos, const double *mass,
+                                          int64_t n_total, const int32_t *active,
+                                          int64_t n_active, int p, const double *vec, double *u,
+                                          double *phi) {
+  if (!c) return FMM_EINVAL;
+  if (n_active > 0 && (!vec || !u || !phi || !mass))
+    return fail(c, FMM_EINVAL, "NULL mass, vec, u or phi");
+  if (c->tree_valid && c->b_reqs.size() != 1)
+    return fail(c, FMM_EINVAL, "the vector-source pass needs a single-system tree");
+  fmm_request q = one_request(pos, mass, n_total, active, n_active, u, phi);
+  int64_t n_all = 0;
+  fmm_status st = check_requests(c, 1, &q, true, &n_all);
+  if (st != FMM_OK) return st;
+  const fmm_request &b = c->b_reqs.empty() ? q : c->b_reqs[0];
+  if (!c->tree_valid || b.pos != pos || b.active != active || b.n_active != n_active ||
+      b.n_total != n_total)
+    return fail(c, FMM_ESTALE, "no tree built for these particles");
+  if (p < 1 || p > c->prm.p_max || !eval_order_supported(p))
+    return fail(c, FMM_EINVAL, "order p=%d unsupported (1..%d)", p, std::min(c->prm.p_max, 6));
+  if (n_active == 0) return FMM_OK;
+  if (!c->dvec && !dalloc(c, &c->dvec, 3 * c->max_n))
+    return fail(c, FMM_ENOMEM, "vector-source scratch");
+  st = upload_requests(c, 1, &q, nullptr);
+  if (st != FMM_OK) return st;
+  EvalArgs e = {};
+  set_eval_args(c, e, n_all, p, c->b_eps);
+  e.n_nodes = c->n_nodes;
+  e.lvl_start_host = c->hh.lvl_start;
+  e.depth = c->depth;
+  HIPCHK(c, launch_dipole(c->t, e, vec, c->dvec, c->stream));
+  return FMM_OK;
+}
+
 extern "C" fmm_status fmm_tree_info(fmm_ctx *c, int64_t info[9]) {
   if (!c || !info) return FMM_EINVAL;
   if (!c->tree_valid) return fail(c, FMM_ESTALE, "no tree");

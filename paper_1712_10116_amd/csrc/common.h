@@ -281,6 +281,15 @@ bool eval_order_supported(int p);
 // the tree and local expansions of the evaluation just queued on stream s
 hipError_t launch_force_gradient(const DevTree &t, int n_nodes, int n, int p, int kernel,
                                  bool mixed, double eps, double *grad, hipStream_t s);
+// vector-source pass (eval.hip): sources m_j v_j on the last build's tree (one
+// system), vec SoA 3 x e.n in active order, dv scratch 3 x cap_n doubles;
+// the request's acc receives +gradient of their potential, pot the potential
+hipError_t launch_dipole(const DevTree &t, const EvalArgs &e, const double *vec, double *dv,
+                         hipStream_t s);
+// its near field (grad.hip): minus sum_j m_j H(x_i - x_j) v_j over the P2P
+// partners into near[0..2], sum_j m_j v_j . grad psi(x_i - x_j) into near[3]
+hipError_t launch_p2p_dipole(const DevTree &t, int n_nodes, int kernel, bool mixed, double eps,
+                             const double *dv, hipStream_t s);
 // hhs.hip
 hipError_t launch_gather_mask_mass(const double *mass, const int32_t *sys, int n_sys,
                                    const int32_t *flag_fast, int mask_fast, double *out,

@@ -52,6 +52,8 @@ struct fmm_ctx {
   int cap_split;
   std::vector<int32_t> h_split;
   double *inv_part;
+  double *dvec;            // [3][max_n] sorted source vectors of the vector-source pass
+                           // (allocated by its first call)
   int64_t stat_calls, stat_parts, stat_builds;
   PhaseTimer timer;
   char err[512];

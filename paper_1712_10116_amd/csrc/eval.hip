@@ -205,6 +205,82 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2m(DevTree t, int n_nodes, bool 
     p2m_cell8<T, P>(t, i, threadIdx.x & 7, harm);
 }
 
+// Moments of vector sources m_j v_j (the vector-source pass): the derivative
+// of a leaf's mass moments along a displacement of each particle by its v_j,
+// Mt[k] = -(m_j/h) sum_a v_a (u_j/h)^(k - e_a)/(k - e_a)!  (a with k_a >= 1),
+// in the scaling of p2m_cell8.  dv: sorted-order SoA vectors, stride cap_n.
+template <typename T, int P>
+__device__ __forceinline__ void p2m_dip_cell8(const DevTree &t, const double *__restrict__ dv,
+                                              int i, int g8, bool harm) {
+  constexpr int K = MI<P>::K;
+  constexpr MI<P> mi{};
+  T *M = (T *)t.M;
+  if (t.nnchild[i] != 0 || skipped(t, i)) return;
+  const double4 g = t.ngeo[i];
+  const double ih = 1.0 / g.w;
+  const int64_t cap = t.cap_n;
+  T acc[K], cmp[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = cmp[k] = T(0);
+  for (int j = t.nbeg[i] + g8; j < t.nend[i]; j += 8) {
+    t.leaf_of[j] = i;
+    T mono[K];
+    monomials<T, P>((T)((t.sx[j] - g.x) * ih), (T)((t.sy[j] - g.y) * ih),
+                    (T)((t.sz[j] - g.z) * ih), mono);
+    const double mh = t.sm[j] * ih;
+    const T w[3] = {(T)(-mh * dv[j]), (T)(-mh * dv[cap + j]), (T)(-mh * dv[2 * cap + j])};
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      T v = T(0);
+      if (mi.x[k] > 0) v = fma(w[0], mono[mi.at(mi.x[k] - 1, mi.y[k], mi.z[k])], v);
+      if (mi.y[k] > 0) v = fma(w[1], mono[mi.at(mi.x[k], mi.y[k] - 1, mi.z[k])], v);
+      if (mi.z[k] > 0) v = fma(w[2], mono[mi.at(mi.x[k], mi.y[k], mi.z[k] - 1)], v);
+      if (sizeof(T) == 4) {  // Kahan-Babuska summation of the FP32 moments
+        T y = v - cmp[k];
+        T s = acc[k] + y;
+        cmp[k] = (s - acc[k]) - y;
+        acc[k] = s;
+      } else {
+        acc[k] += v;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = (T)sum8<double>((double)acc[k] - (double)cmp[k]);
+  if (g8 == 0) {
+    store_row<T, P>(M, t.kmax, i, acc);
+    if (harm) store_folded<T, P>(t, i, acc);
+  }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(FMM_BLOCK) void k_p2m_dip(DevTree t, int n_nodes,
+                                                       const double *__restrict__ dv, bool harm) {
+  const int stride = (gridDim.x * blockDim.x) >> 3;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; i < n_nodes; i += stride)
+    p2m_dip_cell8<T, P>(t, dv, i, threadIdx.x & 7, harm);
+}
+
+// Masses (as k_gather_mass) and the source vectors of the vector-source pass
+// in sorted order: dv[a * cap + j] = vec[a * n + active slot of j] (one
+// system, slots from 0).
+__global__ __launch_bounds__(FMM_BLOCK) void k_gather_dip(DevTree t, int n,
+                                                          const double *__restrict__ vec,
+                                                          double *__restrict__ dv) {
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int s = t.slot[j];
+  const DevReq q = t.reqs[0];
+  const int64_t g = q.active ? q.active[s] : s;
+  const double m = q.mass[g];
+  t.sm[j] = m;
+  t.sm32[j] = (float)m;
+  const int64_t cap = t.cap_n;
+  dv[j] = vec[s];
+  dv[cap + j] = vec[n + s];
+  dv[2 * cap + j] = vec[2 * n + s];
+}
+
 // M2M for a cell with children, lane g8 shifting child g8 (if any); the
 // shifted children are summed over the group.
 template <typename T, int P>
@@ -368,9 +444,11 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2l_small(DevTree t, int depth, b
   }
 }
 
-// L2P + near field + un-permute: one thread per Morton-sorted particle
+// L2P + near field + un-permute: one thread per Morton-sorted particle.
+// sgn = 1 writes the acceleration, minus the gradient of the potential;
+// sgn = -1 writes the gradient itself (the vector-source pass).
 template <typename T, int P>
-__global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, bool dev) {
+__global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, bool dev, double sgn) {
   constexpr int K = MI<P>::K;
   const T *L = (const T *)t.L;
   int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -392,9 +470,9 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p(DevTree t, int n, bool dev) {
   T phi, gx, gy, gz;
   l2p_eval<T, P>(Lt, mono, phi, gx, gy, gz);
   const int64_t cap = t.cap_n;
-  q.acc[i] = t.near[j] - (double)gx * ih;
-  q.acc[nq + i] = t.near[cap + j] - (double)gy * ih;
-  q.acc[2 * nq + i] = t.near[2 * cap + j] - (double)gz * ih;
+  q.acc[i] = sgn * (t.near[j] - (double)gx * ih);
+  q.acc[nq + i] = sgn * (t.near[cap + j] - (double)gy * ih);
+  q.acc[2 * nq + i] = sgn * (t.near[2 * cap + j] - (double)gz * ih);
   q.pot[i] = t.near[3 * cap + j] + (double)phi;
 }
 
@@ -881,7 +959,7 @@ static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   }
   hipStreamWaitEvent(s, e.join, 0);
   hipLaunchKernelGGL((k_l2p<T, P>), dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
-                     s, t, e.n, e.dev);
+                     s, t, e.n, e.dev, 1.0);
   if (tm) tm->stop(s);
 }
 
@@ -937,6 +1015,76 @@ hipError_t launch_evaluate(const DevTree &t, const EvalArgs &e, hipStream_t s) {
     ok = e.kernel == 1 ? dispatch_order<float, 1>(t, e, s) : dispatch_order<float, 0>(t, e, s);
   else
     ok = e.kernel == 1 ? dispatch_order<double, 1>(t, e, s) : dispatch_order<double, 0>(t, e, s);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Vector-source pass on the tree of the last build (one system): sources
+// m_j v_j, output u = +gradient of their potential (the derivative of the
+// accelerations along the displacement field v) and that potential.  All on
+// stream s: gather, dipole P2M, M2M, M2L, L2L, near field (grad.hip), L2P.
+template <typename T, int P, int KERNEL>
+static void run_dipole(const DevTree &t, const EvalArgs &e, const double *vec, double *dv,
+                       hipStream_t s) {
+  const int nn = e.n_nodes;
+  const bool harm = KERNEL == 0;
+  hipLaunchKernelGGL(k_gather_dip, dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0, s,
+                     t, e.n, vec, dv);
+  hipLaunchKernelGGL((k_p2m_dip<T, P>), dim3((8 * nn + FMM_BLOCK - 1) / FMM_BLOCK),
+                     dim3(FMM_BLOCK), 0, s, t, nn, (const double *)dv, harm);
+  if (nn <= SMALL_NODES && e.depth > 0) {
+    hipLaunchKernelGGL((k_m2m_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth, harm,
+                       false);
+  } else {
+    for (int l = e.depth - 1; l >= 0; --l) {
+      int blocks, a0, a1;
+      level_launch(e, l, 8, blocks, a0, a1);
+      if (blocks > 0)
+        hipLaunchKernelGGL((k_m2m<T, P>), dim3(blocks), dim3(FMM_BLOCK), 0, s, t, a0, a1, harm);
+    }
+  }
+  hipLaunchKernelGGL((k_m2l<T, P, KERNEL>), dim3((nn + 3) / 4), dim3(FMM_BLOCK), 0, s, t, nn,
+                     e.eps);
+  if (nn <= SMALL_NODES && e.depth > 0) {
+    hipLaunchKernelGGL((k_l2l_small<T, P>), dim3(1), dim3(FMM_BLOCK), 0, s, t, e.depth, false);
+  } else {
+    for (int l = 1; l <= e.depth; ++l) {
+      int blocks, a0, a1;
+      level_launch(e, l, 1, blocks, a0, a1);
+      if (blocks > 0)
+        hipLaunchKernelGGL((k_l2l<T, P>), dim3(blocks), dim3(FMM_BLOCK), 0, s, t, a0, a1);
+    }
+  }
+  launch_p2p_dipole(t, nn, e.kernel, sizeof(T) == 4, e.eps, dv, s);
+  hipLaunchKernelGGL((k_l2p<T, P>), dim3((e.n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
+                     s, t, e.n, false, -1.0);
+}
+
+template <typename T, int KERNEL>
+static bool dispatch_dipole(const DevTree &t, const EvalArgs &e, const double *vec, double *dv,
+                            hipStream_t s) {
+  switch (e.p) {
+    case 1: run_dipole<T, 1, KERNEL>(t, e, vec, dv, s); return true;
+    case 2: run_dipole<T, 2, KERNEL>(t, e, vec, dv, s); return true;
+    case 3: run_dipole<T, 3, KERNEL>(t, e, vec, dv, s); return true;
+    case 4: run_dipole<T, 4, KERNEL>(t, e, vec, dv, s); return true;
+    case 5: run_dipole<T, 5, KERNEL>(t, e, vec, dv, s); return true;
+    case 6: run_dipole<T, 6, KERNEL>(t, e, vec, dv, s); return true;
+    default: return false;
+  }
+}
+
+hipError_t launch_dipole(const DevTree &t, const EvalArgs &e, const double *vec, double *dv,
+                         hipStream_t s) {
+  if (e.n <= 0) return hipSuccess;
+  bool ok;
+  if (e.mixed)
+    ok = e.kernel == 1 ? dispatch_dipole<float, 1>(t, e, vec, dv, s)
+                       : dispatch_dipole<float, 0>(t, e, vec, dv, s);
+  else
+    ok = e.kernel == 1 ? dispatch_dipole<double, 1>(t, e, vec, dv, s)
+                       : dispatch_dipole<double, 0>(t, e, vec, dv, s);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -164,7 +164,102 @@ bool dispatch_grad(const DevTree &t, int n_nodes, int n, int p, double eps, doub
   }
 }
 
+// Near field of the vector-source pass: for every sink i the sum over the
+// particles j of its leaf's P2P partners (j != i) of m_j H(x_i - x_j) v_j,
+// H = g I + h d d^T the pair Hessian, and of m_j v_j . grad psi(x_i - x_j)
+// = -m_j g (v_j . d), d = x_j - x_i.  Written to near[] in sorted order with
+// the sign of an acceleration (minus the field) so that L2P adds the far
+// field's gradient the same way.  Layout as k_p2p_grad: one wavefront per
+// sink leaf, (sink, phase) lanes, each source leaf staged through LDS 64
+// particles at a time, pair terms in R on FP64 differences, summed in R over
+// one source leaf and then into FP64.
+template <typename R, int KERNEL>
+__global__ __launch_bounds__(FMM_BLOCK) void k_p2p_dip(DevTree t, int n_nodes, double eps,
+                                                       const double *__restrict__ dv) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * blockDim.x) >> 6;
+  const R reps = (R)eps, ie = eps > 0 ? (R)(1.0 / eps) : R(0);
+  const int64_t cap = t.cap_n;
+  __shared__ double4 stage_x[FMM_BLOCK / 64][64];
+  __shared__ double4 stage_v[FMM_BLOCK / 64][64];
+  double4 *sx = stage_x[threadIdx.x >> 6];
+  double4 *sv = stage_v[threadIdx.x >> 6];
+  for (int A = wave; A < n_nodes; A += nwaves) {
+    if (t.nnchild[A] != 0) continue;
+    const int bA = t.nbeg[A], nA = t.nend[A] - bA;
+    const int loff = t.p2p_off[A], cnt = t.p2p_cnt[A];
+    for (int tb = 0; tb < nA; tb += 64) {
+      const int ns = min(64, nA - tb);
+      const int nph = ns <= 4 ? 16 : ns <= 8 ? 8 : ns <= 16 ? 4 : ns <= 32 ? 2 : 1;
+      const int ti = lane / nph, ph = lane % nph;
+      const bool valid = ti < ns;
+      const int i = bA + tb + (valid ? ti : 0);
+      const double xi = t.sx[i], yi = t.sy[i], zi = t.sz[i];
+      double U[4] = {0, 0, 0, 0};
+      for (int q = 0; q < cnt; ++q) {
+        const int B = t.p2p_src[loff + q];
+        const int eB = t.nend[B];
+        R Us[4] = {0, 0, 0, 0};
+        for (int jb = t.nbeg[B]; jb < eB; jb += 64) {
+          const int nj = min(64, eB - jb);
+          if (lane < nj) {
+            const int j = jb + lane;
+            sx[lane] = make_double4(t.sx[j], t.sy[j], t.sz[j], t.sm[j]);
+            sv[lane] = make_double4(dv[j], dv[cap + j], dv[2 * cap + j], 0.0);
+          }
+          __builtin_amdgcn_wave_barrier();
+          for (int u = ph; u < nj; u += nph) {
+            if (jb + u == i) continue;
+            const double4 p = sx[u], v4 = sv[u];
+            const R d[3] = {(R)(p.x - xi), (R)(p.y - yi), (R)(p.z - zi)};
+            const R v[3] = {(R)v4.x, (R)v4.y, (R)v4.z};
+            const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            R g, h;
+            pair_gh<R, KERNEL>(r2, reps, ie, g, h);
+            const R m = (R)p.w;
+            const R dvv = d[0] * v[0] + d[1] * v[1] + d[2] * v[2];
+            const R mg = m * g, mhd = m * h * dvv;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Us[c] += mg * v[c] + mhd * d[c];
+            Us[3] -= mg * dvv;
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) U[c] += (double)Us[c];
+      }
+      for (int o = nph >> 1; o > 0; o >>= 1)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) U[c] += __shfl_xor(U[c], o, 64);
+      if (valid && ph == 0) {
+        t.near[i] = -U[0];
+        t.near[cap + i] = -U[1];
+        t.near[2 * cap + i] = -U[2];
+        t.near[3 * cap + i] = U[3];
+      }
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_p2p_dipole(const DevTree &t, int n_nodes, int kernel, bool mixed, double eps,
+                             const double *dv, hipStream_t s) {
+  const dim3 grid((n_nodes + 3) / 4), blk(FMM_BLOCK);
+  if (mixed) {
+    if (kernel == 1)
+      hipLaunchKernelGGL((k_p2p_dip<float, 1>), grid, blk, 0, s, t, n_nodes, eps, dv);
+    else
+      hipLaunchKernelGGL((k_p2p_dip<float, 0>), grid, blk, 0, s, t, n_nodes, eps, dv);
+  } else {
+    if (kernel == 1)
+      hipLaunchKernelGGL((k_p2p_dip<double, 1>), grid, blk, 0, s, t, n_nodes, eps, dv);
+    else
+      hipLaunchKernelGGL((k_p2p_dip<double, 0>), grid, blk, 0, s, t, n_nodes, eps, dv);
+  }
+  return hipGetLastError();
+}
 
 // One system's tree (request 0 at slot offset 0), n active particles.
 hipError_t launch_force_gradient(const DevTree &t, int n_nodes, int n, int p, int kernel,

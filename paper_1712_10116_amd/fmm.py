@@ -27,6 +27,7 @@ EXPORTED = (
     "serve_submit", "serve_step", "serve_poll", "serve_cancel", "serve_info",
     "fmm_set_small_path", "fmm_set_level_prediction", "trad_step", "fmm_forces_grad",
     "fmm_cosmo_create", "fmm_cosmo_factors", "fmm_cosmo_destroy", "fmm_invariants_noalloc",
+    "fmm_evaluate_dipole", "chin_work_bytes", "chin_init", "chin_step",
 )
 PHASES = ("sort", "tree", "walk", "upward", "m2l", "p2p", "downward")
 
@@ -72,6 +73,12 @@ class HHSState(ctypes.Structure):
     _fields_ = [("pos", ctypes.c_void_p), ("vel", ctypes.c_void_p), ("mass", ctypes.c_void_p),
                 ("a_old", ctypes.c_void_p), ("a_cur", ctypes.c_void_p), ("rung", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("t", ctypes.c_double), ("a_tot", ctypes.c_void_p)]
+
+
+class ChinState(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("vel", ctypes.c_void_p), ("mass", ctypes.c_void_p),
+                ("acc", ctypes.c_void_p), ("work", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("t", ctypes.c_double)]
 
 
 class CosmoParams(ctypes.Structure):
@@ -146,6 +153,10 @@ def lib():
         L.fmm_export_tree.argtypes = [vp] + [vp] * 11
         L.fmm_invariants.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
         L.fmm_invariants_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp]
+        L.fmm_evaluate_dipole.argtypes = [vp, vp, vp, i64, vp, i64, ci, vp, vp, vp]
+        L.chin_work_bytes.argtypes = [i64]
+        L.chin_init.argtypes = [vp, ctypes.POINTER(ChinState), dbl, dbl, ci]
+        L.chin_step.argtypes = [vp, ctypes.POINTER(ChinState), dbl, dbl, ci, dbl, vp]
         L.hhs_init.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams)]
         L.hhs_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
         L.trad_step.argtypes = [vp, ctypes.POINTER(HHSState), ctypes.POINTER(HHSParams), dbl, vp]
@@ -175,9 +186,11 @@ def lib():
         L.serve_cancel.argtypes = [vp, i64]
         L.serve_info.argtypes = [vp, vp]
         for name in EXPORTED:
-            if name not in ("fmm_last_error", "hhs_run_bytes", "serve_footprint"):
+            if name not in ("fmm_last_error", "hhs_run_bytes", "serve_footprint",
+                            "chin_work_bytes"):
                 getattr(L, name).restype = ctypes.c_int
         L.hhs_run_bytes.restype = i64
+        L.chin_work_bytes.restype = i64
         L.serve_footprint.restype = i64
         _lib = L
     return _lib
@@ -301,6 +314,20 @@ class Solver:
                                           n, float(eps), float(theta), int(p), _ptr(acc),
                                           _ptr(pot), _ptr(grad)))
         return acc, pot, grad
+
+    def evaluate_dipole(self, pos, mass, vec, active=None, *, p):
+        """fmm_evaluate_dipole on the last tree: (u (3,n), phi (n)) of the
+        vector sources m_j vec_j (vec (3,n) in active order)."""
+        n_total = pos.shape[1]
+        n = n_total if active is None else active.shape[0]
+        _check_dev(mass, torch.float64, (n_total,), "mass")
+        _check_dev(vec, torch.float64, (3, n), "vec")
+        u = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+        phi = torch.empty((n,), dtype=torch.float64, device=pos.device)
+        self._raise(lib().fmm_evaluate_dipole(self._h, _ptr(pos), _ptr(mass), n_total,
+                                              _ptr(active), n, int(p), _ptr(vec), _ptr(u),
+                                              _ptr(phi)))
+        return u, phi
 
     def _requests(self, systems, with_outputs):
         arr = (Request * len(systems))()
@@ -512,6 +539,40 @@ class HHS:
                                            ctypes.byref(self.params), float(dt_top),
                                            _hptr(stats)))
         return dict(force_calls=int(stats[0]), force_particles=int(stats[1]), builds=int(stats[2]))
+
+
+class Chin:
+    """Device state of the fourth-order integrator (chin_init / chin_step):
+    positions and velocities are updated in place; ``acc`` holds the
+    acceleration at the current positions."""
+
+    def __init__(self, solver, pos, vel, mass, *, eps, theta, p, t=0.0):
+        n = pos.shape[1]
+        for arr, nm, shp in ((pos, "pos", (3, n)), (vel, "vel", (3, n)), (mass, "mass", (n,))):
+            _check_dev(arr, torch.float64, shp, nm)
+        self.solver = solver
+        self.pos, self.vel, self.mass = pos, vel, mass
+        self.acc = torch.zeros((3, n), dtype=torch.float64, device=pos.device)
+        nb = int(lib().chin_work_bytes(n))
+        self.work = torch.empty((nb // 8,), dtype=torch.float64, device=pos.device)
+        self.state = ChinState(pos.data_ptr(), vel.data_ptr(), mass.data_ptr(),
+                               self.acc.data_ptr(), self.work.data_ptr(), n, float(t))
+        self.eps, self.theta, self.p = float(eps), float(theta), int(p)
+
+    @property
+    def t(self):
+        return self.state.t
+
+    def init(self):
+        self.solver._raise(lib().chin_init(self.solver._h, ctypes.byref(self.state), self.eps,
+                                           self.theta, self.p))
+
+    def step(self, h):
+        import numpy as np
+        stats = np.zeros(3, dtype=np.int64)
+        self.solver._raise(lib().chin_step(self.solver._h, ctypes.byref(self.state), self.eps,
+                                           self.theta, self.p, float(h), _hptr(stats)))
+        return dict(evaluations=int(stats[0]), particles=int(stats[1]), builds=int(stats[2]))
 
 
 def _batch_args(systems):
