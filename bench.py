@@ -114,10 +114,22 @@ def time_solver(F, torch, s, tp, tm, acc, pot, prm, steps, warmup, profile):
     return (t1 - t0) / steps, phases, kern
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_leg(args, n, pos, mass, res, prm, line):
     """CPU side: FP64 direct summation (oracle) on a seeded sample of sinks as
-    the force-error reference of every GPU result, and the oracle FMM timed on
-    a bounded sample of the same workload."""
+    the force-error reference of every GPU result, and the oracle FMM timed
+    twice: the whole workload on all host cores (its OpenMP evaluation, equal
+    to the single-threaded one bit for bit), and the single-threaded oracle on
+    a bounded sample of the same recipe."""
     from oracle import oracle as O
     from paper_1712_10116_amd import workloads as W
     rng = np.random.default_rng(2024)
@@ -127,11 +139,24 @@ def cpu_leg(args, n, pos, mass, res, prm, line):
         e = force_error(r["acc"][:, sinks], ref)
         line["force_err"]["vs_direct_sample"][name] = {"rms": e[0], "p99": e[1]}
     line["force_err"]["vs_direct_sample"]["sinks"] = int(len(sinks))
-    # a sample of about 10-30 s of single-thread work: doubled while the
-    # solve takes under 10 s (and the next would stay under about 40 s)
-    ns = min(args.cpu_sample, n)
     kw = dict(p=prm["p"], theta=prm["theta"], eps=0.005, leaf_size=prm["leaf_size"],
               kernel=O.WENDLAND)
+    # all cores, the whole workload: tree build + evaluation, best of up to
+    # three runs (fewer when one takes more than 15 s)
+    threads = O.threads()
+    best = None
+    for _ in range(3):
+        t0 = time.perf_counter()
+        t = O.Tree(pos, **kw)
+        t.evaluate_parallel(mass)
+        dt = time.perf_counter() - t0
+        del t
+        best = dt if best is None else min(best, dt)
+        if dt > 15.0:
+            break
+    # one thread: the plain oracle on a sample of about 10-30 s of work,
+    # doubled while the solve takes under 10 s
+    ns = min(args.cpu_sample, n)
     while True:
         spos, _, smass = W.uniform_sphere(ns, seed=1001)
         t0 = time.perf_counter()
@@ -140,12 +165,89 @@ def cpu_leg(args, n, pos, mass, res, prm, line):
         if t1 - t0 >= 10.0 or ns >= n or 2.2 * (t1 - t0) > 40.0:
             break
         ns = min(n, 2 * ns)
-    line["cpu_baseline"] = {"value": round(ns / (t1 - t0), 1), "unit": "particles/s", "cores": 1,
-                            "kind": "oracle",
-                            "sample": f"one oracle FMM force solve (FP64, single thread, "
-                                      f"p={prm['p']}, theta={prm['theta']}, leaf "
-                                      f"{prm['leaf_size']}) on a {ns}-particle uniform sphere of "
-                                      f"the same recipe, {t1 - t0:.1f} s"}
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    line["cpu_baseline"] = {
+        "value": round(n / best, 1), "unit": "particles/s", "cores": threads, "kind": "oracle",
+        "sample": f"the whole workload ({n} particles, p={prm['p']}, theta={prm['theta']}, leaf "
+                  f"{prm['leaf_size']}): one oracle FMM force solve (FP64, tree build and "
+                  f"evaluation) with its evaluation on {threads} OpenMP threads, best of the "
+                  f"runs, {best:.2f} s",
+        "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "cpus_available": affinity,
+        "single_thread": {"value": round(ns / (t1 - t0), 1), "unit": "particles/s",
+                          "sample": f"the single-threaded oracle on a {ns}-particle uniform "
+                                    f"sphere of the same recipe, {t1 - t0:.1f} s"}}
+
+
+def chin_leg(args, F, torch, line):
+    """The fourth-order integrator of Sec. 4.1 (chin_step) against the KDK
+    leapfrog at equal force evaluations: a Plummer sphere of 65,536 particles
+    (Plummer softening, FP64, p 6, leaf 64; theta 0.4, and theta 1e-6 where
+    every pair is summed directly) advanced to t = 1,
+    Chin with h = 1/16 (16 steps, 1 + 3 x 16 evaluations) against KDK with h =
+    1/48 (48 steps, the closing kick's acceleration reused by the next
+    opening kick: 1 + 48 evaluations); the energy is measured after every
+    Chin step and every third KDK step (same times) by an FP64 direct sum,
+    and the largest relative error of each run is reported.  The KDK kicks
+    and drifts are torch additions around the library's solves."""
+    from paper_1712_10116_amd import workloads as W
+    dev = torch.device("cuda:0")
+    n, t_end, hc = 65536, 1.0, 1.0 / 16
+    pos, vel, m = W.plummer(n, seed=1500)
+    tm = torch.from_numpy(m).to(dev)
+    out = {"n": n, "t_end": t_end, "h_chin": hc, "h_kdk": hc / 3, "precision": "fp64",
+           "p": 6, "leaf_size": 64, "kernel": "plummer", "runs": []}
+    # the FMM at theta 0.4, and every pair summed directly (theta 1e-6), where
+    # the solver's truncation error no longer adds to the integration error
+    for eps, theta in ((0.1, 0.4), (0.1, 1e-6), (0.3, 1e-6)):
+        kw = dict(eps=eps, theta=theta, p=6)
+        s = F.Solver(n, p_max=6, leaf_size=64, kernel=F.PLUMMER, precision=F.FP64)
+        e = F.Solver(n, p_max=4, leaf_size=64, kernel=F.PLUMMER, precision=F.FP64)
+
+        def energy(tp, tv):
+            _, pot = e.forces(tp, tm, eps=eps, theta=1e-6, p=4)
+            inv = e.invariants(vel=tv, mass=tm, pot=pot)
+            return inv["T"] + inv["W"]
+
+        steps = int(round(t_end / hc))
+        tp = torch.from_numpy(pos.copy()).to(dev)
+        tv = torch.from_numpy(vel.copy()).to(dev)
+        E0 = energy(tp, tv)
+        c = F.Chin(s, tp, tv, tm, **kw)
+        c.init()
+        dc, sec_c = [], 0.0
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.step(hc)
+            torch.cuda.synchronize()
+            sec_c += time.perf_counter() - t0
+            dc.append(abs(energy(tp, tv) / E0 - 1))
+        tp = torch.from_numpy(pos.copy()).to(dev)
+        tv = torch.from_numpy(vel.copy()).to(dev)
+        a, _ = s.forces(tp, tm, **kw)
+        h = hc / 3
+        dk, sec_k = [], 0.0
+        for k in range(3 * steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tv.add_(a, alpha=h / 2)
+            tp.add_(tv, alpha=h)
+            a, _ = s.forces(tp, tm, **kw)
+            tv.add_(a, alpha=h / 2)
+            torch.cuda.synchronize()
+            sec_k += time.perf_counter() - t0
+            if k % 3 == 2:
+                dk.append(abs(energy(tp, tv) / E0 - 1))
+        s.close()
+        e.close()
+        out["runs"].append({"eps": eps, "theta": theta, "evaluations": 1 + 3 * steps,
+                            "chin": {"max_energy_err": max(dc), "seconds": round(sec_c, 4)},
+                            "kdk": {"max_energy_err": max(dk), "seconds": round(sec_k, 4)},
+                            "kdk_over_chin": round(max(dk) / max(max(dc), 1e-300), 2)})
+    line["chin"] = out
 
 
 def ensemble_leg(args, F, torch, line):
@@ -257,6 +359,12 @@ def configs_leg(args, F, torch, line):
         inv = s.invariants(mass=tm, acc=acc)
         a = acc.cpu().numpy()
         s.close()
+        sec64 = None
+        if precision[c] == F.MIXED:  # the plain FP64 path at the same parameters
+            s = F.Solver(n, p_max=prm["p"], leaf_size=leaf, kernel=prm["kernel"],
+                         precision=F.FP64)
+            sec64, _, _ = time_solver(F, torch, s, tp, tm, acc, pot, pr, 5, 1, profile=False)
+            s.close()
         rp = autotune.REFERENCE
         r = F.Solver(n, p_max=rp["p"], leaf_size=rp["leaf_size"], kernel=prm["kernel"],
                      precision=F.FP64)
@@ -270,6 +378,9 @@ def configs_leg(args, F, torch, line):
                "ms_per_solve": round(sec * 1e3, 4), "particles_per_s": round(n / sec, 1),
                "force_err_vs_reference_all": {"rms": e_all[0], "p99": e_all[1]},
                "momentum_rel": float(np.abs(inv["F"]).max() / inv["Fabs"])}
+        if sec64 is not None:
+            row["fp64"] = {"ms_per_solve": round(sec64 * 1e3, 4),
+                           "particles_per_s": round(n / sec64, 1)}
         if not args.no_cpu_baseline:
             from oracle import oracle as O
             rng = np.random.default_rng(3000 + c)
@@ -278,7 +389,10 @@ def configs_leg(args, F, torch, line):
                             prm["eps"], sinks=sk)
             e = force_error(a[:, sk], d)
             row["force_err_vs_direct_sample"] = {"rms": e[0], "p99": e[1], "sinks": int(len(sk))}
-        steps, t_end = {0: (8, None), 1: (None, args.collapse_t_end)}.get(c, (0, None))
+        # HHS: 8 steps of the Plummer sphere, the cold collapse to t_end, one
+        # top-level step of the disk (14 rungs) and of the zoom (16 rungs)
+        steps, t_end = {0: (8, None), 1: (None, args.collapse_t_end), 2: (1, None),
+                        3: (1, None)}.get(c, (0, None))
         if steps or t_end:
             s = F.Solver(n, p_max=prm["p"], leaf_size=leaf, kernel=prm["kernel"],
                          precision=precision[c])
@@ -313,7 +427,8 @@ def configs_leg(args, F, torch, line):
                           "momentum_drift": float(np.abs(i1["P"] - i0["P"]).max()),
                           "momentum_scale": pscale if c == 0 else None,
                           "angular_momentum_drift": float(np.abs(i1["L"] - i0["L"]).max()),
-                          "kinetic_energy": [i0["T"], i1["T"]]}
+                          "kinetic_energy": [i0["T"], i1["T"]],
+                          "rung_histogram": torch.bincount(h.rung.long()).cpu().numpy().tolist()}
             if c != 0:  # a cold start has no momentum scale of its own: use m |a| dt
                 row["hhs"]["momentum_scale"] = float(inv["Fabs"]) * h.t
             s.close()
@@ -410,11 +525,13 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=262144, help="particles in the CPU oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-hhs", action="store_true")
+    ap.add_argument("--no-chin", action="store_true",
+                    help="skip the fourth-order integrator against KDK at equal cost")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the high-accuracy reference solve (errors over all particles)")
     ap.add_argument("--no-named", action="store_true",
                     help="skip the run at the workload's own parameters (p 4, theta 0.5, leaf 16)")
-    ap.add_argument("--ensemble", type=int, default=64, metavar="K",
+    ap.add_argument("--ensemble", type=int, default=512, metavar="K",
                     help="requests in the serving ensemble (0: skip; the full stream is 512)")
     ap.add_argument("--ensemble-t-end", type=float, default=1.0)
     ap.add_argument("--ensemble-load", type=float, default=0.7,
@@ -691,6 +808,10 @@ def main():
                         "rung_histogram": torch.bincount(g.rung.long()).cpu().numpy().tolist(),
                         "momentum_change": dp(tpp, tv)}
         s.close()
+
+    if not args.no_chin:
+        progress("fourth-order integrator against KDK")
+        chin_leg(args, F, torch, line)
 
     if "mixed_named" in res:
         r = res["mixed_named"]

@@ -38,6 +38,9 @@
  */
 #include <math.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -91,6 +94,9 @@ typedef struct {
     int k[ORC_PMAX * ORC_PMAX * ORC_PMAX + 64][3];
     int idx[ORC_PMAX + 1][ORC_PMAX + 1][ORC_PMAX + 1];
     double fact[ORC_PMAX + 1];
+    /* index of the sum of multi-indices a and b, or -1 beyond degree p */
+    int sum[(ORC_PMAX + 1) * (ORC_PMAX + 2) * (ORC_PMAX + 3) / 6]
+           [(ORC_PMAX + 1) * (ORC_PMAX + 2) * (ORC_PMAX + 3) / 6];
 } orc_mi;
 
 static void mi_init(orc_mi *mi, int p)
@@ -112,6 +118,12 @@ static void mi_init(orc_mi *mi, int p)
             }
     mi->fact[0] = 1.0;
     for (int i = 1; i <= ORC_PMAX; ++i) mi->fact[i] = mi->fact[i - 1] * i;
+    for (int a = 0; a < mi->K; ++a)
+        for (int b = 0; b < mi->K; ++b) {
+            int x = mi->k[a][0] + mi->k[b][0], y = mi->k[a][1] + mi->k[b][1],
+                z = mi->k[a][2] + mi->k[b][2];
+            mi->sum[a][b] = x + y + z > p ? -1 : mi->idx[x][y][z];
+        }
 }
 
 static double ipow(double x, int e)
@@ -129,13 +141,7 @@ static double mono_over_fact(const orc_mi *mi, const double u[3], int t)
            (ipow(u[2], k[2]) / mi->fact[k[2]]);
 }
 
-static int mi_sum_idx(const orc_mi *mi, int a, int b)
-{
-    int x = mi->k[a][0] + mi->k[b][0], y = mi->k[a][1] + mi->k[b][1],
-        z = mi->k[a][2] + mi->k[b][2];
-    if (x + y + z > mi->p) return -1;
-    return mi->idx[x][y][z];
-}
+static int mi_sum_idx(const orc_mi *mi, int a, int b) { return mi->sum[a][b]; }
 
 static int mi_deg(const orc_mi *mi, int t) { return mi->k[t][0] + mi->k[t][1] + mi->k[t][2]; }
 
@@ -867,6 +873,279 @@ int orc_tree_eval(const orc_tree *t, const double *mass_total, int64_t n_total,
                   const int32_t *active, double *acc, double *pot)
 {
     return orc_tree_eval_ex(t, mass_total, n_total, active, acc, pot, NULL, NULL);
+}
+
+/* tree_eval's evaluation (point masses; acceleration and potential) spread
+ * over OpenMP threads for timing on many cores, with every sum formed in the
+ * order tree_eval forms it, so that the results equal tree_eval's bit for bit
+ * whatever the thread count.  P2M and L2P are independent per leaf, M2M per
+ * parent (levels deepest first) and L2L per child (levels root first).  The
+ * mutual M2L and P2P loops, which add each pair's terms to both of its cells
+ * in pair order, become gathers: every cell walks the pairs it belongs to in
+ * increasing pair index and forms its own side's terms exactly as the pair
+ * loop does (the derivative tensor and the pair kernel depend only on the
+ * pair), so it receives the same terms in the same order.  The derivative
+ * tensors are formed once per pair beforehand; the P2P pair kernel is
+ * evaluated once per side. */
+static int64_t *pair_members(const orc_pair *pr, int64_t np, int64_t nn, int64_t **start)
+{
+    int64_t *cnt = (int64_t *)calloc((size_t)(nn + 1), sizeof(int64_t));
+    if (!cnt) return NULL;
+    for (int64_t q = 0; q < np; ++q) {
+        cnt[pr[q].a + 1]++;
+        if (pr[q].b != pr[q].a) cnt[pr[q].b + 1]++;
+    }
+    for (int64_t c = 0; c < nn; ++c) cnt[c + 1] += cnt[c];
+    int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(cnt[nn] ? cnt[nn] : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nn ? nn : 1));
+    if (!list || !fill) {
+        free(cnt); free(list); free(fill);
+        return NULL;
+    }
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)nn);
+    for (int64_t q = 0; q < np; ++q) {  /* increasing q within every cell */
+        list[fill[pr[q].a]++] = q;
+        if (pr[q].b != pr[q].a) list[fill[pr[q].b]++] = q;
+    }
+    free(fill);
+    *start = cnt;
+    return list;
+}
+
+int orc_tree_eval_par(const orc_tree *t, const double *mass_total, int64_t n_total,
+                      const int32_t *active, double *acc, double *pot)
+{
+    const int64_t n = t->n;
+    if (n == 0) return ORC_OK;
+    (void)n_total;
+    const int p = t->prm.p;
+    orc_mi *mi = (orc_mi *)malloc(sizeof(orc_mi));
+    if (!mi) return ORC_ENOMEM;
+    mi_init(mi, p);
+    const int K = mi->K;
+    const int64_t NN = t->n_nodes;
+    double *M = (double *)calloc((size_t)(NN * K), sizeof(double));
+    double *Lc = (double *)calloc((size_t)(NN * K), sizeof(double));
+    double *m = (double *)malloc(sizeof(double) * n);
+    double *sx[3];
+    for (int d = 0; d < 3; ++d) sx[d] = (double *)malloc(sizeof(double) * n);
+    double *ax = (double *)calloc((size_t)n, sizeof(double));
+    double *ay = (double *)calloc((size_t)n, sizeof(double));
+    double *az = (double *)calloc((size_t)n, sizeof(double));
+    double *ph = (double *)calloc((size_t)n, sizeof(double));
+    int64_t *lvl_cnt = (int64_t *)calloc(ORC_MAXLEVEL + 2, sizeof(int64_t));
+    int64_t *by_lvl = (int64_t *)malloc(sizeof(int64_t) * (size_t)(NN ? NN : 1));
+    int64_t *m2l_start = NULL, *p2p_start = NULL;
+    int64_t *m2l_of = pair_members(t->m2l, t->n_m2l, NN, &m2l_start);
+    int64_t *p2p_of = pair_members(t->p2p, t->n_p2p, NN, &p2p_start);
+    double *Dall = NULL;
+    int rc = ORC_OK;
+    if (!M || !Lc || !m || !sx[0] || !sx[1] || !sx[2] || !ax || !ay || !az || !ph || !lvl_cnt ||
+        !by_lvl || !m2l_of || !p2p_of) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t slot = t->perm[i];
+        int64_t g = active ? active[slot] : slot;
+        m[i] = mass_total[g];
+        for (int d = 0; d < 3; ++d) sx[d][i] = t->x[d][slot];
+    }
+    /* cells grouped by level, pre-order inside a level */
+    for (int64_t c = 0; c < NN; ++c) lvl_cnt[t->nodes[c].level + 1]++;
+    for (int l = 0; l <= ORC_MAXLEVEL; ++l) lvl_cnt[l + 1] += lvl_cnt[l];
+    {
+        int64_t fill[ORC_MAXLEVEL + 1];
+        for (int l = 0; l <= ORC_MAXLEVEL; ++l) fill[l] = lvl_cnt[l];
+        for (int64_t c = 0; c < NN; ++c) by_lvl[fill[t->nodes[c].level]++] = c;
+    }
+    const double e2 = t->prm.kernel == ORC_PLUMMER ? t->prm.eps * t->prm.eps : 0.0;
+
+    /* P2M */
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t c = 0; c < NN; ++c) {
+        const orc_node *nd = &t->nodes[c];
+        if (nd->nchild) continue;
+        for (int64_t i = nd->begin; i < nd->end; ++i) {
+            double u[3] = {sx[0][i] - nd->z[0], sx[1][i] - nd->z[1], sx[2][i] - nd->z[2]};
+            for (int k = 0; k < K; ++k) M[c * K + k] += m[i] * mono_over_fact(mi, u, k);
+        }
+    }
+    /* M2M, deepest level first */
+    for (int l = ORC_MAXLEVEL; l >= 0; --l) {
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t r = lvl_cnt[l]; r < lvl_cnt[l + 1]; ++r) {
+            const int64_t c = by_lvl[r];
+            const orc_node *P = &t->nodes[c];
+            for (int q = 0; q < P->nchild; ++q) {
+                const orc_node *C = &t->nodes[P->child[q]];
+                double d[3] = {C->z[0] - P->z[0], C->z[1] - P->z[1], C->z[2] - P->z[2]};
+                for (int mm = 0; mm < K; ++mm) {
+                    const int *km = mi->k[mm];
+                    double acc_m = 0.0;
+                    for (int kk = 0; kk < K; ++kk) {
+                        const int *kk3 = mi->k[kk];
+                        if (kk3[0] > km[0] || kk3[1] > km[1] || kk3[2] > km[2]) continue;
+                        int diff = mi->idx[km[0] - kk3[0]][km[1] - kk3[1]][km[2] - kk3[2]];
+                        acc_m += M[P->child[q] * K + kk] * mono_over_fact(mi, d, diff);
+                    }
+                    M[c * K + mm] += acc_m;
+                }
+            }
+        }
+    }
+    /* M2L: the derivative tensor of every pair (as the pair loop forms it),
+     * then gathered per cell */
+    Dall = (double *)malloc(sizeof(double) * (size_t)(t->n_m2l * K + 1));
+    if (!Dall) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < t->n_m2l; ++q) {
+        const orc_node *A = &t->nodes[t->m2l[q].a], *B = &t->nodes[t->m2l[q].b];
+        double R[3] = {A->z[0] - B->z[0], A->z[1] - B->z[1], A->z[2] - B->z[2]};
+        orc_derivs(mi, R, e2, Dall + q * K);
+    }
+#pragma omp parallel
+    {
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t x = 0; x < NN; ++x) {
+            for (int64_t r = m2l_start[x]; r < m2l_start[x + 1]; ++r) {
+                const int64_t q = m2l_of[r];
+                int64_t ia = t->m2l[q].a, ib = t->m2l[q].b;
+                const double *D = Dall + q * K;
+                for (int nn = 0; nn < K; ++nn) {
+                    int dn = mi_deg(mi, nn);
+                    double la = 0.0, lb = 0.0;
+                    for (int mm = 0; mm < K; ++mm) {
+                        int s = mi_sum_idx(mi, nn, mm);
+                        if (s < 0) continue;
+                        double sgn_m = (mi_deg(mi, mm) & 1) ? -1.0 : 1.0;
+                        if (x == ia)
+                            la += sgn_m * M[ib * K + mm] * D[s];
+                        else
+                            lb += M[ia * K + mm] * D[s];
+                    }
+                    if (x == ia)
+                        Lc[ia * K + nn] += la;
+                    else
+                        Lc[ib * K + nn] += ((dn & 1) ? -1.0 : 1.0) * lb;
+                }
+            }
+        }
+    }
+    /* L2L, root level first */
+    for (int l = 1; l <= ORC_MAXLEVEL; ++l) {
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t r = lvl_cnt[l - 1]; r < lvl_cnt[l]; ++r) {
+            const int64_t c = by_lvl[r];
+            const orc_node *P = &t->nodes[c];
+            for (int q = 0; q < P->nchild; ++q) {
+                int64_t ic = P->child[q];
+                const orc_node *C = &t->nodes[ic];
+                double d[3] = {C->z[0] - P->z[0], C->z[1] - P->z[1], C->z[2] - P->z[2]};
+                for (int nn = 0; nn < K; ++nn) {
+                    const int *kn = mi->k[nn];
+                    double acc_n = 0.0;
+                    for (int kk = 0; kk < K; ++kk) {
+                        const int *k3 = mi->k[kk];
+                        if (k3[0] < kn[0] || k3[1] < kn[1] || k3[2] < kn[2]) continue;
+                        int diff = mi->idx[k3[0] - kn[0]][k3[1] - kn[1]][k3[2] - kn[2]];
+                        acc_n += Lc[c * K + kk] * mono_over_fact(mi, d, diff);
+                    }
+                    Lc[ic * K + nn] += acc_n;
+                }
+            }
+        }
+    }
+    /* L2P, then P2P gathered per leaf (pairs in increasing order; in a self
+     * pair a particle first takes the terms of the particles before it, as
+     * the second member of those pairs, then those of the particles after it) */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t x = 0; x < NN; ++x) {
+        const orc_node *X = &t->nodes[x];
+        if (X->nchild) continue;
+        for (int64_t i = X->begin; i < X->end; ++i) {
+            double u[3] = {sx[0][i] - X->z[0], sx[1][i] - X->z[1], sx[2][i] - X->z[2]};
+            double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < K; ++k) {
+                double mono = mono_over_fact(mi, u, k);
+                f += mono * Lc[x * K + k];
+                const int *kk = mi->k[k];
+                if (kk[0] + kk[1] + kk[2] < p) {
+                    g[0] += mono * Lc[x * K + mi->idx[kk[0] + 1][kk[1]][kk[2]]];
+                    g[1] += mono * Lc[x * K + mi->idx[kk[0]][kk[1] + 1][kk[2]]];
+                    g[2] += mono * Lc[x * K + mi->idx[kk[0]][kk[1]][kk[2] + 1]];
+                }
+            }
+            ph[i] += f;
+            ax[i] -= g[0];
+            ay[i] -= g[1];
+            az[i] -= g[2];
+        }
+        for (int64_t r = p2p_start[x]; r < p2p_start[x + 1]; ++r) {
+            const int64_t q = p2p_of[r];
+            const orc_node *A = &t->nodes[t->p2p[q].a], *B = &t->nodes[t->p2p[q].b];
+            const int self = t->p2p[q].a == t->p2p[q].b;
+            const int as_a = t->p2p[q].a == x;
+            for (int64_t k = X->begin; k < X->end; ++k) {
+                /* k as the second member: i over A (before k in a self pair) */
+                if (!as_a || self) {
+                    const int64_t iend = self ? k : A->end;
+                    for (int64_t i = A->begin; i < iend; ++i) {
+                        double dx = sx[0][k] - sx[0][i], dy = sx[1][k] - sx[1][i],
+                               dz = sx[2][k] - sx[2][i];
+                        double r2 = sqrt(dx * dx + dy * dy + dz * dz);
+                        double phi, gg;
+                        pair_kernel(t->prm.kernel, t->prm.eps, r2, &phi, &gg);
+                        ax[k] -= m[i] * gg * dx;
+                        ay[k] -= m[i] * gg * dy;
+                        az[k] -= m[i] * gg * dz;
+                        ph[k] += m[i] * phi;
+                    }
+                }
+                /* k as the first member: j over B (after k in a self pair) */
+                if (as_a) {
+                    for (int64_t j = self ? k + 1 : B->begin; j < B->end; ++j) {
+                        double dx = sx[0][j] - sx[0][k], dy = sx[1][j] - sx[1][k],
+                               dz = sx[2][j] - sx[2][k];
+                        double r2 = sqrt(dx * dx + dy * dy + dz * dz);
+                        double phi, gg;
+                        pair_kernel(t->prm.kernel, t->prm.eps, r2, &phi, &gg);
+                        ax[k] += m[j] * gg * dx;
+                        ay[k] += m[j] * gg * dy;
+                        az[k] += m[j] * gg * dz;
+                        ph[k] += m[j] * phi;
+                    }
+                }
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t slot = t->perm[i];
+        acc[slot] = ax[i];
+        acc[n + slot] = ay[i];
+        acc[2 * n + slot] = az[i];
+        pot[slot] = ph[i];
+    }
+done:
+    free(mi); free(M); free(Lc); free(m); free(sx[0]); free(sx[1]); free(sx[2]);
+    free(ax); free(ay); free(az); free(ph); free(lvl_cnt); free(by_lvl);
+    free(m2l_start); free(m2l_of); free(p2p_start); free(p2p_of); free(Dall);
+    return rc;
+}
+
+/* Threads used by orc_tree_eval_par (0: leave OpenMP's default). */
+int orc_threads(int set)
+{
+#ifdef _OPENMP
+    if (set > 0) omp_set_num_threads(set);
+    return omp_get_max_threads();
+#else
+    (void)set;
+    return 1;
+#endif
 }
 
 /* The FMM result for selected sinks only, computed one sink at a time: the

@@ -62,6 +62,9 @@ def lib():
         L.orc_tree_eval_grad.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp, dp]
         L.orc_tree_eval_dipole.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp,
                                            dp]
+        L.orc_tree_eval_par.argtypes = [ctypes.c_void_p, dp, i64, ctypes.c_void_p, dp, dp]
+        L.orc_threads.argtypes = [ctypes.c_int]
+        L.orc_threads.restype = ctypes.c_int
         L.orc_tree_eval_sinks.argtypes = [ctypes.c_void_p, dp, ctypes.c_void_p, ctypes.c_void_p,
                                           i64, dp, dp]
         L.orc_direct.argtypes = [dp, dp, i64, ctypes.c_void_p, i64, ctypes.c_int,
@@ -204,6 +207,17 @@ class Tree:
         return acc, pot
 
 
+    def evaluate_parallel(self, mass):
+        """evaluate() spread over OpenMP threads (orc_threads), each sum formed
+        in evaluate()'s order: the same (acc, pot) bit for bit."""
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        acc = np.zeros((3, self.n))
+        pot = np.zeros(self.n)
+        rc = lib().orc_tree_eval_par(self._h, _dp(mass), self.n_total, _vp(self.active),
+                                     _dp(acc), _dp(pot))
+        assert rc == 0
+        return acc, pot
+
     def evaluate_grad(self, mass):
         """acc (3,n), pot (n) and the force gradient d a_i / d x_i of every
         sink, SoA (6,n) in the order xx, yy, zz, xy, xz, yz (Sec. 4.1)."""
@@ -243,6 +257,12 @@ class Tree:
                                        len(sinks), _dp(acc), _dp(pot))
         assert rc == 0
         return acc, pot
+
+
+def threads(n=0):
+    """Threads of Tree.evaluate_parallel: sets them when n > 0; returns the
+    number in use."""
+    return int(lib().orc_threads(int(n)))
 
 
 def fmm(pos, mass, active=None, *, p, theta, eps, leaf_size, kernel):
