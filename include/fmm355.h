@@ -130,7 +130,9 @@ fmm_status fmm_forces(fmm_ctx *ctx, const double *pos, const double *mass, int64
  * -m_j (g I + (dg/dr)/r d d^T), in the context's precision (pair terms on
  * FP64 differences, summed into FP64 per source leaf).
  * grad: device, 6 x n_active doubles (SoA rows xx, yy, zz, xy, xz, yz), in
- * active order.  Errors as fmm_forces, and FMM_EINVAL for a NULL grad. */
+ * active order.  The first call allocates 6 x max_n doubles in the context
+ * (the near part, staged in Morton order).  Errors as fmm_forces, and
+ * FMM_EINVAL for a NULL grad, FMM_ENOMEM if that staging does not fit. */
 fmm_status fmm_forces_grad(fmm_ctx *ctx, const double *pos, const double *mass, int64_t n_total,
                            const int32_t *active, int64_t n_active, double eps, double theta,
                            int p, double *acc, double *pot, double *grad);

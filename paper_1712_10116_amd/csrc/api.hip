@@ -158,7 +158,7 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   bool ok = dalloc(c, &t.key, n) && dalloc(c, &t.key2, n) && dalloc(c, &t.slot, n) &&
             dalloc(c, &t.slot2, n) && dalloc(c, &t.sx, n) && dalloc(c, &t.sy, n) &&
             dalloc(c, &t.sz, n) && dalloc(c, &t.sm, n) && dalloc(c, &t.sm32, n) &&
-            dalloc(c, &t.leaf_of, n) && dalloc(c, &t.near, 4 * n) &&
+            dalloc(c, &t.leaf_of, n) && dalloc(c, &t.near, 4 * n) && dalloc(c, &t.pak, n) &&
             dalloc(c, &t.scan_part, FMM_SCAN_BLOCKS) && dalloc(c, &t.slot_req, n) &&
             dalloc(c, &t.sort_hist, 256 * ((n + SORT_TILE - 1) / SORT_TILE) + 256) &&
             dalloc(c, &t.sort_dtot, 256) && dalloc(c, &t.scan_blk, n / 1024 + 64) &&
@@ -627,10 +627,13 @@ extern "C" fmm_status fmm_forces_grad(fmm_ctx *c, const double *pos, const doubl
                                       double *grad) {
   if (!c) return FMM_EINVAL;
   if (n_active > 0 && !grad) return fail(c, FMM_EINVAL, "grad is NULL");
+  if (!c->gstage && !dalloc(c, &c->gstage, 6 * c->max_n))
+    return fail(c, FMM_ENOMEM, "force-gradient staging");
   fmm_status st = fmm_forces(c, pos, mass, n_total, active, n_active, eps, theta, p, acc, pot);
   if (st != FMM_OK || n_active == 0) return st;
   HIPCHK(c, launch_force_gradient(c->t, c->n_nodes, (int)n_active, p, c->prm.kernel,
-                                  c->prm.precision == FMM_PREC_MIXED, eps, grad, c->stream));
+                                  c->prm.precision == FMM_PREC_MIXED, eps, c->gstage, grad,
+                                  c->stream));
   return FMM_OK;
 }
 

@@ -90,6 +90,8 @@ struct DevTree {
   float *sm32;
   int32_t *leaf_of;
   double *near;  // [4][cap_n]: ax, ay, az, pot
+  double4 *pak;  // [cap_n] positions packed per active slot by the key pass, so
+                 // that the sorted gather reads one 32-byte record per particle
   // nodes
   int32_t *nbeg, *nend, *nlev, *nparent, *nchild0, *nnchild;
   double4 *ngeo;
@@ -280,7 +282,8 @@ bool eval_order_supported(int p);
 // grad.hip: force gradient of one system's n active particles (SoA 6 x n) on
 // the tree and local expansions of the evaluation just queued on stream s
 hipError_t launch_force_gradient(const DevTree &t, int n_nodes, int n, int p, int kernel,
-                                 bool mixed, double eps, double *grad, hipStream_t s);
+                                 bool mixed, double eps, double *stage, double *grad,
+                                 hipStream_t s);
 // vector-source pass (eval.hip): sources m_j v_j on the last build's tree (one
 // system), vec SoA 3 x e.n in active order, dv scratch 3 x cap_n doubles;
 // the request's acc receives +gradient of their potential, pot the potential

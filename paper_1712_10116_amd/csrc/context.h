@@ -54,6 +54,8 @@ struct fmm_ctx {
   double *inv_part;
   double *dvec;            // [3][max_n] sorted source vectors of the vector-source pass
                            // (allocated by its first call)
+  double *gstage;          // [6][max_n] near part of the force gradient in sorted order
+                           // (allocated by the first fmm_forces_grad)
   int64_t stat_calls, stat_parts, stat_builds;
   PhaseTimer timer;
   char err[512];

@@ -45,16 +45,17 @@ __device__ __forceinline__ void pair_gh(R r2, R eps, R ie, R &g, R &h) {
 // staged through LDS 64 particles at a time; pair terms in R (FP32 in the
 // mixed form, on FP64 differences), summed in R over one source leaf and then
 // into FP64
+// Written in sorted order to stage (6 rows of stride cap_n); k_l2p_grad adds
+// the far part and writes each particle's tensor once in active order.
 template <typename R, int KERNEL>
 __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, double eps,
-                                                        double *__restrict__ grad, int64_t nq,
-                                                        int32_t off) {
+                                                        double *__restrict__ stage) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   const R reps = (R)eps, ie = eps > 0 ? (R)(1.0 / eps) : R(0);
-  __shared__ double4 stage[FMM_BLOCK / 64][64];
-  double4 *st = stage[threadIdx.x >> 6];
+  __shared__ double4 src_lds[FMM_BLOCK / 64][64];
+  double4 *st = src_lds[threadIdx.x >> 6];
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (t.nnchild[A] != 0) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
@@ -102,18 +103,21 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, 
 #pragma unroll
         for (int c = 0; c < 6; ++c) G[c] += __shfl_xor(G[c], o, 64);
       if (valid && ph == 0) {
-        const int64_t k = t.slot[i] - off;
+        const int64_t cap = t.cap_n;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) grad[c * nq + k] = G[c];
+        for (int c = 0; c < 6; ++c) stage[c * cap + i] = G[c];
       }
     }
   }
 }
 
-// adds minus the Hessian of the leaf's local expansion (coefficients scaled
-// by h^|n|, so the second derivatives carry 1/h^2)
+// minus the Hessian of the leaf's local expansion (coefficients scaled by
+// h^|n|, so the second derivatives carry 1/h^2) added to the near part staged
+// in sorted order, written to grad in active order (zero for p = 1: the
+// Hessian of a degree-1 expansion vanishes)
 template <typename T, int P>
 __global__ __launch_bounds__(FMM_BLOCK) void k_l2p_grad(DevTree t, int n,
+                                                        const double *__restrict__ stage,
                                                         double *__restrict__ grad, int64_t nq,
                                                         int32_t off) {
   constexpr MI<P> mi{};
@@ -141,25 +145,30 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_l2p_grad(DevTree t, int n,
       H[c] = fma(Lt[mi.at(a, b, e)], mono[k], H[c]);
     }
   }
-  const int64_t k = t.slot[j] - off;
+  const int64_t k = t.slot[j] - off, cap = t.cap_n;
   const double s2 = ih * ih;
 #pragma unroll
-  for (int c = 0; c < 6; ++c) grad[c * nq + k] -= (double)H[c] * s2;
+  for (int c = 0; c < 6; ++c) grad[c * nq + k] = stage[c * cap + j] - (double)H[c] * s2;
+}
+
+template <typename T, int P>
+void launch_l2p_grad(const DevTree &t, int n, const double *stage, double *grad, hipStream_t s) {
+  hipLaunchKernelGGL((k_l2p_grad<T, P>), dim3((n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK),
+                     0, s, t, n, stage, grad, (int64_t)n, 0);
 }
 
 template <typename T, int KERNEL>
-bool dispatch_grad(const DevTree &t, int n_nodes, int n, int p, double eps, double *grad,
-                   hipStream_t s) {
-  const int nb = (n + FMM_BLOCK - 1) / FMM_BLOCK;
+bool dispatch_grad(const DevTree &t, int n_nodes, int n, int p, double eps, double *stage,
+                   double *grad, hipStream_t s) {
   hipLaunchKernelGGL((k_p2p_grad<T, KERNEL>), dim3((n_nodes + 3) / 4), dim3(FMM_BLOCK), 0, s, t,
-                     n_nodes, eps, grad, (int64_t)n, 0);
+                     n_nodes, eps, stage);
   switch (p) {
-    case 1: return true;  // the Hessian of a degree-1 local expansion is zero
-    case 2: hipLaunchKernelGGL((k_l2p_grad<T, 2>), dim3(nb), dim3(FMM_BLOCK), 0, s, t, n, grad, (int64_t)n, 0); return true;
-    case 3: hipLaunchKernelGGL((k_l2p_grad<T, 3>), dim3(nb), dim3(FMM_BLOCK), 0, s, t, n, grad, (int64_t)n, 0); return true;
-    case 4: hipLaunchKernelGGL((k_l2p_grad<T, 4>), dim3(nb), dim3(FMM_BLOCK), 0, s, t, n, grad, (int64_t)n, 0); return true;
-    case 5: hipLaunchKernelGGL((k_l2p_grad<T, 5>), dim3(nb), dim3(FMM_BLOCK), 0, s, t, n, grad, (int64_t)n, 0); return true;
-    case 6: hipLaunchKernelGGL((k_l2p_grad<T, 6>), dim3(nb), dim3(FMM_BLOCK), 0, s, t, n, grad, (int64_t)n, 0); return true;
+    case 1: launch_l2p_grad<T, 1>(t, n, stage, grad, s); return true;
+    case 2: launch_l2p_grad<T, 2>(t, n, stage, grad, s); return true;
+    case 3: launch_l2p_grad<T, 3>(t, n, stage, grad, s); return true;
+    case 4: launch_l2p_grad<T, 4>(t, n, stage, grad, s); return true;
+    case 5: launch_l2p_grad<T, 5>(t, n, stage, grad, s); return true;
+    case 6: launch_l2p_grad<T, 6>(t, n, stage, grad, s); return true;
     default: return false;
   }
 }
@@ -263,15 +272,16 @@ hipError_t launch_p2p_dipole(const DevTree &t, int n_nodes, int kernel, bool mix
 
 // One system's tree (request 0 at slot offset 0), n active particles.
 hipError_t launch_force_gradient(const DevTree &t, int n_nodes, int n, int p, int kernel,
-                                 bool mixed, double eps, double *grad, hipStream_t s) {
+                                 bool mixed, double eps, double *stage, double *grad,
+                                 hipStream_t s) {
   if (n <= 0) return hipSuccess;
   bool ok;
   if (mixed)
-    ok = kernel == 1 ? dispatch_grad<float, 1>(t, n_nodes, n, p, eps, grad, s)
-                     : dispatch_grad<float, 0>(t, n_nodes, n, p, eps, grad, s);
+    ok = kernel == 1 ? dispatch_grad<float, 1>(t, n_nodes, n, p, eps, stage, grad, s)
+                     : dispatch_grad<float, 0>(t, n_nodes, n, p, eps, stage, grad, s);
   else
-    ok = kernel == 1 ? dispatch_grad<double, 1>(t, n_nodes, n, p, eps, grad, s)
-                     : dispatch_grad<double, 0>(t, n_nodes, n, p, eps, grad, s);
+    ok = kernel == 1 ? dispatch_grad<double, 1>(t, n_nodes, n, p, eps, stage, grad, s)
+                     : dispatch_grad<double, 0>(t, n_nodes, n, p, eps, stage, grad, s);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -161,11 +161,13 @@ __device__ __forceinline__ void make_key(const DevTree &t, int s) {
   const int i = s - q.off;
   int64_t g = q.active ? q.active[i] : i;
   const Box &bx = t.box[r];
-  uint64_t qx = quantise(q.pos[g], bx.o[0], bx.s);
-  uint64_t qy = quantise(q.pos[q.n_total + g], bx.o[1], bx.s);
-  uint64_t qz = quantise(q.pos[2 * q.n_total + g], bx.o[2], bx.s);
+  const double x = q.pos[g], y = q.pos[q.n_total + g], z = q.pos[2 * q.n_total + g];
+  uint64_t qx = quantise(x, bx.o[0], bx.s);
+  uint64_t qy = quantise(y, bx.o[1], bx.s);
+  uint64_t qz = quantise(z, bx.o[2], bx.s);
   t.key[s] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
   t.slot[s] = s;
+  t.pak[s] = make_double4(x, y, z, 0.0);
 }
 
 __global__ __launch_bounds__(FMM_BLOCK) void k_keys(DevTree t, int n) {
@@ -455,17 +457,14 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_split_depth(DevTree t, int n, int
 // ---------------------------------------------------------------------------
 // sorted particle data
 // ---------------------------------------------------------------------------
-// Sorted position j of request r lies in [req_off[r], req_off[r + 1]) as
-// its active slot did (the sort orders by request first), so the request
-// comes from the offsets rather than a random read of slot_req.
+// The key pass left each active slot's position in one 32-byte record, so
+// the random read of the gather touches one memory sector per particle
+// instead of one in each of the three coordinate arrays.
 __device__ __forceinline__ void gather_at(const DevTree &t, int j) {
-  const int s = t.slot[j];
-  const DevReq q = t.reqs[upper_index(t.req_off, t.n_req, j)];
-  const int i = s - q.off;
-  int64_t g = q.active ? q.active[i] : i;
-  t.sx[j] = q.pos[g];
-  t.sy[j] = q.pos[q.n_total + g];
-  t.sz[j] = q.pos[2 * q.n_total + g];
+  const double4 r = t.pak[t.slot[j]];
+  t.sx[j] = r.x;
+  t.sy[j] = r.y;
+  t.sz[j] = r.z;
 }
 
 __global__ __launch_bounds__(FMM_BLOCK) void k_gather_sorted(DevTree t, int n) {
