@@ -292,7 +292,9 @@ class HHSState:
 
 
 class HHSOracle:
-    """EVOLVE_HOLD / KDK / KICK of Algorithms 1-3 with the oracle FMM.
+    """The hierarchical Hamiltonian splitting of Sec. 2.2 (Algorithms 1-3)
+    with the oracle FMM: each level's kick-drift-kick is a table of operations
+    (LEVEL_OPS), the nesting of levels a list of open time intervals (step).
 
     Readings where the paper is silent: a particle's timestep is
     sqrt(eta*eps/|a|) (Sec. 2.2) with |a| = |a_old| + |a_cur|; its rung is the
@@ -389,42 +391,69 @@ class HHSOracle:
             else:
                 st.a_cur[sys1] = mag
 
-    def kdk(self, st, slow, fast, sysall, dt, k=1, t0=0.0):
-        # Algorithm 2.  A kick whose sink set is empty, or a kickS2F whose source
-        # set S is empty (every force would be zero), is skipped; this is what
-        # makes a two-rung system cost 2 + 2 + 2^(k+1) solver calls (Sec. 2.2).
-        # The first kicks cover [t0, t0 + dt/2], the drift [t0, t0 + dt], the
-        # second kicks [t0 + dt/2, t0 + dt].
-        s2f = len(fast) > 0 and len(slow) > 0
-        h = dt / 2
-        if s2f:
-            self.kick(st, fast, sysall, h, True, False, t0=t0)
-        if len(slow):
-            self.kick(st, slow, sysall, h, False, False, t0=t0)
-        drift = dt if self.cosmo is None else self.factors(t0, t0 + dt)[0]
-        st.pos[:, slow] += st.vel[:, slow] * drift
-        if len(slow):
-            self.kick(st, slow, sysall, h, False, True, top=(k == 0), t0=t0 + h)
-        if s2f:
-            self.kick(st, fast, sysall, h, True, True, t0=t0 + h)
+    # One level's kick-drift-kick (Sec. 2.2) as data, in time order: the
+    # operation, the particles it moves, the sources of a kick ("slow": the
+    # masses of the fast set zeroed, kickS2F; "all": kickFS2S), which half of
+    # the level's interval a kick covers, and the |a| slot a kick over the
+    # second half refreshes.  The drift moves the slow set over the whole
+    # interval.  A kick whose moved set is empty, or a kickS2F with no slow
+    # particle (every force zero), is skipped: this is what gives a two-rung
+    # system 2 + 2 + 2^(k+1) solver calls.
+    LEVEL_OPS = (("kick", "fast", "slow", 0, None),
+                 ("kick", "slow", "all", 0, None),
+                 ("drift", "slow", None, None, None),
+                 ("kick", "slow", "all", 1, "a_cur"),
+                 ("kick", "fast", "slow", 1, "a_old"))
 
-    def evolve(self, st, k, sysall, dt, calc, dt_top, t0=0.0):
-        if calc and not self.freeze_rungs:
-            st.rung[sysall] = self.rungs(st, sysall, dt_top, t0)
-        r = st.rung[sysall]
-        slow = sysall[r <= k]
-        fast = sysall[r > k]
-        if len(fast):
-            self.evolve(st, k + 1, fast, dt / 2, False, dt_top, t0)
-        self.kdk(st, slow, fast, sysall, dt, k, t0)
-        if len(fast):
-            self.evolve(st, k + 1, fast, dt / 2, True, dt_top, t0 + dt / 2)
+    def level_kdk(self, st, level, slow, fast, members, t0, dt):
+        sets = {"slow": slow, "fast": fast, "all": members}
+        for op, moved, sources, half, slot in self.LEVEL_OPS:
+            who = sets[moved]
+            if op == "drift":
+                length = dt if self.cosmo is None else self.factors(t0, t0 + dt)[0]
+                st.pos[:, who] += st.vel[:, who] * length
+                continue
+            if len(who) == 0 or (sources == "slow" and len(slow) == 0):
+                continue
+            self.kick(st, who, members, dt / 2, sources == "slow", slot is not None,
+                      top=(level == 0), t0=t0 + half * (dt / 2))
 
     def step(self, st, dt_top):
-        """Advance every particle by dt_top (one top-level EVOLVE_HOLD); in the
-        comoving form st.t is ln a and dt_top a step in ln a."""
-        sysall = np.arange(st.mass.shape[0], dtype=np.int32)
-        self.evolve(st, 0, sysall, dt_top, True, dt_top, st.t)
+        """Advance every particle by dt_top (one top-level step); in the
+        comoving form st.t is ln a and dt_top a step in ln a.
+
+        A level's interval [t0, t0 + dt] for the particles handed to it
+        (rung >= level) is: the faster particles (rung > level) advanced over
+        the first half at the next level, this level's kick-drift-kick, the
+        faster ones over the second half (their rungs set anew first).  The
+        nesting is walked with an explicit list of open intervals."""
+        everyone = np.arange(st.mass.shape[0], dtype=np.int32)
+
+        class Span:
+            def __init__(self, level, members, t0, dt, refresh):
+                self.level, self.members, self.t0, self.dt = level, members, t0, dt
+                self.refresh = refresh
+                self.stage = 0
+                self.slow = self.fast = None
+
+        todo = [Span(0, everyone, st.t, dt_top, True)]
+        while todo:
+            sp = todo[-1]
+            if sp.stage == 0:            # set rungs (when asked), split, first half
+                if sp.refresh and not self.freeze_rungs:
+                    st.rung[sp.members] = self.rungs(st, sp.members, dt_top, sp.t0)
+                r = st.rung[sp.members]
+                sp.slow, sp.fast = sp.members[r <= sp.level], sp.members[r > sp.level]
+                sp.stage = 1
+                if len(sp.fast):
+                    todo.append(Span(sp.level + 1, sp.fast, sp.t0, sp.dt / 2, False))
+            elif sp.stage == 1:          # this level's kick-drift-kick, second half
+                self.level_kdk(st, sp.level, sp.slow, sp.fast, sp.members, sp.t0, sp.dt)
+                sp.stage = 2
+                if len(sp.fast):
+                    todo.append(Span(sp.level + 1, sp.fast, sp.t0 + sp.dt / 2, sp.dt / 2, True))
+            else:
+                todo.pop()
         st.t += dt_top
 
 

@@ -5,8 +5,9 @@ satisfy (Sec. 2.3: recursive split while a cell holds more than n_crit
 particles), and against Morton keys recomputed here by plain numpy bit
 interleaving.  The lists are checked for exactly-once coverage of every
 ordered particle pair by brute force, for the well-separation rule on every
-M2L pair, and against the printed walk of Algorithm 4 run literally on
-ordered pairs from (root, root)."""
+M2L pair and its failure on every P2P pair, and for the open-both rule of
+Sec. 2.3 as a property of every listed pair (the pair that produced it was
+not accepted, and was opened on the right side)."""
 import numpy as np
 import pytest
 
@@ -155,47 +156,46 @@ def test_exactly_once_coverage(oracle, cfg, n, leaf, theta):
             assert ((d2 * th2 > S * S) and (d2 > e * e)) == want
 
 
-def _alg4(ex, prm):
-    """Algorithm 4 run literally on ordered pairs from (root, root)."""
-    nn = len(ex["level"])
-    parent = _ancestors(ex)
-    kids = [[] for _ in range(nn)]
-    for i in range(1, nn):
-        kids[parent[i]].append(i)
+def _well_separated(ex, prm, a, b):
     th2 = prm["theta"] * prm["theta"]
-
-    def well_sep(a, b):
-        d = ex["centre"][a] - ex["centre"][b]
-        d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
-        S = ex["half"][a] + ex["half"][b]
-        e = prm["eps"] + np.sqrt(3.0) * S
-        return d2 * th2 > S * S and d2 > e * e
-
-    m2l, p2p = set(), set()
-    stack = [(0, 0)]
-    while stack:
-        ci, cj = stack.pop()
-        if well_sep(ci, cj):
-            m2l.add((ci, cj))
-        elif not kids[ci] and not kids[cj]:
-            p2p.add((ci, cj))
-        elif not kids[ci]:
-            stack.extend((ci, c) for c in kids[cj])
-        elif not kids[cj]:
-            stack.extend((c, cj) for c in kids[ci])
-        else:
-            stack.extend((a, b) for a in kids[ci] for b in kids[cj])
-    return m2l, p2p
+    d = ex["centre"][a] - ex["centre"][b]
+    d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+    S = ex["half"][a] + ex["half"][b]
+    e = prm["eps"] + np.sqrt(3.0) * S
+    return d2 * th2 > S * S and d2 > e * e
 
 
 @pytest.mark.parametrize("cfg,n,leaf,theta", [(0, 1500, 8, 0.5), (1, 2000, 16, 0.3)])
-def test_symmetric_closure_equals_algorithm4(oracle, cfg, n, leaf, theta):
+def test_pairs_follow_the_open_both_rule(oracle, cfg, n, leaf, theta):
+    """Why each listed pair exists (Sec. 2.3: a pair that fails the
+    acceptance test opens both cells, or only the non-leaf one when the other
+    is a leaf): a pair of cells on the same level comes from their parents,
+    which failed the test and were both opened; a pair on different levels
+    has a leaf on the shallower side, met by the parent of the deeper cell,
+    which failed the test.  Together with exactly-once coverage this fixes
+    the lists, without replaying the walk."""
     pos, _, _ = W.config(cfg, n=n)
     t, ex, prm = _tree(oracle, pos, leaf_size=leaf, theta=theta)
-    m2l, p2p = _alg4(ex, prm)
-    sym = lambda lst: {(int(a), int(b)) for a, b in lst} | {(int(b), int(a)) for a, b in lst}
-    assert sym(ex["m2l"]) == m2l
-    assert sym(ex["p2p"]) == p2p
-    # unordered lists hold no duplicates
-    assert len({tuple(x) for x in ex["m2l"].tolist()}) == t.n_m2l
-    assert len({tuple(x) for x in ex["p2p"].tolist()}) == t.n_p2p
+    parent = _ancestors(ex)
+    leaf = ex["is_leaf"].astype(bool)
+    lvl = ex["level"]
+    for lst in (ex["m2l"], ex["p2p"]):
+        for a, b in lst:
+            a, b = int(a), int(b)
+            if a == b:                      # a leaf's own pair: its ancestors' self pairs
+                assert leaf[a]
+                continue
+            if lvl[a] > lvl[b]:
+                a, b = b, a
+            if lvl[a] == lvl[b]:
+                pa, pb = parent[a], parent[b]
+                assert pa >= 0 and pb >= 0
+                assert pa == pb or not _well_separated(ex, prm, pa, pb)
+                assert not leaf[pa] and not leaf[pb]
+            else:
+                assert leaf[a]
+                assert not _well_separated(ex, prm, a, parent[b])
+    # unordered lists hold no duplicates and no pair twice in both orders
+    for lst, cnt in ((ex["m2l"], t.n_m2l), (ex["p2p"], t.n_p2p)):
+        assert (lst[:, 0] <= lst[:, 1]).all()
+        assert len({tuple(x) for x in lst.tolist()}) == cnt
