@@ -438,6 +438,63 @@ def configs_leg(args, F, torch, line):
     line["configs"] = out
 
 
+def graph_ab_leg(args):
+    """A/B of HIP-graph replay against direct launches for one evaluation on a
+    fixed tree (the pattern of the two kicks of a KDK half, which share a
+    tree): seconds per evaluation each way and the capture + instantiation
+    cost, for a few system sizes (mixed, Wendland, p 4, leaf 16).  Every
+    replay's result is compared with the direct one.  Prints one JSON line."""
+    import torch
+    import paper_1712_10116_amd.fmm as F
+    from paper_1712_10116_amd import workloads as W
+    dev = torch.device("cuda:0")
+    out = {}
+    for n in (2048, 12526, 65536):
+        pos, _, m = W.plummer(n, seed=7)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            s = F.Solver(n, p_max=4, leaf_size=16, kernel=F.WENDLAND, precision=F.MIXED,
+                         stream=stream)
+            tp, tm = torch.from_numpy(pos).to(dev), torch.from_numpy(m).to(dev)
+            acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+            pot = torch.empty(n, dtype=torch.float64, device=dev)
+            s.build(tp, eps=0.01, theta=0.5)
+            s.evaluate(tp, tm, p=4, acc=acc, pot=pot)
+            torch.cuda.synchronize()
+            ref = acc.clone()
+            reps = args.graph_ab
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                s.evaluate(tp, tm, p=4, acc=acc, pot=pot)
+            torch.cuda.synchronize()
+            direct = (time.perf_counter() - t0) / reps
+            g = torch.cuda.CUDAGraph()
+            t0 = time.perf_counter()
+            with torch.cuda.graph(g, stream=stream):
+                s.evaluate(tp, tm, p=4, acc=acc, pot=pot)
+            torch.cuda.synchronize()
+            cap = time.perf_counter() - t0
+            same = True
+            for _ in range(3):   # replays between eager work, each checked
+                acc.zero_()
+                g.replay()
+                torch.cuda.synchronize()
+                same = same and bool(torch.equal(acc, ref))
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                g.replay()
+            torch.cuda.synchronize()
+            rep = (time.perf_counter() - t0) / reps
+            same = same and bool(torch.equal(acc, ref))
+            info = s.tree_info()
+            out[str(n)] = {"direct_us": round(direct * 1e6, 1), "replay_us": round(rep * 1e6, 1),
+                           "capture_instantiate_us": round(cap * 1e6, 1), "replays_equal": same,
+                           "nodes": info["nodes"], "depth": info["depth"]}
+            del g
+            s.close()
+    print(json.dumps({"graph_ab": out}))
+
+
 def collapse_run_leg(args):
     """The cold collapse (uniform sphere at rest, Wendland eps = 0.005, p 4,
     theta 0.5, HHS with 10 rungs) integrated to t = collapse_t_end with N =
@@ -487,10 +544,14 @@ def hhs_request_leg(args):
     import torch
     import paper_1712_10116_amd.fmm as F
     from paper_1712_10116_amd import workloads as W
-    prm = W.PARAMS[4]
+    prm = dict(W.PARAMS[4])
+    if args.hhs_leaf:
+        prm["leaf_size"] = args.hhs_leaf
     pos, vel, m = W.ensemble_request(args.hhs_request)
     s = F.Solver(m.size, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
                  precision=F.MIXED)
+    s.set_small_path(args.hhs_small_path)
+    s.set_level_prediction(args.hhs_predict)
     h = F.HHS(s, torch.from_numpy(pos).cuda(), torch.from_numpy(vel).cuda(),
               torch.from_numpy(m).cuda(), eps=prm["eps"], theta=prm["theta"], p=prm["p"],
               eta=prm["eta"], max_levels=prm["max_levels"])
@@ -505,6 +566,7 @@ def hhs_request_leg(args):
         steps.append(dict(ms=round((time.perf_counter() - t0) * 1e3, 3), **st))
     rungs = torch.bincount(h.rung.long()).cpu().numpy().tolist()
     print(json.dumps({"request": args.hhs_request, "n": int(m.size), "leaf_size": prm["leaf_size"],
+                      "small_path": args.hhs_small_path, "level_prediction": args.hhs_predict,
                       "rung_histogram": rungs, "steps": steps}))
     s.close()
 
@@ -551,6 +613,14 @@ def main():
                     help="only time top-level HHS steps of ensemble request I (mixed, the "
                          "ensemble parameters) and exit; used for kernel traces of small systems")
     ap.add_argument("--hhs-steps", type=int, default=2)
+    ap.add_argument("--hhs-leaf", type=int, default=0, help="leaf size of --hhs-request")
+    ap.add_argument("--hhs-small-path", type=int, default=1, choices=(0, 1, 2),
+                    help="single-workgroup builds in --hhs-request (fmm_set_small_path)")
+    ap.add_argument("--hhs-predict", type=int, default=0, choices=(0, 1),
+                    help="level prediction in --hhs-request (fmm_set_level_prediction)")
+    ap.add_argument("--graph-ab", type=int, default=0, metavar="REPS",
+                    help="only run the HIP-graph replay A/B of one evaluation (REPS repeats "
+                         "each way) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit; used to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -564,6 +634,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}))
+        return
+    if args.graph_ab:
+        graph_ab_leg(args)
         return
     if args.hhs_request >= 0:
         hhs_request_leg(args)
