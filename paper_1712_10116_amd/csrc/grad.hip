@@ -51,7 +51,8 @@ template <typename R, int KERNEL>
 __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, double eps,
                                                         double *__restrict__ stage) {
   const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // neighbouring leaves, which share most of their sources, on one XCD
+  const int wave = (xcd_block<32>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   const R reps = (R)eps, ie = eps > 0 ? (R)(1.0 / eps) : R(0);
   __shared__ double4 src_lds[FMM_BLOCK / 64][64];
@@ -186,7 +187,8 @@ template <typename R, int KERNEL>
 __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_dip(DevTree t, int n_nodes, double eps,
                                                        const double *__restrict__ dv) {
   const int lane = threadIdx.x & 63;
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  // neighbouring leaves, which share most of their sources, on one XCD
+  const int wave = (xcd_block<32>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   const R reps = (R)eps, ie = eps > 0 ? (R)(1.0 / eps) : R(0);
   const int64_t cap = t.cap_n;
