@@ -511,9 +511,9 @@ struct PairKernel {
 // One wavefront per target leaf A.  The particles of every leaf in A's P2P
 // list (A itself included) form one stream, staged into LDS in windows of up
 // to SRC particles -- FP32 offsets from A's centre in the mixed form, absolute
-// FP64 positions in the FP64 form.  Staging is cooperative: the lane holding a
-// source leaf writes the particle index of each of its slots into an LDS table,
-// then consecutive lanes load consecutive slots.
+// FP64 positions in the FP64 form.  Consecutive lanes load consecutive slots,
+// each finding its particle from the list entry that holds the slot (a binary
+// search over the chunk's stream positions, kept in LDS).
 //
 // Lanes = (sink, phase), lane = ti * nph + ph: LP = 64 / nph sinks at a time,
 // phase ph taking window slots ph, ph + nph, ...  The sinks of A are taken 64
@@ -722,13 +722,11 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
   constexpr int SRC = P2PTypes<MIXED>::SRC;
   static_assert(SRC % (P2P_UNROLL * P2P_MAXPH) == 0, "window must hold its padding");
   __shared__ R4 src_all[P2P_WAVES][SRC];
-  __shared__ int idx_all[P2P_WAVES][SRC];
   __shared__ int3 leaf_all[P2P_WAVES][64];  // per list entry of a chunk: stream position, size, first particle
   __shared__ R sink_all[P2P_WAVES][3][64];  // home sink position of each lane
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   R4 *src = src_all[w];
-  int *idx = idx_all[w];
   int3 *lf = leaf_all[w];
   R(*sk)[64] = sink_all[w];
   // the target leaf and all that is read from it are the same in every lane:
@@ -788,32 +786,42 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
         for (int w0 = 0; w0 < total; w0 += SRC) {
           const int W = min(SRC, total - w0);
           const int Wr = (W + blk - 1) / blk * blk;
-          // particle index of every slot of the window, written by the lane
-          // that holds its source leaf
-          {
-            const int3 e = lf[lane];
-            const int a0 = max(e.x, w0), a1 = min(e.x + e.y, w0 + W);
-            for (int s = a0; s < a1; ++s) idx[s - w0] = e.z + (s - e.x);
-          }
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          for (int j = lane; j < Wr; j += 64) {
-            R4 v = P2PTypes<MIXED>::far();
-            if (j < W) {
-              const int k = idx[j];
-              if (MIXED) {
-                v.x = (R)(t.sx[k] - gA.x);
-                v.y = (R)(t.sy[k] - gA.y);
-                v.z = (R)(t.sz[k] - gA.z);
-                v.w = t.sm32[k];
-              } else {
-                v.x = t.sx[k];
-                v.y = t.sy[k];
-                v.z = t.sz[k];
-                v.w = t.sm[k];
+          // consecutive lanes stage consecutive slots, two per lane at a
+          // time; a slot's particle comes from the list entry holding its
+          // stream position, the last entry whose position is not beyond it
+          // (binary search over the chunk's entries)
+          for (int j0 = 0; j0 < Wr; j0 += 128) {
+            const int ja = j0 + lane, jb = ja + 64;
+            const int sa = w0 + ja, sb = w0 + jb;
+            int ea = 0, eb = 0;
+#pragma unroll
+            for (int st = 32; st > 0; st >>= 1) {
+              if (lf[ea + st].x <= sa) ea += st;
+              if (lf[eb + st].x <= sb) eb += st;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int j = h ? jb : ja;
+              if (j < Wr) {
+                R4 v = P2PTypes<MIXED>::far();
+                if (j < W) {
+                  const int3 en = lf[h ? eb : ea];
+                  const int k = en.z + (w0 + j - en.x);
+                  if (MIXED) {
+                    v.x = (R)(t.sx[k] - gA.x);
+                    v.y = (R)(t.sy[k] - gA.y);
+                    v.z = (R)(t.sz[k] - gA.z);
+                    v.w = t.sm32[k];
+                  } else {
+                    v.x = t.sx[k];
+                    v.y = t.sy[k];
+                    v.z = t.sz[k];
+                    v.w = t.sm[k];
+                  }
+                }
+                src[j] = v;
               }
             }
-            src[j] = v;
           }
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
