@@ -281,15 +281,30 @@ __device__ void walk_parent(const DevTree &t, int l, int P, double th2, double e
     if (lane == tg)
 #pragma unroll
       for (int k = 0; k < 3; ++k) mine[k] = S.cnt[tg][k];
+  // one allocation per wavefront and list (the targets' lists laid out in
+  // target order inside it): all wavefronts of a level allocate at about the
+  // same time, and device-scope atomics on one address serialise
   int o[3] = {0, 0, 0};
   int bits = 0;
-  if (lane < S.n) {
-    o[0] = (int)atomicAdd(&h->m2l_cursor, (unsigned)mine[0]);
-    o[1] = (int)atomicAdd(&h->p2p_cursor, (unsigned)mine[1]);
-    o[2] = (int)atomicAdd(&h->open_cursor[l], (unsigned)mine[2]);
-    if ((int64_t)o[0] + mine[0] > t.cap_m2l) bits |= OVF_M2L;
-    if ((int64_t)o[1] + mine[1] > t.cap_p2p) bits |= OVF_P2P;
-    if ((int64_t)o[2] + mine[2] > t.cap_open) bits |= OVF_OPEN;
+  {
+    unsigned *const cur[3] = {&h->m2l_cursor, &h->p2p_cursor, &h->open_cursor[l]};
+    const int64_t cap[3] = {t.cap_m2l, t.cap_p2p, t.cap_open};
+    const int ovf_bit[3] = {OVF_M2L, OVF_P2P, OVF_OPEN};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int incl = mine[k];  // inclusive prefix over the target lanes 0..7
+#pragma unroll
+      for (int d = 1; d < 8; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+      }
+      const int tot = __shfl(incl, 7, 64);
+      int base = 0;
+      if (lane == 0 && tot > 0) base = (int)atomicAdd(cur[k], (unsigned)tot);
+      base = __shfl(base, 0, 64);
+      o[k] = base + incl - mine[k];
+      if (lane < S.n && (int64_t)base + tot > cap[k]) bits |= ovf_bit[k];
+    }
   }
   // if any target's lists do not fit, the wavefront writes none of them and
   // every one of its targets gets empty lists: no count ever covers entries
