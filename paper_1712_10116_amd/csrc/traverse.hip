@@ -26,7 +26,7 @@
 
 #include "common.h"
 
-#define TRAV_WAVES 4
+#define TRAV_WAVES 2
 #define TRAV_CAND 512   // expanded candidates of one block of 64 open-list entries
 #define TRAV_STACK 2048 // descent items (target tag in the top 3 bits)
 // Room kept free for single-item (depth-first) pops: each pops one item and
@@ -70,6 +70,8 @@ struct Sibs {
 
 struct WaveLds {
   int cand[TRAV_CAND];   // candidates expanded from a block of open-list entries
+  int ccat[TRAV_CAND];   // their categories against the 8 targets (3 bits each), kept
+                         // from the counting pass for the writing pass
   int dcand[TRAV_CAND];  // children of popped descent items
   int stack[TRAV_STACK]; // descent items: (target tag << TRAV_TAG) | cell
   double4 geo[8];
@@ -86,12 +88,11 @@ __device__ __forceinline__ void emit(const DevTree &t, Sibs &S, int tg, int cat,
   const unsigned long long bo = __ballot(mine && cat == CAT_OPEN);
   if (WRITE) {
     if (mine && cat == CAT_M2L) t.m2l_src[S.off[tg][0] + S.cnt[tg][0] + __popcll(bm & below)] = C;
-    if (mine && cat == CAT_P2P) {
-      t.p2p_src[S.off[tg][1] + S.cnt[tg][1] + __popcll(bp & below)] = C;
-      pairs += (unsigned long long)S.np[tg] * (unsigned long long)npC -
-               (C == S.id[tg] ? (unsigned long long)S.np[tg] : 0ull);
-    }
+    if (mine && cat == CAT_P2P) t.p2p_src[S.off[tg][1] + S.cnt[tg][1] + __popcll(bp & below)] = C;
     if (mine && cat == CAT_OPEN) open_out[S.off[tg][2] + S.cnt[tg][2] + __popcll(bo & below)] = C;
+  } else if (mine && cat == CAT_P2P) {  // particle pairs, counted once (counting pass)
+    pairs += (unsigned long long)S.np[tg] * (unsigned long long)npC -
+             (C == S.id[tg] ? (unsigned long long)S.np[tg] : 0ull);
   }
   S.cnt[tg][0] += __popcll(bm);
   S.cnt[tg][1] += __popcll(bp);
@@ -167,10 +168,16 @@ __device__ void drain(const DevTree &t, Sibs &S, WaveLds &L, int &sp, int *open_
 }
 
 // One pass over the candidates of a sibling group (pass 0 counts, pass 1 writes).
+// With at most 64 open-list entries (one block of candidates, the usual
+// case) the counting pass keeps every candidate's categories in LDS and the
+// writing pass replays them: it reads no cell data for these candidates (its
+// only global accesses are the list stores and the descents).  ncand: the
+// number of cached candidates, set by the counting pass (0 when it expanded
+// none, e.g. an open list emptied by an overflow) and read by the writing pass.
 template <bool WRITE>
 __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
                            const int *open_in, int *open_out, double th2, double eps,
-                           unsigned long long &pairs) {
+                           unsigned long long &pairs, int &ncand) {
   const int lane = __lane_id();
 #pragma unroll
   for (int tg = 0; tg < 8; ++tg) S.cnt[tg][0] = S.cnt[tg][1] = S.cnt[tg][2] = 0;
@@ -179,6 +186,27 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
   if (l > 0) {
     in_off = t.open_off[P];
     in_cnt = t.open_cnt[P];
+  }
+  const bool cached = in_cnt <= 64;
+  if (!WRITE) ncand = 0;
+  if (WRITE && cached) {
+    const int total = min(ncand, TRAV_CAND);
+    for (int cb = 0; cb < total; cb += 64) {
+      if (sp > TRAV_STACK - TRAV_RESERVE - 512) drain<WRITE>(t, S, L, sp, open_out, th2, eps, pairs);
+      const bool valid = cb + lane < total;
+      const int C = valid ? L.cand[cb + lane] : 0;
+      const int code = valid ? L.ccat[cb + lane] : 0;
+#pragma unroll
+      for (int tg = 0; tg < 8; ++tg) {
+        if (tg < S.n) {
+          const int cat = (code >> (3 * tg)) & 7;
+          emit<WRITE>(t, S, tg, cat, valid, C, 0, open_out, pairs);
+          if (S.leaf[tg]) push_item(t, L, sp, cat == CAT_DEEPEN, tg, C);
+        }
+      }
+    }
+    drain<WRITE>(t, S, L, sp, open_out, th2, eps, pairs);
+    return;
   }
   for (int eb = 0; eb < in_cnt; eb += 64) {
     // expand 64 open-list entries into candidate cells (children, or the leaf itself)
@@ -198,6 +226,7 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
     int total;
     const int pos = wave_excl_scan_int(ec, &total);
     for (int q = 0; q < ec; ++q) L.cand[pos + q] = c0 + q;
+    if (!WRITE && cached) ncand = total;
     __builtin_amdgcn_wave_barrier();
     for (int cb = 0; cb < total; cb += 64) {
       // a chunk pushes at most 64 items per target, 512 in all, and must leave
@@ -212,16 +241,19 @@ __device__ void walk_group(const DevTree &t, int l, int P, Sibs &S, WaveLds &L,
         nC = t.nnchild[C];
         npC = t.nend[C] - t.nbeg[C];
       }
+      int code = 0;
 #pragma unroll
       for (int tg = 0; tg < 8; ++tg) {
         if (tg < S.n) {
           const int cat = valid ? classify(S.id[tg], L.geo[tg], S.leaf[tg], C, gC, nC == 0, th2,
                                            eps)
                                 : CAT_NONE;
+          code |= cat << (3 * tg);
           emit<WRITE>(t, S, tg, cat, valid, C, npC, open_out, pairs);
           if (S.leaf[tg]) push_item(t, L, sp, cat == CAT_DEEPEN, tg, C);
         }
       }
+      if (!WRITE && cached && valid) L.ccat[cb + lane] = code;
     }
     __builtin_amdgcn_wave_barrier();
   }
@@ -273,7 +305,8 @@ __device__ void walk_parent(const DevTree &t, int l, int P, double th2, double e
   const int *open_in = (l & 1) ? t.open_buf0 : t.open_buf1;
   int *open_out = (l & 1) ? t.open_buf1 : t.open_buf0;
   unsigned long long pairs = 0;
-  walk_group<false>(t, l, P, S, L, open_in, open_out, th2, eps, pairs);
+  int ncand = 0;
+  walk_group<false>(t, l, P, S, L, open_in, open_out, th2, eps, pairs, ncand);
   // allocate every target's lists (lane tg handles target tg)
   int mine[3] = {0, 0, 0};
 #pragma unroll
@@ -290,20 +323,27 @@ __device__ void walk_parent(const DevTree &t, int l, int P, double th2, double e
     unsigned *const cur[3] = {&h->m2l_cursor, &h->p2p_cursor, &h->open_cursor[l]};
     const int64_t cap[3] = {t.cap_m2l, t.cap_p2p, t.cap_open};
     const int ovf_bit[3] = {OVF_M2L, OVF_P2P, OVF_OPEN};
+    int incl[3], tot[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      int incl = mine[k];  // inclusive prefix over the target lanes 0..7
+      incl[k] = mine[k];  // inclusive prefix over the target lanes 0..7
 #pragma unroll
       for (int d = 1; d < 8; d <<= 1) {
-        const int y = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += y;
+        const int y = __shfl_up(incl[k], d, 64);
+        if (lane >= d) incl[k] += y;
       }
-      const int tot = __shfl(incl, 7, 64);
-      int base = 0;
-      if (lane == 0 && tot > 0) base = (int)atomicAdd(cur[k], (unsigned)tot);
-      base = __shfl(base, 0, 64);
-      o[k] = base + incl - mine[k];
-      if (lane < S.n && (int64_t)base + tot > cap[k]) bits |= ovf_bit[k];
+      tot[k] = __shfl(incl[k], 7, 64);
+    }
+    // lane k allocates list k: the three in one instruction, one round trip
+    const int tk = lane == 0 ? tot[0] : lane == 1 ? tot[1] : tot[2];
+    int got = 0;
+    if (lane < 3 && tk > 0) got = (int)atomicAdd(lane == 0 ? cur[0] : lane == 1 ? cur[1] : cur[2],
+                                                 (unsigned)tk);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int base = __shfl(got, k, 64);
+      o[k] = base + incl[k] - mine[k];
+      if (lane < S.n && (int64_t)base + tot[k] > cap[k]) bits |= ovf_bit[k];
     }
   }
   // if any target's lists do not fit, the wavefront writes none of them and
@@ -328,7 +368,7 @@ __device__ void walk_parent(const DevTree &t, int l, int P, double th2, double e
   for (int tg = 0; tg < 8; ++tg)
 #pragma unroll
     for (int k = 0; k < 3; ++k) S.off[tg][k] = __shfl(o[k], tg, 64);
-  walk_group<true>(t, l, P, S, L, open_in, open_out, th2, eps, pairs);
+  walk_group<true>(t, l, P, S, L, open_in, open_out, th2, eps, pairs, ncand);
   pairs = wave_sum(pairs);
   if (lane == 0 && pairs) atomicAdd(&h->p2p_pairs, pairs);
 }
