@@ -425,16 +425,28 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
     int32_t prev[FMM_NLEVELS + 2];  // level starts of the last tree: grid estimates
     memcpy(prev, c->hh.lvl_start, sizeof(prev));
     const int prev_nodes = c->n_nodes;
-    HIPCHK(c, launch_sort(c->t, a, c->stream));
-    HIPCHK(c, launch_build_tree(c->t, a, pred, c->stream));
-    HIPCHK(c, launch_traverse_dev(c->t, a, pred, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->pin_hdr, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost,
-                             c->stream));
-    HIPCHK(c, hipEventRecord(c->hdr_ev, c->stream));
     // the evaluation's grids come from the last tree: only for a batch of
     // the same systems within a quarter of its size
     const bool fuse = p_fused > 0 && n_req == (int)c->b_reqs.size() && 4 * n_all >= 3 * c->b_n &&
                       4 * n_all <= 5 * c->b_n;
+    HIPCHK(c, launch_sort(c->t, a, c->stream));
+    HIPCHK(c, launch_build_tree(c->t, a, pred, c->stream));
+    if (fuse) {  // mass gather, P2M and M2M on the second stream, beside the walk
+      EvalArgs u = {};
+      set_eval_args(c, u, n_all, p_fused, eps);
+      u.n_nodes = std::max(prev_nodes, 1);
+      u.lvl_start_host = prev;
+      u.depth = pred;
+      u.dev = true;
+      HIPCHK(c, hipEventRecord(c->fork, c->stream));
+      HIPCHK(c, hipStreamWaitEvent(c->side, c->fork, 0));
+      HIPCHK(c, launch_upward(c->t, u, c->side));
+      HIPCHK(c, hipEventRecord(c->up_done, c->side));
+    }
+    HIPCHK(c, launch_traverse_dev(c->t, a, pred, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->pin_hdr, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipEventRecord(c->hdr_ev, c->stream));
     if (fuse) {
       EvalArgs e = {};
       set_eval_args(c, e, n_all, p_fused, eps);
@@ -442,6 +454,8 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
       e.lvl_start_host = prev;
       e.depth = pred;
       e.dev = true;
+      e.upward_done = true;
+      e.up_done = c->up_done;
       HIPCHK(c, launch_evaluate(c->t, e, c->stream));
     }
     HIPCHK(c, hipEventSynchronize(c->hdr_ev));
@@ -503,11 +517,38 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
     HIPCHK(c, hipEventRecord(c->up_done, c->side));
     up = true;
   }
-  // 2. symmetric walk; regrow a list buffer that turned out too small
+  // 2. symmetric walk; regrow a list buffer that turned out too small.  With
+  // the masses known the evaluation is queued behind the first walk before the
+  // header is read (no host round trip between them): its kernels take the
+  // node count and level bounds from the header and do nothing if a list
+  // buffer overflowed; then the lists are regrown, the walk is redone and
+  // *evaluated stays false (the caller evaluates again).
   for (int attempt = 0; attempt < 10; ++attempt) {
     HIPCHK(c, launch_traverse(c->t, a, c->stream));
-    st = read_header(c);
-    if (st != FMM_OK) return st;
+    bool queued = false;
+    if (up && evaluated && attempt == 0) {
+      // the header copy goes behind the walk, the evaluation behind it; the
+      // host waits for the copy only
+      HIPCHK(c, hipMemcpyAsync(c->pin_hdr, c->t.hdr, sizeof(Header), hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipEventRecord(c->hdr_ev, c->stream));
+      EvalArgs e = {};
+      set_eval_args(c, e, n_all, p_fused, eps);
+      e.n_nodes = lvl[FMM_NLEVELS];
+      e.lvl_start_host = lvl;
+      e.depth = depth;
+      e.dev = true;
+      e.exact = true;
+      e.upward_done = true;
+      e.up_done = c->up_done;
+      HIPCHK(c, launch_evaluate(c->t, e, c->stream));
+      queued = true;
+      HIPCHK(c, hipEventSynchronize(c->hdr_ev));
+      memcpy(&c->hh, c->pin_hdr, sizeof(Header));
+    } else {
+      st = read_header(c);
+      if (st != FMM_OK) return st;
+    }
     const Header &h = c->hh;
     if (h.overflow & OVF_STACK) return fail(c, FMM_EOVERFLOW, "walk descent stack overflow");
     if (h.overflow & (OVF_M2L | OVF_P2P | OVF_OPEN)) {
@@ -530,6 +571,10 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
     record_levels(c, max_level);
     st = finish(depth);
     if (st == FMM_OK && upward) *upward = up;
+    if (st == FMM_OK && queued) {
+      count_evaluation(c, n_req, reqs);
+      *evaluated = true;
+    }
     return st;
   }
   return fail(c, FMM_EOVERFLOW, "list workspace still too small after regrowth");

@@ -270,6 +270,10 @@ struct EvalArgs {
   // depth are estimates (grid sizes, loop bounds) and the kernels take the
   // tree's sizes from the header
   bool dev;
+  // with dev: n_nodes, lvl_start_host and depth are the tree's exact sizes (the
+  // tree is final, only the lists may have overflowed): grids are exact, and
+  // the kernels still take the sizes from the header and skip an overflowed build
+  bool exact;
   // mass gather, P2M and M2M already queued by launch_upward (on the side
   // stream, beside the walk); the main stream waits for up_done before M2L
   bool upward_done;

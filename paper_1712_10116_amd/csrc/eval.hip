@@ -885,6 +885,10 @@ static void level_launch(const EvalArgs &e, int l, int per_cell, int &blocks, in
     blocks = cnt > 0 ? (per_cell * cnt + FMM_BLOCK - 1) / FMM_BLOCK : 0;
     a0 = ls;
     a1 = le;
+  } else if (e.exact) {
+    blocks = cnt > 0 ? (per_cell * cnt + FMM_BLOCK - 1) / FMM_BLOCK : 0;
+    a0 = -1 - l;
+    a1 = 0;
   } else {
     blocks = (per_cell * (cnt + cnt / 4 + 32) + FMM_BLOCK - 1) / FMM_BLOCK;
     a0 = -1 - l;
@@ -923,7 +927,7 @@ static void run_upward(const DevTree &t, const EvalArgs &e, hipStream_t s) {
 template <typename T, int P, int KERNEL>
 static void run_passes(const DevTree &t, const EvalArgs &e, hipStream_t s) {
   const int nn = e.n_nodes;  // exact, or (e.dev) an estimate that sets grid sizes
-  const int ga = e.dev ? nn + nn / 4 + 64 : nn;
+  const int ga = e.dev && !e.exact ? nn + nn / 4 + 64 : nn;
   const int narg = e.dev ? -1 : nn;  // -1: node count read on the device
   PhaseTimer *tm = e.tm;
   hipEventRecord(e.fork, s);
