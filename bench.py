@@ -591,6 +591,9 @@ def main():
                     help="skip the fourth-order integrator against KDK at equal cost")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the high-accuracy reference solve (errors over all particles)")
+    ap.add_argument("--classic", action="store_true",
+                    help="time the headline solves with the classic build sequence (three "
+                         "header readbacks) instead of level prediction")
     ap.add_argument("--no-named", action="store_true",
                     help="skip the run at the workload's own parameters (p 4, theta 0.5, leaf 16)")
     ap.add_argument("--ensemble", type=int, default=512, metavar="K",
@@ -679,15 +682,23 @@ def main():
                      "runners_up": [{k: (round(v, 6) if isinstance(v, float) else v)
                                      for k, v in r.items()} for r in ok[1:4]]}
     # the same (theta, p, leaf) for both precisions: equal truncation error
-    runs = [("mixed", F.MIXED, prm), ("fp64", F.FP64, prm)]
+    # a steady loop over one system: the library's level prediction (tree and
+    # walk queued for the split depth of the recent builds, one header
+    # readback per solve) is on unless --classic; the classic sequence (three
+    # readbacks) is timed beside it
+    predict = not args.classic
+    runs = [("mixed", F.MIXED, prm, predict), ("fp64", F.FP64, prm, predict)]
+    if predict:
+        runs.append(("mixed_classic", F.MIXED, prm, False))
     named = dict(p=4, theta=0.5, eps=eps, leaf_size=16)
     if not args.no_named and named != prm:
-        runs.append(("mixed_named", F.MIXED, named))
+        runs.append(("mixed_named", F.MIXED, named, predict))
     res = {}
-    for name, prec, pr in runs:
+    for name, prec, pr, pred in runs:
         progress(f"timed solves: {name}")
         s = F.Solver(n, p_max=pr["p"], leaf_size=pr["leaf_size"], kernel=F.WENDLAND,
                      precision=prec)
+        s.set_level_prediction(pred)
         acc = torch.empty((3, n), dtype=torch.float64, device=dev)
         pot = torch.empty((n,), dtype=torch.float64, device=dev)
         sec, phases, kt = time_solver(F, torch, s, tp, tm, acc, pot, pr, args.steps,
@@ -752,7 +763,8 @@ def main():
                                f"{prm['leaf_size']} (autotuned for rms force error <= "
                                f"{args.target}), mixed FP32/FP64",
                    "n": n, "p": prm["p"], "theta": prm["theta"], "eps": eps,
-                   "leaf_size": prm["leaf_size"], "parallelism": "single GPU"},
+                   "leaf_size": prm["leaf_size"], "level_prediction": predict,
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "force_err": {"mixed_vs_fp64_gpu": {"rms": e_mf[0], "p99": e_mf[1]},
                       "vs_reference_all": {}, "vs_direct_sample": {},
@@ -760,6 +772,9 @@ def main():
         "fp64": {"value": round(n / fp64["sec"], 1), "ms_per_step": round(fp64["sec"] * 1e3, 4),
                  "phases_ms": {k: round(v[0] / steps, 4) for k, v in fp64["phases"].items()}},
         "momentum_rel": {"mixed": mixed["momentum"], "fp64": fp64["momentum"]},
+        "classic_sequence": ({"value": round(n / res["mixed_classic"]["sec"], 1),
+                              "ms_per_step": round(res["mixed_classic"]["sec"] * 1e3, 4)}
+                             if "mixed_classic" in res else None),
         "phases_ms": {k: round(v[0] / steps, 4) for k, v in ph.items()},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in d.items()}
                     for k, d in kern.items()},
@@ -786,6 +801,7 @@ def main():
         with torch.cuda.stream(st):
             sv = F.Solver(n, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=F.WENDLAND,
                           precision=F.MIXED, stream=st)
+            sv.set_level_prediction(predict)
             pair.append((sv, st, torch.empty((3, n), dtype=torch.float64, device=dev),
                          torch.empty((n,), dtype=torch.float64, device=dev)))
     kw2 = dict(eps=eps, theta=prm["theta"], p=prm["p"])

@@ -595,8 +595,20 @@ __device__ __forceinline__ void p2p_block(const R4 *src, int f0, int self_idx, R
       }
       return;
     }
+    // a pair of the wavefront lies inside the radius: every pair of the block
+    // through PairKernel, on the differences already formed
+#pragma unroll
+    for (int u = 0; u < P2P_UNROLL; ++u) {
+      R mg, tp;
+      PairKernel<R, KERNEL>::eval(r2[u], mj[u], eps2, inv_eps, inv_eps3, mg, tp);
+      sx = fma(mg, dx[u], sx);
+      sy = fma(mg, dy[u], sy);
+      sz = fma(mg, dz[u], sz);
+      sp += tp;
+    }
+    return;
   }
-  // every pair through PairKernel (the block's sources read again)
+  // Plummer: every pair through PairKernel
   R4 svs[P2P_UNROLL];
 #pragma unroll
   for (int u = 0; u < P2P_UNROLL; ++u) svs[u] = src[f0 + u * NPH];
