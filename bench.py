@@ -591,6 +591,8 @@ def main():
                     help="skip the fourth-order integrator against KDK at equal cost")
     ap.add_argument("--no-reference", action="store_true",
                     help="skip the high-accuracy reference solve (errors over all particles)")
+    ap.add_argument("--no-inflight", action="store_true",
+                    help="skip the leg with two independent solves in flight")
     ap.add_argument("--classic", action="store_true",
                     help="time the headline solves with the classic build sequence (three "
                          "header readbacks) instead of level prediction")
@@ -793,36 +795,37 @@ def main():
     # alternately, so that one solve's latency-bound build (sort, tree, walk)
     # runs beside the other's evaluation (serving-style throughput; each call
     # is still one complete solve)
-    progress("two solves in flight")
-    sa = torch.cuda.Stream()
-    sb = torch.cuda.Stream()
-    pair = []
-    for st in (sa, sb):
-        with torch.cuda.stream(st):
-            sv = F.Solver(n, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=F.WENDLAND,
-                          precision=F.MIXED, stream=st)
-            sv.set_level_prediction(predict)
-            pair.append((sv, st, torch.empty((3, n), dtype=torch.float64, device=dev),
-                         torch.empty((n,), dtype=torch.float64, device=dev)))
-    kw2 = dict(eps=eps, theta=prm["theta"], p=prm["p"])
-    torch.cuda.synchronize()
-    for sv, st, a2, p2 in pair:
-        with torch.cuda.stream(st):
-            sv.forces(tp, tm, acc=a2, pot=p2, **kw2)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(2 * args.steps):
-        sv, st, a2, p2 = pair[k % 2]
-        with torch.cuda.stream(st):
-            sv.forces(tp, tm, acc=a2, pot=p2, **kw2)
-    torch.cuda.synchronize()
-    sec2 = (time.perf_counter() - t0) / (2 * args.steps)
-    same = bool(torch.equal(pair[0][2], pair[1][2]))
-    for sv, *_ in pair:
-        sv.close()
-    line["two_in_flight"] = {"solves": 2 * args.steps, "ms_per_solve": round(sec2 * 1e3, 4),
-                             "particles_per_s": round(n / sec2, 1),
-                             "results_equal": same, "precision": "mixed"}
+    if not args.no_inflight:
+        progress("two solves in flight")
+        sa = torch.cuda.Stream()
+        sb = torch.cuda.Stream()
+        pair = []
+        for st in (sa, sb):
+            with torch.cuda.stream(st):
+                sv = F.Solver(n, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=F.WENDLAND,
+                              precision=F.MIXED, stream=st)
+                sv.set_level_prediction(predict)
+                pair.append((sv, st, torch.empty((3, n), dtype=torch.float64, device=dev),
+                             torch.empty((n,), dtype=torch.float64, device=dev)))
+        kw2 = dict(eps=eps, theta=prm["theta"], p=prm["p"])
+        torch.cuda.synchronize()
+        for sv, st, a2, p2 in pair:
+            with torch.cuda.stream(st):
+                sv.forces(tp, tm, acc=a2, pot=p2, **kw2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(2 * args.steps):
+            sv, st, a2, p2 = pair[k % 2]
+            with torch.cuda.stream(st):
+                sv.forces(tp, tm, acc=a2, pot=p2, **kw2)
+        torch.cuda.synchronize()
+        sec2 = (time.perf_counter() - t0) / (2 * args.steps)
+        same = bool(torch.equal(pair[0][2], pair[1][2]))
+        for sv, *_ in pair:
+            sv.close()
+        line["two_in_flight"] = {"solves": 2 * args.steps, "ms_per_solve": round(sec2 * 1e3, 4),
+                                 "particles_per_s": round(n / sec2, 1),
+                                 "results_equal": same, "precision": "mixed"}
 
     # force gradient d a_i/d x_i beside the forces (the input of the fourth-order
     # integrator the paper proposes in Sec. 4.1), same particles and parameters
