@@ -430,7 +430,10 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
     const bool fuse = p_fused > 0 && n_req == (int)c->b_reqs.size() && 4 * n_all >= 3 * c->b_n &&
                       4 * n_all <= 5 * c->b_n;
     HIPCHK(c, launch_sort(c->t, a, c->stream));
-    HIPCHK(c, launch_build_tree(c->t, a, pred, c->stream));
+    if (build_tree_direct_ok(a.leaf_size))
+      HIPCHK(c, launch_build_tree_direct(c->t, a, pred, c->stream));
+    else
+      HIPCHK(c, launch_build_tree(c->t, a, pred, c->stream));
     if (fuse) {  // mass gather, P2M and M2M on the second stream, beside the walk
       EvalArgs u = {};
       set_eval_args(c, u, n_all, p_fused, eps);
@@ -463,7 +466,7 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
     if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
     const int need = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
     if (need <= pred &&
-        !(c->hh.overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN | OVF_STACK))) {
+        !(c->hh.overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN | OVF_STACK | OVF_DEPTH))) {
       record_levels(c, need);
       st = finish(tree_depth());
       if (st == FMM_OK && fuse) {
@@ -473,17 +476,20 @@ static fmm_status build_impl(fmm_ctx *c, int n_req, const fmm_request *reqs, dou
       return st;
     }
   }
-  // 1. tree; one readback of the level sizes (exact launches for the walk)
+  // 1. tree; one readback of the level sizes (exact launches for the walk).
+  // With the direct build the split depth need not be read first.
   int max_level = 0;
+  const bool direct = build_tree_direct_ok(a.leaf_size);
   for (int attempt = 0;; ++attempt) {
     if (attempt == 4) return fail(c, FMM_EOVERFLOW, "node workspace still too small");
     HIPCHK(c, launch_sort(c->t, a, c->stream));
+    if (direct) HIPCHK(c, launch_build_tree_direct(c->t, a, FMM_MAXLEVEL, c->stream));
     st = read_header(c);
     if (st != FMM_OK) return st;
     if (c->hh.nonfinite) return fail(c, FMM_ENONFINITE, "non-finite input position");
     // no cell below level split_depth + 1 holds more than leaf_size particles
     max_level = std::min(FMM_MAXLEVEL, c->hh.max_prefix + 1);
-    if (!(c->hh.overflow & OVF_NODES)) {
+    if (!direct && !(c->hh.overflow & OVF_NODES)) {
       HIPCHK(c, launch_build_tree(c->t, a, max_level, c->stream));
       st = read_header(c);
       if (st != FMM_OK) return st;

@@ -36,6 +36,9 @@
 #define OVF_P2P 4
 #define OVF_OPEN 8
 #define OVF_STACK 16
+// the tree holds cells deeper than the levels the (predicted) walk covers: the
+// cells below them have no lists, so nothing may be evaluated on it
+#define OVF_DEPTH 32
 
 struct Header {
   int32_t lvl_start[FMM_NLEVELS + 2];  // nodes of level l: [lvl_start[l], lvl_start[l+1])
@@ -246,6 +249,11 @@ hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s);
 // whole build up to the walk in one workgroup (a.n <= SMALL_N)
 hipError_t launch_build_small(const DevTree &t, const BuildArgs &a, hipStream_t s);
 hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, int max_level, hipStream_t s);
+// every split level in a fixed number of launches (no host read of the split
+// depth first); only for leaf sizes up to the window kept in LDS
+bool build_tree_direct_ok(int leaf_size);
+hipError_t launch_build_tree_direct(const DevTree &t, const BuildArgs &a, int walk_levels,
+                                    hipStream_t s);
 // traverse.hip
 hipError_t launch_traverse(const DevTree &t, const BuildArgs &a, hipStream_t s);
 // levels 0..levels, level bounds read on the device (tree sizes not yet known)

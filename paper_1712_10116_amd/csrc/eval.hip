@@ -79,7 +79,8 @@ __device__ __forceinline__ bool has_sink(const DevTree &t, int A, int bA, int nA
 // nothing is evaluated on a tree or lists whose build overflowed a
 // workspace (node arrays, list buffers or descent stack).
 __device__ __forceinline__ bool tree_incomplete(const DevTree &t) {
-  return (t.hdr->overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN | OVF_STACK)) != 0;
+  return (t.hdr->overflow & (OVF_NODES | OVF_M2L | OVF_P2P | OVF_OPEN | OVF_STACK | OVF_DEPTH)) !=
+         0;
 }
 __device__ __forceinline__ int node_count(const DevTree &t, int n) {
   if (n >= 0) return n;

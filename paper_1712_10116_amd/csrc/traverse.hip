@@ -420,7 +420,7 @@ __global__ void k_reset_lists(Header *h) {
     h->m2l_cursor = 0;
     h->p2p_cursor = 0;
     h->p2p_pairs = 0;
-    h->overflow &= OVF_NODES;
+    h->overflow &= OVF_NODES | OVF_DEPTH;
   }
   if (i < FMM_NLEVELS) h->open_cursor[i] = 0;
 }

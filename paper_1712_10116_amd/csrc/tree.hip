@@ -688,6 +688,201 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_tree_emit(DevTree t, int l, int l
 }
 
 // ---------------------------------------------------------------------------
+// Every split level at once (leaf_size <= TD_MAXLEAF): a fixed number of
+// launches whatever the depth, and no host read of the split depth first.
+//
+// The cell of level l that holds sorted particle i (a run of keys sharing
+// their first l octal digits) holds more than L = leaf_size particles exactly
+// when some k in [i - L, i] of the same system has keys k and k + L sharing
+// those digits (then k .. k + L, which contains i, lies in the run; and a run
+// of more than L particles contains such a window around any of its
+// particles).  With c(k) the common leading levels of keys k and k + L, the
+// cells along i's path are split at levels 0 .. m, m the largest c(k) over
+// that window, and i's leaf is at level d(i) = m + 1 (0 when no window fits
+// in the system; at most FMM_MAXLEVEL).  A cell of level l >= 1 exists when
+// its parent is split, i.e. l <= d(i) for its particles, and particle i
+// starts one at every level l from cp(i) + 1 to d(i), cp(i) the common
+// levels of keys i - 1 and i (0 at the first particle of a system); it ends
+// the run of every level l from cp(i + 1) + 1 (0 at the system's last
+// particle) to d(i).  Nodes are numbered level by level, in sorted order
+// within a level, as the level-by-level split numbers them, so the two build
+// the same tree bit for bit.
+// ---------------------------------------------------------------------------
+#define TD_THREADS 1024
+#define TD_WAVES (TD_THREADS / 64)
+#define TD_MAXLEAF 1024
+
+__device__ __forceinline__ int common_levels(uint64_t a, uint64_t b) {
+  const uint64_t x = a ^ b;
+  return x == 0 ? FMM_MAXLEVEL : (__clzll(x) - 1) / 3;
+}
+
+// c(i) into slot2 (free after the sort): -1 when i + L is past the system
+__global__ __launch_bounds__(FMM_BLOCK) void k_tree_pairs(DevTree t, int n, int L) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int r = t.n_req > 1 ? upper_index(t.req_off, t.n_req, i) : 0;
+  t.slot2[i] = i + L < t.req_off[r + 1] ? common_levels(t.key[i], t.key[i + L]) : -1;
+}
+
+// per-particle level data, packed: d | lo << 8 | lo2 << 16 (lo: first level
+// >= 1 at which i starts a cell; lo2: first level at which i ends a run)
+__device__ __forceinline__ void td_unpack(uint64_t v, int &d, int &lo, int &lo2) {
+  d = (int)(v & 255u);
+  lo = (int)((v >> 8) & 255u);
+  lo2 = (int)((v >> 16) & 255u);
+}
+
+// d, lo, lo2 of every particle into key2, and per level l >= 1 the number of
+// cells of level l that start in each block of TD_THREADS particles into
+// hist[(l - 1) * nblk + block]
+__global__ __launch_bounds__(TD_THREADS) void k_tree_levels(DevTree t, int n, int L, int nblk,
+                                                            uint32_t *hist) {
+  __shared__ int cw[TD_THREADS + TD_MAXLEAF];  // c over [b0 - L, b0 + TD_THREADS)
+  __shared__ int wcnt[TD_WAVES][FMM_MAXLEVEL];
+  const int b0 = blockIdx.x * TD_THREADS;
+  for (int k = threadIdx.x; k < TD_THREADS + L; k += TD_THREADS) {
+    const int g = b0 - L + k;
+    cw[k] = (g >= 0 && g < n) ? t.slot2[g] : -1;
+  }
+  __syncthreads();
+  const int i = b0 + threadIdx.x;
+  int lo = 1, hi = 0;
+  if (i < n) {
+    const int r = t.n_req > 1 ? upper_index(t.req_off, t.n_req, i) : 0;
+    const int rs = t.req_off[r], re = t.req_off[r + 1];
+    int m = -1;
+    for (int k = max(i - L, rs); k <= i; ++k) m = max(m, cw[k - b0 + L]);
+    const int d = m < 0 ? 0 : min(FMM_MAXLEVEL, m + 1);
+    const int cpi = i == rs ? 0 : common_levels(t.key[i - 1], t.key[i]);
+    const int lo2 = i + 1 == re ? 0 : common_levels(t.key[i], t.key[i + 1]) + 1;
+    lo = cpi + 1;
+    hi = d;
+    t.key2[i] = (uint64_t)d | ((uint64_t)lo << 8) | ((uint64_t)lo2 << 16);
+  }
+  const int w = threadIdx.x >> 6;
+  for (int l = 1; l <= FMM_MAXLEVEL; ++l) {
+    const unsigned long long b = __ballot(lo <= l && l <= hi);
+    if ((threadIdx.x & 63) == 0) wcnt[w][l - 1] = __popcll(b);
+  }
+  __syncthreads();
+  if (threadIdx.x < FMM_MAXLEVEL) {
+    int s = 0;
+    for (int ww = 0; ww < TD_WAVES; ++ww) s += wcnt[ww][threadIdx.x];
+    hist[(size_t)threadIdx.x * nblk + blockIdx.x] = (uint32_t)s;
+  }
+}
+
+// The nodes of levels >= 1 and the children of the roots.  hist holds, per
+// level, each block's exclusive offset among the level's cells, tot the
+// level totals.  A split cell's child count is written first as the end of
+// its children (by the particle that ends the cell) and turned into a count
+// by k_tree_nchild.
+__global__ __launch_bounds__(TD_THREADS) void k_tree_nodes(DevTree t, int n, int nblk,
+                                                           const uint32_t *hist,
+                                                           const uint32_t *tot, int walk_levels) {
+  __shared__ int wpre[TD_WAVES][FMM_MAXLEVEL];
+  __shared__ int lvs_s[FMM_NLEVELS + 2];
+  __shared__ int leaves_w[TD_WAVES];
+  if (threadIdx.x == 0) {
+    lvs_s[0] = 0;
+    lvs_s[1] = t.n_req;
+    for (int l = 1; l <= FMM_NLEVELS; ++l)
+      lvs_s[l + 1] = lvs_s[l] + (l <= FMM_MAXLEVEL ? (int)tot[l - 1] : 0);
+  }
+  const int b0 = blockIdx.x * TD_THREADS;
+  const int i = b0 + threadIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int d = 0, lo = 1, lo2 = FMM_MAXLEVEL + 1, r = 0;
+  if (i < n) {
+    td_unpack(t.key2[i], d, lo, lo2);
+    r = t.n_req > 1 ? upper_index(t.req_off, t.n_req, i) : 0;
+  }
+  const int hi = i < n ? d : 0;
+  const unsigned long long below = lanes_below_mask();
+  int rank[FMM_MAXLEVEL + 2];  // exclusive rank among the level's cell starts, levels 1..
+  for (int l = 1; l <= FMM_MAXLEVEL; ++l) {
+    const unsigned long long b = __ballot(lo <= l && l <= hi);
+    rank[l] = __popcll(b & below);
+    if (lane == 0) wpre[w][l - 1] = __popcll(b);
+  }
+  rank[0] = rank[FMM_MAXLEVEL + 1] = 0;
+  __syncthreads();
+  if (threadIdx.x < FMM_MAXLEVEL) {  // exclusive prefix over the waves, in place
+    int run = 0;
+    for (int ww = 0; ww < TD_WAVES; ++ww) {
+      const int c = wpre[ww][threadIdx.x];
+      wpre[ww][threadIdx.x] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int l = 1; l <= FMM_MAXLEVEL; ++l)
+    rank[l] += wpre[w][l - 1] + (int)hist[(size_t)(l - 1) * nblk + blockIdx.x];
+  const int64_t cap = t.cap_nodes;
+  int leaves = 0;
+  if (i < n) {
+    const Box box = t.box[r];
+    // cells that start at i
+    for (int l = lo; l <= hi; ++l) {
+      const int64_t k = (int64_t)lvs_s[l] + rank[l];
+      const bool split = l < d;
+      leaves += !split;
+      if (k >= cap) continue;
+      const bool ps = lo <= l - 1;  // i also starts its parent
+      t.nbeg[k] = i;
+      t.nlev[k] = l;
+      t.nparent[k] = l == 1 ? r : lvs_s[l - 1] + rank[l - 1] + (ps ? 1 : 0) - 1;
+      t.nchild0[k] = split ? lvs_s[l + 1] + rank[l + 1] : -1;
+      if (!split) t.nnchild[k] = 0;
+      t.nreq[k] = r;
+      t.ngeo[k] = cell_geometry(box, t.key[i] >> (3 * (FMM_MAXLEVEL - l)), l);
+    }
+    // the root's children start at the system's first particle
+    if (lo == 1 && i == t.req_off[r] && d > 0 && r < cap) t.nchild0[r] = lvs_s[1] + rank[1];
+    // runs that end at i
+    for (int l = lo2; l <= hi; ++l) {
+      const bool split = l < d;
+      const int incl_next = split ? rank[l + 1] + (lo <= l + 1 ? 1 : 0) : 0;
+      if (l == 0) {
+        if (split && r < cap) t.nnchild[r] = lvs_s[1] + incl_next;
+        continue;
+      }
+      const int64_t k = (int64_t)lvs_s[l] + rank[l] + (lo <= l ? 1 : 0) - 1;
+      if (k >= cap) continue;
+      t.nend[k] = i + 1;
+      if (split) t.nnchild[k] = lvs_s[l + 1] + incl_next;
+    }
+  }
+  leaves = wave_sum(leaves);
+  if (lane == 0) leaves_w[w] = leaves;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int ww = 0; ww < TD_WAVES; ++ww) s += leaves_w[ww];
+    if (s) atomicAdd((int *)&t.hdr->n_leaves, s);
+    if (blockIdx.x == 0) {
+      Header *h = t.hdr;
+      for (int l = 0; l < FMM_NLEVELS + 2; ++l) h->lvl_start[l] = lvs_s[l];
+      if (lvs_s[FMM_NLEVELS + 1] > cap) h->overflow |= OVF_NODES;
+      int deepest = 0;
+      for (int l = 1; l <= FMM_MAXLEVEL; ++l)
+        if (lvs_s[l + 1] > lvs_s[l]) deepest = l;
+      if (deepest > walk_levels) h->overflow |= OVF_DEPTH;
+    }
+  }
+}
+
+// split cells: child count = end of the children - first child
+__global__ __launch_bounds__(FMM_BLOCK) void k_tree_nchild(DevTree t) {
+  const int total = min(t.hdr->lvl_start[FMM_NLEVELS + 1], (int)t.cap_nodes);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < total; k += gridDim.x * blockDim.x) {
+    const int c0 = t.nchild0[k];
+    if (c0 >= 0) t.nnchild[k] -= c0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Small batches (at most SMALL_N active particles in all): the whole build up
 // to the walk -- slots, boxes, roots, keys, every sort pass, sorted gather,
 // split depth and every split level -- in one workgroup, one launch, with no
@@ -942,6 +1137,34 @@ hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_sorted, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
     hipLaunchKernelGGL(k_split_depth, dim3(std::min(nb, 512)), dim3(FMM_BLOCK), 0, s, t, n,
                        a.leaf_size);
+  }
+  if (a.tm) a.tm->stop(s);
+  return hipGetLastError();
+}
+
+// Every level at once (see k_tree_levels); false when leaf_size is beyond the
+// window that fits in LDS (then launch_build_tree builds level by level).
+bool build_tree_direct_ok(int leaf_size) { return leaf_size >= 1 && leaf_size <= TD_MAXLEAF; }
+
+// walk_levels: the levels the walk that follows covers (a deeper tree is
+// flagged with OVF_DEPTH and not evaluated)
+hipError_t launch_build_tree_direct(const DevTree &t, const BuildArgs &a, int walk_levels,
+                                    hipStream_t s) {
+  const int n = a.n;
+  if (a.tm) a.tm->start(PH_TREE, s);
+  if (n > 0) {
+    const int L = a.leaf_size;
+    const int nblk = (n + TD_THREADS - 1) / TD_THREADS;
+    hipLaunchKernelGGL(k_tree_pairs, dim3((n + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0, s,
+                       t, n, L);
+    hipLaunchKernelGGL(k_tree_levels, dim3(nblk), dim3(TD_THREADS), 0, s, t, n, L, nblk,
+                       t.sort_hist);
+    hipLaunchKernelGGL(k_sort_digit_scan, dim3(FMM_MAXLEVEL), dim3(FMM_BLOCK), 0, s, t.sort_hist,
+                       nblk, t.sort_dtot);
+    hipLaunchKernelGGL(k_tree_nodes, dim3(nblk), dim3(TD_THREADS), 0, s, t, n, nblk, t.sort_hist,
+                       t.sort_dtot, walk_levels);
+    hipLaunchKernelGGL(k_tree_nchild, dim3(std::min(1024, std::max(1, n / 256))), dim3(FMM_BLOCK),
+                       0, s, t);
   }
   if (a.tm) a.tm->stop(s);
   return hipGetLastError();
