@@ -7,7 +7,7 @@
 // Output SoA, 6 rows of n: xx, yy, zz, xy, xz, yz, in active order.
 //
 // Both parts run in the evaluation's precision (the near part's pair terms
-// on FP64 differences, summed into FP64 per source leaf).
+// on offsets from the sink leaf's centre, summed into FP64 per source leaf).
 #include "common.h"
 #include "expansion.h"
 
@@ -27,24 +27,32 @@ __device__ __forceinline__ void pair_gh(R r2, R eps, R ie, R &g, R &h) {
     h = R(-3) * g * is;
   } else {
     const R ir = fast_rsqrt<R>(r2);
-    const R r = r2 * ir;
-    if (r >= eps) {
+    if (r2 >= eps * eps) {
       const R ir2 = ir * ir;
       g = ir2 * ir;
       h = R(-3) * g * ir2;
     } else {
-      const R u = r2 > R(0) ? r * ie : R(0), ie3 = ie * ie * ie;
+      const R u = r2 > R(0) ? r2 * ir * ie : R(0), ie3 = ie * ie * ie;
       g = ((((R(21) * u - R(90)) * u + R(140)) * u - R(84)) * u * u + R(14)) * ie3;
       h = (((R(105) * u - R(360)) * u + R(420)) * u - R(168)) * ie3 * ie * ie;
     }
   }
 }
 
+// A staged source: its offset from the sink leaf's centre and its mass, in R.
+template <typename R>
+struct alignas(4 * sizeof(R)) SrcR {
+  R x, y, z, m;
+};
+
 // near part: one wavefront per sink leaf, lanes over its sinks (and, for
 // leaves of at most 32, over 2-16 phases of the sources), each source leaf
-// staged through LDS 64 particles at a time; pair terms in R (FP32 in the
-// mixed form, on FP64 differences), summed in R over one source leaf and then
-// into FP64
+// staged through LDS 64 particles at a time as offsets from the sink leaf's
+// centre in R (FP32 in the mixed form: cell-local offsets, as in the forces'
+// P2P); pair terms in R, summed in R over one source leaf and then into FP64.
+// Per pair: m h d (3 products) and six FMAs of it with d for the h d d^T
+// part; the g I part is one sum of m g per source leaf.  The self pair (d = 0)
+// is masked by a select, so an infinite g or h there never reaches a sum.
 // Written in sorted order to stage (6 rows of stride cap_n); k_l2p_grad adds
 // the far part and writes each particle's tensor once in active order.
 template <typename R, int KERNEL>
@@ -52,15 +60,17 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, 
                                                         double *__restrict__ stage) {
   const int lane = threadIdx.x & 63;
   // neighbouring leaves, which share most of their sources, on one XCD
-  const int wave = (xcd_block<32>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
+  const int wave =
+      __builtin_amdgcn_readfirstlane((xcd_block<32>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6);
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   const R reps = (R)eps, ie = eps > 0 ? (R)(1.0 / eps) : R(0);
-  __shared__ double4 src_lds[FMM_BLOCK / 64][64];
-  double4 *st = src_lds[threadIdx.x >> 6];
+  __shared__ SrcR<R> src_lds[FMM_BLOCK / 64][64];
+  SrcR<R> *st = src_lds[threadIdx.x >> 6];
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (t.nnchild[A] != 0) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
     const int loff = t.p2p_off[A], cnt = t.p2p_cnt[A];
+    const double4 gA = t.ngeo[A];
     for (int tb = 0; tb < nA; tb += 64) {
       // lanes = (sink, phase): nph phases share each sink and take every
       // nph-th source, so a leaf of fewer than 64 sinks still fills the wave
@@ -69,35 +79,50 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_grad(DevTree t, int n_nodes, 
       const int ti = lane / nph, ph = lane % nph;
       const bool valid = ti < ns;
       const int i = bA + tb + (valid ? ti : 0);
-      const double xi = t.sx[i], yi = t.sy[i], zi = t.sz[i];
+      // the sink's offset, formed exactly as a staged source's
+      const R xi = (R)(t.sx[i] - gA.x), yi = (R)(t.sy[i] - gA.y), zi = (R)(t.sz[i] - gA.z);
       double G[6] = {0, 0, 0, 0, 0, 0};
       for (int q = 0; q < cnt; ++q) {
         const int B = t.p2p_src[loff + q];
         const int eB = t.nend[B];
         R Gs[6] = {0, 0, 0, 0, 0, 0};
+        R Gg = 0;
         for (int jb = t.nbeg[B]; jb < eB; jb += 64) {
           // up to 64 sources of leaf B staged in LDS by the wave's lanes
           const int nj = min(64, eB - jb);
+          SrcR<R> e{R(0), R(0), R(0), R(0)};
           if (lane < nj)
-            st[lane] = make_double4(t.sx[jb + lane], t.sy[jb + lane], t.sz[jb + lane],
-                                    t.sm[jb + lane]);
+            e = SrcR<R>{(R)(t.sx[jb + lane] - gA.x), (R)(t.sy[jb + lane] - gA.y),
+                        (R)(t.sz[jb + lane] - gA.z), (R)t.sm[jb + lane]};
+          st[lane] = e;
           __builtin_amdgcn_wave_barrier();
-          for (int u = ph; u < nj; u += nph) {
-            if (jb + u == i) continue;
-            const double4 sv = st[u];
-            const R d[3] = {(R)(sv.x - xi), (R)(sv.y - yi), (R)(sv.z - zi)};
-            const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          // every lane takes the same number of steps: slot ph + k, k = 0, nph,
+          // ..., stays below 64 (nph divides 64); slots past nj hold zeros
+          const int si = i - jb - ph, lim = nj - ph;
+          for (int k = 0; k < nj; k += nph) {
+            const SrcR<R> sv = st[ph + k];
+            const R dx = sv.x - xi, dy = sv.y - yi, dz = sv.z - zi;
+            const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             R g, h;
             pair_gh<R, KERNEL>(r2, reps, ie, g, h);
-            const R m = (R)sv.w;
-#pragma unroll
-            for (int c = 0; c < 6; ++c)
-              Gs[c] += m * (-h * d[CA[c]] * d[CB[c]] - (CA[c] == CB[c] ? g : R(0)));
+            const bool skip = k == si || k >= lim;
+            const R mg = skip ? R(0) : sv.m * g;
+            const R mh = skip ? R(0) : sv.m * h;
+            const R hx = mh * dx, hy = mh * dy, hz = mh * dz;
+            Gg += mg;
+            Gs[0] = fma(-hx, dx, Gs[0]);
+            Gs[1] = fma(-hy, dy, Gs[1]);
+            Gs[2] = fma(-hz, dz, Gs[2]);
+            Gs[3] = fma(-hx, dy, Gs[3]);
+            Gs[4] = fma(-hx, dz, Gs[4]);
+            Gs[5] = fma(-hy, dz, Gs[5]);
           }
           __builtin_amdgcn_wave_barrier();
         }
 #pragma unroll
-        for (int c = 0; c < 6; ++c) G[c] += (double)Gs[c];
+        for (int c = 0; c < 3; ++c) G[c] += (double)(Gs[c] - Gg);
+#pragma unroll
+        for (int c = 3; c < 6; ++c) G[c] += (double)Gs[c];
       }
       // the phases of a sink are consecutive lanes: fold them onto phase 0
       for (int o = nph >> 1; o > 0; o >>= 1)
@@ -181,32 +206,34 @@ bool dispatch_grad(const DevTree &t, int n_nodes, int n, int p, double eps, doub
 // the sign of an acceleration (minus the field) so that L2P adds the far
 // field's gradient the same way.  Layout as k_p2p_grad: one wavefront per
 // sink leaf, (sink, phase) lanes, each source leaf staged through LDS 64
-// particles at a time, pair terms in R on FP64 differences, summed in R over
-// one source leaf and then into FP64.
+// particles at a time (offsets from the sink leaf's centre, mass and vector
+// in R), pair terms in R, summed in R over one source leaf and then into FP64.
 template <typename R, int KERNEL>
 __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_dip(DevTree t, int n_nodes, double eps,
                                                        const double *__restrict__ dv) {
   const int lane = threadIdx.x & 63;
   // neighbouring leaves, which share most of their sources, on one XCD
-  const int wave = (xcd_block<32>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6;
+  const int wave =
+      __builtin_amdgcn_readfirstlane((xcd_block<32>(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) >> 6);
   const int nwaves = (gridDim.x * blockDim.x) >> 6;
   const R reps = (R)eps, ie = eps > 0 ? (R)(1.0 / eps) : R(0);
   const int64_t cap = t.cap_n;
-  __shared__ double4 stage_x[FMM_BLOCK / 64][64];
-  __shared__ double4 stage_v[FMM_BLOCK / 64][64];
-  double4 *sx = stage_x[threadIdx.x >> 6];
-  double4 *sv = stage_v[threadIdx.x >> 6];
+  __shared__ SrcR<R> stage_x[FMM_BLOCK / 64][64];
+  __shared__ SrcR<R> stage_v[FMM_BLOCK / 64][64];
+  SrcR<R> *sx = stage_x[threadIdx.x >> 6];
+  SrcR<R> *sv = stage_v[threadIdx.x >> 6];
   for (int A = wave; A < n_nodes; A += nwaves) {
     if (t.nnchild[A] != 0) continue;
     const int bA = t.nbeg[A], nA = t.nend[A] - bA;
     const int loff = t.p2p_off[A], cnt = t.p2p_cnt[A];
+    const double4 gA = t.ngeo[A];
     for (int tb = 0; tb < nA; tb += 64) {
       const int ns = min(64, nA - tb);
       const int nph = ns <= 4 ? 16 : ns <= 8 ? 8 : ns <= 16 ? 4 : ns <= 32 ? 2 : 1;
       const int ti = lane / nph, ph = lane % nph;
       const bool valid = ti < ns;
       const int i = bA + tb + (valid ? ti : 0);
-      const double xi = t.sx[i], yi = t.sy[i], zi = t.sz[i];
+      const R xi = (R)(t.sx[i] - gA.x), yi = (R)(t.sy[i] - gA.y), zi = (R)(t.sz[i] - gA.z);
       double U[4] = {0, 0, 0, 0};
       for (int q = 0; q < cnt; ++q) {
         const int B = t.p2p_src[loff + q];
@@ -214,26 +241,33 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_p2p_dip(DevTree t, int n_nodes, d
         R Us[4] = {0, 0, 0, 0};
         for (int jb = t.nbeg[B]; jb < eB; jb += 64) {
           const int nj = min(64, eB - jb);
+          SrcR<R> ex{R(0), R(0), R(0), R(0)}, ev{R(0), R(0), R(0), R(0)};
           if (lane < nj) {
             const int j = jb + lane;
-            sx[lane] = make_double4(t.sx[j], t.sy[j], t.sz[j], t.sm[j]);
-            sv[lane] = make_double4(dv[j], dv[cap + j], dv[2 * cap + j], 0.0);
+            ex = SrcR<R>{(R)(t.sx[j] - gA.x), (R)(t.sy[j] - gA.y), (R)(t.sz[j] - gA.z),
+                         (R)t.sm[j]};
+            ev = SrcR<R>{(R)dv[j], (R)dv[cap + j], (R)dv[2 * cap + j], R(0)};
           }
+          sx[lane] = ex;
+          sv[lane] = ev;
           __builtin_amdgcn_wave_barrier();
-          for (int u = ph; u < nj; u += nph) {
-            if (jb + u == i) continue;
-            const double4 p = sx[u], v4 = sv[u];
-            const R d[3] = {(R)(p.x - xi), (R)(p.y - yi), (R)(p.z - zi)};
-            const R v[3] = {(R)v4.x, (R)v4.y, (R)v4.z};
-            const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+          // same number of steps on every lane, as in k_p2p_grad
+          const int si = i - jb - ph, lim = nj - ph;
+          for (int k = 0; k < nj; k += nph) {
+            const SrcR<R> p = sx[ph + k], v = sv[ph + k];
+            const R dx = p.x - xi, dy = p.y - yi, dz = p.z - zi;
+            const R r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             R g, h;
             pair_gh<R, KERNEL>(r2, reps, ie, g, h);
-            const R m = (R)p.w;
-            const R dvv = d[0] * v[0] + d[1] * v[1] + d[2] * v[2];
-            const R mg = m * g, mhd = m * h * dvv;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) Us[c] += mg * v[c] + mhd * d[c];
-            Us[3] -= mg * dvv;
+            const bool skip = k == si || k >= lim;
+            const R mg = skip ? R(0) : p.m * g;
+            const R mh = skip ? R(0) : p.m * h;
+            const R dvv = fma(dz, v.z, fma(dy, v.y, dx * v.x));
+            const R mhd = mh * dvv;
+            Us[0] = fma(mg, v.x, fma(mhd, dx, Us[0]));
+            Us[1] = fma(mg, v.y, fma(mhd, dy, Us[1]));
+            Us[2] = fma(mg, v.z, fma(mhd, dz, Us[2]));
+            Us[3] = fma(-mg, dvv, Us[3]);
           }
           __builtin_amdgcn_wave_barrier();
         }
