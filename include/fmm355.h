@@ -495,15 +495,23 @@ fmm_status serve_destroy(fmm_server *srv);
  * the request's id. */
 fmm_status serve_submit(fmm_server *srv, const serve_request *rq, int64_t *id);
 
-/* One scheduling step: admit queued requests in order while a slot and arena
- * space are free (uploading them, with one batched initial force solve; a
- * request's top-level step is the largest sqrt(eta eps / |a_i|) at t = 0
- * rounded down to a power of two, at most dt_max, and its last step is cut to
- * end at t_end), then advance every resident request by one top-level step in
- * one hhs_step_batched, and retire those that reached t_end (their outputs
- * downloaded, their arena space freed).  Synchronous.  A result does not
- * depend on the other requests served with it.  Outputs (may be NULL): the
- * resident and queued counts after the step. */
+/* One scheduling step: rounds of the batched HHS driver (Algorithms 1-3 of
+ * Sec. 2.2) over the resident requests, for about 2 ms of host time or until
+ * a request finishes or nothing is left to do.  Each round first admits
+ * queued requests in order while a slot and arena space are free (uploading
+ * them, with one batched initial force solve; a request's top-level step is
+ * the largest sqrt(eta eps / |a_i|) at t = 0 rounded down to a power of two,
+ * at most dt_max, and its last step is cut to end at t_end); then every
+ * resident request advances until it needs the device, a request that ended
+ * its top-level step begins the next one (or, at t_end, is retired: outputs
+ * downloaded, arena space and slot freed), and either all pending split
+ * counts are read back at once or all pending KDK halves are solved in shared
+ * launches.  Requests at different points of their steps share launches;
+ * none waits for another to end its step.  The last round's device work may
+ * still run on the context's stream on return; a result handed out by
+ * serve_poll is complete (its outputs written).  A result does not depend on
+ * the other requests served with it.  Outputs (may be NULL): the resident and
+ * queued counts after the step. */
 fmm_status serve_step(fmm_server *srv, int *n_resident, int *n_queued);
 
 /* Up to max_out finished requests, in completion order. */
@@ -513,7 +521,7 @@ fmm_status serve_poll(fmm_server *srv, serve_result *out, int max_out, int *n_ou
 fmm_status serve_cancel(fmm_server *srv, int64_t id);
 
 /* info[0] resident, [1] queued, [2] finished not yet polled, [3] arena bytes
- * in use, [4] arena bytes, [5] serve_step calls that advanced requests. */
+ * in use, [4] arena bytes, [5] scheduling rounds run. */
 fmm_status serve_info(const fmm_server *srv, int64_t info[6]);
 
 #ifdef __cplusplus

@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <new>
 #include <type_traits>
 #include <vector>
 
@@ -112,9 +113,8 @@ void hhs_run_launch_min_amag(hhs_run *r, const hhs_state *st, double *out) {
   hhs_launch_min_sum(st->a_old, st->a_cur, st->n, r->pot, out, r->ctx->stream);
 }
 
-namespace {
-
-struct Frame {
+// One level of a system's EVOLVE_HOLD recursion.
+struct HhsFrame {
   int k;
   const int32_t *sys;
   int n_sys;
@@ -124,6 +124,26 @@ struct Frame {
   int n_fast, n_slow;
   double t0;  // start of the frame's step (ln a in the comoving form)
 };
+
+enum HhsSysState { S_RUN, S_WAIT_SPLIT, S_WAIT_HALF, S_DONE };
+
+// One system of a batched run; its frame stack persists between rounds.
+struct HhsSys {
+  hhs_run *run;
+  hhs_state *st;
+  int slot;  // its split counter (c->split_cnt[slot]), fixed for its life
+  double dt_top;
+  std::vector<HhsFrame> stack;
+  HhsSysState state;
+  int half;
+  int64_t kicks, parts;  // force evaluations of this system, and their active particles
+  bool range_err;        // a comoving factor fell outside the cosmology table
+};
+
+namespace {
+
+using Frame = HhsFrame;
+using Sys = HhsSys;
 
 // Comoving form (Sec. 3.5): the factor that replaces the length of a kick
 // (integral of dt/a) or a drift (integral of dt/a^2) over [x0, x0 + dx] in
@@ -138,19 +158,6 @@ bool step_factor(const hhs_params *hp, double x0, double dx, bool kick, double *
   *out = kick ? k : d;
   return true;
 }
-
-enum SysState { S_RUN, S_WAIT_SPLIT, S_WAIT_HALF, S_DONE };
-
-struct Sys {
-  hhs_run *run;
-  hhs_state *st;
-  double dt_top;
-  std::vector<Frame> stack;
-  SysState state;
-  int half;
-  int64_t kicks, parts;  // force evaluations of this system, and their active particles
-  bool range_err;        // a comoving factor fell outside the cosmology table
-};
 
 // One kick of Algorithm 3 inside a KDK half: which set is kicked, with which
 // masses, and which |a| slot a second kick refreshes.
@@ -174,7 +181,8 @@ int kicks_of_half(const Frame &f, int half, Kick out[2]) {
 
 // Runs system S until it waits on the device or finishes; false when the
 // rung recursion would go deeper than the scratch holds.
-bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
+bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp) {
+  const int slot = S.slot;
   hhs_run *r = S.run;
   hhs_state *st = S.st;
   while (S.state == S_RUN) {
@@ -261,13 +269,13 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, int slot) {
 // evaluation takes the kicked set as its sinks (P2P skips leaves without one);
 // the second kickFS2S of a top-level KDK evaluates the whole system when the
 // bound of Eq. 9 needs |a|_tot.
-static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const hhs_params *hp,
-                             int64_t *kicks) {
+static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int W,
+                             const hhs_params *hp, int64_t *kicks) {
   std::vector<fmm_request> q(W);
   std::vector<Kick> kk(2 * W, Kick{false, false});
   std::vector<int> nk(W);
   for (int w = 0; w < W; ++w) {
-    Sys &S = sys[grp[w]];
+    Sys &S = *sys[grp[w]];
     const Frame &f = S.stack.back();
     q[w] = fmm_request{S.st->pos, S.st->n, f.sys, f.n_sys, nullptr, S.run->acc, S.run->pot};
     nk[w] = kicks_of_half(f, S.half, &kk[2 * w]);
@@ -277,7 +285,7 @@ static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const 
   for (int slot = 0; slot < 2; ++slot) {
     bool any = false;
     for (int w = 0; w < W; ++w) {
-      Sys &S = sys[grp[w]];
+      Sys &S = *sys[grp[w]];
       const Frame &f = S.stack.back();
       q[w].mass = nullptr;
       if (slot >= nk[w]) continue;
@@ -305,7 +313,7 @@ static fmm_status serve_half(fmm_ctx *c, Sys *sys, const int *grp, int W, const 
     if (e != FMM_OK) return e;
     for (int w = 0; w < W; ++w) {
       if (slot >= nk[w]) continue;
-      Sys &S = sys[grp[w]];
+      Sys &S = *sys[grp[w]];
       const Frame &f = S.stack.back();
       const Kick &K = kk[2 * w + slot];
       const int k = f.k;
@@ -406,6 +414,100 @@ extern "C" fmm_status hhs_init_batched(fmm_ctx *c, int n_sys, hhs_run *const *ru
   return FMM_OK;
 }
 
+HhsSys *hhs_sys_create(hhs_run *run, hhs_state *st, int slot) {
+  HhsSys *S = new (std::nothrow) HhsSys();
+  if (!S) return nullptr;
+  S->run = run;
+  S->st = st;
+  S->slot = slot;
+  S->state = S_DONE;
+  S->half = 0;
+  S->kicks = S->parts = 0;
+  S->range_err = false;
+  return S;
+}
+
+void hhs_sys_destroy(HhsSys *S) { delete S; }
+
+void hhs_sys_begin(HhsSys *S, double dt_top) {
+  S->dt_top = dt_top;
+  S->state = S_RUN;
+  S->half = 0;
+  S->range_err = false;
+  S->stack.clear();
+  S->stack.push_back(Frame{0, S->run->all_idx, (int)S->st->n, dt_top, true, 0, 0, 0, S->st->t});
+}
+
+bool hhs_sys_idle(const HhsSys *S) { return S->state == S_DONE; }
+
+void hhs_sys_counts(const HhsSys *S, int64_t *kicks, int64_t *parts) {
+  *kicks = S->kicks;
+  *parts = S->parts;
+}
+
+fmm_status hhs_sys_advance(fmm_ctx *c, HhsSys *const *sys, int n_sys, const hhs_params *hp) {
+  int ns = 0;
+  for (int i = 0; i < n_sys; ++i) ns = std::max(ns, sys[i]->slot + 1);
+  fmm_status e = ensure_split_slots(c, ns);
+  if (e != FMM_OK) return e;
+  for (int i = 0; i < n_sys; ++i)
+    if (sys[i]->state == S_RUN && !advance(c, *sys[i], hp))
+      return fmm_fail(c, FMM_EINVAL,
+                      sys[i]->range_err ? "system %d: scale factor outside the cosmology table"
+                                        : "system %d: rung recursion deeper than max_levels",
+                      i);
+  return FMM_OK;
+}
+
+fmm_status hhs_sys_serve(fmm_ctx *c, HhsSys *const *sys, int n_sys, const hhs_params *hp,
+                         int64_t *kicks, bool *served) {
+  *served = false;
+  std::vector<int> wait;
+  int ns = 0;
+  for (int i = 0; i < n_sys; ++i)
+    if (sys[i]->state == S_WAIT_SPLIT) {
+      wait.push_back(i);
+      ns = std::max(ns, sys[i]->slot + 1);
+    }
+  if (!wait.empty()) {  // one readback for every pending split
+    if ((int)c->h_split.size() < ns) c->h_split.resize(ns);
+    if (hipMemcpyAsync(c->h_split.data(), c->split_cnt, sizeof(int32_t) * ns,
+                       hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      return fmm_fail(c, FMM_EDEVICE, "split readback failed");
+    for (int i : wait) {
+      Frame &f = sys[i]->stack.back();
+      f.n_fast = c->h_split[sys[i]->slot];
+      f.n_slow = f.n_sys - f.n_fast;
+      sys[i]->state = S_RUN;
+    }
+    *served = true;
+    return FMM_OK;
+  }
+  for (int i = 0; i < n_sys; ++i)
+    if (sys[i]->state == S_WAIT_HALF) wait.push_back(i);
+  if (wait.empty()) return FMM_OK;
+  // systems waiting on a KDK half, packed greedily into groups that fit the
+  // context; one batched build and two evaluation slots per group
+  size_t g0 = 0;
+  while (g0 < wait.size()) {
+    size_t g1 = g0;
+    int64_t tot = 0;
+    while (g1 < wait.size()) {
+      const int64_t m = sys[wait[g1]]->stack.back().n_sys;
+      if (g1 > g0 && tot + m > c->max_n) break;
+      tot += m;
+      ++g1;
+    }
+    fmm_status e = serve_half(c, sys, wait.data() + g0, (int)(g1 - g0), hp, kicks);
+    if (e != FMM_OK) return e;
+    g0 = g1;
+  }
+  for (int i : wait) sys[i]->state = S_RUN;
+  *served = true;
+  return FMM_OK;
+}
+
 fmm_status hhs_step_batched_ex(fmm_ctx *c, int n_sys, hhs_run *const *runs,
                                hhs_state *const *states, const hhs_params *hp,
                                const double *dt_top, int64_t stats[3], int64_t *sys_stats) {
@@ -414,9 +516,8 @@ fmm_status hhs_step_batched_ex(fmm_ctx *c, int n_sys, hhs_run *const *runs,
   if (n_sys < 1 || !runs || !states || !dt_top) return fmm_fail(c, FMM_EINVAL, "no systems");
   e = check_distinct(c, n_sys, runs, states);
   if (e != FMM_OK) return e;
-  e = ensure_split_slots(c, n_sys);
-  if (e != FMM_OK) return e;
-  std::vector<Sys> sys(n_sys);
+  std::vector<HhsSys> sys(n_sys);
+  std::vector<HhsSys *> ps(n_sys);
   for (int i = 0; i < n_sys; ++i) {
     e = check_system(c, runs[i], states[i], hp);
     if (e != FMM_OK) return e;
@@ -425,61 +526,23 @@ fmm_status hhs_step_batched_ex(fmm_ctx *c, int n_sys, hhs_run *const *runs,
     Sys &S = sys[i];
     S.run = runs[i];
     S.st = states[i];
-    S.dt_top = dt_top[i];
-    S.state = S_RUN;
-    S.half = 0;
+    S.slot = i;
     S.kicks = S.parts = 0;
-    S.range_err = false;
-    S.stack.push_back(
-        Frame{0, runs[i]->all_idx, (int)states[i]->n, dt_top[i], true, 0, 0, 0, states[i]->t});
+    hhs_sys_begin(&S, dt_top[i]);
+    ps[i] = &S;
   }
   const int64_t c0 = c->stat_parts, b0 = c->stat_builds;
   int64_t kicks = 0;
-  std::vector<int> wait;
-  c->h_split.resize(n_sys);
+  // rounds: every running system advances until it waits on the device or
+  // ends its step, then either all pending splits or all pending KDK halves
+  // are served; the step ends when nothing waits
   for (;;) {
-    for (int i = 0; i < n_sys; ++i)
-      if (sys[i].state == S_RUN && !advance(c, sys[i], hp, i))
-        return fmm_fail(c, FMM_EINVAL,
-                        sys[i].range_err ? "system %d: scale factor outside the cosmology table"
-                                         : "system %d: rung recursion deeper than max_levels",
-                        i);
-    wait.clear();
-    for (int i = 0; i < n_sys; ++i)
-      if (sys[i].state == S_WAIT_SPLIT) wait.push_back(i);
-    if (!wait.empty()) {  // one readback for every pending split
-      if (hipMemcpyAsync(c->h_split.data(), c->split_cnt, sizeof(int32_t) * n_sys,
-                         hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-          hipStreamSynchronize(c->stream) != hipSuccess)
-        return fmm_fail(c, FMM_EDEVICE, "split readback failed");
-      for (int i : wait) {
-        Frame &f = sys[i].stack.back();
-        f.n_fast = c->h_split[i];
-        f.n_slow = f.n_sys - f.n_fast;
-        sys[i].state = S_RUN;
-      }
-      continue;
-    }
-    for (int i = 0; i < n_sys; ++i)
-      if (sys[i].state == S_WAIT_HALF) wait.push_back(i);
-    if (wait.empty()) break;  // every system finished its top-level step
-    // systems waiting on a KDK half, packed greedily into groups that fit
-    // the context; one batched build and two evaluation slots per group
-    size_t g0 = 0;
-    while (g0 < wait.size()) {
-      size_t g1 = g0;
-      int64_t tot = 0;
-      while (g1 < wait.size()) {
-        const int64_t m = sys[wait[g1]].stack.back().n_sys;
-        if (g1 > g0 && tot + m > c->max_n) break;
-        tot += m;
-        ++g1;
-      }
-      e = serve_half(c, sys.data(), wait.data() + g0, (int)(g1 - g0), hp, &kicks);
-      if (e != FMM_OK) return e;
-      g0 = g1;
-    }
-    for (int i : wait) sys[i].state = S_RUN;
+    e = hhs_sys_advance(c, ps.data(), n_sys, hp);
+    if (e != FMM_OK) return e;
+    bool served;
+    e = hhs_sys_serve(c, ps.data(), n_sys, hp, &kicks, &served);
+    if (e != FMM_OK) return e;
+    if (!served) break;
   }
   if (hipStreamSynchronize(c->stream) != hipSuccess)
     return fmm_fail(c, FMM_EDEVICE, "hhs_step synchronisation failed");

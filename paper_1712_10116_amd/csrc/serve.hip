@@ -5,11 +5,16 @@
 // All device memory of resident requests comes from one arena allocated at
 // creation.  A request is admitted, in arrival order, when a slot is free and
 // its footprint (state + integrator scratch) fits in the arena; it is then
-// resident until it finishes.  Each serve_step advances every resident request
-// by one top-level step through hhs_step_batched, so the force solves of all
-// of them share launches; requests that arrive meanwhile join at the next
-// step.  Because a batched step leaves every system exactly as a step of it
-// alone would, a request's result does not depend on what it was served with.
+// resident until it finishes.  serve_step runs rounds of the batched HHS
+// driver over all resident requests: in a round every request advances until
+// it needs the device (a split count or a KDK half), then all pending split
+// counts are read back at once, or all pending KDK halves are solved in shared
+// launches.  A request that ends its top-level step begins the next one in
+// the same round, and a request admitted between rounds joins the next one,
+// so requests at different points of their steps (and of different depths)
+// share launches instead of waiting for the slowest to end its step.  Every
+// request follows exactly the operations of a run of it alone, so its result
+// does not depend on what it was served with.
 #include <math.h>
 
 #include <algorithm>
@@ -108,9 +113,16 @@ struct Req {
   int64_t off, bytes;  // arena block
   hhs_state st;
   hhs_run *run;
-  double dt_top;
-  int64_t steps, calls, parts;
+  HhsSys *sys;  // its frame stack in the batched driver
+  int slot;     // its split counter, one of [0, max_slots)
+  double dt_top, dt_cur;
+  bool stepping, last;  // a step of dt_cur is in progress; it ends at t_end
+  int64_t steps;
 };
+
+// Host time after which serve_step returns between rounds, so that the caller
+// can hand over requests that arrived meanwhile.
+constexpr double kQuantum = 2e-3;
 
 }  // namespace
 
@@ -124,6 +136,7 @@ struct fmm_server {
   std::vector<std::unique_ptr<Req>> resident;
   std::deque<serve_result> done;
   int64_t next_id, ticks;
+  std::vector<int> free_slots;
   double *dmin;  // [max_slots] device minima of |a| at admission
   std::vector<double> hmin;
   std::chrono::steady_clock::time_point t0;
@@ -165,6 +178,7 @@ extern "C" fmm_status serve_create(fmm_ctx *c, const hhs_params *hp, const serve
     return fmm_fail(c, FMM_ENOMEM, "server minima");
   }
   s->hmin.resize(sp->max_slots);
+  for (int k = sp->max_slots - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->arena.reset((char *)s->block, sp->arena_bytes);
   *out = s;
   return FMM_OK;
@@ -173,6 +187,9 @@ extern "C" fmm_status serve_create(fmm_ctx *c, const hhs_params *hp, const serve
 static void drop_resident(fmm_server *s, Req &r) {
   hhs_run_destroy(r.run);  // waits for the stream; the run's memory is the arena's
   r.run = nullptr;
+  hhs_sys_destroy(r.sys);
+  r.sys = nullptr;
+  s->free_slots.push_back(r.slot);
   s->arena.release(r.off, r.bytes);
 }
 
@@ -224,6 +241,12 @@ static fmm_status admit(fmm_server *s) {
     r.st.n = n;
     r.st.t = 0.0;
     fmm_status e = hhs_run_create_at(c, n, s->hp.max_levels, base + sb, &r.run);
+    if (e == FMM_OK) {
+      // a slot is free: fewer than max_slots requests are resident
+      r.slot = s->free_slots.back();
+      r.sys = hhs_sys_create(r.run, &r.st, r.slot);
+      if (!r.sys) e = fmm_fail(c, FMM_ENOMEM, "request driver state");
+    }
     if (e == FMM_OK &&
         (hipMemcpyAsync(r.st.pos, r.rq.pos, 24 * n, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
          hipMemcpyAsync(r.st.vel, r.rq.vel, 24 * n, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
@@ -233,9 +256,13 @@ static fmm_status admit(fmm_server *s) {
       e = fmm_fail(c, FMM_EDEVICE, "request upload failed");
     if (e != FMM_OK) {
       if (r.run) hhs_run_destroy(r.run);
+      r.run = nullptr;
+      hhs_sys_destroy(r.sys);
+      r.sys = nullptr;
       s->arena.release(off, r.bytes);
       return e;
     }
+    s->free_slots.pop_back();
     r.t_admit = now_s(s);
     s->resident.push_back(std::move(s->queue.front()));
     s->queue.pop_front();
@@ -270,71 +297,101 @@ static fmm_status admit(fmm_server *s) {
   return FMM_OK;
 }
 
+// Retires the finished requests of the resident list (outputs downloaded,
+// results recorded, memory and slot freed), keeping the others in order.
+static fmm_status retire(fmm_server *s) {
+  fmm_ctx *c = s->ctx;
+  for (auto &rp : s->resident) {
+    Req &r = *rp;
+    if (r.stepping || !r.last) continue;
+    if (hipMemcpyAsync(r.rq.pos_out, r.st.pos, 24 * r.rq.n, hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(r.rq.vel_out, r.st.vel, 24 * r.rq.n, hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess)
+      return fmm_fail(c, FMM_EDEVICE, "result download failed");
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return fmm_fail(c, FMM_EDEVICE, "result download failed");
+  const double t = now_s(s);
+  std::vector<std::unique_ptr<Req>> keep;
+  for (auto &rp : s->resident) {
+    if (rp->stepping || !rp->last) {
+      keep.push_back(std::move(rp));
+      continue;
+    }
+    serve_result res;
+    res.id = rp->id;
+    res.n = rp->rq.n;
+    res.steps = rp->steps;
+    hhs_sys_counts(rp->sys, &res.force_calls, &res.force_particles);
+    res.dt_top = rp->dt_top;
+    res.t_end = rp->st.t;
+    res.t_submit = rp->t_submit;
+    res.t_admit = rp->t_admit;
+    res.t_done = t;
+    s->done.push_back(res);
+    drop_resident(s, *rp);
+  }
+  s->resident.swap(keep);
+  return FMM_OK;
+}
+
 extern "C" fmm_status serve_step(fmm_server *s, int *n_resident, int *n_queued) {
   if (!s) return FMM_EINVAL;
   fmm_ctx *c = s->ctx;
-  fmm_status e = admit(s);
-  if (e != FMM_OK) return e;
-  const int R = (int)s->resident.size();
-  if (R > 0) {
-    std::vector<hhs_run *> runs(R);
-    std::vector<hhs_state *> sts(R);
-    std::vector<double> dts(R);
-    std::vector<char> last(R);
-    std::vector<int64_t> per(2 * R);
-    for (int i = 0; i < R; ++i) {
-      Req &r = *s->resident[i];
-      runs[i] = r.run;
-      sts[i] = &r.st;
-      const double left = r.rq.t_end - r.st.t;
-      last[i] = r.dt_top >= left;
-      dts[i] = last[i] ? left : r.dt_top;
-    }
-    int64_t stats[3];
-    e = hhs_step_batched_ex(c, R, runs.data(), sts.data(), &s->hp, dts.data(), stats, per.data());
+  const auto t_start = std::chrono::steady_clock::now();
+  std::vector<HhsSys *> ps;
+  for (;;) {
+    fmm_status e = admit(s);
     if (e != FMM_OK) return e;
-    ++s->ticks;
-    bool any = false;
-    for (int i = 0; i < R; ++i) {
-      Req &r = *s->resident[i];
-      r.steps++;
-      r.calls += per[2 * i];
-      r.parts += per[2 * i + 1];
-      if (!last[i]) continue;
-      any = true;
-      if (hipMemcpyAsync(r.rq.pos_out, r.st.pos, 24 * r.rq.n, hipMemcpyDeviceToHost, c->stream) !=
-              hipSuccess ||
-          hipMemcpyAsync(r.rq.vel_out, r.st.vel, 24 * r.rq.n, hipMemcpyDeviceToHost, c->stream) !=
-              hipSuccess)
-        return fmm_fail(c, FMM_EDEVICE, "result download failed");
-    }
-    if (any) {
-      if (hipStreamSynchronize(c->stream) != hipSuccess)
-        return fmm_fail(c, FMM_EDEVICE, "result download failed");
-      const double t = now_s(s);
-      std::vector<std::unique_ptr<Req>> keep;
-      for (int i = 0; i < R; ++i) {
-        std::unique_ptr<Req> &rp = s->resident[i];
-        if (!last[i]) {
-          keep.push_back(std::move(rp));
+    if (s->resident.empty()) break;
+    ps.clear();
+    for (auto &r : s->resident) ps.push_back(r->sys);
+    e = hhs_sys_advance(c, ps.data(), (int)ps.size(), &s->hp);
+    if (e != FMM_OK) return e;
+    // a request whose step ended is retired at t_end, else it begins its
+    // next step (as does a request just admitted) and advances to its first
+    // device wait, so that it joins this round
+    bool restarted = false, finished = false;
+    for (auto &rp : s->resident) {
+      Req &r = *rp;
+      if (!hhs_sys_idle(r.sys)) continue;
+      if (r.stepping) {
+        r.stepping = false;
+        r.st.t += r.dt_cur;
+        r.steps++;
+        if (r.last) {
+          finished = true;
           continue;
         }
-        serve_result res;
-        res.id = rp->id;
-        res.n = rp->rq.n;
-        res.steps = rp->steps;
-        res.force_calls = rp->calls;
-        res.force_particles = rp->parts;
-        res.dt_top = rp->dt_top;
-        res.t_end = rp->st.t;
-        res.t_submit = rp->t_submit;
-        res.t_admit = rp->t_admit;
-        res.t_done = t;
-        s->done.push_back(res);
-        drop_resident(s, *rp);
       }
-      s->resident.swap(keep);
+      const double left = r.rq.t_end - r.st.t;
+      r.last = r.dt_top >= left;
+      r.dt_cur = r.last ? left : r.dt_top;
+      hhs_sys_begin(r.sys, r.dt_cur);
+      r.stepping = true;
+      restarted = true;
     }
+    if (restarted) {
+      e = hhs_sys_advance(c, ps.data(), (int)ps.size(), &s->hp);
+      if (e != FMM_OK) return e;
+    }
+    if (finished) {
+      e = retire(s);
+      if (e != FMM_OK) return e;
+      ps.clear();
+      for (auto &r : s->resident) ps.push_back(r->sys);
+    }
+    bool served = false;
+    int64_t kicks = 0;
+    if (!ps.empty()) {
+      e = hhs_sys_serve(c, ps.data(), (int)ps.size(), &s->hp, &kicks, &served);
+      if (e != FMM_OK) return e;
+    }
+    ++s->ticks;
+    const double spent =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (finished || !served || spent >= kQuantum) break;
   }
   if (n_resident) *n_resident = (int)s->resident.size();
   if (n_queued) *n_queued = (int)s->queue.size();

@@ -36,6 +36,7 @@ def run(server, requests, t_end, arrivals=None, clock=time.perf_counter, log=Non
     start = clock()
     outstanding = 0
     steps = 0
+    last_log = -1e9
     while nxt < n or outstanding:
         now = clock() - start
         while nxt < n and arr[order[nxt]] <= now:
@@ -48,8 +49,9 @@ def run(server, requests, t_end, arrivals=None, clock=time.perf_counter, log=Non
         if outstanding:
             nr, nq = server.step()
             steps += 1
-            if log is not None:
-                log(f"step {steps}: {nr} resident, {nq} queued, {clock() - start:.1f} s")
+            if log is not None and clock() - last_log >= 2.0:   # a line every 2 s at most
+                last_log = clock()
+                log(f"step {steps}: {nr} resident, {nq} queued, {last_log - start:.1f} s")
             for r in server.poll():
                 k, t_sub = ids.pop(r["id"])
                 # server clock: t_done - t_submit; driver clock: hand-over delay
