@@ -1154,10 +1154,15 @@ int orc_threads(int set)
  * list, each pair taken from the side of the path cell), L2L down that path,
  * L2P, and P2P over its leaf's partners.  By linearity this is the same
  * arithmetic as orc_tree_eval for those sinks, up to summation order.
- * sinks: active slots; outputs acc (SoA 3 x n_sinks), pot (n_sinks). */
-int orc_tree_eval_sinks(const orc_tree *t, const double *mass_total, const int32_t *active,
-                        const int64_t *sinks, int64_t n_sinks, double *acc, double *pot)
+ * sinks: active slots; outputs acc (SoA 3 x n_sinks), pot (n_sinks), and,
+ * when grad is not NULL, the force gradient (SoA 6 x n_sinks: xx, yy, zz,
+ * xy, xz, yz; Sec. 4.1) as orc_tree_eval_grad forms it: minus the Hessian of
+ * the leaf's local expansion plus -m_j (g I + (dg/dr)/r d d^T) per partner. */
+static int eval_sinks(const orc_tree *t, const double *mass_total, const int32_t *active,
+                      const int64_t *sinks, int64_t n_sinks, double *acc, double *pot,
+                      double *grad)
 {
+    static const int ca[6] = {0, 1, 2, 0, 0, 1}, cb[6] = {0, 1, 2, 1, 2, 2};
     const int64_t n = t->n, NN = t->n_nodes;
     if (n == 0 || n_sinks == 0) return ORC_OK;
     const int p = t->prm.p;
@@ -1310,6 +1315,20 @@ int orc_tree_eval_sinks(const orc_tree *t, const double *mass_total, const int32
             }
         }
         double ax = -g[0], ay = -g[1], az = -g[2], ph = f;
+        double G6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (grad) { /* minus the Hessian: L[k + e_a + e_b] for |k| <= p - 2 */
+            for (int k = 0; k < K; ++k) {
+                const int *kk = mi->k[k];
+                if (kk[0] + kk[1] + kk[2] > p - 2) continue;
+                double mono = mono_over_fact(mi, u, k);
+                for (int c6 = 0; c6 < 6; ++c6) {
+                    int e[3] = {kk[0], kk[1], kk[2]};
+                    e[ca[c6]] += 1;
+                    e[cb[c6]] += 1;
+                    G6[c6] -= mono * L[mi->idx[e[0]][e[1]][e[2]]];
+                }
+            }
+        }
         for (int64_t q = pdeg[c]; q < pdeg[c + 1]; ++q) {
             const orc_node *B = &t->nodes[padj[q]];
             for (int64_t j = B->begin; j < B->end; ++j) {
@@ -1323,8 +1342,16 @@ int orc_tree_eval_sinks(const orc_tree *t, const double *mass_total, const int32
                 ay += m[j] * gg * dy;
                 az += m[j] * gg * dz;
                 ph += m[j] * phi;
+                if (grad) {
+                    double h = pair_dg_over_r(t->prm.kernel, t->prm.eps, r);
+                    double dv[3] = {dx, dy, dz};
+                    for (int c6 = 0; c6 < 6; ++c6)
+                        G6[c6] += m[j] * (-h * dv[ca[c6]] * dv[cb[c6]] - (ca[c6] == cb[c6] ? gg : 0.0));
+                }
             }
         }
+        if (grad)
+            for (int c6 = 0; c6 < 6; ++c6) grad[c6 * n_sinks + s] = G6[c6];
         acc[s] = ax;
         acc[n_sinks + s] = ay;
         acc[2 * n_sinks + s] = az;
@@ -1333,6 +1360,20 @@ int orc_tree_eval_sinks(const orc_tree *t, const double *mass_total, const int32
     free(mi); free(M); free(m); free(inv); free(parent); free(deg); free(adj);
     free(pdeg); free(padj); free(D); free(Lpath);
     return ORC_OK;
+}
+
+int orc_tree_eval_sinks(const orc_tree *t, const double *mass_total, const int32_t *active,
+                        const int64_t *sinks, int64_t n_sinks, double *acc, double *pot)
+{
+    return eval_sinks(t, mass_total, active, sinks, n_sinks, acc, pot, NULL);
+}
+
+int orc_tree_eval_sinks_grad(const orc_tree *t, const double *mass_total, const int32_t *active,
+                             const int64_t *sinks, int64_t n_sinks, double *acc, double *pot,
+                             double *grad)
+{
+    if (!grad) return ORC_EINVAL;
+    return eval_sinks(t, mass_total, active, sinks, n_sinks, acc, pot, grad);
 }
 
 /* One complete FMM force evaluation: acceleration (SoA 3 x n_active) and

@@ -67,6 +67,8 @@ def lib():
         L.orc_threads.restype = ctypes.c_int
         L.orc_tree_eval_sinks.argtypes = [ctypes.c_void_p, dp, ctypes.c_void_p, ctypes.c_void_p,
                                           i64, dp, dp]
+        L.orc_tree_eval_sinks_grad.argtypes = [ctypes.c_void_p, dp, ctypes.c_void_p,
+                                               ctypes.c_void_p, i64, dp, dp, dp]
         L.orc_direct.argtypes = [dp, dp, i64, ctypes.c_void_p, i64, ctypes.c_int,
                                  ctypes.c_double, dp, dp]
         L.orc_derivs_export.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp,
@@ -257,6 +259,19 @@ class Tree:
                                        len(sinks), _dp(acc), _dp(pot))
         assert rc == 0
         return acc, pot
+
+    def evaluate_sinks_grad(self, mass, sinks):
+        """evaluate_sinks plus the force gradient of those sinks, SoA (6, n)
+        as evaluate_grad orders it (Sec. 4.1)."""
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        sinks = np.ascontiguousarray(sinks, dtype=np.int64)
+        acc = np.zeros((3, len(sinks)))
+        pot = np.zeros(len(sinks))
+        grad = np.zeros((6, len(sinks)))
+        rc = lib().orc_tree_eval_sinks_grad(self._h, _dp(mass), _vp(self.active), _vp(sinks),
+                                            len(sinks), _dp(acc), _dp(pot), _dp(grad))
+        assert rc == 0
+        return acc, pot, grad
 
 
 def threads(n=0):

@@ -8,7 +8,10 @@ in, and at the leaf sizes and softening lengths no other parity case reaches.
   potentials within 1e-12 of the oracle on 256 seeded sinks plus every
   particle of two leaves holding more than 64 (the P2P kernel takes a leaf's
   sinks 64 at a time, so those leaves run its second pass); mixed precision
-  within 2e-6 rms on the same sinks;
+  within 2e-6 rms on the same sinks; the force gradient (fmm_forces_grad, the
+  input of the fourth-order integrator of Sec. 4.1) on the same sinks against
+  the oracle's per-sink gradient, FP64 within 1e-10 and mixed within 1e-5 rms
+  of each tensor's size, its forces equal to those of fmm_forces bit for bit;
 * a 20,000-particle sphere at leaf 128, compared element by element with the
   oracle FMM in both kernels and both precisions (every leaf of 65..128
   particles included);
@@ -68,8 +71,8 @@ def headline(request, oracle):
     in_big = np.concatenate([ref["perm"][ref["begin"][c]:ref["end"][c]] for c in pick])
     rnd = np.random.default_rng(77).choice(N, 256, replace=False)
     sinks = np.unique(np.concatenate([rnd, in_big]))
-    ra, rp = t.evaluate_sinks(m, sinks)
-    return leaf, pos, m, t, ref, sinks, ra, rp
+    ra, rp, rg = t.evaluate_sinks_grad(m, sinks)
+    return leaf, pos, m, t, ref, sinks, ra, rp, rg
 
 
 def test_headline_tree_and_lists_bit_exact(headline):
@@ -84,7 +87,7 @@ def test_headline_tree_and_lists_bit_exact(headline):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_headline_forces(headline, precision):
-    leaf, pos, m, t, ref, sinks, ra, rp = headline
+    leaf, pos, m, t, ref, sinks, ra, rp, _ = headline
     a, pt, _, _ = _solve(pos, m, p=6, theta=0.5, eps=EPS, leaf=leaf, kernel=0,
                          precision=precision)
     e = _rel(a[:, sinks], ra)
@@ -94,6 +97,27 @@ def test_headline_forces(headline, precision):
     else:
         assert np.sqrt((e * e).mean()) < 2e-6 and np.sqrt((ep * ep).mean()) < 2e-6, (
             np.sqrt((e * e).mean()), np.sqrt((ep * ep).mean()))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_headline_force_gradient(headline, precision):
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    leaf, pos, m, t, ref, sinks, ra, rp, rg = headline
+    s = F.Solver(N, p_max=6, leaf_size=leaf, kernel=0, precision=precision)
+    tp = torch.from_numpy(pos).cuda()
+    tm = torch.from_numpy(m).cuda()
+    a, pt, g = s.forces_grad(tp, tm, eps=EPS, theta=0.5, p=6)
+    a2, pt2 = s.forces(tp, tm, eps=EPS, theta=0.5, p=6)
+    torch.cuda.synchronize()
+    assert torch.equal(a, a2) and torch.equal(pt, pt2)
+    g = g.cpu().numpy()[:, sinks]
+    s.close()
+    e = np.sqrt(((g - rg) ** 2).sum(axis=0)) / np.sqrt((rg * rg).sum(axis=0))
+    if precision == 0:
+        assert e.max() < 1e-10, e.max()
+    else:
+        assert np.sqrt((e * e).mean()) < 1e-5, (np.sqrt((e * e).mean()), e.max())
 
 
 @pytest.mark.parametrize("kernel", [0, 1])

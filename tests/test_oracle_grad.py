@@ -100,3 +100,21 @@ def test_converges_in_p(oracle):
         errs.append(np.sqrt(((g - ref) ** 2).sum() / (ref ** 2).sum()))
     assert all(b < a for a, b in zip(errs, errs[1:])), errs
     assert errs[-1] < 1e-3, errs
+
+
+def test_sampled_sinks_equal_full_evaluation(oracle):
+    """The per-sink evaluation (path M2L/L2L, the leaf's partners) gives the
+    force gradient of the full evaluation, and the same forces as the plain
+    per-sink call; a dropped Hessian term or a wrong pair sign fails it."""
+    for kernel, eps in ((oracle.WENDLAND, 0.05), (oracle.PLUMMER, 0.01)):
+        pos, _, m = W.uniform_sphere(3000, seed=44)
+        m = m * np.random.default_rng(45).uniform(0.5, 1.5, m.size)
+        t = oracle.Tree(pos, None, p=5, theta=0.5, eps=eps, leaf_size=24, kernel=kernel)
+        _, _, full = t.evaluate_grad(m)
+        sinks = np.random.default_rng(46).choice(m.size, 200, replace=False)
+        a, pt, g = t.evaluate_sinks_grad(m, sinks)
+        a2, pt2 = t.evaluate_sinks(m, sinks)
+        assert np.array_equal(a, a2) and np.array_equal(pt, pt2)
+        ref = full[:, sinks]
+        scale = np.sqrt((ref * ref).sum(axis=0))
+        assert (np.sqrt(((g - ref) ** 2).sum(axis=0)) / scale).max() < 1e-12
