@@ -52,35 +52,42 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_fast_flags(const int32_t *__restr
 }
 
 // stable partition of sys into slow and fast lists (+ positions within sys);
-// pre = exclusive scan of the fast flags; count[0] = number of fast
+// pre = exclusive scan of the fast flags; count[0] = number of fast; per
+// position i of sys, fflag[i] = 1 when fast and sflag[i] = 1 when slow (the
+// sink flags of the two kicks of a KDK half)
 __global__ __launch_bounds__(FMM_BLOCK) void k_split_scatter(
     const int32_t *__restrict__ sys, int n_sys, const int32_t *__restrict__ rung, int k,
     const uint32_t *__restrict__ pre, int32_t *__restrict__ slow, int32_t *__restrict__ slow_pos,
-    int32_t *__restrict__ fast, int32_t *__restrict__ fast_pos, int32_t *__restrict__ count) {
+    int32_t *__restrict__ fast, int32_t *__restrict__ fast_pos, int32_t *__restrict__ count,
+    uint8_t *__restrict__ fflag, uint8_t *__restrict__ sflag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_sys) return;
   int p = sys[i];
   int f = (int)pre[i];
-  if (rung[p] > k) {
+  const bool is_fast = rung[p] > k;
+  if (is_fast) {
     fast[f] = p;
     fast_pos[f] = i;
   } else {
     slow[i - f] = p;
     slow_pos[i - f] = i;
   }
-  if (i == n_sys - 1) count[0] = f + (rung[p] > k ? 1 : 0);
+  fflag[i] = is_fast ? 1 : 0;
+  sflag[i] = is_fast ? 0 : 1;
+  if (i == n_sys - 1) count[0] = f + (is_fast ? 1 : 0);
 }
 
-__global__ __launch_bounds__(FMM_BLOCK) void k_copy_f64(const double *__restrict__ a,
-                                                        double *__restrict__ b, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i];
-}
-
-__global__ __launch_bounds__(FMM_BLOCK) void k_zero_at(const int32_t *__restrict__ idx, int n,
-                                                       double *__restrict__ v) {
+// out[p] = mass[p] for the slow particles of the joint set sys, 0 for the
+// fast ones (fflag per position of sys)
+__global__ __launch_bounds__(FMM_BLOCK) void k_masked_mass(const int32_t *__restrict__ sys,
+                                                           int n_sys,
+                                                           const uint8_t *__restrict__ fflag,
+                                                           const double *__restrict__ mass,
+                                                           double *__restrict__ out) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[idx[i]] = 0.0;
+  if (i >= n_sys) return;
+  const int p = sys[i];
+  out[p] = fflag[i] ? 0.0 : mass[p];
 }
 
 // v[p] += a[q] dt for p = set[i], q = setpos[i]; on a second kick also |a|
@@ -168,13 +175,6 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_rung_kick(const double *__restric
   vel[n + i] = vy;
   vel[2 * n + i] = vz;
   if (amag) amag[i] = sqrt(ax * ax + ay * ay + az * az);
-}
-
-// flag[setpos[i]] = 1 (the flags were cleared first)
-__global__ __launch_bounds__(FMM_BLOCK) void k_set_flags(const int32_t *__restrict__ setpos,
-                                                         int n_set, uint8_t *__restrict__ flag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_set) flag[setpos[i]] = 1;
 }
 
 // flag[i] = 1 for the particles whose step ends at the tick (rung >= rmin)
@@ -299,19 +299,20 @@ void hhs_launch_norm_at(const int32_t *sys, int n_sys, const double *acc, double
 
 void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
                       uint32_t *scan_part, int32_t *slow, int32_t *slow_pos, int32_t *fast,
-                      int32_t *fast_pos, int32_t *count, hipStream_t s) {
+                      int32_t *fast_pos, int32_t *count, uint8_t *fflag, uint8_t *sflag,
+                      hipStream_t s) {
   if (n_sys <= 0) return;
   hipLaunchKernelGGL(k_fast_flags, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, rung, k, flag);
   hhs_launch_scan_u32(flag, n_sys, scan_part, s);
   hipLaunchKernelGGL(k_split_scatter, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, rung, k, flag,
-                     slow, slow_pos, fast, fast_pos, count);
+                     slow, slow_pos, fast, fast_pos, count, fflag, sflag);
 }
 
-void hhs_launch_masked_mass(const double *mass, int64_t n, const int32_t *fast, int n_fast,
-                            double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy_f64, NB(n), dim3(FMM_BLOCK), 0, s, mass, out, n);
-  if (n_fast > 0)
-    hipLaunchKernelGGL(k_zero_at, NB(n_fast), dim3(FMM_BLOCK), 0, s, fast, n_fast, out);
+void hhs_launch_masked_mass(const int32_t *sys, int n_sys, const uint8_t *fflag,
+                            const double *mass, double *out, hipStream_t s) {
+  if (n_sys > 0)
+    hipLaunchKernelGGL(k_masked_mass, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, fflag, mass,
+                       out);
 }
 
 void hhs_launch_kick(const int32_t *set, const int32_t *setpos, int n_set, const double *acc,
@@ -346,14 +347,6 @@ void trad_launch_kick(const double *acc, const int32_t *rung, int64_t n, double 
   if (n > 0)
     hipLaunchKernelGGL(k_rung_kick, NB(n), dim3(FMM_BLOCK), 0, s, acc, rung, n, dt_top, rmin,
                        twice, vel, amag);
-}
-
-void hhs_launch_sink_flags(const int32_t *setpos, int n_set, int n_sys, uint8_t *flag,
-                           hipStream_t s) {
-  if (n_sys <= 0) return;
-  hipMemsetAsync(flag, 0, (size_t)n_sys, s);
-  if (n_set > 0)
-    hipLaunchKernelGGL(k_set_flags, NB(n_set), dim3(FMM_BLOCK), 0, s, setpos, n_set, flag);
 }
 
 void trad_launch_flags(const int32_t *rung, int64_t n, int rmin, uint8_t *flag, hipStream_t s) {

@@ -37,6 +37,7 @@ struct hhs_run {
   uint32_t *flag, *scan_part;
   uint8_t *sinks;  // sink flags of one evaluation over the joint set
   std::vector<int32_t *> slow, slow_pos, fast, fast_pos;  // per rung
+  std::vector<uint8_t *> fflag, sflag;  // per rung: fast / slow flags by joint-set position
   double *mmask, *acc, *pot;
 };
 
@@ -56,6 +57,8 @@ static int64_t run_layout(hhs_run *r, char *base, int64_t n, int levels) {
   q->slow_pos.resize(levels);
   q->fast.resize(levels);
   q->fast_pos.resize(levels);
+  q->fflag.resize(levels);
+  q->sflag.resize(levels);
   take(&q->all_idx, n);
   take(&q->flag, n);
   take(&q->sinks, n);
@@ -68,6 +71,8 @@ static int64_t run_layout(hhs_run *r, char *base, int64_t n, int levels) {
     take(&q->slow_pos[l], n);
     take(&q->fast[l], n);
     take(&q->fast_pos[l], n);
+    take(&q->fflag[l], n);
+    take(&q->sflag[l], n);
   }
   return (off + 255) & ~(int64_t)255;
 }
@@ -210,7 +215,7 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp) {
         }
         hhs_launch_split(f.sys, f.n_sys, st->rung, k, r->flag, r->scan_part, r->slow[k],
                          r->slow_pos[k], r->fast[k], r->fast_pos[k], c->split_cnt + slot,
-                         c->stream);
+                         r->fflag[k], r->sflag[k], c->stream);
         f.pc = 1;
         S.state = S_WAIT_SPLIT;
         return true;
@@ -292,7 +297,7 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
       any = true;
       const Kick &K = kk[2 * w + slot];
       if (K.s2f) {
-        hhs_launch_masked_mass(S.st->mass, S.st->n, S.run->fast[f.k], f.n_fast, S.run->mmask,
+        hhs_launch_masked_mass(f.sys, f.n_sys, S.run->fflag[f.k], S.st->mass, S.run->mmask,
                                c->stream);
         q[w].mass = S.run->mmask;
       } else {
@@ -301,12 +306,8 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
       const int n_set = K.s2f ? f.n_fast : f.n_slow;
       const bool all = n_set == f.n_sys ||
                        (!K.s2f && K.second && f.k == 0 && hp->eta1 > 0 && S.st->a_tot);
-      q[w].sinks = nullptr;
-      if (!all) {
-        hhs_launch_sink_flags(K.s2f ? S.run->fast_pos[f.k] : S.run->slow_pos[f.k], n_set,
-                              f.n_sys, S.run->sinks, c->stream);
-        q[w].sinks = S.run->sinks;
-      }
+      // the kicked set's flags by joint-set position, written by the split
+      q[w].sinks = all ? nullptr : K.s2f ? S.run->fflag[f.k] : S.run->sflag[f.k];
     }
     if (!any) continue;
     e = fmm_evaluate_batched(c, W, q.data(), hp->p);

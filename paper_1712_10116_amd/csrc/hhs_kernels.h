@@ -12,11 +12,15 @@ void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const 
 // out[sys[q]] = |a| of row q of acc (SoA, n_sys rows)
 void hhs_launch_norm_at(const int32_t *sys, int n_sys, const double *acc, double *out,
                         hipStream_t s);
+// stable split of the joint set sys at rung k; fflag / sflag (n_sys bytes):
+// 1 at the positions of its fast / slow particles
 void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
                       uint32_t *scan_part, int32_t *slow, int32_t *slow_pos, int32_t *fast,
-                      int32_t *fast_pos, int32_t *count, hipStream_t s);
-void hhs_launch_masked_mass(const double *mass, int64_t n, const int32_t *fast, int n_fast,
-                            double *out, hipStream_t s);
+                      int32_t *fast_pos, int32_t *count, uint8_t *fflag, uint8_t *sflag,
+                      hipStream_t s);
+// out[sys[i]] = 0 where fflag[i], else mass[sys[i]] (the rest of out untouched)
+void hhs_launch_masked_mass(const int32_t *sys, int n_sys, const uint8_t *fflag,
+                            const double *mass, double *out, hipStream_t s);
 void hhs_launch_kick(const int32_t *set, const int32_t *setpos, int n_set, const double *acc,
                      int64_t n_joint, double *vel, int64_t n, double dt, double *amag,
                      hipStream_t s);
@@ -33,9 +37,6 @@ void trad_launch_kick(const double *acc, const int32_t *rung, int64_t n, double 
                       bool twice, double *vel, double *amag, hipStream_t s);
 void trad_launch_drift(const double *vel, const int32_t *rung, int64_t n, double dt_top, int rmin,
                        double *pos, hipStream_t s);
-// flags over a joint set of n_sys particles: 1 at positions setpos[0..n_set)
-void hhs_launch_sink_flags(const int32_t *setpos, int n_set, int n_sys, uint8_t *flag,
-                           hipStream_t s);
 // flag[i] = rung[i] >= rmin (the sinks of a tick)
 void trad_launch_flags(const int32_t *rung, int64_t n, int rmin, uint8_t *flag, hipStream_t s);
 // out[0] = min_i (a[i] + b[i]) over n >= 1 values; part holds
