@@ -10,16 +10,10 @@
 // rung = smallest k with dt_top 2^-k <= sqrt(eta eps / a), a = |a_old| + |a_cur|,
 // decided as (dt_k dt_k) a <= eta eps (no square root), clamped to L-1; with
 // a_tot (Eq. 9) the rung must also satisfy (dt_k dt_k) |a|_tot <= eta1 eps
-__global__ __launch_bounds__(FMM_BLOCK) void k_rungs(const int32_t *__restrict__ sys, int n_sys,
-                                                     const double *__restrict__ a_old,
-                                                     const double *__restrict__ a_cur,
-                                                     const double *__restrict__ a_tot,
-                                                     int32_t *__restrict__ rung, double dt_top,
-                                                     double eta_eps, double eta1_eps,
-                                                     int max_levels) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_sys) return;
-  int p = sys[i];
+__device__ __forceinline__ int rung_of(int p, const double *__restrict__ a_old,
+                                       const double *__restrict__ a_cur,
+                                       const double *__restrict__ a_tot, double dt_top,
+                                       double eta_eps, double eta1_eps, int max_levels) {
   double a = a_old[p] + a_cur[p];
   const double at = a_tot ? a_tot[p] : 0.0;
   int r = max_levels - 1;
@@ -29,7 +23,20 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_rungs(const int32_t *__restrict__
     if (a_tot) ok = ok && (dtk * dtk) * at <= eta1_eps;
     if (ok) r = k;
   }
-  rung[p] = r;
+  return r;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_rungs(const int32_t *__restrict__ sys, int n_sys,
+                                                     const double *__restrict__ a_old,
+                                                     const double *__restrict__ a_cur,
+                                                     const double *__restrict__ a_tot,
+                                                     int32_t *__restrict__ rung, double dt_top,
+                                                     double eta_eps, double eta1_eps,
+                                                     int max_levels) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_sys) return;
+  const int p = sys[i];
+  rung[p] = rung_of(p, a_old, a_cur, a_tot, dt_top, eta_eps, eta1_eps, max_levels);
 }
 
 // out[sys[q]] = |a| of row q of a joint-set acceleration (SoA, n_sys rows)
@@ -281,6 +288,100 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_invariants(const double *__restri
 }
 
 // ---------------------------------------------------------------------------
+// The per-system kernels of many systems in one launch.  The arguments of at
+// most HHS_BATCH systems travel by value in the kernel's argument block.
+// Kicks and drifts: block b serves item w with blk0[w] <= b < blk0[w + 1]
+// (running counts of each item's blocks of FMM_BLOCK elements), so a block
+// stays inside one system's range.  Rungs and split: one workgroup per
+// system, which walks its joint set in tiles of SPLIT_THREADS.
+
+__device__ __forceinline__ int batch_item(const int *blk0, int count, int b) {
+  int w = 0;
+  while (w + 1 < count && blk0[w + 1] <= b) ++w;
+  return w;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_kick_batched(HhsKickBatch B) {
+  const int w = batch_item(B.blk0, B.count, blockIdx.x);
+  const HhsKickItem &K = B.it[w];
+  const int i = (blockIdx.x - B.blk0[w]) * FMM_BLOCK + threadIdx.x;
+  if (i >= K.n_set) return;
+  const int p = K.set[i], q = K.setpos[i];
+  const int64_t nj = K.n_joint, n = K.n;
+  const double ax = K.acc[q], ay = K.acc[nj + q], az = K.acc[2 * nj + q];
+  K.vel[p] += ax * K.dt;
+  K.vel[n + p] += ay * K.dt;
+  K.vel[2 * n + p] += az * K.dt;
+  if (K.amag) K.amag[p] = sqrt(ax * ax + ay * ay + az * az);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_drift_batched(HhsDriftBatch B) {
+  const int w = batch_item(B.blk0, B.count, blockIdx.x);
+  const HhsDriftItem &D = B.it[w];
+  const int i = (blockIdx.x - B.blk0[w]) * FMM_BLOCK + threadIdx.x;
+  if (i >= D.n_set) return;
+  const int p = D.set[i];
+  const int64_t n = D.n;
+  D.pos[p] += D.vel[p] * D.dt;
+  D.pos[n + p] += D.vel[n + p] * D.dt;
+  D.pos[2 * n + p] += D.vel[2 * n + p] * D.dt;
+}
+
+// Rungs (when asked) and the stable slow/fast split of one joint set per
+// workgroup: per tile, each thread's fast flag, the tile's exclusive scan
+// (wave ballots, then the waves' totals), and the scatter with the fast count
+// of the earlier tiles carried along.  The same outputs as hhs_launch_rungs
+// followed by hhs_launch_split.
+#define SPLIT_THREADS 1024
+__global__ __launch_bounds__(SPLIT_THREADS) void k_split_batched(HhsSplitBatch B) {
+  __shared__ int wtot[SPLIT_THREADS / 64];
+  const HhsSplitItem &S = B.it[blockIdx.x];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int carry = 0;
+  for (int base = 0; base < S.n_sys; base += SPLIT_THREADS) {
+    const int i = base + tid;
+    const bool valid = i < S.n_sys;
+    int p = 0;
+    bool fast = false;
+    if (valid) {
+      p = S.sys[i];
+      int r;
+      if (S.do_rungs) {
+        r = rung_of(p, S.a_old, S.a_cur, S.a_tot, S.dt_top, S.eta_eps, S.eta1_eps,
+                    S.max_levels);
+        S.rung[p] = r;
+      } else {
+        r = S.rung[p];
+      }
+      fast = r > S.k;
+    }
+    const unsigned long long bal = __ballot(fast);
+    if (lane == 0) wtot[w] = __popcll(bal);
+    __syncthreads();
+    int before = carry, total = 0;
+    for (int v = 0; v < SPLIT_THREADS / 64; ++v) {
+      before += v < w ? wtot[v] : 0;
+      total += wtot[v];
+    }
+    if (valid) {
+      const int f = before + __popcll(bal & below);  // fast ones before element i
+      if (fast) {
+        S.fast[f] = p;
+        S.fast_pos[f] = i;
+      } else {
+        S.slow[i - f] = p;
+        S.slow_pos[i - f] = i;
+      }
+      S.fflag[i] = fast ? 1 : 0;
+      S.sflag[i] = fast ? 0 : 1;
+    }
+    carry += total;
+    __syncthreads();  // wtot is rewritten by the next tile
+  }
+  if (tid == 0) S.count[0] = carry;
+}
+
 #define NB(n) dim3((unsigned)(((n) + FMM_BLOCK - 1) / FMM_BLOCK))
 
 void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const double *a_cur,
@@ -373,4 +474,56 @@ void launch_invariants(const double *pos, const double *vel, const double *mass,
                        hipStream_t s) {
   hipLaunchKernelGGL(k_invariants, dim3(nblk), dim3(FMM_BLOCK), 0, s, pos, vel, mass, acc, pot, n,
                      part);
+}
+
+void hhs_launch_kicks(const HhsKickItem *items, int n_items, hipStream_t s) {
+  HhsKickBatch B;
+  B.count = 0;
+  B.blk0[0] = 0;
+  auto flush = [&]() {
+    if (B.count > 0)
+      hipLaunchKernelGGL(k_kick_batched, dim3(B.blk0[B.count]), dim3(FMM_BLOCK), 0, s, B);
+    B.count = 0;
+  };
+  for (int j = 0; j < n_items; ++j) {
+    if (items[j].n_set <= 0) continue;
+    B.it[B.count] = items[j];
+    B.blk0[B.count + 1] = B.blk0[B.count] + (items[j].n_set + FMM_BLOCK - 1) / FMM_BLOCK;
+    if (++B.count == HHS_BATCH) flush();
+  }
+  flush();
+}
+
+void hhs_launch_drifts(const HhsDriftItem *items, int n_items, hipStream_t s) {
+  HhsDriftBatch B;
+  B.count = 0;
+  B.blk0[0] = 0;
+  auto flush = [&]() {
+    if (B.count > 0)
+      hipLaunchKernelGGL(k_drift_batched, dim3(B.blk0[B.count]), dim3(FMM_BLOCK), 0, s, B);
+    B.count = 0;
+  };
+  for (int j = 0; j < n_items; ++j) {
+    if (items[j].n_set <= 0) continue;
+    B.it[B.count] = items[j];
+    B.blk0[B.count + 1] = B.blk0[B.count] + (items[j].n_set + FMM_BLOCK - 1) / FMM_BLOCK;
+    if (++B.count == HHS_BATCH) flush();
+  }
+  flush();
+}
+
+void hhs_launch_splits(const HhsSplitItem *items, int n_items, hipStream_t s) {
+  HhsSplitBatch B;
+  B.count = 0;
+  auto flush = [&]() {
+    if (B.count > 0)
+      hipLaunchKernelGGL(k_split_batched, dim3(B.count), dim3(SPLIT_THREADS), 0, s, B);
+    B.count = 0;
+  };
+  for (int j = 0; j < n_items; ++j) {
+    if (items[j].n_sys <= 0) continue;
+    B.it[B.count] = items[j];
+    if (++B.count == HHS_BATCH) flush();
+  }
+  flush();
 }

@@ -185,8 +185,17 @@ int kicks_of_half(const Frame &f, int half, Kick out[2]) {
 }
 
 // Runs system S until it waits on the device or finishes; false when the
-// rung recursion would go deeper than the scratch holds.
-bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp) {
+// rung recursion would go deeper than the scratch holds.  The rung
+// assignment + split and the drift it reaches are appended to splits and
+// drifts, which the caller launches (batched over systems) before anything
+// else is queued for S.
+struct SplitReq {
+  HhsSplitItem it;
+  hhs_run *run;  // its scan scratch, for the multi-workgroup split
+};
+
+bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, std::vector<SplitReq> &splits,
+             std::vector<HhsDriftItem> &drifts) {
   const int slot = S.slot;
   hhs_run *r = S.run;
   hhs_state *st = S.st;
@@ -199,8 +208,21 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp) {
     const int k = f.k;
     if (k >= r->levels) return false;
     switch (f.pc) {
-      case 0:  // (re)assign rungs, split into slow {rung <= k} and fast {rung > k}
-        if (f.calc && !hp->freeze_rungs) {
+      case 0: {  // (re)assign rungs, split into slow {rung <= k} and fast {rung > k}
+        HhsSplitItem it{};
+        it.sys = f.sys;
+        it.n_sys = f.n_sys;
+        it.rung = st->rung;
+        it.k = k;
+        it.slow = r->slow[k];
+        it.slow_pos = r->slow_pos[k];
+        it.fast = r->fast[k];
+        it.fast_pos = r->fast_pos[k];
+        it.count = c->split_cnt + slot;
+        it.fflag = r->fflag[k];
+        it.sflag = r->sflag[k];
+        it.do_rungs = f.calc && !hp->freeze_rungs;
+        if (it.do_rungs) {
           // comoving form: a rung's step in ln a is compared in physical
           // time, d(ln a) / H at the start of the subsystem's step
           double h2 = 1.0;
@@ -208,17 +230,19 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp) {
             const double H = cosmo_hubble(hp->cosmo, exp(f.t0));
             h2 = H * H;
           }
-          hhs_launch_rungs(f.sys, f.n_sys, st->a_old, st->a_cur,
-                           hp->eta1 > 0 ? st->a_tot : nullptr, st->rung, S.dt_top,
-                           (hp->eta * hp->eps) * h2, (hp->eta1 * hp->eps) * h2, hp->max_levels,
-                           c->stream);
+          it.a_old = st->a_old;
+          it.a_cur = st->a_cur;
+          it.a_tot = hp->eta1 > 0 ? st->a_tot : nullptr;
+          it.dt_top = S.dt_top;
+          it.eta_eps = (hp->eta * hp->eps) * h2;
+          it.eta1_eps = (hp->eta1 * hp->eps) * h2;
+          it.max_levels = hp->max_levels;
         }
-        hhs_launch_split(f.sys, f.n_sys, st->rung, k, r->flag, r->scan_part, r->slow[k],
-                         r->slow_pos[k], r->fast[k], r->fast_pos[k], c->split_cnt + slot,
-                         r->fflag[k], r->sflag[k], c->stream);
+        splits.push_back(SplitReq{it, r});
         f.pc = 1;
         S.state = S_WAIT_SPLIT;
         return true;
+      }
       case 1: {  // first half of the fast system's evolution
         f.pc = 2;
         if (f.n_fast > 0) {
@@ -241,7 +265,8 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp) {
           S.range_err = true;
           return false;
         }
-        hhs_launch_drift(r->slow[k], f.n_slow, st->vel, st->pos, st->n, fd, c->stream);
+        if (f.n_slow > 0)
+          drifts.push_back(HhsDriftItem{r->slow[k], st->vel, st->pos, st->n, fd, f.n_slow});
         f.pc = 4;
         if ((f.n_fast > 0 && f.n_slow > 0) || f.n_slow > 0) {
           S.half = 1;
@@ -312,6 +337,8 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
     if (!any) continue;
     e = fmm_evaluate_batched(c, W, q.data(), hp->p);
     if (e != FMM_OK) return e;
+    std::vector<HhsKickItem> kick_items;
+    std::vector<int> norms;  // systems whose solve also gives |a|_tot
     for (int w = 0; w < W; ++w) {
       if (slot >= nk[w]) continue;
       Sys &S = *sys[grp[w]];
@@ -323,18 +350,26 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
       if (!step_factor(hp, S.half ? f.t0 + 0.5 * f.dt : f.t0, 0.5 * f.dt, true, &fk))
         return fmm_fail(c, FMM_EINVAL, "scale factor outside the cosmology table");
       if (K.s2f)
-        hhs_launch_kick(S.run->fast[k], S.run->fast_pos[k], f.n_fast, S.run->acc, f.n_sys,
-                        S.st->vel, S.st->n, fk, K.second ? S.st->a_old : nullptr, c->stream);
+        kick_items.push_back(HhsKickItem{S.run->fast[k], S.run->fast_pos[k], S.run->acc,
+                                         S.st->vel, K.second ? S.st->a_old : nullptr, f.n_sys,
+                                         S.st->n, fk, f.n_fast});
       else
-        hhs_launch_kick(S.run->slow[k], S.run->slow_pos[k], f.n_slow, S.run->acc, f.n_sys,
-                        S.st->vel, S.st->n, fk, K.second ? S.st->a_cur : nullptr, c->stream);
+        kick_items.push_back(HhsKickItem{S.run->slow[k], S.run->slow_pos[k], S.run->acc,
+                                         S.st->vel, K.second ? S.st->a_cur : nullptr, f.n_sys,
+                                         S.st->n, fk, f.n_slow});
       // Eq. 9: the second kickFS2S of a top-level KDK sees every particle as a
       // sink, so its solve gives |a|_tot for the whole system
-      if (!K.s2f && K.second && k == 0 && hp->eta1 > 0 && S.st->a_tot)
-        hhs_launch_norm_at(f.sys, f.n_sys, S.run->acc, S.st->a_tot, c->stream);
+      if (!K.s2f && K.second && k == 0 && hp->eta1 > 0 && S.st->a_tot) norms.push_back(w);
       ++*kicks;
       ++S.kicks;
       S.parts += f.n_sys;
+    }
+    // the slot's kicks (and |a|_tot) read acc before the next slot rewrites it
+    hhs_launch_kicks(kick_items.data(), (int)kick_items.size(), c->stream);
+    for (int w : norms) {
+      Sys &S = *sys[grp[w]];
+      const Frame &f = S.stack.back();
+      hhs_launch_norm_at(f.sys, f.n_sys, S.run->acc, S.st->a_tot, c->stream);
     }
   }
   return FMM_OK;
@@ -451,12 +486,32 @@ fmm_status hhs_sys_advance(fmm_ctx *c, HhsSys *const *sys, int n_sys, const hhs_
   for (int i = 0; i < n_sys; ++i) ns = std::max(ns, sys[i]->slot + 1);
   fmm_status e = ensure_split_slots(c, ns);
   if (e != FMM_OK) return e;
+  std::vector<SplitReq> splits;
+  std::vector<HhsSplitItem> small;
+  std::vector<HhsDriftItem> drifts;
   for (int i = 0; i < n_sys; ++i)
-    if (sys[i]->state == S_RUN && !advance(c, *sys[i], hp))
+    if (sys[i]->state == S_RUN && !advance(c, *sys[i], hp, splits, drifts))
       return fmm_fail(c, FMM_EINVAL,
                       sys[i]->range_err ? "system %d: scale factor outside the cosmology table"
                                         : "system %d: rung recursion deeper than max_levels",
                       i);
+  // a system reaches at most one drift or split per round, and they touch
+  // different arrays: the drifts first, then the splits (one workgroup per
+  // joint set up to HHS_SPLIT_MAX_N, the multi-workgroup kernels beyond)
+  hhs_launch_drifts(drifts.data(), (int)drifts.size(), c->stream);
+  for (const SplitReq &q : splits) {
+    const HhsSplitItem &it = q.it;
+    if (it.n_sys <= HHS_SPLIT_MAX_N) {
+      small.push_back(it);
+      continue;
+    }
+    if (it.do_rungs)
+      hhs_launch_rungs(it.sys, it.n_sys, it.a_old, it.a_cur, it.a_tot, it.rung, it.dt_top,
+                       it.eta_eps, it.eta1_eps, it.max_levels, c->stream);
+    hhs_launch_split(it.sys, it.n_sys, it.rung, it.k, q.run->flag, q.run->scan_part, it.slow,
+                     it.slow_pos, it.fast, it.fast_pos, it.count, it.fflag, it.sflag, c->stream);
+  }
+  hhs_launch_splits(small.data(), (int)small.size(), c->stream);
   return FMM_OK;
 }
 

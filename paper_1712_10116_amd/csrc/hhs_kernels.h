@@ -49,3 +49,54 @@ void hhs_launch_min_sum(const double *a, const double *b, int64_t n, double *par
 void launch_invariants(const double *pos, const double *vel, const double *mass,
                        const double *acc, const double *pot, int64_t n, double *part, int nblk,
                        hipStream_t s);
+
+// Batched launches: the kicks, drifts or rung assignments + splits of many
+// systems (items with an empty set are skipped), HHS_BATCH systems per launch.
+// A kick item is k_kick's arguments (hhs_launch_kick); a drift item
+// hhs_launch_drift's; a split item those of hhs_launch_rungs (used when
+// do_rungs) and hhs_launch_split for one joint set, whose split runs in one
+// workgroup (meant for sets of at most HHS_SPLIT_MAX_N).
+#define HHS_BATCH 16
+#define HHS_SPLIT_MAX_N 16384
+struct HhsKickItem {
+  const int32_t *set, *setpos;
+  const double *acc;
+  double *vel, *amag;
+  int64_t n_joint, n;
+  double dt;
+  int n_set;
+};
+struct HhsDriftItem {
+  const int32_t *set;
+  const double *vel;
+  double *pos;
+  int64_t n;
+  double dt;
+  int n_set;
+};
+struct HhsSplitItem {
+  const int32_t *sys;
+  int32_t *rung;
+  const double *a_old, *a_cur, *a_tot;
+  int32_t *slow, *slow_pos, *fast, *fast_pos, *count;
+  uint8_t *fflag, *sflag;
+  double dt_top, eta_eps, eta1_eps;
+  int n_sys, k, max_levels, do_rungs;
+};
+struct HhsKickBatch {
+  HhsKickItem it[HHS_BATCH];
+  int blk0[HHS_BATCH + 1];
+  int count;
+};
+struct HhsDriftBatch {
+  HhsDriftItem it[HHS_BATCH];
+  int blk0[HHS_BATCH + 1];
+  int count;
+};
+struct HhsSplitBatch {
+  HhsSplitItem it[HHS_BATCH];
+  int count;
+};
+void hhs_launch_kicks(const HhsKickItem *items, int n_items, hipStream_t s);
+void hhs_launch_drifts(const HhsDriftItem *items, int n_items, hipStream_t s);
+void hhs_launch_splits(const HhsSplitItem *items, int n_items, hipStream_t s);
