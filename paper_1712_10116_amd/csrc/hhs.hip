@@ -97,34 +97,6 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_masked_mass(const int32_t *__rest
   out[p] = fflag[i] ? 0.0 : mass[p];
 }
 
-// v[p] += a[q] dt for p = set[i], q = setpos[i]; on a second kick also |a|
-__global__ __launch_bounds__(FMM_BLOCK) void k_kick(const int32_t *__restrict__ set,
-                                                    const int32_t *__restrict__ setpos, int n_set,
-                                                    const double *__restrict__ acc, int64_t n_joint,
-                                                    double *__restrict__ vel, int64_t n,
-                                                    double dt, double *__restrict__ amag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_set) return;
-  int p = set[i], q = setpos[i];
-  double ax = acc[q], ay = acc[n_joint + q], az = acc[2 * n_joint + q];
-  vel[p] += ax * dt;
-  vel[n + p] += ay * dt;
-  vel[2 * n + p] += az * dt;
-  if (amag) amag[p] = sqrt(ax * ax + ay * ay + az * az);
-}
-
-__global__ __launch_bounds__(FMM_BLOCK) void k_drift(const int32_t *__restrict__ set, int n_set,
-                                                     const double *__restrict__ vel,
-                                                     double *__restrict__ pos, int64_t n,
-                                                     double dt) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_set) return;
-  int p = set[i];
-  pos[p] += vel[p] * dt;
-  pos[n + p] += vel[n + p] * dt;
-  pos[2 * n + p] += vel[2 * n + p] * dt;
-}
-
 __global__ __launch_bounds__(FMM_BLOCK) void k_iota(int32_t *__restrict__ v, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = i;
@@ -414,20 +386,6 @@ void hhs_launch_masked_mass(const int32_t *sys, int n_sys, const uint8_t *fflag,
   if (n_sys > 0)
     hipLaunchKernelGGL(k_masked_mass, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, fflag, mass,
                        out);
-}
-
-void hhs_launch_kick(const int32_t *set, const int32_t *setpos, int n_set, const double *acc,
-                     int64_t n_joint, double *vel, int64_t n, double dt, double *amag,
-                     hipStream_t s) {
-  if (n_set > 0)
-    hipLaunchKernelGGL(k_kick, NB(n_set), dim3(FMM_BLOCK), 0, s, set, setpos, n_set, acc, n_joint,
-                       vel, n, dt, amag);
-}
-
-void hhs_launch_drift(const int32_t *set, int n_set, const double *vel, double *pos, int64_t n,
-                      double dt, hipStream_t s) {
-  if (n_set > 0)
-    hipLaunchKernelGGL(k_drift, NB(n_set), dim3(FMM_BLOCK), 0, s, set, n_set, vel, pos, n, dt);
 }
 
 void hhs_launch_iota(int32_t *v, int n, hipStream_t s) {

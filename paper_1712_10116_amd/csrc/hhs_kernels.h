@@ -21,11 +21,6 @@ void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k,
 // out[sys[i]] = 0 where fflag[i], else mass[sys[i]] (the rest of out untouched)
 void hhs_launch_masked_mass(const int32_t *sys, int n_sys, const uint8_t *fflag,
                             const double *mass, double *out, hipStream_t s);
-void hhs_launch_kick(const int32_t *set, const int32_t *setpos, int n_set, const double *acc,
-                     int64_t n_joint, double *vel, int64_t n, double dt, double *amag,
-                     hipStream_t s);
-void hhs_launch_drift(const int32_t *set, int n_set, const double *vel, double *pos, int64_t n,
-                      double dt, hipStream_t s);
 void hhs_launch_iota(int32_t *v, int n, hipStream_t s);
 void hhs_launch_amag(const double *acc, int64_t n, double *a_cur, double *a_old, hipStream_t s);
 // Individual-timestep integrator: cnt[k] = particles on rung k (32 ints,
@@ -52,10 +47,12 @@ void launch_invariants(const double *pos, const double *vel, const double *mass,
 
 // Batched launches: the kicks, drifts or rung assignments + splits of many
 // systems (items with an empty set are skipped), HHS_BATCH systems per launch.
-// A kick item is k_kick's arguments (hhs_launch_kick); a drift item
-// hhs_launch_drift's; a split item those of hhs_launch_rungs (used when
-// do_rungs) and hhs_launch_split for one joint set, whose split runs in one
-// workgroup (meant for sets of at most HHS_SPLIT_MAX_N).
+// Kick: vel[p] += acc[q] dt for p = set[i], q = setpos[i] (acc SoA with
+// n_joint rows, vel with n), and amag[p] = |acc[q]| when amag is not NULL.
+// Drift: pos[p] += vel[p] dt for p = set[i].  Split: the arguments of
+// hhs_launch_rungs (used when do_rungs) and hhs_launch_split for one joint
+// set, whose split runs in one workgroup (meant for sets of at most
+// HHS_SPLIT_MAX_N).
 #define HHS_BATCH 16
 #define HHS_SPLIT_MAX_N 16384
 struct HhsKickItem {
