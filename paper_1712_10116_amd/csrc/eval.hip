@@ -350,8 +350,12 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_m2l(DevTree t, int n_nodes, doubl
 #pragma unroll
     for (int k = 0; k < K; ++k)
       if (!HARM || mi.z[k] <= 1) acc[k] = T(0);
+    // the next source's index is read one iteration ahead, so that the
+    // loads of a source's geometry and moments do not wait on it
+    int Bn = lane < cnt ? t.m2l_src[off + lane] : 0;
     for (int q = lane; q < cnt; q += 64) {
-      const int B = t.m2l_src[off + q];
+      const int B = Bn;
+      if (q + 64 < cnt) Bn = t.m2l_src[off + q + 64];
       const double4 gB = t.ngeo[B];
       const T X = (T)((gA.x - gB.x) * ih), Y = (T)((gA.y - gB.y) * ih),
               Z = (T)((gA.z - gB.z) * ih);
@@ -744,7 +748,7 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
   R(*sk)[64] = sink_all[w];
   // the target leaf and all that is read from it are the same in every lane:
   // kept in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(xcd_block<32>(blockIdx.x, gridDim.x) * P2P_WAVES + w);
+  const int wave = __builtin_amdgcn_readfirstlane(xcd_block<64>(blockIdx.x, gridDim.x) * P2P_WAVES + w);
   const int nwaves = gridDim.x * P2P_WAVES;
   const R eps2 = (R)(eps * eps);
   const R inv_eps = eps > 0 ? (R)(1.0 / eps) : R(0);
