@@ -265,8 +265,10 @@ def ensemble_leg(args, F, torch, line):
     reqs = [W.ensemble_request(i) for i in range(K)]
     ntot = sum(r[2].size for r in reqs)
     # leaf size by the autotuner on the serving workload itself: a short closed
-    # loop (the first 16 requests, one top-level step each) per candidate
-    probe = reqs[:16]
+    # loop (the first 64 requests, one top-level step each) per candidate; with
+    # 16 the loop is too lightly loaded to rank leaf 32 against 64 as the full
+    # stream does
+    probe = reqs[:64]
 
     def probe_run(leaf):
         sv = F.Solver(args.ensemble_max_n, p_max=prm["p"], leaf_size=leaf, kernel=prm["kernel"],

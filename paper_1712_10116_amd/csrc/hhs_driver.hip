@@ -295,7 +295,8 @@ bool advance(fmm_ctx *c, Sys &S, const hhs_params *hp, std::vector<SplitReq> &sp
 
 // The KDK halves of W waiting systems: their trees in one batched build, then
 // the kicks of the half in two batched evaluation slots (a system with no kick
-// in a slot is skipped there), each followed by its systems' kicks.  Each
+// in a slot is skipped there), each followed by its systems' kicks; the build
+// and the first slot's evaluation are one fmm_forces_batched call.  Each
 // evaluation takes the kicked set as its sinks (P2P skips leaves without one);
 // the second kickFS2S of a top-level KDK evaluates the whole system when the
 // bound of Eq. 9 needs |a|_tot.
@@ -310,8 +311,7 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
     q[w] = fmm_request{S.st->pos, S.st->n, f.sys, f.n_sys, nullptr, S.run->acc, S.run->pot};
     nk[w] = kicks_of_half(f, S.half, &kk[2 * w]);
   }
-  fmm_status e = fmm_build_batched(c, W, q.data(), hp->eps, hp->theta);
-  if (e != FMM_OK) return e;
+  fmm_status e;
   for (int slot = 0; slot < 2; ++slot) {
     bool any = false;
     for (int w = 0; w < W; ++w) {
@@ -334,9 +334,19 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
       // the kicked set's flags by joint-set position, written by the split
       q[w].sinks = all ? nullptr : K.s2f ? S.run->fflag[f.k] : S.run->sflag[f.k];
     }
-    if (!any) continue;
-    e = fmm_evaluate_batched(c, W, q.data(), hp->p);
-    if (e != FMM_OK) return e;
+    if (slot == 0) {
+      // the first slot's masses and sinks are known before the tree: one call
+      // builds and evaluates (upward pass beside the walk, the evaluation
+      // queued behind the walk without a host wait between them)
+      e = any ? fmm_forces_batched(c, W, q.data(), hp->eps, hp->theta, hp->p)
+              : fmm_build_batched(c, W, q.data(), hp->eps, hp->theta);
+      if (e != FMM_OK) return e;
+      if (!any) continue;
+    } else {
+      if (!any) continue;
+      e = fmm_evaluate_batched(c, W, q.data(), hp->p);
+      if (e != FMM_OK) return e;
+    }
     std::vector<HhsKickItem> kick_items;
     std::vector<int> norms;  // systems whose solve also gives |a|_tot
     for (int w = 0; w < W; ++w) {
