@@ -1,7 +1,8 @@
 """HHS integrator on the GPU (Sec. 2.2, Algorithms 1-3) against the oracle's
 numpy HHS driving the oracle FMM: same rungs, positions and velocities after
-several top-level steps (FP64), solver-call accounting, and total momentum
-conserved to round-off on the GPU in both precisions."""
+several top-level steps (FP64), also with joint sets past the one-workgroup
+split, solver-call accounting, and total momentum conserved to round-off on
+the GPU in both precisions."""
 import numpy as np
 import pytest
 
@@ -68,6 +69,24 @@ def test_hhs_matches_oracle(oracle, n, steps):
     np.testing.assert_allclose(gac, st.a_cur, rtol=1e-10)
     np.testing.assert_allclose(gao, st.a_old, rtol=1e-10, atol=1e-300)
     assert len(np.unique(grung)) >= 3
+
+
+def test_hhs_large_joint_set_matches_oracle(oracle):
+    """A joint set above 16,384 particles takes the multi-workgroup rung and
+    split kernels (smaller ones share one batched launch); one step of two
+    levels against the oracle, as above."""
+    pos, vel, m = W.plummer(17000, seed=1000)
+    prm = dict(PRM0)
+    prm["max_levels"] = 2
+    dt_top = 1.0 / 16
+    st, calls = _oracle_hhs(oracle, pos, vel, m, prm, 1, dt_top)
+    assert (st.rung == 1).sum() > 16384       # the fast set's own split is the large one too
+    gp, gv, grung, gao, gac, stats, inv = _gpu_hhs(pos, vel, m, prm, 1, dt_top)
+    np.testing.assert_array_equal(grung, st.rung)
+    assert [s["force_calls"] for s in stats] == calls
+    assert np.abs(gp - st.pos).max() / np.abs(pos).max() < 1e-10
+    assert np.abs(gv - st.vel).max() / np.abs(vel).max() < 1e-10
+    np.testing.assert_allclose(gac, st.a_cur, rtol=1e-10)
 
 
 def _boosted(n, seed=1000):
@@ -228,6 +247,43 @@ def test_hhs_batched_equals_solo(precision, max_n):
         assert h.t == b.t
         t.close()
     assert calls == solo_calls
+    for h in hs:
+        h.run.close()
+    s.close()
+
+
+def test_hhs_many_systems_batched_equals_solo():
+    """More systems than one batched integrator launch takes (16): 20 small
+    systems stepped together end bit-identical to each stepped alone."""
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    prm = dict(PRM0)
+    systems = [W.plummer(300 + 37 * k, seed=1100 + k) for k in range(20)]
+    dts = [1.0 / 16 if k % 3 else 1.0 / 32 for k in range(20)]
+    total = sum(m.size for _, _, m in systems)
+    s = F.Solver(total, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
+                 precision=1)
+    kw = dict(eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
+              max_levels=prm["max_levels"])
+    hs = []
+    for pos, vel, m in systems:
+        run = F.HHSRun(s, m.size, prm["max_levels"])
+        hs.append(F.HHS(s, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda(),
+                        torch.from_numpy(m).cuda(), run=run, **kw))
+    F.hhs_init_batched(s, hs)
+    F.hhs_step_batched(s, hs, dts)
+    torch.cuda.synchronize()
+    for k, (pos, vel, m) in enumerate(systems):
+        t = F.Solver(m.size, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
+                     precision=1)
+        h = F.HHS(t, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda(),
+                  torch.from_numpy(m).cuda(), **kw)
+        h.init()
+        h.step(dts[k])
+        torch.cuda.synchronize()
+        for name in ("pos", "vel", "rung", "a_old", "a_cur"):
+            assert torch.equal(getattr(h, name), getattr(hs[k], name)), (k, name)
+        t.close()
     for h in hs:
         h.run.close()
     s.close()
