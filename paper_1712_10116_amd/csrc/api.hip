@@ -155,12 +155,18 @@ extern "C" fmm_status fmm_create(const fmm_params *prm, int64_t max_n, void *str
   t.cap_n = max_n;
   int64_t n = max_n;
   int64_t cap_nodes = 8 * n / prm->leaf_size + 1024;
+  // radix histograms: one column per tile, and for sorts of at most
+  // SORT_RAW_TILES tiles one slice per pass
+  const int64_t sort_tiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const int64_t sort_hist_n =
+      256 * std::max<int64_t>(sort_tiles, SORT_MAX_PASSES * std::min<int64_t>(sort_tiles, SORT_RAW_TILES)) +
+      256;
   bool ok = dalloc(c, &t.key, n) && dalloc(c, &t.key2, n) && dalloc(c, &t.slot, n) &&
             dalloc(c, &t.slot2, n) && dalloc(c, &t.sx, n) && dalloc(c, &t.sy, n) &&
             dalloc(c, &t.sz, n) && dalloc(c, &t.sm, n) && dalloc(c, &t.sm32, n) &&
             dalloc(c, &t.leaf_of, n) && dalloc(c, &t.near, 4 * n) && dalloc(c, &t.pak, n) &&
             dalloc(c, &t.scan_part, FMM_SCAN_BLOCKS) && dalloc(c, &t.slot_req, n) &&
-            dalloc(c, &t.sort_hist, 256 * ((n + SORT_TILE - 1) / SORT_TILE) + 256) &&
+            dalloc(c, &t.sort_hist, sort_hist_n) &&
             dalloc(c, &t.sort_dtot, 256) && dalloc(c, &t.scan_blk, n / 1024 + 64) &&
             dalloc(c, &t.hdr, 1) && alloc_reqs(c, 16) && alloc_nodes(c, cap_nodes);
   if (ok) {

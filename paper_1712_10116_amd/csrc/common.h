@@ -22,6 +22,8 @@
 #define FMM_SCAN_BLOCKS 256
 #define FMM_BBOX_BLOCKS 256  // box-reduction blocks per request, at most
 #define SORT_TILE 4096       // keys per radix-sort tile (one histogram column)
+#define SORT_RAW_TILES 16    // sorts of at most this many tiles run without digit-scan launches
+#define SORT_MAX_PASSES 12   // 8 key digits + at most 4 request digits
 // single-workgroup ("small") build, walk and level passes
 #define SMALL_WAVES 8
 #define SMALL_THREADS (SMALL_WAVES * 64)

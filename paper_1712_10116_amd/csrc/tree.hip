@@ -188,12 +188,14 @@ __device__ __forceinline__ uint32_t sort_digit(const uint64_t *key, const int32_
                 : (uint32_t)(key[i] >> shift) & 255u;
 }
 
+// clear_slices > 0: also clears this tile's column of the clear_slices
+// histograms that follow hist (one per later raw pass, 256 * nblk apart)
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__restrict__ key,
                                                             const int32_t *__restrict__ slot,
                                                             const int32_t *__restrict__ slot_req,
                                                             int n, int shift, int by_req,
                                                             uint32_t *__restrict__ hist,
-                                                            int nblk) {
+                                                            int nblk, int clear_slices) {
   __shared__ uint32_t h[256];
   if (threadIdx.x < 256) h[threadIdx.x] = 0;
   __syncthreads();
@@ -204,7 +206,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_hist(const uint64_t *__re
     if (i < n) atomicAdd(&h[sort_digit(key, slot, slot_req, i, shift, by_req)], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < 256) hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < 256) {
+    hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    for (int p = 1; p <= clear_slices; ++p)
+      hist[(size_t)p * 256 * nblk + threadIdx.x * nblk + blockIdx.x] = 0u;
+  }
 }
 
 // Per-digit exclusive scan over the blocks: hist[d][0..nblk) in place, digit
@@ -320,15 +326,20 @@ __device__ __forceinline__ uint32_t scan256(uint32_t v, uint32_t *wsum) {
 // counts and each tile sums what it needs itself (no digit-scan launch);
 // raw = 0: hist holds each digit's exclusive prefix over the tiles and dtot
 // the digit totals.
-#define SORT_RAW_TILES 16
+// hist_next (raw passes but the last, else NULL): the next pass's raw counts,
+// zero on entry, are accumulated here (digit next_shift / next_by_req of each
+// element, by the tile of its destination), so that pass needs no histogram
+// launch of its own; counts do not depend on the order they are added in.
 __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const int32_t *__restrict__ sin, uint64_t *__restrict__ kout,
     int32_t *__restrict__ sout, const int32_t *__restrict__ slot_req, int n, int shift, int by_req,
-    const uint32_t *__restrict__ hist, int nblk, const uint32_t *__restrict__ dtot, int raw) {
+    const uint32_t *__restrict__ hist, int nblk, const uint32_t *__restrict__ dtot, int raw,
+    uint32_t *__restrict__ hist_next, int next_shift, int next_by_req) {
   // keys | slots | digits of the reordered tile; the per-wave digit counters
   // of the ranking step live in the front of the same space before that
   __shared__ __align__(16) unsigned char smem[SORT_TILE * 13];
   __shared__ uint32_t lstart[256], gbase[256], wsum[SORT_WAVES];
+  __shared__ uint32_t lnext[256 * SORT_RAW_TILES];  // next pass's counts, [digit][tile]
   uint64_t *skey = (uint64_t *)smem;
   int32_t *sslot = (int32_t *)(smem + 8 * SORT_TILE);
   uint8_t *sdig = smem + 12 * SORT_TILE;
@@ -414,6 +425,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
   }
   __syncthreads();
   const int tn = min(SORT_TILE, n - tile);
+  const bool count_next = hist_next != nullptr && nblk <= SORT_RAW_TILES;
+  if (count_next)
+    for (int d = tid; d < 256 * nblk; d += SORT_THREADS) lnext[d] = 0;
+  __syncthreads();
 #pragma unroll
   for (int it = 0; it < SORT_ITEMS; ++it) {
     const int j = it * SORT_THREADS + tid;
@@ -421,7 +436,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_sort_scatter(
       const uint32_t dst = gbase[sdig[j]] + (uint32_t)j;
       kout[dst] = skey[j];
       sout[dst] = sslot[j];
+      if (count_next) {
+        const uint32_t d = next_by_req ? ((uint32_t)slot_req[sslot[j]] >> next_shift) & 255u
+                                       : (uint32_t)(skey[j] >> next_shift) & 255u;
+        atomicAdd(&lnext[d * nblk + dst / SORT_TILE], 1u);
+      }
     }
+  }
+  if (count_next) {
+    __syncthreads();
+    for (int d = tid; d < 256 * nblk; d += SORT_THREADS)
+      if (lnext[d]) atomicAdd(&hist_next[d], lnext[d]);
   }
 }
 
@@ -1120,17 +1145,29 @@ hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
     // request id; an even number of passes leaves the result in key/slot
     int req_passes = 0;
     if (a.n_req > 1) req_passes = a.n_req > 65536 ? 4 : (a.n_req > 256 ? 2 : 2);
-    for (int pass = 0; pass < 8 + req_passes; ++pass) {
+    const int passes = 8 + req_passes;
+    const int raw = nblk <= SORT_RAW_TILES;
+    // raw passes: one histogram slice per pass, the first counted by
+    // k_sort_hist (which clears the others), each later one by the scatter
+    // before it
+    const int slice = 256 * nblk;
+    for (int pass = 0; pass < passes; ++pass) {
       const int by_req = pass >= 8;
       const int shift = by_req ? (pass - 8) * 8 : pass * 8;
-      hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, sin, t.slot_req, n,
-                         shift, by_req, t.sort_hist, nblk);
-      const int raw = nblk <= SORT_RAW_TILES;
+      const int nx = pass + 1;
+      const int next_by_req = nx >= 8;
+      const int next_shift = next_by_req ? (nx - 8) * 8 : nx * 8;
+      uint32_t *hist = raw ? t.sort_hist + (size_t)pass * slice : t.sort_hist;
+      uint32_t *hist_next = raw && nx < passes ? t.sort_hist + (size_t)nx * slice : nullptr;
+      if (!raw || pass == 0)
+        hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, sin, t.slot_req,
+                           n, shift, by_req, hist, nblk, raw ? passes - 1 : 0);
       if (!raw)
         hipLaunchKernelGGL(k_sort_digit_scan, dim3(256), dim3(FMM_BLOCK), 0, s, t.sort_hist, nblk,
                            t.sort_dtot);
       hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(SORT_THREADS), 0, s, kin, sin, kout, sout,
-                         t.slot_req, n, shift, by_req, t.sort_hist, nblk, t.sort_dtot, raw);
+                         t.slot_req, n, shift, by_req, hist, nblk, t.sort_dtot, raw, hist_next,
+                         next_shift, next_by_req);
       uint64_t *tk = kin; kin = kout; kout = tk;
       int32_t *ts = sin; sin = sout; sout = ts;
     }
