@@ -179,3 +179,42 @@ def test_open_loop_driver():
     assert st["p99_s"] >= st["p50_s"] > 0
     srv.close()
     s.close()
+
+
+def test_many_residents_alone_equals_mix():
+    """More residents than one batched integrator launch takes (16): 20 small
+    requests arriving in three waves while others are part-way through their
+    top-level steps end bit-identical to each served alone."""
+    from paper_1712_10116_amd import fmm as F
+    reqs = [(W.plummer if k % 2 else W.king)(200 + 23 * k, seed=7100 + k,
+                                             **({} if k % 2 else dict(henon=True)))
+            for k in range(20)]
+    t_end = [0.125 if k % 3 else 0.1875 for k in range(20)]
+    fp = sum(F.Server.footprint(m.size, PRM["max_levels"]) for _, _, m in reqs)
+    s = _solver(8192, 1)
+    alone = []
+    srv = _server(s, fp, 1)
+    for k, (pos, vel, m) in enumerate(reqs):
+        got = {}
+        rid = srv.submit(pos, vel, m, t_end[k])
+        _drain(srv, got)
+        alone.append(got[rid])
+    srv.close()
+    srv = _server(s, fp + (1 << 20), 20)
+    got, ids = {}, []
+    for wave in (range(0, 8), range(8, 15), range(15, 20)):
+        for k in wave:
+            ids.append(srv.submit(*reqs[k], t_end[k]))
+        for _ in range(3):
+            srv.step()
+            for r in srv.poll():
+                got[r["id"]] = r
+    _drain(srv, got)
+    assert len(got) == 20
+    for k, rid in enumerate(ids):
+        a, b = alone[k], got[rid]
+        assert np.array_equal(a["pos"], b["pos"]) and np.array_equal(a["vel"], b["vel"]), k
+        for f in ("steps", "force_calls", "force_particles", "dt_top", "t_end"):
+            assert a[f] == b[f], (k, f)
+    srv.close()
+    s.close()
