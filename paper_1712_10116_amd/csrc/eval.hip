@@ -748,7 +748,7 @@ __global__ __launch_bounds__(P2P_WAVES * 64, MIXED ? 4 : 2) void k_p2p(DevTree t
   R(*sk)[64] = sink_all[w];
   // the target leaf and all that is read from it are the same in every lane:
   // kept in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(xcd_block<64>(blockIdx.x, gridDim.x) * P2P_WAVES + w);
+  const int wave = __builtin_amdgcn_readfirstlane(xcd_block<32>(blockIdx.x, gridDim.x) * P2P_WAVES + w);
   const int nwaves = gridDim.x * P2P_WAVES;
   const R eps2 = (R)(eps * eps);
   const R inv_eps = eps > 0 ? (R)(1.0 / eps) : R(0);
