@@ -309,7 +309,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void k_split_batched(HhsSplitBatch B
   __shared__ int wtot[SPLIT_THREADS / 64];
   const HhsSplitItem &S = B.it[blockIdx.x];
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const unsigned long long below = lanes_below_mask();
   int carry = 0;
   for (int base = 0; base < S.n_sys; base += SPLIT_THREADS) {
     const int i = base + tid;
