@@ -49,26 +49,15 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_norm_at(const int32_t *__restrict
   out[sys[q]] = sqrt(ax * ax + ay * ay + az * az);
 }
 
-// flag[i] = 1 if sys[i] is fast at rung k (rung > k)
-__global__ __launch_bounds__(FMM_BLOCK) void k_fast_flags(const int32_t *__restrict__ sys, int n_sys,
-                                                          const int32_t *__restrict__ rung, int k,
-                                                          uint32_t *__restrict__ flag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_sys) return;
-  flag[i] = rung[sys[i]] > k ? 1u : 0u;
-}
-
 // stable partition of sys into slow and fast lists (+ positions within sys);
 // pre = exclusive scan of the fast flags; count[0] = number of fast; per
 // position i of sys, fflag[i] = 1 when fast and sflag[i] = 1 when slow (the
 // sink flags of the two kicks of a KDK half)
-__global__ __launch_bounds__(FMM_BLOCK) void k_split_scatter(
-    const int32_t *__restrict__ sys, int n_sys, const int32_t *__restrict__ rung, int k,
+__device__ __forceinline__ void split_scatter_at(
+    int i, const int32_t *__restrict__ sys, int n_sys, const int32_t *__restrict__ rung, int k,
     const uint32_t *__restrict__ pre, int32_t *__restrict__ slow, int32_t *__restrict__ slow_pos,
     int32_t *__restrict__ fast, int32_t *__restrict__ fast_pos, int32_t *__restrict__ count,
     uint8_t *__restrict__ fflag, uint8_t *__restrict__ sflag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_sys) return;
   int p = sys[i];
   int f = (int)pre[i];
   const bool is_fast = rung[p] > k;
@@ -84,17 +73,68 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_split_scatter(
   if (i == n_sys - 1) count[0] = f + (is_fast ? 1 : 0);
 }
 
-// out[p] = mass[p] for the slow particles of the joint set sys, 0 for the
-// fast ones (fflag per position of sys)
-__global__ __launch_bounds__(FMM_BLOCK) void k_masked_mass(const int32_t *__restrict__ sys,
-                                                           int n_sys,
-                                                           const uint8_t *__restrict__ fflag,
-                                                           const double *__restrict__ mass,
-                                                           double *__restrict__ out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_sys) return;
-  const int p = sys[i];
-  out[p] = fflag[i] ? 0.0 : mass[p];
+// Exclusive scan of m uint32 values in place (any m), over tiles of
+// SCAN_TILE: the tiles' sums, an exclusive scan of the sums, then each tile's
+// own scan plus its offset.  One workgroup of FMM_BLOCK threads per tile (per
+// scan for the sums).
+#define SCAN_TILE 1024
+__device__ __forceinline__ void scan_tile_sum(const uint32_t *v, int m, uint32_t *part, int b) {
+  __shared__ uint32_t r[FMM_BLOCK];
+  const int base = b * SCAN_TILE;
+  uint32_t s = 0;
+  for (int i = base + threadIdx.x; i < min(m, base + SCAN_TILE); i += FMM_BLOCK) s += v[i];
+  r[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = FMM_BLOCK / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) r[threadIdx.x] += r[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[b] = r[0];
+}
+
+__device__ __forceinline__ void scan_tile_sums(uint32_t *part, int nb) {
+  __shared__ uint32_t v[FMM_BLOCK];
+  uint32_t run = 0;
+  for (int base = 0; base < nb; base += FMM_BLOCK) {
+    int i = base + threadIdx.x;
+    uint32_t x = i < nb ? part[i] : 0u;
+    v[threadIdx.x] = x;
+    __syncthreads();
+    for (int off = 1; off < FMM_BLOCK; off <<= 1) {
+      uint32_t y = threadIdx.x >= off ? v[threadIdx.x - off] : 0u;
+      __syncthreads();
+      v[threadIdx.x] += y;
+      __syncthreads();
+    }
+    if (i < nb) part[i] = run + v[threadIdx.x] - x;
+    run += v[FMM_BLOCK - 1];
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void scan_tile_down(uint32_t *v, int m, const uint32_t *part, int b) {
+  __shared__ uint32_t w[FMM_BLOCK];
+  const int base = b * SCAN_TILE + threadIdx.x * 4;
+  uint32_t x[4], s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    x[k] = base + k < m ? v[base + k] : 0u;
+    s += x[k];
+  }
+  w[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < FMM_BLOCK; off <<= 1) {
+    uint32_t y = threadIdx.x >= off ? w[threadIdx.x - off] : 0u;
+    __syncthreads();
+    w[threadIdx.x] += y;
+    __syncthreads();
+  }
+  uint32_t run = part[b] + w[threadIdx.x] - s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < m) v[base + k] = run;
+    run += x[k];
+  }
 }
 
 __global__ __launch_bounds__(FMM_BLOCK) void k_iota(int32_t *__restrict__ v, int n) {
@@ -299,6 +339,17 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_drift_batched(HhsDriftBatch B) {
   D.pos[2 * n + p] += D.vel[2 * n + p] * D.dt;
 }
 
+// out[p] = mass[p] for the slow particles of a joint set, 0 for the fast ones
+// (fflag per position of the joint set)
+__global__ __launch_bounds__(FMM_BLOCK) void k_masked_mass_batched(HhsMaskBatch B) {
+  const int w = batch_item(B.blk0, B.count, blockIdx.x);
+  const HhsMaskItem &M = B.it[w];
+  const int i = (blockIdx.x - B.blk0[w]) * FMM_BLOCK + threadIdx.x;
+  if (i >= M.n_sys) return;
+  const int p = M.sys[i];
+  M.out[p] = M.fflag[i] ? 0.0 : M.mass[p];
+}
+
 // Rungs (when asked) and the stable slow/fast split of one joint set per
 // workgroup: per tile, each thread's fast flag, the tile's exclusive scan
 // (wave ballots, then the waves' totals), and the scatter with the fast count
@@ -354,6 +405,52 @@ __global__ __launch_bounds__(SPLIT_THREADS) void k_split_batched(HhsSplitBatch B
   if (tid == 0) S.count[0] = carry;
 }
 
+// Joint sets beyond one workgroup's reach: the multi-workgroup split (rung
+// assignment fused with the fast flags, the tiled scan, the scatter) of up
+// to HHS_BATCH systems per launch.  Element kernels: block b serves item w
+// with eblk0[w] <= b < eblk0[w + 1] (blocks of FMM_BLOCK elements); tile
+// kernels likewise over tblk0 (tiles of SCAN_TILE elements); the tile sums
+// of item w are scanned by block w.
+__global__ __launch_bounds__(FMM_BLOCK) void k_bigsplit_flags(HhsBigSplitBatch B) {
+  const int w = batch_item(B.eblk0, B.count, blockIdx.x);
+  const HhsSplitItem &S = B.it[w];
+  const int i = (blockIdx.x - B.eblk0[w]) * FMM_BLOCK + threadIdx.x;
+  if (i >= S.n_sys) return;
+  const int p = S.sys[i];
+  int r;
+  if (S.do_rungs) {
+    r = rung_of(p, S.a_old, S.a_cur, S.a_tot, S.dt_top, S.eta_eps, S.eta1_eps, S.max_levels);
+    S.rung[p] = r;
+  } else {
+    r = S.rung[p];
+  }
+  B.flag[w][i] = r > S.k ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_bigsplit_reduce(HhsBigSplitBatch B) {
+  const int w = batch_item(B.tblk0, B.count, blockIdx.x);
+  scan_tile_sum(B.flag[w], B.it[w].n_sys, B.part[w], blockIdx.x - B.tblk0[w]);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_bigsplit_partials(HhsBigSplitBatch B) {
+  const int w = blockIdx.x;
+  scan_tile_sums(B.part[w], B.tblk0[w + 1] - B.tblk0[w]);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_bigsplit_down(HhsBigSplitBatch B) {
+  const int w = batch_item(B.tblk0, B.count, blockIdx.x);
+  scan_tile_down(B.flag[w], B.it[w].n_sys, B.part[w], blockIdx.x - B.tblk0[w]);
+}
+
+__global__ __launch_bounds__(FMM_BLOCK) void k_bigsplit_scatter(HhsBigSplitBatch B) {
+  const int w = batch_item(B.eblk0, B.count, blockIdx.x);
+  const HhsSplitItem &S = B.it[w];
+  const int i = (blockIdx.x - B.eblk0[w]) * FMM_BLOCK + threadIdx.x;
+  if (i < S.n_sys)
+    split_scatter_at(i, S.sys, S.n_sys, S.rung, S.k, B.flag[w], S.slow, S.slow_pos, S.fast,
+                     S.fast_pos, S.count, S.fflag, S.sflag);
+}
+
 #define NB(n) dim3((unsigned)(((n) + FMM_BLOCK - 1) / FMM_BLOCK))
 
 void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const double *a_cur,
@@ -368,24 +465,6 @@ void hhs_launch_norm_at(const int32_t *sys, int n_sys, const double *acc, double
                         hipStream_t s) {
   if (n_sys > 0)
     hipLaunchKernelGGL(k_norm_at, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, acc, out);
-}
-
-void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
-                      uint32_t *scan_part, int32_t *slow, int32_t *slow_pos, int32_t *fast,
-                      int32_t *fast_pos, int32_t *count, uint8_t *fflag, uint8_t *sflag,
-                      hipStream_t s) {
-  if (n_sys <= 0) return;
-  hipLaunchKernelGGL(k_fast_flags, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, rung, k, flag);
-  hhs_launch_scan_u32(flag, n_sys, scan_part, s);
-  hipLaunchKernelGGL(k_split_scatter, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, rung, k, flag,
-                     slow, slow_pos, fast, fast_pos, count, fflag, sflag);
-}
-
-void hhs_launch_masked_mass(const int32_t *sys, int n_sys, const uint8_t *fflag,
-                            const double *mass, double *out, hipStream_t s) {
-  if (n_sys > 0)
-    hipLaunchKernelGGL(k_masked_mass, NB(n_sys), dim3(FMM_BLOCK), 0, s, sys, n_sys, fflag, mass,
-                       out);
 }
 
 void hhs_launch_iota(int32_t *v, int n, hipStream_t s) {
@@ -481,6 +560,52 @@ void hhs_launch_splits(const HhsSplitItem *items, int n_items, hipStream_t s) {
   for (int j = 0; j < n_items; ++j) {
     if (items[j].n_sys <= 0) continue;
     B.it[B.count] = items[j];
+    if (++B.count == HHS_BATCH) flush();
+  }
+  flush();
+}
+
+void hhs_launch_masked_masses(const HhsMaskItem *items, int n_items, hipStream_t s) {
+  HhsMaskBatch B;
+  B.count = 0;
+  B.blk0[0] = 0;
+  auto flush = [&]() {
+    if (B.count > 0)
+      hipLaunchKernelGGL(k_masked_mass_batched, dim3(B.blk0[B.count]), dim3(FMM_BLOCK), 0, s, B);
+    B.count = 0;
+  };
+  for (int j = 0; j < n_items; ++j) {
+    if (items[j].n_sys <= 0) continue;
+    B.it[B.count] = items[j];
+    B.blk0[B.count + 1] = B.blk0[B.count] + (items[j].n_sys + FMM_BLOCK - 1) / FMM_BLOCK;
+    if (++B.count == HHS_BATCH) flush();
+  }
+  flush();
+}
+
+void hhs_launch_big_splits(const HhsSplitItem *items, uint32_t *const *flags,
+                           uint32_t *const *parts, int n_items, hipStream_t s) {
+  HhsBigSplitBatch B;
+  B.count = 0;
+  B.eblk0[0] = B.tblk0[0] = 0;
+  auto flush = [&]() {
+    if (B.count == 0) return;
+    const dim3 eg(B.eblk0[B.count]), tg(B.tblk0[B.count]), blk(FMM_BLOCK);
+    hipLaunchKernelGGL(k_bigsplit_flags, eg, blk, 0, s, B);
+    hipLaunchKernelGGL(k_bigsplit_reduce, tg, blk, 0, s, B);
+    hipLaunchKernelGGL(k_bigsplit_partials, dim3(B.count), blk, 0, s, B);
+    hipLaunchKernelGGL(k_bigsplit_down, tg, blk, 0, s, B);
+    hipLaunchKernelGGL(k_bigsplit_scatter, eg, blk, 0, s, B);
+    B.count = 0;
+  };
+  for (int j = 0; j < n_items; ++j) {
+    const int m = items[j].n_sys;
+    if (m <= 0) continue;
+    B.it[B.count] = items[j];
+    B.flag[B.count] = flags[j];
+    B.part[B.count] = parts[j];
+    B.eblk0[B.count + 1] = B.eblk0[B.count] + (m + FMM_BLOCK - 1) / FMM_BLOCK;
+    B.tblk0[B.count + 1] = B.tblk0[B.count] + (m + SCAN_TILE - 1) / SCAN_TILE;
     if (++B.count == HHS_BATCH) flush();
   }
   flush();

@@ -314,6 +314,7 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
   fmm_status e;
   for (int slot = 0; slot < 2; ++slot) {
     bool any = false;
+    std::vector<HhsMaskItem> masks;
     for (int w = 0; w < W; ++w) {
       Sys &S = *sys[grp[w]];
       const Frame &f = S.stack.back();
@@ -322,8 +323,7 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
       any = true;
       const Kick &K = kk[2 * w + slot];
       if (K.s2f) {
-        hhs_launch_masked_mass(f.sys, f.n_sys, S.run->fflag[f.k], S.st->mass, S.run->mmask,
-                               c->stream);
+        masks.push_back(HhsMaskItem{f.sys, S.run->fflag[f.k], S.st->mass, S.run->mmask, f.n_sys});
         q[w].mass = S.run->mmask;
       } else {
         q[w].mass = S.st->mass;
@@ -334,6 +334,7 @@ static fmm_status serve_half(fmm_ctx *c, HhsSys *const *sys, const int *grp, int
       // the kicked set's flags by joint-set position, written by the split
       q[w].sinks = all ? nullptr : K.s2f ? S.run->fflag[f.k] : S.run->sflag[f.k];
     }
+    hhs_launch_masked_masses(masks.data(), (int)masks.size(), c->stream);
     if (slot == 0) {
       // the first slot's masses and sinks are known before the tree: one call
       // builds and evaluates (upward pass beside the walk, the evaluation
@@ -497,7 +498,8 @@ fmm_status hhs_sys_advance(fmm_ctx *c, HhsSys *const *sys, int n_sys, const hhs_
   fmm_status e = ensure_split_slots(c, ns);
   if (e != FMM_OK) return e;
   std::vector<SplitReq> splits;
-  std::vector<HhsSplitItem> small;
+  std::vector<HhsSplitItem> small, big;
+  std::vector<uint32_t *> big_flag, big_part;
   std::vector<HhsDriftItem> drifts;
   for (int i = 0; i < n_sys; ++i)
     if (sys[i]->state == S_RUN && !advance(c, *sys[i], hp, splits, drifts))
@@ -515,13 +517,12 @@ fmm_status hhs_sys_advance(fmm_ctx *c, HhsSys *const *sys, int n_sys, const hhs_
       small.push_back(it);
       continue;
     }
-    if (it.do_rungs)
-      hhs_launch_rungs(it.sys, it.n_sys, it.a_old, it.a_cur, it.a_tot, it.rung, it.dt_top,
-                       it.eta_eps, it.eta1_eps, it.max_levels, c->stream);
-    hhs_launch_split(it.sys, it.n_sys, it.rung, it.k, q.run->flag, q.run->scan_part, it.slow,
-                     it.slow_pos, it.fast, it.fast_pos, it.count, it.fflag, it.sflag, c->stream);
+    big.push_back(it);
+    big_flag.push_back(q.run->flag);
+    big_part.push_back(q.run->scan_part);
   }
   hhs_launch_splits(small.data(), (int)small.size(), c->stream);
+  hhs_launch_big_splits(big.data(), big_flag.data(), big_part.data(), (int)big.size(), c->stream);
   return FMM_OK;
 }
 

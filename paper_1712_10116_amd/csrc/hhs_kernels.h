@@ -1,10 +1,8 @@
-// Launchers of the HHS and reduction kernels (hhs.hip) and the shared
-// single-workgroup scan (tree.hip).
+// Launchers of the HHS and reduction kernels (hhs.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-void hhs_launch_scan_u32(uint32_t *v, int m, uint32_t *part, hipStream_t s);
 // a_tot NULL: the bound of Eq. 9 is off
 void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const double *a_cur,
                       const double *a_tot, int32_t *rung, double dt_top, double eta_eps,
@@ -12,15 +10,6 @@ void hhs_launch_rungs(const int32_t *sys, int n_sys, const double *a_old, const 
 // out[sys[q]] = |a| of row q of acc (SoA, n_sys rows)
 void hhs_launch_norm_at(const int32_t *sys, int n_sys, const double *acc, double *out,
                         hipStream_t s);
-// stable split of the joint set sys at rung k; fflag / sflag (n_sys bytes):
-// 1 at the positions of its fast / slow particles
-void hhs_launch_split(const int32_t *sys, int n_sys, const int32_t *rung, int k, uint32_t *flag,
-                      uint32_t *scan_part, int32_t *slow, int32_t *slow_pos, int32_t *fast,
-                      int32_t *fast_pos, int32_t *count, uint8_t *fflag, uint8_t *sflag,
-                      hipStream_t s);
-// out[sys[i]] = 0 where fflag[i], else mass[sys[i]] (the rest of out untouched)
-void hhs_launch_masked_mass(const int32_t *sys, int n_sys, const uint8_t *fflag,
-                            const double *mass, double *out, hipStream_t s);
 void hhs_launch_iota(int32_t *v, int n, hipStream_t s);
 void hhs_launch_amag(const double *acc, int64_t n, double *a_cur, double *a_old, hipStream_t s);
 // Individual-timestep integrator: cnt[k] = particles on rung k (32 ints,
@@ -45,8 +34,9 @@ void launch_invariants(const double *pos, const double *vel, const double *mass,
                        const double *acc, const double *pot, int64_t n, double *part, int nblk,
                        hipStream_t s);
 
-// Batched launches: the kicks, drifts or rung assignments + splits of many
-// systems (items with an empty set are skipped), HHS_BATCH systems per launch.
+// Batched launches: the kicks, drifts, masked masses or rung assignments +
+// splits of many systems (items with an empty set are skipped), HHS_BATCH
+// systems per launch.
 // Kick: vel[p] += acc[q] dt for p = set[i], q = setpos[i] (acc SoA with
 // n_joint rows, vel with n), and amag[p] = |acc[q]| when amag is not NULL.
 // Drift: pos[p] += vel[p] dt for p = set[i].  Split: the arguments of
@@ -94,6 +84,34 @@ struct HhsSplitBatch {
   HhsSplitItem it[HHS_BATCH];
   int count;
 };
+// Splits of joint sets beyond HHS_SPLIT_MAX_N: the split items plus each
+// system's flag (n_sys) and tile-sum (n_sys / 1024 + 1) scratch.
+struct HhsBigSplitBatch {
+  HhsSplitItem it[HHS_BATCH];
+  uint32_t *flag[HHS_BATCH], *part[HHS_BATCH];
+  int eblk0[HHS_BATCH + 1], tblk0[HHS_BATCH + 1];
+  int count;
+};
+// by-value kernel arguments stay within the 4 KiB that a launch carries
+static_assert(sizeof(HhsBigSplitBatch) <= 4096 && sizeof(HhsSplitBatch) <= 4096,
+              "batch exceeds the kernel argument space");
+// Masked masses of kickS2F: out[sys[i]] = 0 where fflag[i], else mass[sys[i]]
+// (the rest of out untouched).
+struct HhsMaskItem {
+  const int32_t *sys;
+  const uint8_t *fflag;
+  const double *mass;
+  double *out;
+  int n_sys;
+};
+struct HhsMaskBatch {
+  HhsMaskItem it[HHS_BATCH];
+  int blk0[HHS_BATCH + 1];
+  int count;
+};
 void hhs_launch_kicks(const HhsKickItem *items, int n_items, hipStream_t s);
 void hhs_launch_drifts(const HhsDriftItem *items, int n_items, hipStream_t s);
 void hhs_launch_splits(const HhsSplitItem *items, int n_items, hipStream_t s);
+void hhs_launch_masked_masses(const HhsMaskItem *items, int n_items, hipStream_t s);
+void hhs_launch_big_splits(const HhsSplitItem *items, uint32_t *const *flags,
+                           uint32_t *const *parts, int n_items, hipStream_t s);

@@ -238,68 +238,6 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_sort_digit_scan(uint32_t *hist, i
   if (threadIdx.x == 0) dtot[blockIdx.x] = run;
 }
 
-// Generic exclusive scan of m uint32 values (three launches, any m):
-// block sums, scan of the block sums, block-local scans plus offsets.
-#define SCAN_TILE 1024
-__global__ __launch_bounds__(FMM_BLOCK) void k_scan_reduce(const uint32_t *v, int m, uint32_t *part) {
-  __shared__ uint32_t r[FMM_BLOCK];
-  int base = blockIdx.x * SCAN_TILE;
-  uint32_t s = 0;
-  for (int i = base + threadIdx.x; i < min(m, base + SCAN_TILE); i += FMM_BLOCK) s += v[i];
-  r[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = FMM_BLOCK / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) r[threadIdx.x] += r[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = r[0];
-}
-
-__global__ __launch_bounds__(FMM_BLOCK) void k_scan_partials(uint32_t *part, int nb) {
-  __shared__ uint32_t v[FMM_BLOCK];
-  uint32_t run = 0;
-  for (int base = 0; base < nb; base += FMM_BLOCK) {
-    int i = base + threadIdx.x;
-    uint32_t x = i < nb ? part[i] : 0u;
-    v[threadIdx.x] = x;
-    __syncthreads();
-    for (int off = 1; off < FMM_BLOCK; off <<= 1) {
-      uint32_t y = threadIdx.x >= off ? v[threadIdx.x - off] : 0u;
-      __syncthreads();
-      v[threadIdx.x] += y;
-      __syncthreads();
-    }
-    if (i < nb) part[i] = run + v[threadIdx.x] - x;
-    run += v[FMM_BLOCK - 1];
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(FMM_BLOCK) void k_scan_down(uint32_t *v, int m, const uint32_t *part) {
-  __shared__ uint32_t w[FMM_BLOCK];
-  const int base = blockIdx.x * SCAN_TILE + threadIdx.x * 4;
-  uint32_t x[4], s = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    x[k] = base + k < m ? v[base + k] : 0u;
-    s += x[k];
-  }
-  w[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < FMM_BLOCK; off <<= 1) {
-    uint32_t y = threadIdx.x >= off ? w[threadIdx.x - off] : 0u;
-    __syncthreads();
-    w[threadIdx.x] += y;
-    __syncthreads();
-  }
-  uint32_t run = part[blockIdx.x] + w[threadIdx.x] - s;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (base + k < m) v[base + k] = run;
-    run += x[k];
-  }
-}
-
 // Exclusive scan of one value per thread over threads 0..255 of a block
 // (the others pass 0 and get 0); every thread of the block must call it.
 __device__ __forceinline__ uint32_t scan256(uint32_t v, uint32_t *wsum) {
@@ -1223,10 +1161,4 @@ hipError_t launch_build_tree(const DevTree &t, const BuildArgs &a, int max_level
   return hipGetLastError();
 }
 
-void hhs_launch_scan_u32(uint32_t *v, int m, uint32_t *part, hipStream_t s) {
-  if (m <= 0) return;
-  const int nb = (m + SCAN_TILE - 1) / SCAN_TILE;
-  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(FMM_BLOCK), 0, s, v, m, part);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(FMM_BLOCK), 0, s, part, nb);
-  hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(FMM_BLOCK), 0, s, v, m, part);
-}
+
