@@ -289,6 +289,48 @@ def test_hhs_many_systems_batched_equals_solo():
     s.close()
 
 
+def test_hhs_large_systems_batched_equals_solo():
+    """Several joint sets above 16,384 particles split in one batched
+    multi-workgroup launch sequence (beside a small set in the single-workgroup
+    one): each system ends bit-identical to the same system stepped alone."""
+    import torch
+    from paper_1712_10116_amd import fmm as F
+    prm = dict(PRM0)
+    prm["max_levels"] = 2
+    sizes = [17000, 2000, 20500, 16500]
+    systems = [W.plummer(n, seed=1200 + k) for k, n in enumerate(sizes)]
+    dts = [1.0 / 16, 1.0 / 16, 1.0 / 32, 1.0 / 16]
+    s = F.Solver(sum(sizes), p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
+                 precision=1)
+    kw = dict(eps=prm["eps"], theta=prm["theta"], p=prm["p"], eta=prm["eta"],
+              max_levels=prm["max_levels"])
+    hs = []
+    for pos, vel, m in systems:
+        run = F.HHSRun(s, m.size, prm["max_levels"])
+        hs.append(F.HHS(s, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda(),
+                        torch.from_numpy(m).cuda(), run=run, **kw))
+    F.hhs_init_batched(s, hs)
+    F.hhs_step_batched(s, hs, dts)
+    torch.cuda.synchronize()
+    big = 0
+    for k, (pos, vel, m) in enumerate(systems):
+        t = F.Solver(m.size, p_max=prm["p"], leaf_size=prm["leaf_size"], kernel=prm["kernel"],
+                     precision=1)
+        h = F.HHS(t, torch.from_numpy(pos.copy()).cuda(), torch.from_numpy(vel.copy()).cuda(),
+                  torch.from_numpy(m).cuda(), **kw)
+        h.init()
+        h.step(dts[k])
+        torch.cuda.synchronize()
+        for name in ("pos", "vel", "rung", "a_old", "a_cur"):
+            assert torch.equal(getattr(h, name), getattr(hs[k], name)), (k, name)
+        big += m.size > 16384
+        t.close()
+    assert big == 3
+    for h in hs:
+        h.run.close()
+    s.close()
+
+
 def test_hhs_eq9_matches_oracle(oracle):
     """The total-acceleration bound of Eq. (9) binding on part of the system."""
     pos, vel, m = W.plummer(1024, seed=1000)
