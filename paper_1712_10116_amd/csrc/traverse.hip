@@ -28,7 +28,7 @@
 
 #define TRAV_WAVES 2
 #define TRAV_CAND 512   // expanded candidates of one block of 64 open-list entries
-#define TRAV_STACK 2048 // descent items (target tag in the top 3 bits)
+#define TRAV_STACK 768  // descent items (target tag in the top 3 bits)
 // Room kept free for single-item (depth-first) pops: each pops one item and
 // pushes at most its 8 children, one level deeper, so a depth-first run from
 // any state grows the stack by at most 7 per level below it.
