@@ -155,7 +155,7 @@ __device__ __forceinline__ uint64_t quantise(double x, double o, double s) {
   return (uint64_t)q;
 }
 
-__device__ __forceinline__ void make_key(const DevTree &t, int s) {
+__device__ __forceinline__ void make_key(const DevTree &t, int s, uint64_t *key, int32_t *slot) {
   const int r = t.slot_req[s];
   const DevReq q = t.reqs[r];
   const int i = s - q.off;
@@ -165,14 +165,16 @@ __device__ __forceinline__ void make_key(const DevTree &t, int s) {
   uint64_t qx = quantise(x, bx.o[0], bx.s);
   uint64_t qy = quantise(y, bx.o[1], bx.s);
   uint64_t qz = quantise(z, bx.o[2], bx.s);
-  t.key[s] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
-  t.slot[s] = s;
+  key[s] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+  slot[s] = s;
   t.pak[s] = make_double4(x, y, z, 0.0);
 }
 
-__global__ __launch_bounds__(FMM_BLOCK) void k_keys(DevTree t, int n) {
+// keys and slots into key2 / slot2 when the sort that follows makes an odd
+// number of passes (so that its result lands in key / slot)
+__global__ __launch_bounds__(FMM_BLOCK) void k_keys(DevTree t, int n, int odd) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < n) make_key(t, s);
+  if (s < n) make_key(t, s, odd ? t.key2 : t.key, odd ? t.slot2 : t.slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -909,7 +911,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_build_small(DevTree t, int n,
   }
   if (__syncthreads_or(bad) && tid == 0) h->nonfinite = 1;
   for (int r = tid; r < t.n_req; r += T) root_init(t, r, leaf_size);
-  for (int q = tid; q < n; q += T) make_key(t, q);
+  for (int q = tid; q < n; q += T) make_key(t, q, t.key, t.slot);
   __syncthreads();
   if (n <= T) {
     // at most one particle per thread: the rank of (request, key, slot) among
@@ -1075,15 +1077,17 @@ hipError_t launch_sort(const DevTree &t, const BuildArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_tree_init, dim3((a.n_req + FMM_BLOCK - 1) / FMM_BLOCK), dim3(FMM_BLOCK), 0,
                      s, t, a.leaf_size);
   if (n > 0) {
-    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n);
     const int nblk = (n + SORT_TILE - 1) / SORT_TILE;
-    uint64_t *kin = t.key, *kout = t.key2;
-    int32_t *sin = t.slot, *sout = t.slot2;
-    // 8 passes over the 63-bit key, then (several requests) passes over the
-    // request id; an even number of passes leaves the result in key/slot
+    // 8 passes over the 63-bit key, then (several requests) one pass per byte
+    // of the largest request id; with an odd number of passes the keys start
+    // in key2 / slot2, so that the result always lands in key / slot
     int req_passes = 0;
-    if (a.n_req > 1) req_passes = a.n_req > 65536 ? 4 : (a.n_req > 256 ? 2 : 2);
+    if (a.n_req > 1) req_passes = a.n_req > 65536 ? 4 : (a.n_req > 256 ? 2 : 1);
     const int passes = 8 + req_passes;
+    const int odd = passes & 1;
+    hipLaunchKernelGGL(k_keys, dim3(nb), dim3(FMM_BLOCK), 0, s, t, n, odd);
+    uint64_t *kin = odd ? t.key2 : t.key, *kout = odd ? t.key : t.key2;
+    int32_t *sin = odd ? t.slot2 : t.slot, *sout = odd ? t.slot : t.slot2;
     const int raw = nblk <= SORT_RAW_TILES;
     // raw passes: one histogram slice per pass, the first counted by
     // k_sort_hist (which clears the others), each later one by the scatter
