@@ -353,8 +353,8 @@ __global__ __launch_bounds__(FMM_BLOCK) void k_masked_mass_batched(HhsMaskBatch 
 // Rungs (when asked) and the stable slow/fast split of one joint set per
 // workgroup: per tile, each thread's fast flag, the tile's exclusive scan
 // (wave ballots, then the waves' totals), and the scatter with the fast count
-// of the earlier tiles carried along.  The same outputs as hhs_launch_rungs
-// followed by hhs_launch_split.
+// of the earlier tiles carried along.  The same outputs as the five
+// multi-workgroup launches of hhs_launch_big_splits.
 #define SPLIT_THREADS 1024
 __global__ __launch_bounds__(SPLIT_THREADS) void k_split_batched(HhsSplitBatch B) {
   __shared__ int wtot[SPLIT_THREADS / 64];

@@ -39,10 +39,11 @@ void launch_invariants(const double *pos, const double *vel, const double *mass,
 // systems per launch.
 // Kick: vel[p] += acc[q] dt for p = set[i], q = setpos[i] (acc SoA with
 // n_joint rows, vel with n), and amag[p] = |acc[q]| when amag is not NULL.
-// Drift: pos[p] += vel[p] dt for p = set[i].  Split: the arguments of
-// hhs_launch_rungs (used when do_rungs) and hhs_launch_split for one joint
-// set, whose split runs in one workgroup (meant for sets of at most
-// HHS_SPLIT_MAX_N).
+// Drift: pos[p] += vel[p] dt for p = set[i].  Split: the rung assignment
+// (when do_rungs; the rule of hhs_launch_rungs) and the stable slow/fast
+// split of one joint set at rung k; one workgroup per set up to
+// HHS_SPLIT_MAX_N, the multi-workgroup launches of hhs_launch_big_splits
+// beyond.
 #define HHS_BATCH 16
 #define HHS_SPLIT_MAX_N 16384
 struct HhsKickItem {
