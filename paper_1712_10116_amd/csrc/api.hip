@@ -205,6 +205,7 @@ extern "C" fmm_status fmm_destroy(fmm_ctx *c) {
     if (c->up_ev[k]) (void)hipEventDestroy(c->up_ev[k]);
   }
   if (c->pin_hdr) (void)hipHostFree(c->pin_hdr);
+  if (c->pin_split) (void)hipHostFree(c->pin_split);
   if (c->side) {
     (void)hipStreamSynchronize(c->side);
     (void)hipStreamDestroy(c->side);

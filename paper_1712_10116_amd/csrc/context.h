@@ -50,7 +50,7 @@ struct fmm_ctx {
   hhs_run *own_run;       // scratch of hhs_init / hhs_step (one system)
   int32_t *split_cnt;     // [cap_split] fast-set sizes of pending splits
   int cap_split;
-  std::vector<int32_t> h_split;
+  int32_t *pin_split;     // [cap_split] pinned destination of split-count readbacks
   double *inv_part;
   double *dvec;            // [3][max_n] sorted source vectors of the vector-source pass
                            // (allocated by its first call)

@@ -390,8 +390,15 @@ static fmm_status ensure_split_slots(fmm_ctx *c, int n) {
   if (n <= c->cap_split) return FMM_OK;
   if (c->split_cnt) fmm_dfree(c, c->split_cnt);
   c->split_cnt = nullptr;
-  int cap = std::max(n, 2 * c->cap_split);
+  const int cap = std::max(n, 2 * c->cap_split);
+  if (c->pin_split) (void)hipHostFree(c->pin_split);
+  c->pin_split = nullptr;
+  c->cap_split = 0;
   if (!fmm_dalloc(c, &c->split_cnt, cap)) return fmm_fail(c, FMM_ENOMEM, "split counters");
+  if (hipHostMalloc((void **)&c->pin_split, sizeof(int32_t) * cap) != hipSuccess) {
+    c->pin_split = nullptr;
+    return fmm_fail(c, FMM_ENOMEM, "split readback buffer");
+  }
   c->cap_split = cap;
   return FMM_OK;
 }
@@ -537,14 +544,14 @@ fmm_status hhs_sys_serve(fmm_ctx *c, HhsSys *const *sys, int n_sys, const hhs_pa
       ns = std::max(ns, sys[i]->slot + 1);
     }
   if (!wait.empty()) {  // one readback for every pending split
-    if ((int)c->h_split.size() < ns) c->h_split.resize(ns);
-    if (hipMemcpyAsync(c->h_split.data(), c->split_cnt, sizeof(int32_t) * ns,
+    if (ns > c->cap_split) return fmm_fail(c, FMM_EINVAL, "split slot beyond the counters");
+    if (hipMemcpyAsync(c->pin_split, c->split_cnt, sizeof(int32_t) * ns,
                        hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
       return fmm_fail(c, FMM_EDEVICE, "split readback failed");
     for (int i : wait) {
       Frame &f = sys[i]->stack.back();
-      f.n_fast = c->h_split[sys[i]->slot];
+      f.n_fast = c->pin_split[sys[i]->slot];
       f.n_slow = f.n_sys - f.n_fast;
       sys[i]->state = S_RUN;
     }
@@ -702,10 +709,11 @@ extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp,
     hhs_launch_rungs(r->all_idx, (int)n, st->a_old, st->a_cur, nullptr, st->rung, dt_top,
                      hp->eta * hp->eps, 0.0, hp->max_levels, s);
   trad_launch_rung_hist(st->rung, n, c->split_cnt, s);
-  int32_t cnt[32];
-  if (hipMemcpyAsync(cnt, c->split_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s) != hipSuccess ||
+  if (hipMemcpyAsync(c->pin_split, c->split_cnt, sizeof(int32_t) * 32, hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fmm_fail(c, FMM_EDEVICE, "rung readback failed");
+  const int32_t *cnt = c->pin_split;
   int R = 0;
   for (int k = 0; k < 32; ++k) {
     if (cnt[k] < 0 || (cnt[k] > 0 && k >= hp->max_levels))
