@@ -713,7 +713,8 @@ extern "C" fmm_status trad_step(fmm_ctx *c, hhs_state *st, const hhs_params *hp,
                      s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fmm_fail(c, FMM_EDEVICE, "rung readback failed");
-  const int32_t *cnt = c->pin_split;
+  int32_t cnt[32];  // kept for the ticks below, whatever later calls do with the buffer
+  std::copy(c->pin_split, c->pin_split + 32, cnt);
   int R = 0;
   for (int k = 0; k < 32; ++k) {
     if (cnt[k] < 0 || (cnt[k] > 0 && k >= hp->max_levels))
